@@ -1,0 +1,311 @@
+"""Pins for the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: modularity is pinned by closed
+forms (Eq. 1), Eq. 2 by exact differences of the pinned Eq. 1, the whole
+pipeline by exhaustive search over all partitions of small graphs, by planted
+partitions it must recover, and by the Leiden invariants (nesting,
+connectivity, Alg. 5).
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _graph_from_case(c):
+    kind = c["graph"]
+    if kind == "cliques_with_bridge":
+        g = gen.cliques_with_bridge(c["s"])
+        blocks = np.repeat(np.arange(2), c["s"])
+    elif kind == "ring_of_cliques":
+        g = gen.ring_of_cliques(c["k"], c["s"])
+        blocks = np.repeat(np.arange(c["k"]), c["s"])
+    elif kind == "disjoint_cliques":
+        edges = []
+        for q in range(c["k"]):
+            edges += gen.clique_edges(range(q * c["s"], (q + 1) * c["s"]))
+        g = gen.from_edges(c["k"] * c["s"], edges)
+        blocks = np.repeat(np.arange(c["k"]), c["s"])
+    elif kind == "cycle":
+        n = c["n"]
+        g = gen.from_edges(n, [(i, (i + 1) % n) for i in range(n)])
+        blocks = np.arange(n)
+    else:
+        raise KeyError(kind)
+    part = c["partition"]
+    if part == "cliques" or part == "singletons":
+        mem = blocks
+    elif part == "one":
+        mem = np.zeros(g.n, np.int32)
+    elif part == "pairs":
+        mem = blocks // 2
+    else:
+        raise KeyError(part)
+    return g, np.asarray(mem, np.int32)
+
+
+def _golden():
+    with open(os.path.join(GOLDEN, "modularity_closed_forms.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("case", _golden()["cases"], ids=lambda c: "%s-%s-%s" % (c["graph"], c["partition"], c["gamma"]))
+def test_modularity_closed_forms(case):
+    g, mem = _graph_from_case(case)
+    q = oracle.modularity(g, mem, float(Fraction(case["gamma"])))
+    assert q == pytest.approx(float(Fraction(case["q"])), abs=1e-15)
+
+
+def test_modularity_range_random_partitions():
+    # Sec. 3.2: Q lies in [-1/2, 1] for gamma = 1.
+    rng = np.random.default_rng(7)
+    for seed in range(20):
+        g = gen.random_graph(30, 0.15, seed, wmax=5)
+        for _ in range(10):
+            mem = rng.integers(0, rng.integers(1, 31), g.n).astype(np.int32)
+            q = oracle.modularity(g, mem)
+            assert -0.5 - 1e-12 <= q <= 1.0 + 1e-12
+
+
+# ---------------------------------------------------------------- Eq. 2 ---
+
+def _exact_q(g, mem, gamma):
+    """Eq. 1 in exact rationals, used only to difference two partitions."""
+    W = Fraction(0)
+    S1 = Fraction(0)
+    tot = {}
+    for i in range(g.n):
+        for e in range(g.offsets[i], g.offsets[i + 1]):
+            w = Fraction(int(g.weights[e]))
+            W += w
+            tot[mem[i]] = tot.get(mem[i], 0) + w
+            if mem[g.indices[e]] == mem[i]:
+                S1 += w
+    return S1 / W - gamma * sum(t * t for t in tot.values()) / (W * W)
+
+
+@pytest.mark.parametrize("gamma", [Fraction(1, 2), Fraction(1), Fraction(3, 2)])
+def test_delta_modularity_equals_difference_of_eq1(gamma):
+    rng = np.random.default_rng(int(gamma * 100))
+    checked = 0
+    for seed in range(12):
+        g = gen.random_graph(9, 0.4, 100 + seed, wmax=4, self_loops=True)
+        if g.m == 0:
+            continue
+        for _ in range(6):
+            mem = rng.integers(0, 4, g.n).astype(np.int32)
+            i = int(rng.integers(0, g.n))
+            c = int(rng.integers(0, 4))
+            if c == mem[i]:
+                continue
+            after = mem.copy()
+            after[i] = c
+            want = _exact_q(g, after, gamma) - _exact_q(g, mem, gamma)
+            got = oracle.delta_modularity(g, mem, i, c, float(gamma))
+            assert got == pytest.approx(float(want), abs=1e-12)
+            checked += 1
+    assert checked > 30
+
+
+# ------------------------------------------------- exhaustive optimum ---
+
+def _all_partitions(n):
+    """All set partitions of n items as restricted growth strings (numpy)."""
+    rows = np.zeros((1, 1), np.int64)
+    for k in range(1, n):
+        mx = rows.max(axis=1)
+        new = []
+        for lab in range(k + 1):
+            sel = rows[mx + 1 >= lab]
+            new.append(np.hstack([sel, np.full((len(sel), 1), lab)]))
+        rows = np.vstack(new)
+    return rows
+
+
+def _max_modularity(g):
+    """Exhaustive maximum of Eq. 1 (gamma = 1) with exact integer arithmetic."""
+    P = _all_partitions(g.n)
+    W = int(g.weights.sum())
+    K = np.array([int(g.weights[g.offsets[i]:g.offsets[i + 1]].sum()) for i in range(g.n)], np.int64)
+    src = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    S1 = np.zeros(len(P), np.int64)
+    for s, d, w in zip(src, g.indices, g.weights.astype(np.int64)):
+        S1 += np.where(P[:, s] == P[:, d], w, 0)
+    S2 = np.zeros(len(P), np.int64)
+    for c in range(g.n):
+        tc = ((P == c) * K).sum(axis=1)
+        S2 += tc * tc
+    num = W * S1 - S2  # Q = num / W^2
+    best = int(num.max())
+    return Fraction(best, W * W)
+
+
+def test_partition_enumeration_counts():
+    # Bell numbers: a check of the enumerator itself.
+    assert [len(_all_partitions(n)) for n in range(1, 9)] == [1, 2, 5, 15, 52, 203, 877, 4140]
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+@pytest.mark.parametrize("s", [3, 4, 5])
+def test_leiden_reaches_optimum_on_clique_pairs(mode, s):
+    g = gen.cliques_with_bridge(s)
+    want = Fraction(_golden()["optima"]["cliques_with_bridge_%d" % s])
+    assert _max_modularity(g) == want  # exhaustive over Bell(2s) partitions
+    r = oracle.leiden(g, mode=mode)
+    assert r.q == pytest.approx(float(want), abs=1e-15)
+    assert np.array_equal(r.membership, np.repeat([0, 1], s))
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_leiden_complete_graph_single_community(mode):
+    g = gen.from_edges(5, gen.clique_edges(range(5)))
+    r = oracle.leiden(g, mode=mode)
+    assert np.all(r.membership == 0)
+    assert r.q == pytest.approx(0.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_leiden_never_beats_exhaustive_optimum(mode):
+    for seed in range(8):
+        g = gen.random_graph(8 + seed % 3, 0.45, 300 + seed, wmax=3)
+        if g.m == 0:
+            continue
+        best = _max_modularity(g)
+        r = oracle.leiden(g, mode=mode)
+        assert r.q <= float(best) + 1e-12
+        # and the reported Q is the modularity of the returned partition
+        assert r.q == oracle.modularity(g, r.membership)
+
+
+# ------------------------------------------------ structured recoveries ---
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_ring_of_cliques_finds_cliques(mode):
+    k, s = 10, 5  # k < s(s-1)+2: single cliques are optimal
+    g = gen.ring_of_cliques(k, s)
+    r = oracle.leiden(g, mode=mode)
+    assert np.array_equal(r.membership, np.repeat(np.arange(k), s))
+    assert r.q == pytest.approx(89 / 110, abs=1e-15)
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_ring_of_cliques_resolution_limit(mode):
+    # k > s(s-1)+2: merging neighbouring cliques raises modularity, so the
+    # result must not be the single cliques.
+    k, s = 30, 3
+    g = gen.ring_of_cliques(k, s)
+    r = oracle.leiden(g, mode=mode)
+    assert r.q > 43 / 60 + 0.05
+    assert len(np.unique(r.membership)) < k
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_recovers_easy_planted_partition(mode):
+    g = gen.planted(10, 60, 0.5, 0.005, seed=11)
+    r = oracle.leiden(g, mode=mode)
+    # same partition as the planted blocks (up to relabelling)
+    pairs = set(zip(r.membership.tolist(), g.truth.tolist()))
+    assert len(pairs) == 10 and len(np.unique(r.membership)) == 10
+    assert r.q == pytest.approx(oracle.modularity(g, g.truth), abs=1e-15)
+
+
+# --------------------------------------------------------- aggregation ---
+
+def test_aggregation_invariants():
+    for seed in range(6):
+        g = gen.random_graph(40, 0.12, 500 + seed, wmax=7, self_loops=(seed % 2 == 0))
+        rng = np.random.default_rng(seed)
+        lab = rng.integers(0, 9, g.n)
+        _, lab = np.unique(lab, return_inverse=True)
+        lab = lab.astype(np.int32)
+        nc = int(lab.max()) + 1
+        y_off, y_idx, y_w = oracle.aggregate(g, lab, nc)
+        W = float(g.weights.astype(np.float64).sum())
+        assert y_w.sum() == W  # total weight preserved
+        K = np.array([g.weights[g.offsets[i]:g.offsets[i + 1]].astype(np.float64).sum() for i in range(g.n)])
+        Ky = np.array([y_w[y_off[c]:y_off[c + 1]].sum() for c in range(nc)])
+        assert np.array_equal(Ky, np.bincount(lab, weights=K, minlength=nc))
+        A = {}
+        for c in range(nc):
+            for e in range(y_off[c], y_off[c + 1]):
+                A[(c, int(y_idx[e]))] = y_w[e]
+        for (c, d), w in A.items():
+            assert A[(d, c)] == w  # symmetric
+        # Q of any coarser partition is the same on G and on G''
+        yg = gen.Graph(nc, len(y_idx), y_off, y_idx, y_w.astype(np.float32))
+        for t in range(4):
+            coarse = rng.integers(0, 3, nc).astype(np.int32)
+            assert oracle.modularity(yg, coarse) == oracle.modularity(g, coarse[lab])
+
+
+# ----------------------------------------------------- Leiden invariants ---
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+@pytest.mark.parametrize("maker", [
+    lambda: gen.planted(8, 120, 0.08, 0.004, seed=21),
+    lambda: gen.grid(48, 48),
+    lambda: gen.rmat(11, 8, seed=5),
+], ids=["planted", "grid", "rmat"])
+def test_leiden_invariants(mode, maker):
+    g = maker()
+    r = oracle.leiden(g, mode=mode, trace=True)
+    # zero internally-disconnected communities (Alg. 5)
+    assert oracle.disconnected(g, r.membership) == 0
+    top = np.arange(g.n)
+    cur = g
+    for p, t in enumerate(r.passes):
+        # refined communities nest inside the local-moving ones
+        pairs = np.unique(np.stack([t.refined, t.bound]), axis=1)
+        assert len(np.unique(pairs[0])) == pairs.shape[1]
+        # each refined community is connected in the pass graph
+        assert oracle.disconnected(cur, t.refined) == 0
+        if t.y_off is not None:
+            u, lab = np.unique(t.refined, return_inverse=True)
+            cur = gen.Graph(len(u), len(t.y_idx), t.y_off, t.y_idx, t.y_w.astype(np.float32))
+            top = lab[top]
+    assert r.q == oracle.modularity(g, r.membership)
+    # canonical labels: first occurrence order
+    _, first = np.unique(r.membership, return_index=True)
+    assert np.all(np.diff(first) > 0) and r.membership[0] == 0
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_edge_cases(mode):
+    # edgeless graph: identity, Q = 0
+    g = gen.Graph(5, 0, np.zeros(6, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))
+    r = oracle.leiden(g, mode=mode)
+    assert np.array_equal(r.membership, np.arange(5)) and r.q == 0.0
+    # one edge plus isolated vertices
+    g = gen.from_edges(4, [(1, 2)])
+    r = oracle.leiden(g, mode=mode)
+    assert r.membership[1] == r.membership[2]
+    assert len(np.unique(r.membership)) == 3
+    assert r.q == pytest.approx(0.0, abs=1e-15)  # one edge: Q = 1 - 1 = 0
+    # self-loop only
+    g = gen.from_edges(3, [(0, 0), (1, 2)])
+    r = oracle.leiden(g, mode=mode)
+    assert r.membership[0] != r.membership[1] and r.membership[1] == r.membership[2]
+
+
+def test_det_mode_rejects_non_integer_weights():
+    g = gen.from_edges(3, [(0, 1), (1, 2)], [1.5, 2.0])
+    with pytest.raises(ValueError):
+        oracle.leiden(g, mode=oracle.DET_SYNC)
+    r = oracle.leiden(g, mode=oracle.SEQ_ASYNC)
+    assert np.all(r.membership == 0) or len(np.unique(r.membership)) >= 1
+
+
+def test_det_mode_is_reproducible_and_traced():
+    g = gen.planted(6, 80, 0.1, 0.01, seed=4)
+    a = oracle.leiden(g, mode=oracle.DET_SYNC, trace=True)
+    b = oracle.leiden(g, mode=oracle.DET_SYNC, trace=True)
+    assert np.array_equal(a.membership, b.membership) and a.q == b.q
+    for x, y in zip(a.passes, b.passes):
+        assert np.array_equal(x.bound, y.bound) and np.array_equal(x.refined, y.refined)
