@@ -1,0 +1,158 @@
+/*
+ * gvl.h -- C ABI of libgvl.so, a GPU (MI355X / gfx950) implementation of the
+ * data-parallel hot path of GVE-Leiden (Sahu, arXiv:2312.13936): the
+ * per-vertex neighbour-community scan shared by local-moving (Alg. 2) and
+ * refinement (Alg. 3), and the aggregation into a super-vertex graph
+ * (Alg. 4), driven by the pass loop of Alg. 1.
+ *
+ * Problem statement (Sec. 3.1-3.2): given an undirected weighted graph G as
+ * a symmetric CSR, return a community membership C: V -> Gamma that
+ * maximises the modularity of Eq. 1 (with resolution gamma multiplying the
+ * null-model term), and the modularity of the returned C.
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are DEVICE pointers owned by the caller; the library
+ *     never frees them.  Other pointers are host pointers.
+ *   - Work is enqueued on the HIP stream given to gvl_create.  gvl_leiden
+ *     returns after the modularity has been copied back to the host.
+ *   - Errors are returned as gvl_status codes; nothing is thrown across the
+ *     ABI.  On error the membership buffer content is unspecified.
+ *   - A context is not thread safe; use one context per host thread.
+ *   - The library performs no device allocation on the gvl_leiden path: all
+ *     device scratch lives in a caller-provided workspace whose size is
+ *     given by gvl_workspace_bytes.
+ */
+#ifndef GVL_H
+#define GVL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GVL_OK = 0,
+  GVL_E_INVALID_ARG = -1,       /* null pointer, negative size, bad option value */
+  GVL_E_BAD_CSR = -2,           /* offsets not monotone / out of range, index out of range */
+  GVL_E_NONINTEGER_WEIGHT = -4, /* deterministic mode: weight not an integer in [1, 2^24] or total > 2^40 */
+  GVL_E_RESOLUTION = -5,        /* resolution < 0, or (deterministic mode) not p / 65536 with p <= 2^24 */
+  GVL_E_WORKSPACE = -6,         /* workspace null or smaller than gvl_workspace_bytes */
+  GVL_E_HIP = -8                /* a HIP runtime call failed */
+} gvl_status;
+
+enum { GVL_MODE_FAST = 0, GVL_MODE_DET = 1 };
+
+typedef struct gvl_ctx* gvl_ctx_t;
+
+/* Options.  Defaults (gvl_default_options) follow Sec. 4.1 of the paper:
+ * tolerance 0.01, tolerance drop 10, aggregation tolerance 0.8, at most 20
+ * iterations per local-moving phase; passes are capped at 20. */
+typedef struct {
+  int32_t mode;                  /* GVL_MODE_FAST: asynchronous local-moving (Sec. 4.1);
+                                    GVL_MODE_DET: synchronous moves, exact integer gains,
+                                    lowest-id ties -- bit-reproducible */
+  double tolerance;              /* initial per-iteration tolerance tau (Alg. 2 convergence) */
+  double tolerance_drop;         /* threshold scaling: tau /= tolerance_drop after each pass */
+  double aggregation_tolerance;  /* stop when |Gamma| / |V'| exceeds this (Alg. 1) */
+  int32_t max_iterations;        /* cap on local-moving iterations per pass */
+  int32_t max_passes;            /* cap on passes */
+  int32_t refine_sweeps;         /* cap on synchronous refinement sweeps per pass */
+  int32_t subsweeps;             /* S <= 64: local-moving and refinement visit the vertices in S
+                                    pseudo-random groups in turn (sub-sweeps) */
+  int32_t validate;              /* 0: none; 1: CSR bounds and weight checks on the device */
+  int32_t profile;               /* 1: time every kernel class with HIP events (fills gvl_stats ms_*) */
+  int32_t debug_trace;           /* 1: keep per-pass labels and super-vertex CSRs for gvl_debug_* */
+  int32_t reserved[7];
+} gvl_options;
+
+#define GVL_MAX_PASS_STATS 64
+
+typedef struct {
+  int32_t passes;
+  int32_t termination;           /* 0 converged, 1 low shrink, 2 max passes, 3 empty graph */
+  int64_t num_communities;
+  int32_t iterations[GVL_MAX_PASS_STATS];     /* local-moving iterations per pass */
+  int32_t refine_sweeps[GVL_MAX_PASS_STATS];  /* refinement sweeps per pass */
+  int64_t nv[GVL_MAX_PASS_STATS];             /* |V'| per pass */
+  int64_t ne[GVL_MAX_PASS_STATS];             /* arcs of G' per pass */
+  int64_t ncom[GVL_MAX_PASS_STATS];           /* |Gamma| after refinement per pass */
+  /* device time per phase (profile = 1), milliseconds */
+  double ms_move, ms_refine, ms_aggregate, ms_other, ms_total;
+  /* algorithmic work counted by the kernels themselves */
+  int64_t scan_vertices;   /* vertices scanned by move + refine decision kernels */
+  int64_t scan_arcs;       /* arcs read by those kernels */
+  int64_t scan_candidates; /* distinct candidate communities evaluated */
+  int64_t scan_moves;      /* vertices that changed community */
+  int64_t agg_vertices;    /* vertices folded into super-vertices */
+  int64_t agg_arcs;        /* arcs read by aggregation */
+  int64_t agg_out_arcs;    /* arcs written to super-vertex graphs */
+  double ms_scan_kernels;  /* summed duration of scan decision kernels (profile = 1) */
+  double ms_agg_kernels;   /* summed duration of the aggregation row kernels (profile = 1) */
+  int64_t scan_launches;
+  int64_t agg_launches;
+  int64_t scan_refine_arcs;      /* part of scan_arcs read by refinement */
+  double ms_scan_move_kernels;   /* part of ms_scan_kernels spent in local-moving */
+} gvl_stats;
+
+/* Create a context bound to `device` and to the HIP stream `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  Allocates a few KB of pinned
+ * host memory for scalar read-backs. */
+gvl_status gvl_create(gvl_ctx_t* ctx, int device, void* hip_stream);
+gvl_status gvl_destroy(gvl_ctx_t ctx);
+
+/* Fill `opt` with the defaults for `mode` (32 sub-sweep groups, validation on). */
+gvl_status gvl_default_options(gvl_options* opt, int32_t mode);
+
+/* Device workspace needed by gvl_leiden for a graph with n vertices and m
+ * arcs (both directions counted).  O(n + m); see the layout in the source. */
+gvl_status gvl_workspace_bytes(int64_t n, int64_t m, const gvl_options* opt, size_t* bytes);
+
+/* Leiden community detection (Alg. 1-4; Eq. 1-2).
+ *   n, m          vertices and arcs; m = d_offsets[n]; 0 <= m < 2^31.
+ *   d_offsets     int32[n+1], d_offsets[0] = 0, non-decreasing.
+ *   d_indices     int32[m], neighbours; must describe a symmetric graph
+ *                 (each undirected edge stored in both rows, a self-loop
+ *                 once).  Rows need not be sorted.
+ *   d_weights     float[m] positive weights, or NULL for unit weights.
+ *   resolution    gamma >= 0 (1 = modularity of Eq. 1).
+ *   d_workspace   device buffer of at least gvl_workspace_bytes bytes.
+ *   d_membership  int32[n] output: community of each vertex, numbered by
+ *                 first occurrence over v = 0..n-1.
+ *   modularity    host double output: Eq. 1 of d_membership.
+ *   stats         host output, may be NULL.
+ * Deterministic mode additionally requires integer weights in [1, 2^24],
+ * total weight <= 2^40 and resolution = p / 65536 with integer p <= 2^24;
+ * its results are identical on every run. */
+gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,
+                      const int32_t* d_indices, const float* d_weights, double resolution,
+                      const gvl_options* opt, void* d_workspace, size_t workspace_bytes,
+                      int32_t* d_membership, double* modularity, gvl_stats* stats);
+
+/* Eq. 1 for a given membership (labels in [0, n)) on the device. */
+gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,
+                          const int32_t* d_indices, const float* d_weights,
+                          const int32_t* d_membership, double resolution, void* d_workspace,
+                          size_t workspace_bytes, double* modularity);
+
+/* Debug export of the last gvl_leiden run made with debug_trace = 1.
+ * For pass p: n_out = |V'|, m_out = arcs of the super-vertex graph built in
+ * pass p (-1 if the pass did not aggregate).  Host buffers may be NULL.
+ * bound/refined: int32[n_out] local-moving and refinement labels.
+ * y_off: int32[ncom+1], y_idx: int32[m_out], y_w: double[m_out]: the
+ * super-vertex CSR with rows compacted and sorted by neighbour id. */
+gvl_status gvl_debug_pass_info(gvl_ctx_t ctx, int32_t pass, int64_t* n_out, int64_t* ncom_out,
+                               int64_t* m_out);
+gvl_status gvl_debug_export_pass(gvl_ctx_t ctx, int32_t pass, int32_t* bound, int32_t* refined,
+                                 int32_t* y_off, int32_t* y_idx, double* y_w);
+/* Movers per local-moving iteration / refinement sweep of pass p (debug_trace = 1). */
+gvl_status gvl_debug_pass_movers(gvl_ctx_t ctx, int32_t pass, int64_t* movers, int32_t max_it,
+                                 int64_t* refine_movers, int32_t max_sw);
+
+const char* gvl_status_string(gvl_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GVL_H */

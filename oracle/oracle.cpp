@@ -21,10 +21,11 @@
 //          once (Sec. 4.1 asynchronous updates with T = 1).  FP64 gains as
 //          the paper's configuration states (Sec. 5.1.2).
 //   mode 1 "det-sync": the deterministic synchronous variant (not in the
-//          paper): every active vertex decides from the state at the start
-//          of its sub-sweep, moves are applied together, ties go to the
-//          lowest community id, and every sum and gain is an exact integer
-//          (gains are int128 keys).  Used for bit-exact parity.
+//          paper): vertices are split into S pseudo-random groups visited in
+//          turn; inside a group every active vertex decides from the state at
+//          the start of the group and the moves are applied together; ties
+//          go to the lowest community id, and every sum and gain is an exact
+//          integer (gains are int128 keys).  Used for bit-exact parity.
 //
 // Readings of points the paper leaves open (all shared with the GPU path by
 // specification, not by code):
@@ -35,7 +36,8 @@
 //       counted as iterations performed): local-moving ran one iteration
 //       and refinement moved no vertex.
 //   R3  |Gamma| = number of distinct refined labels; stop when
-//       |Gamma| / |V'| > aggregation tolerance.
+//       (|Gamma| - Z) / (|V'| - Z) > aggregation tolerance, where Z counts
+//       the vertices of G' without arcs (they can never merge).
 //   R4  the result is the flattening of the last refinement.
 //   R5  a move is taken only for a strictly positive gain; ties go to the
 //       lowest community id; the own community is never a candidate.
@@ -94,6 +96,14 @@ struct Opts {
   double resolution;
   int32_t trace;
 };
+
+// Sub-sweep group of vertex i: the MurmurHash3 32-bit finalizer of i, mod S
+// (a fixed pseudo-random split of the vertices into S groups).
+uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+  return h;
+}
+int32_t group_of(i64 i, int32_t S) { return (int32_t)(fmix32((uint32_t)i) % (uint32_t)S); }
 
 struct Result {
   std::vector<int32_t> membership;
@@ -255,7 +265,8 @@ int32_t move_det(const Graph& g, State& st, double tau, const Opts& o, i64 W, i6
     i64 moved = 0;
     for (int32_t sub = 0; sub < S; ++sub) {
       std::vector<i64> group;
-      for (i64 i = sub; i < n; i += S) {
+      for (i64 i = 0; i < n; ++i) {
+        if (group_of(i, S) != sub) continue;
         target[i] = -1;
         if (!unprocessed[i]) continue;
         unprocessed[i] = 0;
@@ -333,49 +344,58 @@ int32_t refine_seq(const Graph& g, State& st, const std::vector<int32_t>& bound,
 }
 
 // ---------------------------------------------------- Alg. 3, det-sync ---
-// Sweeps until no vertex moves (at most refine_sweeps).  In a sweep every
-// isolated vertex (community of size one) picks its best in-bound target
-// from the state at the start of the sweep; it moves only if no other vertex
-// picked its own community as a target.
+// Sweeps until no vertex moves (at most refine_sweeps).  Each sweep visits
+// the S vertex groups in turn; inside a group every isolated vertex
+// (community of size one) picks its best in-bound target from the state at
+// the start of the group, and moves only if no vertex of the group picked
+// its own community as a target.
 int32_t refine_det(const Graph& g, State& st, const std::vector<int32_t>& bound, const Opts& o,
                    i64 W, i64 p, std::vector<i64>* movers) {
   const i64 n = g.n;
+  const int32_t S = std::max<int32_t>(1, o.subsweeps);
   std::vector<int32_t> target(n, -1);
   std::vector<char> targeted(n, 0);
   Table H(n);
   int32_t sw = 0;
   for (; sw < std::max<int32_t>(1, o.refine_sweeps); ++sw) {
-    for (i64 i = 0; i < n; ++i) {
-      target[i] = -1;
-      const int32_t d = st.C[i];
-      if (st.size[d] != 1 || st.K[i] == 0.0) continue;
-      scan(H, g, st.C, i, &bound);
-      const i64 kid = (i64)H.get(d), ki = (i64)st.K[i];
-      int32_t best = -1;
-      i128 bk = 0;
-      for (int32_t c : H.keys) {
-        if (c == d) continue;
-        i128 x = gain_key((i64)H.val[c], kid, ki, (i64)st.S[c], (i64)st.S[d], W, p);
-        if (best < 0 || x > bk || (x == bk && c < best)) { best = c; bk = x; }
+    i64 moved = 0;
+    for (int32_t sub = 0; sub < S; ++sub) {
+      std::vector<i64> group;
+      for (i64 i = 0; i < n; ++i) {
+        if (group_of(i, S) != sub) continue;
+        target[i] = -1;
+        const int32_t d = st.C[i];
+        if (st.size[d] != 1 || st.K[i] == 0.0) continue;
+        scan(H, g, st.C, i, &bound);
+        const i64 kid = (i64)H.get(d), ki = (i64)st.K[i];
+        int32_t best = -1;
+        i128 bk = 0;
+        for (int32_t c : H.keys) {
+          if (c == d) continue;
+          i128 x = gain_key((i64)H.val[c], kid, ki, (i64)st.S[c], (i64)st.S[d], W, p);
+          if (best < 0 || x > bk || (x == bk && c < best)) { best = c; bk = x; }
+        }
+        H.clear();
+        if (best < 0 || !(bk > 0)) continue;
+        if (st.size[best] == 1 && best > d) continue;  // min-label rule
+        target[i] = best;
+        group.push_back(i);
       }
-      H.clear();
-      if (best < 0 || !(bk > 0)) continue;
-      if (st.size[best] == 1 && best > d) continue;  // min-label rule
-      target[i] = best;
+      for (i64 i : group) targeted[target[i]] = 1;
+      std::vector<i64> go;
+      for (i64 i : group)
+        if (!targeted[st.C[i]]) go.push_back(i);
+      for (i64 i : group) targeted[target[i]] = 0;
+      for (i64 i : go) {
+        const int32_t d = st.C[i], c = target[i];
+        st.S[d] -= st.K[i]; st.S[c] += st.K[i];
+        st.size[d] -= 1; st.size[c] += 1;
+        st.C[i] = c;
+      }
+      moved += (i64)go.size();
     }
-    std::fill(targeted.begin(), targeted.end(), 0);
-    for (i64 i = 0; i < n; ++i) if (target[i] >= 0) targeted[target[i]] = 1;
-    std::vector<i64> go;
-    for (i64 i = 0; i < n; ++i)
-      if (target[i] >= 0 && !targeted[st.C[i]]) go.push_back(i);
-    for (i64 i : go) {
-      const int32_t d = st.C[i], c = target[i];
-      st.S[d] -= st.K[i]; st.S[c] += st.K[i];
-      st.size[d] -= 1; st.size[c] += 1;
-      st.C[i] = c;
-    }
-    if (movers) movers->push_back((i64)go.size());
-    if (go.empty()) { ++sw; break; }
+    if (movers) movers->push_back(moved);
+    if (moved == 0) { ++sw; break; }
   }
   return sw;
 }
@@ -488,7 +508,14 @@ int run_leiden(const Graph& g0, const Opts& o, Result& res) {
     for (i64 x : tr.refine_movers) refine_moved += x;
     bool stop = false;
     if (first && refine_moved == 0) { res.termination = 0; stop = true; }
-    else if ((double)ncom / (double)n > o.aggregation_tolerance) { res.termination = 1; stop = true; }
+    else {
+      // vertices without arcs stay singletons for ever: they are left out of
+      // both counts of the shrink ratio
+      i64 z = 0;
+      for (i64 i = 0; i < n; ++i) if (cur.off[i + 1] == cur.off[i]) ++z;
+      if (n > z && (double)(ncom - z) / (double)(n - z) > o.aggregation_tolerance) { res.termination = 1; stop = true; }
+      if (n == z) { res.termination = 1; stop = true; }
+    }
     if (stop) {
       final_refined = st.C;
       res.passes.push_back(std::move(tr));
@@ -555,7 +582,7 @@ typedef struct {
   int32_t max_iterations;        // 20
   int32_t max_passes;            // 20
   int32_t refine_sweeps;         // seq-async: 1; det-sync: cap on sweeps
-  int32_t subsweeps;             // det-sync: vertex groups i mod S per iteration
+  int32_t subsweeps;             // det-sync: pseudo-random vertex groups visited in turn
   double resolution;             // gamma
   int32_t trace;                 // keep per-pass labels and super-vertex CSRs
 } oracle_opts;
@@ -568,7 +595,7 @@ void oracle_default_opts(oracle_opts* o, int32_t mode) {
   o->max_iterations = 20;
   o->max_passes = 20;
   o->refine_sweeps = mode == 1 ? 20 : 1;
-  o->subsweeps = mode == 1 ? 4 : 1;
+  o->subsweeps = mode == 1 ? 32 : 1;
   o->resolution = 1.0;
   o->trace = 0;
 }

@@ -1,0 +1,266 @@
+"""Python binding of libgvl.so: GVE-Leiden's hot path as hand-written HIP for MI355X.
+
+The functions named ``gvl_*`` mirror the C ABI of ``include/gvl.h`` one to
+one and only marshal arguments (device pointers come from torch tensors,
+the stream from ``torch.cuda.current_stream()``).  ``leiden`` and
+``modularity`` are conveniences that also allocate the output and the
+workspace as torch tensors.  Every step of the algorithm runs in the HIP
+kernels; there is no CPU or PyTorch fallback: if libgvl.so is missing the
+import of the library fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgvl.so")
+
+GVL_MODE_FAST = 0
+GVL_MODE_DET = 1
+GVL_MAX_PASS_STATS = 64
+
+STATUS = {0: "GVL_OK", -1: "GVL_E_INVALID_ARG", -2: "GVL_E_BAD_CSR", -4: "GVL_E_NONINTEGER_WEIGHT",
+          -5: "GVL_E_RESOLUTION", -6: "GVL_E_WORKSPACE", -8: "GVL_E_HIP"}
+
+
+class GvlError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__("%s returned %s (%d)" % (where, STATUS.get(code, "?"), code))
+        self.code = code
+
+
+class gvl_options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("tolerance", ctypes.c_double),
+                ("tolerance_drop", ctypes.c_double), ("aggregation_tolerance", ctypes.c_double),
+                ("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
+                ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
+                ("debug_trace", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+_P = GVL_MAX_PASS_STATS
+
+
+class gvl_stats(ctypes.Structure):
+    _fields_ = [("passes", ctypes.c_int32), ("termination", ctypes.c_int32),
+                ("num_communities", ctypes.c_int64),
+                ("iterations", ctypes.c_int32 * _P), ("refine_sweeps", ctypes.c_int32 * _P),
+                ("nv", ctypes.c_int64 * _P), ("ne", ctypes.c_int64 * _P), ("ncom", ctypes.c_int64 * _P),
+                ("ms_move", ctypes.c_double), ("ms_refine", ctypes.c_double),
+                ("ms_aggregate", ctypes.c_double), ("ms_other", ctypes.c_double),
+                ("ms_total", ctypes.c_double),
+                ("scan_vertices", ctypes.c_int64), ("scan_arcs", ctypes.c_int64),
+                ("scan_candidates", ctypes.c_int64), ("scan_moves", ctypes.c_int64),
+                ("agg_vertices", ctypes.c_int64), ("agg_arcs", ctypes.c_int64),
+                ("agg_out_arcs", ctypes.c_int64),
+                ("ms_scan_kernels", ctypes.c_double), ("ms_agg_kernels", ctypes.c_double),
+                ("scan_launches", ctypes.c_int64), ("agg_launches", ctypes.c_int64),
+                ("scan_refine_arcs", ctypes.c_int64), ("ms_scan_move_kernels", ctypes.c_double)]
+
+
+EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
+           "gvl_modularity", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
+           "gvl_status_string"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgvl.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise OSError("libgvl.so not found at %s: build it with paper_2312_13936_amd/build.py" % path)
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dbl, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    lib.gvl_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, vp]
+    lib.gvl_destroy.argtypes = [vp]
+    lib.gvl_default_options.argtypes = [ctypes.POINTER(gvl_options), i32]
+    lib.gvl_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(gvl_options), ctypes.POINTER(sz)]
+    lib.gvl_leiden.argtypes = [vp, i64, i64, vp, vp, vp, dbl, ctypes.POINTER(gvl_options), vp, sz, vp,
+                               ctypes.POINTER(dbl), ctypes.POINTER(gvl_stats)]
+    lib.gvl_modularity.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(dbl)]
+    lib.gvl_debug_pass_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.gvl_debug_export_pass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+    lib.gvl_debug_pass_movers.argtypes = [vp, i32, vp, i32, vp, i32]
+    for f in EXPORTS[:-1]:
+        getattr(lib, f).restype = ctypes.c_int
+    lib.gvl_status_string.argtypes = [ctypes.c_int]
+    lib.gvl_status_string.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(code: int, where: str):
+    if code != 0:
+        raise GvlError(code, where)
+
+
+# ------------------------------------------------------------ C-ABI mirror ---
+
+def gvl_create(device: int = 0, stream: Optional[int] = None) -> ctypes.c_void_p:
+    h = ctypes.c_void_p()
+    _check(load_library().gvl_create(ctypes.byref(h), device, stream), "gvl_create")
+    return h
+
+
+def gvl_destroy(ctx) -> None:
+    _check(load_library().gvl_destroy(ctx), "gvl_destroy")
+
+
+def gvl_default_options(mode: int = GVL_MODE_FAST) -> gvl_options:
+    o = gvl_options()
+    _check(load_library().gvl_default_options(ctypes.byref(o), mode), "gvl_default_options")
+    return o
+
+
+def gvl_workspace_bytes(n: int, m: int, opt: gvl_options) -> int:
+    b = ctypes.c_size_t(0)
+    _check(load_library().gvl_workspace_bytes(n, m, ctypes.byref(opt), ctypes.byref(b)), "gvl_workspace_bytes")
+    return int(b.value)
+
+
+def gvl_leiden(ctx, n, m, d_offsets, d_indices, d_weights, resolution, opt, d_workspace, workspace_bytes,
+               d_membership, stats: Optional[gvl_stats] = None) -> float:
+    q = ctypes.c_double(0.0)
+    code = load_library().gvl_leiden(ctx, n, m, d_offsets, d_indices, d_weights, resolution, ctypes.byref(opt),
+                                     d_workspace, workspace_bytes, d_membership, ctypes.byref(q),
+                                     ctypes.byref(stats) if stats is not None else None)
+    _check(code, "gvl_leiden")
+    return q.value
+
+
+def gvl_modularity(ctx, n, m, d_offsets, d_indices, d_weights, d_membership, resolution, d_workspace,
+                   workspace_bytes) -> float:
+    q = ctypes.c_double(0.0)
+    code = load_library().gvl_modularity(ctx, n, m, d_offsets, d_indices, d_weights, d_membership, resolution,
+                                         d_workspace, workspace_bytes, ctypes.byref(q))
+    _check(code, "gvl_modularity")
+    return q.value
+
+
+def gvl_debug_pass_info(ctx, p: int):
+    n, ncom, m = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load_library().gvl_debug_pass_info(ctx, p, ctypes.byref(n), ctypes.byref(ncom), ctypes.byref(m)),
+           "gvl_debug_pass_info")
+    return n.value, ncom.value, m.value
+
+
+def gvl_debug_export_pass(ctx, p: int):
+    n, ncom, m = gvl_debug_pass_info(ctx, p)
+    bound = np.zeros(max(n, 1), np.int32)
+    refined = np.zeros(max(n, 1), np.int32)
+    y_off = np.zeros(ncom + 1, np.int32) if m >= 0 else None
+    y_idx = np.zeros(max(m, 1), np.int32) if m >= 0 else None
+    y_w = np.zeros(max(m, 1), np.float64) if m >= 0 else None
+    ptr = lambda a: None if a is None else a.ctypes.data
+    _check(load_library().gvl_debug_export_pass(ctx, p, ptr(bound), ptr(refined), ptr(y_off), ptr(y_idx),
+                                                 ptr(y_w)), "gvl_debug_export_pass")
+    if m >= 0:
+        y_idx, y_w = y_idx[:m], y_w[:m]
+    return bound[:n], refined[:n], y_off, y_idx, y_w
+
+
+def gvl_debug_pass_movers(ctx, p: int, max_it: int = 64, max_sw: int = 64):
+    mv = np.full(max_it, -1, np.int64)
+    rmv = np.full(max_sw, -1, np.int64)
+    _check(load_library().gvl_debug_pass_movers(ctx, p, mv.ctypes.data, max_it, rmv.ctypes.data, max_sw),
+           "gvl_debug_pass_movers")
+    return mv[mv >= 0].tolist(), rmv[rmv >= 0].tolist()
+
+
+def gvl_status_string(code: int) -> str:
+    return load_library().gvl_status_string(code).decode()
+
+
+# -------------------------------------------------------------- convenience ---
+
+@dataclass
+class LeidenResult:
+    membership: "object"   # torch.int32 tensor on the device
+    modularity: float
+    stats: gvl_stats
+
+
+class Leiden:
+    """Owns a context and a reusable workspace on one device and stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.ctx = gvl_create(device, self.stream.cuda_stream)
+        self.ws = None
+
+    def close(self):
+        if self.ctx is not None:
+            gvl_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace(self, nbytes: int):
+        if self.ws is None or self.ws.numel() < nbytes:
+            self.ws = self.torch.empty(max(nbytes, 256), dtype=self.torch.uint8, device=self.device)
+        return self.ws
+
+    @staticmethod
+    def options(mode: int = GVL_MODE_FAST, **kw) -> gvl_options:
+        o = gvl_default_options(mode)
+        for k, v in kw.items():
+            if not hasattr(o, k):
+                raise AttributeError("gvl_options has no field %r" % k)
+            setattr(o, k, v)
+        return o
+
+    def run(self, offsets, indices, weights=None, resolution: float = 1.0, opt: Optional[gvl_options] = None,
+            membership=None) -> LeidenResult:
+        torch = self.torch
+        opt = opt if opt is not None else self.options()
+        n = offsets.numel() - 1
+        m = indices.numel()
+        for t, dt in ((offsets, torch.int32), (indices, torch.int32)):
+            if t.dtype != dt or t.device != self.device or not t.is_contiguous():
+                raise ValueError("offsets/indices must be contiguous int32 tensors on %s" % self.device)
+        if weights is not None and (weights.dtype != torch.float32 or weights.device != self.device
+                                    or not weights.is_contiguous() or weights.numel() != m):
+            raise ValueError("weights must be a contiguous float32 tensor of length m on %s" % self.device)
+        wsb = gvl_workspace_bytes(n, m, opt)
+        ws = self.workspace(wsb)
+        if membership is None:
+            membership = torch.empty(max(n, 1), dtype=torch.int32, device=self.device)
+        st = gvl_stats()
+        q = gvl_leiden(self.ctx, n, m, offsets.data_ptr(), indices.data_ptr(),
+                       None if weights is None else weights.data_ptr(), float(resolution), opt,
+                       ws.data_ptr(), ws.numel(), membership.data_ptr(), st)
+        return LeidenResult(membership[:n], q, st)
+
+    def modularity(self, offsets, indices, weights, membership, resolution: float = 1.0) -> float:
+        n = offsets.numel() - 1
+        m = indices.numel()
+        opt = self.options()
+        ws = self.workspace(gvl_workspace_bytes(n, m, opt))
+        return gvl_modularity(self.ctx, n, m, offsets.data_ptr(), indices.data_ptr(),
+                              None if weights is None else weights.data_ptr(), membership.data_ptr(),
+                              float(resolution), ws.data_ptr(), ws.numel())
+
+
+def leiden(offsets, indices, weights=None, resolution: float = 1.0, mode: int = GVL_MODE_FAST, **kw):
+    """One-shot Leiden on device tensors; returns (membership, modularity, stats)."""
+    eng = Leiden(offsets.device.index or 0)
+    try:
+        r = eng.run(offsets, indices, weights, resolution, eng.options(mode, **kw))
+        return r.membership, r.modularity, r.stats
+    finally:
+        eng.close()

@@ -1,0 +1,222 @@
+// Device-side building blocks shared by the gvl kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace gvl {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+
+typedef __int128 i128;
+typedef unsigned long long u64;
+
+// ------------------------------------------------------------- graph view ---
+// CSR row i occupies [off[i], off[i] + degree(i)).  Input graphs are plain
+// CSR (deg == nullptr, degree = off[i+1] - off[i]); super-vertex graphs are
+// "holey": rows are allocated with an over-estimated capacity and deg[] holds
+// the filled length (Alg. 4).  w == nullptr means unit weights.
+template <class WT>
+struct GraphView {
+  int64_t n;
+  const int32_t* off;
+  const int32_t* deg;
+  const int32_t* idx;
+  const WT* w;
+  __device__ __forceinline__ int32_t begin(int64_t i) const { return off[i]; }
+  __device__ __forceinline__ int32_t degree(int64_t i) const {
+    return deg ? deg[i] : off[i + 1] - off[i];
+  }
+  __device__ __forceinline__ double weight(int64_t e) const { return w ? (double)w[e] : 1.0; }
+};
+
+// ------------------------------------------------------------ wave helpers ---
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+
+// Orders the LDS traffic of one wavefront: every lane's earlier LDS
+// operations complete before any lane's later ones.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ u64 lanemask_lt() {
+  const int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+template <int W>
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, W); }
+template <int W>
+__device__ __forceinline__ int shfl_xor_i(int v, int m) { return __shfl_xor(v, m, W); }
+template <int W>
+__device__ __forceinline__ long long shfl_xor_ll(long long v, int m) { return __shfl_xor(v, m, W); }
+
+__device__ __forceinline__ i128 make_i128(long long hi, unsigned long long lo) {
+  return (i128)(((unsigned __int128)(unsigned long long)hi << 64) | (unsigned __int128)lo);
+}
+
+template <int W>
+__device__ __forceinline__ i128 shfl_xor_i128(i128 v, int m) {
+  long long hi = (long long)(v >> 64);
+  long long lo = (long long)(unsigned long long)v;
+  hi = __shfl_xor(hi, m, W);
+  lo = __shfl_xor(lo, m, W);
+  return make_i128(hi, (unsigned long long)lo);
+}
+
+// (gain, id) ordering: larger gain wins, equal gains go to the lower id;
+// id < 0 means "no candidate".
+__device__ __forceinline__ bool better_f(double g2, int32_t c2, double g, int32_t c) {
+  return c2 >= 0 && (c < 0 || g2 > g || (g2 == g && c2 < c));
+}
+__device__ __forceinline__ bool better_k(i128 k2, int32_t c2, i128 k, int32_t c) {
+  return c2 >= 0 && (c < 0 || k2 > k || (k2 == k && c2 < c));
+}
+
+template <int W>
+__device__ __forceinline__ void argmax_f(double& g, int32_t& c) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) {
+    double g2 = shfl_xor_d<W>(g, o);
+    int32_t c2 = shfl_xor_i<W>(c, o);
+    if (better_f(g2, c2, g, c)) { g = g2; c = c2; }
+  }
+}
+template <int W>
+__device__ __forceinline__ void argmax_k(i128& k, int32_t& c) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) {
+    i128 k2 = shfl_xor_i128<W>(k, o);
+    int32_t c2 = shfl_xor_i<W>(c, o);
+    if (better_k(k2, c2, k, c)) { k = k2; c = c2; }
+  }
+}
+
+template <int W, class T>
+__device__ __forceinline__ T sum_xor(T v) {
+#pragma unroll
+  for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+  return v;
+}
+
+// Exact 128-bit accumulation into two 64-bit words (lo, hi) with carry:
+// correct modulo 2^128 for any order of concurrent callers.
+__device__ __forceinline__ void atomic_add_i128(u64* lohi, i128 v) {
+  const u64 lo = (u64)v;
+  u64 hi = (u64)(v >> 64);
+  const u64 old = atomicAdd(&lohi[0], lo);
+  if (old + lo < old) hi += 1ull;
+  atomicAdd(&lohi[1], hi);
+}
+
+// -------------------------------------------------------------- hashing ---
+// Open addressing with linear probing, power-of-two capacity 2^lg.
+// Multiplicative (Fibonacci) hashing of the community id.
+__device__ __forceinline__ uint32_t hslot(int32_t c, int lg) {
+  return ((uint32_t)c * 0x9E3779B1u) >> (32 - lg);
+}
+
+// LDS table insert: H[c] += w.
+__device__ __forceinline__ void lds_insert(int32_t* keys, double* vals, int lg, int32_t c, double w) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = hslot(c, lg);
+  while (true) {
+    int32_t k = keys[h];
+    if (k == c) { atomicAdd(&vals[h], w); return; }
+    if (k == kEmpty) {
+      int32_t old = atomicCAS(&keys[h], kEmpty, c);
+      if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return; }
+    }
+    h = (h + 1u) & mask;
+  }
+}
+
+__device__ __forceinline__ double lds_lookup(const int32_t* keys, const double* vals, int lg, int32_t c) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = hslot(c, lg);
+  while (true) {
+    int32_t k = keys[h];
+    if (k == c) return vals[h];
+    if (k == kEmpty) return 0.0;
+    h = (h + 1u) & mask;
+  }
+}
+
+// Global-memory table (hubs and giant communities).  Every probe is an
+// atomic performed at L2, so no stale L1 line is ever consulted.
+__device__ __forceinline__ void glb_insert(int32_t* keys, double* vals, int lg, int32_t c, double w) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = hslot(c, lg);
+  while (true) {
+    int32_t old = atomicCAS(&keys[h], kEmpty, c);
+    if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return; }
+    h = (h + 1u) & mask;
+  }
+}
+
+__device__ __forceinline__ int32_t glb_load_key(const int32_t* keys, uint32_t h) {
+  return __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double glb_load_val(const double* vals, uint32_t h) {
+  return __hip_atomic_load(vals + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double glb_lookup(const int32_t* keys, const double* vals, int lg, int32_t c) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = hslot(c, lg);
+  while (true) {
+    int32_t k = glb_load_key(keys, h);
+    if (k == c) return glb_load_val(vals, h);
+    if (k == kEmpty) return 0.0;
+    h = (h + 1u) & mask;
+  }
+}
+
+// Sub-sweep group of vertex i: MurmurHash3's 32-bit finalizer of i, mod S.
+__device__ __forceinline__ int group_of(int64_t i, int S) {
+  uint32_t h = (uint32_t)i;
+  h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+  return (int)(h % (uint32_t)S);
+}
+
+__host__ __device__ __forceinline__ int ceil_log2(int64_t x) {
+  int l = 0;
+  while (((int64_t)1 << l) < x) ++l;
+  return l;
+}
+
+// -------------------------------------------------------- block reductions ---
+// Sum over the block (blockDim.x multiple of 64, <= 1024); the result is
+// valid in thread 0.  `red` is LDS scratch of >= 16 entries.
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T* red) {
+  v = sum_xor<kWave>(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  T s = T(0);
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) s += red[k];
+  return s;
+}
+
+__device__ __forceinline__ i128 block_sum_i128(i128 v, i128* red) {
+#pragma unroll
+  for (int o = kWave / 2; o > 0; o >>= 1) v += shfl_xor_i128<kWave>(v, o);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  i128 s = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < (int)(blockDim.x / kWave); ++k) s += red[k];
+  return s;
+}
+
+}  // namespace gvl

@@ -1,0 +1,897 @@
+// Host driver of the Leiden pass loop (Alg. 1) and the C ABI of libgvl.so.
+//
+// Per pass on the current graph G' (the input at pass 0, then a holey
+// super-vertex graph):
+//   1. vertex weights K', initial labels C' and community totals Sigma'
+//   2. degree binning of the vertices
+//   3. local-moving iterations (Alg. 2) until the summed gain <= tau
+//   4. refinement sweeps inside the local-moving bounds (Alg. 3)
+//   5. |Gamma| = distinct refined labels; stop on convergence / low shrink
+//   6. renumbering, dendrogram lookup, aggregation (Alg. 4) into the other
+//      graph buffer, move-based labels of the super-vertices, tau /= drop
+// then the canonical relabelling of the result and Eq. 1.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "gvl.h"
+#include "kernels.hpp"
+
+namespace gvl {
+
+// Scalars shared between the device and one pinned host mirror.
+struct Scalars {
+  double dq;                        // fast: summed move gains of an iteration
+  unsigned long long dq128[2];      // det: exact summed move keys (lo, hi)
+  unsigned long long cnt[8];        // kernel work counters (cumulative)
+  int32_t flags[4];                 // input checks
+  double accW;                      // total weight
+  double acc_d[2];                  // modularity: S1, S2 (floating)
+  unsigned long long acc_u[2];      // modularity: S2 exact (lo, hi)
+  int32_t total;                    // scan totals read back
+  int32_t pad;
+};
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static inline int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Device workspace, carved out of the caller's buffer.
+struct Workspace {
+  double *K, *Sig;
+  int32_t *size, *C, *CB, *start, *target, *newid, *brank, *lab, *rank, *cnt, *cv, *list, *scan_tmp;
+  uint8_t *flag, *targeted;
+  int32_t *off[2], *deg[2], *idx[2];
+  void* w[2];
+  int32_t* tbl_keys;
+  double* tbl_vals;
+  int64_t tbl_entries;
+  // hub path
+  int32_t *hp_chunk, *hp_tbl, *hp_slice, *hp_active, *hp_done, *apre;
+  double* hp_kid;
+  int2 *chunk_tasks, *slice_tasks;
+  double* pb_g;
+  i128_t* pb_k;
+  int32_t* pb_c;
+  int64_t max_tasks;
+  Scalars* sc;
+  BinBuf* bb;
+  size_t bytes;
+};
+
+static int64_t table_entries(int64_t n) { return std::max<int64_t>(4 * next_pow2(2 * std::max<int64_t>(n, 1)), 1 << 16); }
+
+static Workspace carve(int64_t n, int64_t m, bool det, char* base) {
+  Workspace w;
+  memset(&w, 0, sizeof(w));
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + o : nullptr;
+    o += align_up(bytes);
+    return p;
+  };
+  const size_t N = (size_t)std::max<int64_t>(n, 1), M = (size_t)std::max<int64_t>(m, 1);
+  const size_t ws = det ? sizeof(double) : sizeof(float);
+  w.sc = (Scalars*)take(sizeof(Scalars));
+  w.bb = (BinBuf*)take(sizeof(BinBuf));
+  w.K = (double*)take(8 * N);
+  w.Sig = (double*)take(8 * N);
+  w.size = (int32_t*)take(4 * N);
+  w.C = (int32_t*)take(4 * N);
+  w.CB = (int32_t*)take(4 * N);
+  w.start = (int32_t*)take(4 * N);
+  w.target = (int32_t*)take(4 * N);
+  w.newid = (int32_t*)take(4 * (N + 1));
+  w.brank = (int32_t*)take(4 * (N + 1));
+  w.lab = (int32_t*)take(4 * N);
+  w.rank = (int32_t*)take(4 * (N + 1));
+  w.cnt = (int32_t*)take(4 * (N + 1));
+  w.cv = (int32_t*)take(4 * N);
+  w.list = (int32_t*)take(4 * N);
+  w.scan_tmp = (int32_t*)take(4 * ((size_t)scan_tiles((int64_t)N + 1) + 2));
+  w.flag = (uint8_t*)take(N);
+  w.targeted = (uint8_t*)take(N);
+  for (int b = 0; b < 2; ++b) {
+    w.off[b] = (int32_t*)take(4 * (N + 1));
+    w.deg[b] = (int32_t*)take(4 * N);
+    w.idx[b] = (int32_t*)take(4 * M);
+    w.w[b] = (void*)take(ws * M);
+  }
+  w.tbl_entries = table_entries(n);
+  w.tbl_keys = (int32_t*)take(4 * (size_t)w.tbl_entries);
+  w.tbl_vals = (double*)take(8 * (size_t)w.tbl_entries);
+  w.hp_chunk = (int32_t*)take(4 * (N + 1));
+  w.hp_tbl = (int32_t*)take(4 * (N + 1));
+  w.hp_slice = (int32_t*)take(4 * (N + 1));
+  w.hp_active = (int32_t*)take(4 * N);
+  w.hp_done = (int32_t*)take(4 * N);
+  w.apre = (int32_t*)take(4 * (N + 1));
+  w.hp_kid = (double*)take(8 * N);
+  // chunk tasks <= H + M / kHubChunk; slice tasks <= H + M / (kHubSlice / 4)
+  w.max_tasks = (int64_t)N + (int64_t)M / 1024 + 2;
+  w.chunk_tasks = (int2*)take(sizeof(int2) * (size_t)w.max_tasks);
+  w.slice_tasks = (int2*)take(sizeof(int2) * (size_t)w.max_tasks);
+  w.pb_g = (double*)take(8 * (size_t)w.max_tasks);
+  w.pb_k = (i128_t*)take(16 * (size_t)w.max_tasks);
+  w.pb_c = (int32_t*)take(4 * (size_t)w.max_tasks);
+  w.bytes = o;
+  return w;
+}
+
+// Deterministic int128 -> double: hi * 2^64 + lo (one rounding in the add).
+static double i128_to_double(unsigned long long lo, unsigned long long hi) {
+  return (double)(long long)hi * 18446744073709551616.0 + (double)lo;
+}
+
+struct PassDebug {
+  int64_t n = 0, ncom = 0, m = -1;
+  std::vector<int32_t> bound, refined, y_off, y_idx;
+  std::vector<double> y_w;
+  std::vector<int64_t> movers, refine_movers;
+};
+
+}  // namespace gvl
+
+using namespace gvl;
+
+struct gvl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Scalars* host = nullptr;  // pinned
+  BinBuf* hbins = nullptr;  // pinned
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
+  std::vector<PassDebug> trace;
+};
+
+namespace {
+
+#define HIP_TRY(x)                                   \
+  do {                                               \
+    hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) {                          \
+      fprintf(stderr, "gvl: %s failed: %s\n", #x, hipGetErrorString(e_)); \
+      return GVL_E_HIP;                              \
+    }                                                \
+  } while (0)
+
+// Event pairs for per-phase timing (profile = 1).  Phase spans include the
+// host read-backs between launches; kernel spans bracket only the launches
+// of one kernel class.
+enum { kEvMove = 0, kEvRefine = 1, kEvAgg = 2, kEvOther = 3, kEvScanMoveK = 4, kEvScanRefineK = 5,
+       kEvAggK = 6, kEvClasses = 7 };
+
+struct Timer {
+  gvl_ctx* ctx;
+  bool on;
+  struct Span { int cls; hipEvent_t a, b; };
+  std::vector<Span> spans;
+  hipEvent_t get() {
+    if (ctx->ev_used == ctx->events.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->events.push_back(e);
+    }
+    return ctx->events[ctx->ev_used++];
+  }
+  int begin(int cls) {
+    if (!on) return -1;
+    hipEvent_t e = get();
+    if (!e) return -1;
+    (void)hipEventRecord(e, ctx->stream);
+    spans.push_back({cls, e, nullptr});
+    return (int)spans.size() - 1;
+  }
+  void end(int h) {
+    if (h < 0) return;
+    hipEvent_t e = get();
+    if (!e) return;
+    (void)hipEventRecord(e, ctx->stream);
+    spans[h].b = e;
+  }
+  void totals(double* ms) {
+    for (int k = 0; k < kEvClasses; ++k) ms[k] = 0.0;
+    for (auto& sp : spans) {
+      float t = 0.f;
+      if (sp.b && hipEventElapsedTime(&t, sp.a, sp.b) == hipSuccess) ms[sp.cls] += t;
+    }
+  }
+};
+
+gvl_status readback(gvl_ctx* ctx, Scalars* dev) {
+  HIP_TRY(hipMemcpyAsync(ctx->host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return GVL_OK;
+}
+
+// Bin the items of a graph (or of a capacity array) into S groups and fill
+// `list`: bins 0..kHubBin-1 of every group (group-major), then the hub bin
+// of every group in group order.
+gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int32_t* deg, int64_t n, int S,
+                     BinInfo& bins) {
+  hipStream_t st = ctx->stream;
+  fill_i32(st, (int32_t*)ws.bb, 0, (int64_t)(sizeof(BinBuf) / sizeof(int32_t)));
+  bin_count(st, off, deg, n, S, ws.bb);
+  HIP_TRY(hipMemcpyAsync(ctx->hbins, ws.bb, sizeof(BinBuf), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  bins.S = S;
+  int32_t acc = 0;
+  for (int g = 0; g < S; ++g) {
+    bins.gstart[g] = acc;
+    for (int b = 0; b < kHubBin; ++b) {
+      bins.count[g][b] = ctx->hbins->counts[g * kNumBins + b];
+      bins.start[g][b] = acc;
+      ctx->hbins->cursors[g * kNumBins + b] = acc;
+      acc += bins.count[g][b];
+    }
+    bins.gend[g] = acc;
+  }
+  bins.gstart[S] = acc;
+  bins.H0 = acc;
+  for (int g = 0; g < S; ++g) {
+    bins.count[g][kHubBin] = ctx->hbins->counts[g * kNumBins + kHubBin];
+    bins.start[g][kHubBin] = acc;
+    ctx->hbins->cursors[g * kNumBins + kHubBin] = acc;
+    acc += bins.count[g][kHubBin];
+  }
+  bins.H = acc - bins.H0;
+  bins.binned = acc;
+  for (int b = 0; b < kNumBins; ++b) bins.maxsize[b] = ctx->hbins->maxsize[b];
+  HIP_TRY(hipMemcpyAsync(ws.bb->cursors, ctx->hbins->cursors, sizeof(int32_t) * S * kNumBins,
+                         hipMemcpyHostToDevice, st));
+  bin_scatter(st, off, deg, n, S, ws.bb, ws.list);
+  return GVL_OK;
+}
+
+// Hub plan of one graph (or of the giant communities of an aggregation):
+// chunk / table / slice offsets on the device, task lists, and batches of
+// consecutive hubs of one group whose tables fit the table region together.
+struct HubBatch {
+  int32_t h0, h1, c0, c1, s0, s1;
+  int64_t tbase, tend;
+};
+struct HubPlan {
+  int32_t H = 0;
+  int32_t T = 0;
+  std::vector<std::vector<HubBatch>> groups;  // per group
+};
+
+gvl_status build_hub_plan(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, bool agg, const GraphDesc& g,
+                          const int32_t* yoff, int64_t ncom, HubPlan& plan) {
+  hipStream_t st = ctx->stream;
+  plan = HubPlan();
+  plan.H = bins.H;
+  plan.groups.assign(bins.S, {});
+  if (bins.H == 0) return GVL_OK;
+  const int32_t* items = ws.list + bins.H0;
+  const int32_t H = bins.H;
+  if (agg) gagg_setup(st, yoff, items, H, ncom, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  else hub_setup(st, g.off, g.deg, items, H, g.n, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  exclusive_scan(st, ws.hp_chunk, H, ws.scan_tmp);
+  exclusive_scan(st, ws.hp_tbl, H, ws.scan_tmp);
+  exclusive_scan(st, ws.hp_slice, H, ws.scan_tmp);
+  std::vector<int32_t> hc(H + 1), ht(H + 1), hs(H + 1);
+  HIP_TRY(hipMemcpyAsync(hc.data(), ws.hp_chunk, sizeof(int32_t) * (H + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ht.data(), ws.hp_tbl, sizeof(int32_t) * (H + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hs.data(), ws.hp_slice, sizeof(int32_t) * (H + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hc[H] > ws.max_tasks || hs[H] > ws.max_tasks) return GVL_E_WORKSPACE;
+  plan.T = hc[H];
+  hub_tasks(st, H, ws.hp_chunk, ws.hp_slice, ws.chunk_tasks, ws.slice_tasks);
+  const int64_t region = ws.tbl_entries;
+  for (int grp = 0; grp < bins.S; ++grp) {
+    int32_t a = bins.start[grp][kHubBin] - bins.H0;
+    const int32_t e = a + bins.count[grp][kHubBin];
+    while (a < e) {
+      int32_t b = a + 1;
+      while (b < e && (int64_t)(ht[b + 1] - ht[a]) * kTblUnit <= region) ++b;
+      HubBatch hb;
+      hb.h0 = a; hb.h1 = b;
+      hb.c0 = hc[a]; hb.c1 = hc[b];
+      hb.s0 = hs[a]; hb.s1 = hs[b];
+      hb.tbase = (int64_t)ht[a] * kTblUnit;
+      hb.tend = (int64_t)ht[b] * kTblUnit;
+      plan.groups[grp].push_back(hb);
+      a = b;
+    }
+  }
+  return GVL_OK;
+}
+
+HubArgs hub_args(Workspace& ws, const BinInfo& bins) {
+  HubArgs h;
+  memset(&h, 0, sizeof(h));
+  h.items = ws.list + bins.H0;
+  h.chunk_off = ws.hp_chunk; h.tbl_off = ws.hp_tbl; h.slice_off = ws.hp_slice;
+  h.chunk_tasks = ws.chunk_tasks; h.slice_tasks = ws.slice_tasks;
+  h.active = ws.hp_active; h.kid = ws.hp_kid; h.done = ws.hp_done;
+  h.pb_g = ws.pb_g; h.pb_k = ws.pb_k; h.pb_c = ws.pb_c;
+  h.tbl_keys = ws.tbl_keys; h.tbl_vals = ws.tbl_vals;
+  h.apre = ws.apre;
+  return h;
+}
+
+// Table slots below `clean` are known to be empty: every use leaves its
+// slots empty, so only the first use of a slot in a call needs clearing.
+struct TableState {
+  int64_t clean = 0;
+  void ensure(hipStream_t st, Workspace& ws, int64_t extent) {
+    if (extent <= clean) return;
+    fill_i32(st, ws.tbl_keys + clean, kEmpty, extent - clean);
+    fill_f64(st, ws.tbl_vals + clean, 0.0, extent - clean);
+    clean = extent;
+  }
+};
+
+// K' (row sums) of a graph: short rows by kernel, hub rows by chunks.
+void graph_weights(gvl_ctx* ctx, Workspace& ws, const GraphDesc& g, int64_t m, const BinInfo& bins,
+                   const HubPlan& plan, int validate) {
+  hipStream_t st = ctx->stream;
+  vertex_weights(st, g, m, ws.K, &ws.sc->accW, ws.sc->flags, validate);
+  if (plan.H > 0) {
+    HubArgs h = hub_args(ws, bins);
+    hub_weights(st, g, h, 0, plan.T, ws.K, &ws.sc->accW, ws.sc->flags, validate);
+  }
+}
+
+void export_graph(gvl_ctx* ctx, const GraphDesc& g, int64_t ncom, PassDebug& pd) {
+  std::vector<int32_t> off(ncom + 1), deg(ncom);
+  (void)hipMemcpyAsync(off.data(), g.off, sizeof(int32_t) * (ncom + 1), hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipMemcpyAsync(deg.data(), g.deg, sizeof(int32_t) * ncom, hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  const int64_t cap = off[ncom];
+  std::vector<int32_t> idx(std::max<int64_t>(cap, 1));
+  std::vector<double> wd(std::max<int64_t>(cap, 1));
+  std::vector<float> wf;
+  (void)hipMemcpyAsync(idx.data(), g.idx, sizeof(int32_t) * cap, hipMemcpyDeviceToHost, ctx->stream);
+  if (g.w_double) {
+    (void)hipMemcpyAsync(wd.data(), g.w, sizeof(double) * cap, hipMemcpyDeviceToHost, ctx->stream);
+  } else {
+    wf.resize(std::max<int64_t>(cap, 1));
+    (void)hipMemcpyAsync(wf.data(), g.w, sizeof(float) * cap, hipMemcpyDeviceToHost, ctx->stream);
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  pd.y_off.assign(ncom + 1, 0);
+  pd.y_idx.clear();
+  pd.y_w.clear();
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t r = 0; r < ncom; ++r) {
+    row.clear();
+    for (int32_t k = 0; k < deg[r]; ++k) {
+      const int64_t e = (int64_t)off[r] + k;
+      row.push_back({idx[e], g.w_double ? wd[e] : (double)wf[e]});
+    }
+    std::sort(row.begin(), row.end());
+    for (auto& x : row) { pd.y_idx.push_back(x.first); pd.y_w.push_back(x.second); }
+    pd.y_off[r + 1] = (int32_t)pd.y_idx.size();
+  }
+  pd.m = (int64_t)pd.y_idx.size();
+}
+
+template <class T>
+std::vector<T> to_host(gvl_ctx* ctx, const T* d, int64_t n) {
+  std::vector<T> h(std::max<int64_t>(n, 1));
+  (void)hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  h.resize(n);
+  return h;
+}
+
+// Eq. 1 of `membership` on the input graph, computed on the device.
+gvl_status modularity_device(gvl_ctx* ctx, Workspace& ws, const GraphDesc& in, const int32_t* membership,
+                             double W, bool integral, double gamma, double* q) {
+  hipStream_t st = ctx->stream;
+  BinInfo bins;
+  gvl_status s = make_bins(ctx, ws, in.off, in.deg, in.n, 1, bins);
+  if (s != GVL_OK) return s;
+  HubPlan plan;
+  s = build_hub_plan(ctx, ws, bins, false, in, nullptr, 0, plan);
+  if (s != GVL_OK) return s;
+  fill_f64(st, ws.Sig, 0.0, in.n);
+  fill_f64(st, ws.sc->acc_d, 0.0, 2);
+  fill_u64(st, ws.sc->acc_u, 0ull, 2);
+  modularity_partial(st, in, membership, ws.Sig, ws.sc->acc_d);
+  if (plan.H > 0) hub_modularity(st, in, hub_args(ws, bins), 0, plan.T, membership, ws.Sig, ws.sc->acc_d);
+  modularity_squares(st, ws.Sig, in.n, integral, ws.sc->acc_d, ws.sc->acc_u);
+  s = readback(ctx, ws.sc);
+  if (s != GVL_OK) return s;
+  const double S1 = ctx->host->acc_d[0];
+  const double S2 = integral ? i128_to_double(ctx->host->acc_u[0], ctx->host->acc_u[1]) : ctx->host->acc_d[1];
+  *q = (W == 0.0) ? 0.0 : S1 / W - gamma * (S2 / (W * W));
+  return GVL_OK;
+}
+
+gvl_status check_args(gvl_ctx* ctx, int64_t n, int64_t m, const int32_t* off, const int32_t* idx,
+                      double resolution, const gvl_options* opt, void* wsp, size_t wsb) {
+  if (!ctx || !opt || n < 0 || m < 0 || m > 2147483647LL || n > 2147483646LL) return GVL_E_INVALID_ARG;
+  if (n > 0 && !off) return GVL_E_INVALID_ARG;
+  if (m > 0 && !idx) return GVL_E_INVALID_ARG;
+  if (!(resolution >= 0.0) || !std::isfinite(resolution)) return GVL_E_RESOLUTION;
+  if (opt->mode != GVL_MODE_FAST && opt->mode != GVL_MODE_DET) return GVL_E_INVALID_ARG;
+  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 1 ||
+      opt->subsweeps > kMaxGroups ||
+      !(opt->tolerance_drop > 0.0) || !(opt->aggregation_tolerance >= 0.0))
+    return GVL_E_INVALID_ARG;
+  size_t need = 0;
+  gvl_workspace_bytes(n, m, opt, &need);
+  if (!wsp || wsb < need) return GVL_E_WORKSPACE;
+  return GVL_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gvl_status_string(gvl_status s) {
+  switch (s) {
+    case GVL_OK: return "ok";
+    case GVL_E_INVALID_ARG: return "invalid argument";
+    case GVL_E_BAD_CSR: return "malformed CSR input";
+    case GVL_E_NONINTEGER_WEIGHT: return "weights not valid for this mode";
+    case GVL_E_RESOLUTION: return "invalid resolution";
+    case GVL_E_WORKSPACE: return "workspace missing or too small";
+    case GVL_E_HIP: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+gvl_status gvl_default_options(gvl_options* o, int32_t mode) {
+  if (!o || (mode != GVL_MODE_FAST && mode != GVL_MODE_DET)) return GVL_E_INVALID_ARG;
+  memset(o, 0, sizeof(*o));
+  o->mode = mode;
+  o->tolerance = 0.01;
+  o->tolerance_drop = 10.0;
+  o->aggregation_tolerance = 0.8;
+  o->max_iterations = 20;
+  o->max_passes = 20;
+  o->refine_sweeps = 20;
+  o->subsweeps = 32;
+  o->validate = 1;
+  return GVL_OK;
+}
+
+gvl_status gvl_workspace_bytes(int64_t n, int64_t m, const gvl_options* opt, size_t* bytes) {
+  if (!bytes || n < 0 || m < 0) return GVL_E_INVALID_ARG;
+  const bool det = opt && opt->mode == GVL_MODE_DET;
+  *bytes = carve(n, m, det, nullptr).bytes;
+  return GVL_OK;
+}
+
+gvl_status gvl_create(gvl_ctx_t* out, int device, void* hip_stream) {
+  if (!out) return GVL_E_INVALID_ARG;
+  *out = nullptr;
+  gvl_ctx* c = new gvl_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipSetDevice(device) != hipSuccess ||
+      hipHostMalloc((void**)&c->host, sizeof(Scalars), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->hbins, sizeof(BinBuf), hipHostMallocDefault) != hipSuccess) {
+    if (c->host) (void)hipHostFree(c->host);
+    delete c;
+    return GVL_E_HIP;
+  }
+  memset(c->host, 0, sizeof(Scalars));
+  memset(c->hbins, 0, sizeof(BinBuf));
+  *out = c;
+  return GVL_OK;
+}
+
+gvl_status gvl_destroy(gvl_ctx_t c) {
+  if (!c) return GVL_E_INVALID_ARG;
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->host) (void)hipHostFree(c->host);
+  if (c->hbins) (void)hipHostFree(c->hbins);
+  delete c;
+  return GVL_OK;
+}
+
+gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off, const int32_t* d_idx,
+                          const float* d_w, const int32_t* d_membership, double resolution, void* d_ws,
+                          size_t ws_bytes, double* modularity) {
+  gvl_options opt;
+  gvl_default_options(&opt, GVL_MODE_FAST);
+  gvl_status s = check_args(ctx, n, m, d_off, d_idx, resolution, &opt, d_ws, ws_bytes);
+  if (s != GVL_OK) return s;
+  if (!modularity || (n > 0 && !d_membership)) return GVL_E_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GVL_E_HIP;
+  Workspace ws = carve(n, m, false, (char*)d_ws);
+  hipStream_t st = ctx->stream;
+  *modularity = 0.0;
+  if (n == 0) return GVL_OK;
+  GraphDesc in{n, d_off, nullptr, d_idx, d_w, false};
+  fill_u64(st, (unsigned long long*)ws.sc, 0ull, sizeof(Scalars) / 8);
+  check_offsets(st, d_off, n, m, ws.sc->flags);
+  s = readback(ctx, ws.sc);
+  if (s != GVL_OK) return s;
+  if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
+  BinInfo bins;
+  s = make_bins(ctx, ws, d_off, nullptr, n, 1, bins);
+  if (s != GVL_OK) return s;
+  HubPlan plan;
+  s = build_hub_plan(ctx, ws, bins, false, in, nullptr, 0, plan);
+  if (s != GVL_OK) return s;
+  graph_weights(ctx, ws, in, m, bins, plan, 1);
+  s = readback(ctx, ws.sc);
+  if (s != GVL_OK) return s;
+  if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
+  if (ctx->host->flags[2]) return GVL_E_NONINTEGER_WEIGHT;
+  const double W = ctx->host->accW;
+  const bool integral = ctx->host->flags[1] == 0;
+  return modularity_device(ctx, ws, in, d_membership, W, integral, resolution, modularity);
+}
+
+gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off, const int32_t* d_idx,
+                      const float* d_w, double resolution, const gvl_options* opt, void* d_ws,
+                      size_t ws_bytes, int32_t* d_membership, double* modularity, gvl_stats* stats) {
+  gvl_status s = check_args(ctx, n, m, d_off, d_idx, resolution, opt, d_ws, ws_bytes);
+  if (s != GVL_OK) return s;
+  if (!modularity || (n > 0 && !d_membership)) return GVL_E_INVALID_ARG;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GVL_E_HIP;
+  const bool det = opt->mode == GVL_MODE_DET;
+  gvl_stats st_local;
+  gvl_stats* S = stats ? stats : &st_local;
+  memset(S, 0, sizeof(*S));
+  ctx->trace.clear();
+  ctx->ev_used = 0;
+  *modularity = 0.0;
+  if (n == 0) { S->termination = 3; return GVL_OK; }
+
+  hipStream_t st = ctx->stream;
+  Workspace ws = carve(n, m, det, (char*)d_ws);
+  Timer tm{ctx, opt->profile != 0, {}};
+  const GraphDesc input{n, d_off, nullptr, d_idx, d_w, false};
+  int32_t* top = d_membership;
+  TableState tstate;
+
+  // ---- input checks
+  int h = tm.begin(kEvOther);
+  fill_u64(st, (unsigned long long*)ws.sc, 0ull, sizeof(Scalars) / 8);
+  fill_i32(st, ws.hp_done, 0, n);
+  if (opt->validate) {
+    check_offsets(st, d_off, n, m, ws.sc->flags);
+    s = readback(ctx, ws.sc);
+    if (s != GVL_OK) return s;
+    if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
+  }
+
+  ScanArgs a;
+  memset(&a, 0, sizeof(a));
+  a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
+  a.target = ws.target; a.targeted = ws.targeted;
+  a.dq = &ws.sc->dq; a.dq128 = ws.sc->dq128; a.cnt = ws.sc->cnt;
+  a.tbl_keys = ws.tbl_keys; a.tbl_vals = ws.tbl_vals;
+
+  const int grid_cap = 256 * 16;
+  GraphDesc cur = input;
+  int buf = 0;
+  double tau = opt->tolerance;
+  bool ended = false;
+  int32_t pass = 0;
+  S->termination = 2;
+  int64_t ncom = n;
+  unsigned long long moves_before = 0, out_before = 0;
+  double Wd = 0.0;
+  bool integral = true;
+  long long Wi = 0, p = 0;
+  tm.end(h);
+
+  for (pass = 0; pass < opt->max_passes; ++pass) {
+    const int64_t nn = cur.n;
+    PassDebug pd;
+    pd.n = nn;
+    // ---- 1. degree bins, hub plan, vertex weights K', initial labels
+    h = tm.begin(kEvOther);
+    BinInfo bins;
+    s = make_bins(ctx, ws, cur.off, cur.deg, nn, opt->subsweeps, bins);
+    if (s != GVL_OK) return s;
+    HubPlan plan;
+    s = build_hub_plan(ctx, ws, bins, false, cur, nullptr, 0, plan);
+    if (s != GVL_OK) return s;
+    fill_f64(st, &ws.sc->accW, 0.0, 1);
+    graph_weights(ctx, ws, cur, pass == 0 ? m : 0, bins, plan, pass == 0 ? opt->validate : 0);
+    s = readback(ctx, ws.sc);
+    if (s != GVL_OK) return s;
+    if (pass == 0) {
+      if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
+      if (ctx->host->flags[2]) return GVL_E_NONINTEGER_WEIGHT;
+      Wd = ctx->host->accW;
+      integral = ctx->host->flags[1] == 0;
+      if (det) {
+        if (!integral || Wd > 1099511627776.0) return GVL_E_NONINTEGER_WEIGHT;
+        const double pd_ = resolution * 65536.0;
+        if (pd_ != std::floor(pd_) || pd_ > 16777216.0) return GVL_E_RESOLUTION;
+        Wi = (long long)Wd;
+        p = (long long)pd_;
+      }
+      if (Wd == 0.0) {
+        iota_i32(st, top, n);
+        HIP_TRY(hipStreamSynchronize(st));
+        S->termination = 3;
+        S->num_communities = n;
+        return GVL_OK;
+      }
+      a.inv_m = 2.0 / Wd;
+      a.gk_scale = 2.0 * resolution / (Wd * Wd);
+      a.W = Wi;
+      a.p = p;
+    }
+    if (pass < GVL_MAX_PASS_STATS) {
+      S->nv[pass] = nn;
+      S->ne[pass] = (pass == 0) ? m : (int64_t)(ctx->host->cnt[6] - out_before);
+    }
+    out_before = ctx->host->cnt[6];
+    if (pass > 0) {
+      copy_i32(st, ws.C, ws.start, nn);
+      fill_f64(st, ws.Sig, 0.0, nn);
+      fill_i32(st, ws.size, 0, nn);
+      community_totals(st, ws.C, ws.K, ws.Sig, ws.size, nn);
+    } else {
+      iota_i32(st, ws.C, nn);
+      copy_f64(st, ws.Sig, ws.K, nn);
+      set_size_one(st, ws.size, nn);
+    }
+    HubArgs hargs = hub_args(ws, bins);
+    fill_u8(st, ws.flag, 1, nn);
+    fill_i32(st, ws.target, -1, nn);
+    tm.end(h);
+
+    // Decisions of one group: short rows by the binned kernels, hubs by the
+    // chunked path (batch by batch through the table region).
+    auto decide_group = [&](int grp, int phase) {
+      if (phase == kMove)
+        launch_decide_move(st, cur, a, ws.list, bins.count[grp], bins.start[grp], det, grid_cap, 0,
+                           &S->scan_launches);
+      else
+        launch_decide_refine(st, cur, a, ws.list, bins.count[grp], bins.start[grp], det, grid_cap, 0,
+                             &S->scan_launches);
+      for (const HubBatch& hb : plan.groups[grp]) {
+        tstate.ensure(st, ws, hb.tend - hb.tbase);
+        hargs.tbase = hb.tbase;
+        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, phase, det, &S->scan_launches);
+      }
+    };
+    auto commit_group = [&](int grp, int phase) {
+      const int32_t* l0 = ws.list + bins.gstart[grp];
+      const int32_t n0 = bins.gend[grp] - bins.gstart[grp];
+      const int32_t* l1 = ws.list + bins.start[grp][kHubBin];
+      const int32_t n1 = bins.count[grp][kHubBin];
+      if (phase == kMove) {
+        launch_commit_move(st, cur, a, l0, n0);
+        launch_commit_move(st, cur, a, l1, n1);
+      } else {
+        launch_commit_refine(st, cur, a, l0, n0);
+        launch_commit_refine(st, cur, a, l1, n1);
+        launch_refine_cleanup(st, a, l0, n0);
+        launch_refine_cleanup(st, a, l1, n1);
+      }
+    };
+
+    // ---- 2. local-moving (Alg. 2)
+    h = tm.begin(kEvMove);
+    int32_t iters = 0;
+    bool first_conv = false;
+    for (int32_t it = 0; it < opt->max_iterations; ++it) {
+      fill_u64(st, (unsigned long long*)&ws.sc->dq, 0ull, 3);
+      int hk = det ? -1 : tm.begin(kEvScanMoveK);
+      for (int32_t grp = 0; grp < bins.S; ++grp) {
+        if (det) hk = tm.begin(kEvScanMoveK);
+        decide_group(grp, kMove);
+        if (det) {
+          tm.end(hk);
+          commit_group(grp, kMove);
+        }
+      }
+      if (!det) tm.end(hk);
+      s = readback(ctx, ws.sc);
+      if (s != GVL_OK) return s;
+      ++iters;
+      const unsigned long long mv = ctx->host->cnt[3] - moves_before;
+      moves_before = ctx->host->cnt[3];
+      pd.movers.push_back((int64_t)mv);
+      double dq;
+      if (det) {
+        dq = i128_to_double(ctx->host->dq128[0], ctx->host->dq128[1]) * 2.0 /
+             (65536.0 * (double)Wi * (double)Wi);
+      } else {
+        dq = ctx->host->dq;
+      }
+      if (dq <= tau) {
+        if (it == 0) first_conv = true;
+        break;
+      }
+    }
+    tm.end(h);
+    // ---- 3. refinement (Alg. 3)
+    h = tm.begin(kEvRefine);
+    copy_i32(st, ws.CB, ws.C, nn);
+    iota_i32(st, ws.C, nn);
+    copy_f64(st, ws.Sig, ws.K, nn);
+    set_size_one(st, ws.size, nn);
+    fill_u8(st, ws.targeted, 0, nn);
+    int32_t sweeps = 0;
+    int64_t refine_moved = 0;
+    for (int32_t sw = 0; sw < opt->refine_sweeps; ++sw) {
+      for (int32_t grp = 0; grp < bins.S; ++grp) {
+        const int hk = tm.begin(kEvScanRefineK);
+        decide_group(grp, kRefine);
+        tm.end(hk);
+        commit_group(grp, kRefine);
+      }
+      s = readback(ctx, ws.sc);
+      if (s != GVL_OK) return s;
+      ++sweeps;
+      const unsigned long long mv = ctx->host->cnt[3] - moves_before;
+      moves_before = ctx->host->cnt[3];
+      pd.refine_movers.push_back((int64_t)mv);
+      refine_moved += (int64_t)mv;
+      if (mv == 0) break;
+    }
+    tm.end(h);
+    // ---- 4. count communities; stop on convergence or low shrink
+    h = tm.begin(kEvOther);
+    fill_i32(st, ws.newid, 0, nn + 1);
+    mark_used(st, ws.C, nn, ws.newid);
+    exclusive_scan(st, ws.newid, nn, ws.scan_tmp);
+    HIP_TRY(hipMemcpyAsync(&ctx->host->total, ws.newid + nn, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ncom = ctx->host->total;
+    if (pass < GVL_MAX_PASS_STATS) {
+      S->iterations[pass] = iters;
+      S->refine_sweeps[pass] = sweeps;
+      S->ncom[pass] = ncom;
+    }
+    pd.ncom = ncom;
+    if (opt->debug_trace) {
+      pd.bound = to_host(ctx, ws.CB, nn);
+      pd.refined = to_host(ctx, ws.C, nn);
+    }
+    // vertices without arcs stay singletons: they are left out of the ratio
+    const int64_t z = nn - bins.binned;
+    bool stop = false;
+    if (first_conv && refine_moved == 0) { S->termination = 0; stop = true; }
+    else if (nn == z || (double)(ncom - z) / (double)(nn - z) > opt->aggregation_tolerance) {
+      S->termination = 1;
+      stop = true;
+    }
+    if (stop) {
+      if (opt->debug_trace) ctx->trace.push_back(std::move(pd));
+      ended = true;
+      tm.end(h);
+      break;
+    }
+    // ---- 5. renumber + dendrogram lookup
+    lookup_top(st, top, n, ws.C, ws.newid, pass == 0);
+    tm.end(h);
+    if (pass + 1 < opt->max_passes) {
+      // ---- 6. aggregation (Alg. 4)
+      h = tm.begin(kEvAgg);
+      const int nb = buf;
+      buf ^= 1;
+      int32_t* yoff = ws.off[nb];
+      int32_t* ydeg = ws.deg[nb];
+      fill_i32(st, ws.cnt, 0, ncom + 1);
+      fill_i32(st, yoff, 0, ncom + 1);
+      agg_count(st, cur, ws.C, ws.newid, ws.lab, ws.rank, ws.cnt, yoff);
+      exclusive_scan(st, ws.cnt, ncom, ws.scan_tmp);
+      exclusive_scan(st, yoff, ncom, ws.scan_tmp);
+      agg_fill(st, ws.lab, ws.rank, ws.cnt, nn, ws.cv);
+      fill_i32(st, ydeg, 0, ncom);
+      BinInfo cb;
+      s = make_bins(ctx, ws, yoff, nullptr, ncom, 1, cb);
+      if (s != GVL_OK) return s;
+      HubPlan gp;
+      s = build_hub_plan(ctx, ws, cb, true, cur, yoff, ncom, gp);
+      if (s != GVL_OK) return s;
+      AggArgs g;
+      memset(&g, 0, sizeof(g));
+      g.lab = ws.lab; g.coff = ws.cnt; g.cv = ws.cv; g.yoff = yoff; g.ydeg = ydeg;
+      g.yidx = ws.idx[nb]; g.yw = ws.w[nb]; g.yw_double = det; g.cnt = ws.sc->cnt;
+      g.tbl_keys = ws.tbl_keys; g.tbl_vals = ws.tbl_vals; g.ncom = ncom;
+      const int hk = tm.begin(kEvAggK);
+      launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], grid_cap, 0, &S->agg_launches);
+      if (gp.H > 0) {
+        member_degrees(st, cur, ws.cv, nn, ws.apre);
+        exclusive_scan(st, ws.apre, nn, ws.scan_tmp);
+        HubArgs gh = hub_args(ws, cb);
+        for (const HubBatch& hb : gp.groups[0]) {
+          tstate.ensure(st, ws, hb.tend - hb.tbase);
+          gh.tbase = hb.tbase;
+          gagg_rows(st, cur, g, gh, hb.c0, hb.c1, hb.s0, hb.s1, &S->agg_launches);
+        }
+      }
+      tm.end(hk);
+      // move-based labels of the super-vertices (Alg. 1)
+      fill_i32(st, ws.brank, 0, nn + 1);
+      mark_used(st, ws.CB, nn, ws.brank);
+      exclusive_scan(st, ws.brank, nn, ws.scan_tmp);
+      next_labels(st, ws.lab, ws.CB, ws.brank, nn, ws.start);
+      GraphDesc nxt{ncom, yoff, ydeg, ws.idx[nb], ws.w[nb], det};
+      if (opt->debug_trace) export_graph(ctx, nxt, ncom, pd);
+      cur = nxt;
+      tm.end(h);
+    }
+    if (opt->debug_trace) ctx->trace.push_back(std::move(pd));
+    tau = tau / opt->tolerance_drop;
+  }
+  // ---- result: flatten the last refinement, canonical labels, Eq. 1
+  h = tm.begin(kEvOther);
+  if (ended) lookup_raw(st, top, n, ws.C, pass == 0);
+  S->passes = ended ? pass + 1 : pass;
+  fill_i32(st, ws.rank, std::numeric_limits<int32_t>::max(), n);
+  first_occurrence(st, top, n, ws.rank);
+  first_flags(st, top, ws.rank, n, ws.newid);
+  exclusive_scan(st, ws.newid, n, ws.scan_tmp);
+  apply_canonical(st, top, ws.rank, ws.newid, n);
+  HIP_TRY(hipMemcpyAsync(&ctx->host->total, ws.newid + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  S->num_communities = ctx->host->total;
+  s = modularity_device(ctx, ws, input, top, Wd, integral, resolution, modularity);
+  if (s != GVL_OK) return s;
+  tm.end(h);
+  HIP_TRY(hipStreamSynchronize(st));
+  S->scan_vertices = (int64_t)ctx->host->cnt[0];
+  S->scan_arcs = (int64_t)ctx->host->cnt[1];
+  S->scan_candidates = (int64_t)ctx->host->cnt[2];
+  S->scan_moves = (int64_t)ctx->host->cnt[3];
+  S->agg_vertices = (int64_t)ctx->host->cnt[4];
+  S->agg_arcs = (int64_t)ctx->host->cnt[5];
+  S->agg_out_arcs = (int64_t)ctx->host->cnt[6];
+  S->scan_refine_arcs = (int64_t)ctx->host->cnt[7];
+  if (tm.on) {
+    double ms[kEvClasses];
+    tm.totals(ms);
+    S->ms_move = ms[kEvMove];
+    S->ms_refine = ms[kEvRefine];
+    S->ms_aggregate = ms[kEvAgg];
+    S->ms_other = ms[kEvOther];
+    S->ms_total = ms[kEvMove] + ms[kEvRefine] + ms[kEvAgg] + ms[kEvOther];
+    S->ms_scan_kernels = ms[kEvScanMoveK] + ms[kEvScanRefineK];
+    S->ms_scan_move_kernels = ms[kEvScanMoveK];
+    S->ms_agg_kernels = ms[kEvAggK];
+  }
+  return GVL_OK;
+}
+
+gvl_status gvl_debug_pass_info(gvl_ctx_t ctx, int32_t pass, int64_t* n_out, int64_t* ncom_out, int64_t* m_out) {
+  if (!ctx || pass < 0 || pass >= (int32_t)ctx->trace.size()) return GVL_E_INVALID_ARG;
+  const PassDebug& p = ctx->trace[pass];
+  if (n_out) *n_out = p.n;
+  if (ncom_out) *ncom_out = p.ncom;
+  if (m_out) *m_out = p.m;
+  return GVL_OK;
+}
+
+gvl_status gvl_debug_export_pass(gvl_ctx_t ctx, int32_t pass, int32_t* bound, int32_t* refined, int32_t* y_off,
+                                 int32_t* y_idx, double* y_w) {
+  if (!ctx || pass < 0 || pass >= (int32_t)ctx->trace.size()) return GVL_E_INVALID_ARG;
+  const PassDebug& p = ctx->trace[pass];
+  if (bound && !p.bound.empty()) memcpy(bound, p.bound.data(), sizeof(int32_t) * p.bound.size());
+  if (refined && !p.refined.empty()) memcpy(refined, p.refined.data(), sizeof(int32_t) * p.refined.size());
+  if (p.m >= 0) {
+    if (y_off) memcpy(y_off, p.y_off.data(), sizeof(int32_t) * p.y_off.size());
+    if (y_idx && p.m > 0) memcpy(y_idx, p.y_idx.data(), sizeof(int32_t) * p.y_idx.size());
+    if (y_w && p.m > 0) memcpy(y_w, p.y_w.data(), sizeof(double) * p.y_w.size());
+  }
+  return GVL_OK;
+}
+
+gvl_status gvl_debug_pass_movers(gvl_ctx_t ctx, int32_t pass, int64_t* movers, int32_t max_it,
+                                 int64_t* refine_movers, int32_t max_sw) {
+  if (!ctx || pass < 0 || pass >= (int32_t)ctx->trace.size()) return GVL_E_INVALID_ARG;
+  const PassDebug& p = ctx->trace[pass];
+  for (int32_t k = 0; movers && k < max_it && k < (int32_t)p.movers.size(); ++k) movers[k] = p.movers[k];
+  for (int32_t k = 0; refine_movers && k < max_sw && k < (int32_t)p.refine_movers.size(); ++k)
+    refine_movers[k] = p.refine_movers[k];
+  return GVL_OK;
+}
+
+}  // extern "C"

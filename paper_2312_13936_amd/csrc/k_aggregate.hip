@@ -1,0 +1,251 @@
+// Aggregation (Alg. 4): rows of the super-vertex graph G''.
+//
+// For each community c (a super-vertex), every arc (j, w) of every member i
+// of c -- self-loops included -- adds w to H[lab[j]], where lab[j] is the
+// renumbered community of j.  The distinct (d, H[d]) pairs are written into
+// row c of the holey CSR, whose capacity yoff[c+1] - yoff[c] is the total
+// degree of c's members (an over-estimate), and ydeg[c] receives the count.
+//
+// Communities are binned by that capacity; small ones map a group of G lanes
+// with an LDS table, large ones a workgroup with an LDS table, giant ones a
+// workgroup with a global-memory table.  Members with fewer than G arcs are
+// walked one per lane; larger members are walked by all lanes of the group
+// so that their rows stream coalesced.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace gvl {
+
+template <class WTin, class WTout, int G, int LG>
+__global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs a,
+                                                      const int32_t* __restrict__ list,
+                                                      int32_t count) {
+  constexpr int TS = 1 << LG;
+  constexpr int GPB = kBlock / G;
+  __shared__ int32_t skeys[GPB * TS];
+  __shared__ double svals[GPB * TS];
+  __shared__ unsigned long long red_u[16];
+  const int gl = threadIdx.x % G;
+  const int gb = threadIdx.x / G;
+  const int gbase = (lane_id() / G) * G;  // first lane of this group in the wavefront
+  const u64 gmask = (G == 64) ? ~0ull : ((1ull << G) - 1ull);
+  int32_t* keys = skeys + gb * TS;
+  double* vals = svals + gb * TS;
+  WTout* yw = (WTout*)a.yw;
+  for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
+  wave_sync();
+  unsigned long long nv = 0, na = 0, no = 0;
+  for (int64_t v = (int64_t)blockIdx.x * GPB + gb; v < count; v += (int64_t)gridDim.x * GPB) {
+    const int32_t c = list[v];
+    const int32_t mb = a.coff[c], me = a.coff[c + 1];
+    // members with short rows: one lane each
+    for (int32_t k = mb + gl; k < me; k += G) {
+      const int32_t i = a.cv[k];
+      const int32_t beg = g.begin(i), deg = g.degree(i);
+      ++nv;
+      if (deg >= G) continue;
+      na += (unsigned long long)deg;
+      for (int32_t e = 0; e < deg; ++e)
+        lds_insert(keys, vals, LG, a.lab[g.idx[beg + e]], g.weight(beg + e));
+    }
+    // members with long rows: the whole group
+    for (int32_t kb = mb; kb < me; kb += G) {
+      const int32_t k = kb + gl;
+      const int32_t i = (k < me) ? a.cv[k] : 0;
+      const bool big = (k < me) && g.degree(i) >= G;
+      u64 mask = (__ballot(big) >> gbase) & gmask;
+      while (mask) {
+        const int q = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int32_t ii = __shfl(i, q, G);
+        const int32_t beg = g.begin(ii), deg = g.degree(ii);
+        if (gl == 0) na += (unsigned long long)deg;
+        for (int32_t e = gl; e < deg; e += G)
+          lds_insert(keys, vals, LG, a.lab[g.idx[beg + e]], g.weight(beg + e));
+      }
+    }
+    wave_sync();
+    // emit the row: group exclusive scan of per-lane occupied counts
+    int cnt = 0;
+    for (int s = gl; s < TS; s += G) cnt += (keys[s] != kEmpty);
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) {
+      const int t = __shfl_up(incl, o, G);
+      if (gl >= o) incl += t;
+    }
+    const int total = __shfl(incl, G - 1, G);
+    int32_t pos = a.yoff[c] + (incl - cnt);
+    for (int s = gl; s < TS; s += G) {
+      const int32_t d = keys[s];
+      if (d == kEmpty) continue;
+      a.yidx[pos] = d;
+      yw[pos] = (WTout)vals[s];
+      ++pos;
+    }
+    if (gl == 0) { a.ydeg[c] = total; no += (unsigned long long)total; }
+    wave_sync();
+    for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
+    wave_sync();
+  }
+  nv = block_sum<unsigned long long>(nv, red_u);
+  na = block_sum<unsigned long long>(na, red_u);
+  no = block_sum<unsigned long long>(no, red_u);
+  if (threadIdx.x == 0) {
+    if (nv) atomicAdd(&a.cnt[4], nv);
+    if (na) atomicAdd(&a.cnt[5], na);
+    if (no) atomicAdd(&a.cnt[6], no);
+  }
+}
+
+// One workgroup per community.  LG > 0: LDS table; LG == 0: global table of
+// next_pow2(2 min(capacity, |Gamma|)) slots in this workgroup's slice.
+template <class WTin, class WTout, int LG>
+__global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs a,
+                                                      const int32_t* __restrict__ list,
+                                                      int32_t count) {
+  constexpr bool GLB = (LG == 0);
+  constexpr int TS = GLB ? 1 : (1 << LG);
+  __shared__ int32_t skeys[TS];
+  __shared__ double svals[TS];
+  __shared__ int s_wsum[kBlock / kWave];
+  __shared__ unsigned long long red_u[16];
+  int32_t* keys = GLB ? a.tbl_keys + (int64_t)blockIdx.x * a.tbl_slot : skeys;
+  double* vals = GLB ? a.tbl_vals + (int64_t)blockIdx.x * a.tbl_slot : svals;
+  WTout* yw = (WTout*)a.yw;
+  if (!GLB) {
+    for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+    __syncthreads();
+  }
+  unsigned long long nv = 0, na = 0, no = 0;
+  for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
+    const int32_t c = list[v];
+    const int32_t mb = a.coff[c], me = a.coff[c + 1];
+    int lg = LG;
+    if (GLB) {
+      int64_t cap = (int64_t)a.yoff[c + 1] - a.yoff[c];
+      if (cap > a.ncom) cap = a.ncom;
+      lg = ceil_log2(2 * cap);
+      for (int s = threadIdx.x; s < (1 << lg); s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+      __syncthreads();
+    }
+    const int ts = 1 << lg;
+    for (int32_t kb = mb; kb < me; kb += kBlock) {
+      const int32_t k = kb + threadIdx.x;
+      const int32_t i = (k < me) ? a.cv[k] : 0;
+      const int32_t deg = (k < me) ? g.degree(i) : 0;
+      if (k < me) ++nv;
+      if (k < me && deg < kWave) {
+        const int32_t beg = g.begin(i);
+        na += (unsigned long long)deg;
+        for (int32_t e = 0; e < deg; ++e) {
+          const int32_t d = a.lab[g.idx[beg + e]];
+          if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
+          else lds_insert(keys, vals, lg, d, g.weight(beg + e));
+        }
+      }
+      u64 mask = __ballot(k < me && deg >= kWave);
+      while (mask) {
+        const int q = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int32_t ii = __shfl(i, q);
+        const int32_t beg = g.begin(ii), dg = g.degree(ii);
+        if (lane_id() == 0) na += (unsigned long long)dg;
+        for (int32_t e = lane_id(); e < dg; e += kWave) {
+          const int32_t d = a.lab[g.idx[beg + e]];
+          if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
+          else lds_insert(keys, vals, lg, d, g.weight(beg + e));
+        }
+      }
+    }
+    __syncthreads();
+    // emit: block exclusive scan of per-thread occupied counts
+    int cnt = 0;
+    for (int s = threadIdx.x; s < ts; s += kBlock) {
+      const int32_t d = GLB ? glb_load_key(keys, s) : keys[s];
+      cnt += (d != kEmpty);
+    }
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int t = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += t;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < kBlock / kWave; ++k) {
+      if (k < w) before += s_wsum[k];
+      total += s_wsum[k];
+    }
+    int32_t pos = a.yoff[c] + before + (incl - cnt);
+    for (int s = threadIdx.x; s < ts; s += kBlock) {
+      const int32_t d = GLB ? glb_load_key(keys, s) : keys[s];
+      if (d == kEmpty) continue;
+      a.yidx[pos] = d;
+      yw[pos] = (WTout)(GLB ? glb_load_val(vals, s) : vals[s]);
+      ++pos;
+    }
+    if (threadIdx.x == 0) { a.ydeg[c] = total; no += (unsigned long long)total; }
+    __syncthreads();
+    if (!GLB) {
+      for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+      __syncthreads();
+    }
+  }
+  nv = block_sum<unsigned long long>(nv, red_u);
+  na = block_sum<unsigned long long>(na, red_u);
+  no = block_sum<unsigned long long>(no, red_u);
+  if (threadIdx.x == 0) {
+    if (nv) atomicAdd(&a.cnt[4], nv);
+    if (na) atomicAdd(&a.cnt[5], na);
+    if (no) atomicAdd(&a.cnt[6], no);
+  }
+}
+
+template <class WTin, class WTout>
+static void agg_bins(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const int32_t* list,
+                     const int32_t* count, const int32_t* start, int grid_cap, int hub_grid, int64_t* launches) {
+  GraphView<WTin> g;
+  g.n = gd.n; g.off = gd.off; g.deg = gd.deg; g.idx = gd.idx; g.w = (const WTin*)gd.w;
+  auto grid_for = [&](int64_t items, int per_block, int cap) {
+    int64_t b = (items + per_block - 1) / per_block;
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+  };
+#define GVL_AGG_BIN(B, G, LG)                                                                   \
+  if (count[B] > 0) {                                                                      \
+    hipLaunchKernelGGL((k_agg_group<WTin, WTout, G, LG>),                                       \
+                       dim3(grid_for(count[B], kBlock / (G), grid_cap)), dim3(kBlock), 0, st, \
+                       g, a, list + start[B], count[B]);                              \
+    ++*launches;                                                                                \
+  }
+  GVL_AGG_BIN(0, 4, 3)
+  GVL_AGG_BIN(1, 8, 4)
+  GVL_AGG_BIN(2, 16, 5)
+  GVL_AGG_BIN(3, 32, 6)
+  GVL_AGG_BIN(4, 64, 8)
+#undef GVL_AGG_BIN
+  if (count[5] > 0) {
+    hipLaunchKernelGGL((k_agg_block<WTin, WTout, 11>), dim3(grid_for(count[5], 1, grid_cap)),
+                       dim3(kBlock), 0, st, g, a, list + start[5], count[5]);
+    ++*launches;
+  }
+  (void)hub_grid;  // giant communities go through the chunked hub path
+}
+
+void launch_agg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const int32_t* list,
+                     const int32_t* count, const int32_t* start, int grid_cap, int hub_grid,
+                     int64_t* launches) {
+  if (g.w_double) {
+    agg_bins<double, double>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
+  } else if (a.yw_double) {
+    agg_bins<float, double>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
+  } else {
+    agg_bins<float, float>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
+  }
+}
+
+}  // namespace gvl

@@ -1,0 +1,541 @@
+// Hub path of the neighbour-community scan (Alg. 2 / Alg. 3) and of the
+// aggregation rows (Alg. 4) for items with very long rows: R-MAT hubs reach
+// hundreds of thousands of arcs, and a single workgroup per hub would leave
+// the GPU idle behind them.
+//
+// Every hub's arcs are cut into chunks of kHubChunk.  One workgroup per chunk
+// pre-aggregates the chunk in an LDS table and merges the distinct
+// (community, weight) pairs into the hub's global table with atomics.  The
+// table is then read back in slices by several workgroups: for the scan each
+// slice computes its best candidate (Eq. 2) and the last slice to finish
+// reduces the partial bests and applies the decision; for the aggregation
+// each slice appends its entries to the super-vertex row.
+#include "scan_kernels.hpp"
+
+namespace gvl {
+
+static inline int grid_items(int64_t n, int per, int cap) {
+  int64_t b = (n + per - 1) / per;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+__device__ __forceinline__ int64_t table_slots(int64_t arcs, int64_t n) {
+  int64_t x = arcs < n ? arcs : n;
+  int64_t t = kTblUnit;
+  while (t < 2 * x) t <<= 1;
+  return t;
+}
+
+__device__ __forceinline__ int32_t* tbl_keys_of(const HubArgs& h, int32_t p) {
+  return h.tbl_keys + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
+}
+__device__ __forceinline__ double* tbl_vals_of(const HubArgs& h, int32_t p) {
+  return h.tbl_vals + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
+}
+__device__ __forceinline__ int tbl_lg(const HubArgs& h, int32_t p) {
+  return ceil_log2((int64_t)(h.tbl_off[p + 1] - h.tbl_off[p]) * kTblUnit);
+}
+
+// ------------------------------------------------------------------ plan ---
+__global__ void k_hub_setup(const int32_t* off, const int32_t* deg, const int32_t* items, int32_t H, int64_t n,
+                            int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = items[p];
+    const int64_t d = deg ? deg[i] : off[i + 1] - off[i];
+    const int64_t ts = table_slots(d, n);
+    chunk_off[p] = (int32_t)((d + kHubChunk - 1) / kHubChunk);
+    tbl_off[p] = (int32_t)(ts / kTblUnit);
+    slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
+  }
+}
+void hub_setup(hipStream_t st, const int32_t* off, const int32_t* deg, const int32_t* items, int32_t H, int64_t n,
+               int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off) {
+  if (H > 0)
+    hipLaunchKernelGGL(k_hub_setup, dim3(grid_items(H, kBlock, 4096)), dim3(kBlock), 0, st, off, deg, items, H, n,
+                       chunk_off, tbl_off, slice_off);
+}
+
+__global__ void k_gagg_setup(const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom, int32_t* chunk_off,
+                             int32_t* tbl_off, int32_t* slice_off) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = items[p];
+    const int64_t cap = (int64_t)yoff[c + 1] - yoff[c];
+    const int64_t ts = table_slots(cap, ncom);
+    chunk_off[p] = (int32_t)((cap + kHubChunk - 1) / kHubChunk);
+    tbl_off[p] = (int32_t)(ts / kTblUnit);
+    slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
+  }
+}
+void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom, int32_t* chunk_off,
+                int32_t* tbl_off, int32_t* slice_off) {
+  if (H > 0)
+    hipLaunchKernelGGL(k_gagg_setup, dim3(grid_items(H, kBlock, 4096)), dim3(kBlock), 0, st, yoff, items, H, ncom,
+                       chunk_off, tbl_off, slice_off);
+}
+
+__global__ void k_hub_tasks(int32_t H, const int32_t* chunk_off, const int32_t* slice_off, int2* chunk_tasks,
+                            int2* slice_tasks) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
+    for (int32_t c = 0; c < chunk_off[p + 1] - chunk_off[p]; ++c) chunk_tasks[chunk_off[p] + c] = make_int2((int)p, c);
+    for (int32_t c = 0; c < slice_off[p + 1] - slice_off[p]; ++c) slice_tasks[slice_off[p] + c] = make_int2((int)p, c);
+  }
+}
+void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_t* slice_off, int2* chunk_tasks,
+               int2* slice_tasks) {
+  if (H > 0)
+    hipLaunchKernelGGL(k_hub_tasks, dim3(grid_items(H, kBlock, 4096)), dim3(kBlock), 0, st, H, chunk_off, slice_off,
+                       chunk_tasks, slice_tasks);
+}
+
+// ------------------------------------------------------------------ scan ---
+template <int PH, bool DET>
+__global__ void k_hub_prep(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
+  for (int64_t p = h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t i = h.items[p];
+    const bool act = Decide<PH, DET>::eligible(a, i);
+    h.active[p] = act ? 1 : 0;
+    if (PH == kMove && act) a.flag[i] = 0;  // processed (Alg. 2 prune)
+  }
+}
+
+// Chunk gather: H_chunk[C[j]] += w over the chunk's arcs (j != i; in
+// refinement only j inside i's bound), merged into the hub's global table.
+template <class WT, int PH>
+__global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t t0,
+                                                       int32_t t1) {
+  constexpr int TS = 1 << kHubGatherLg;
+  __shared__ int32_t skeys[TS];
+  __shared__ double svals[TS];
+  for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
+  __syncthreads();
+  unsigned long long na = 0;
+  for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
+    const int2 task = h.chunk_tasks[t];
+    const int32_t p = task.x;
+    if (!h.active[p]) continue;  // uniform over the workgroup
+    const int32_t i = h.items[p];
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t e0 = task.y * kHubChunk;
+    const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
+    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      const int32_t j = g.idx[beg + e];
+      if (j == i) continue;
+      if (PH == kRefine && a.CB[j] != bi) continue;
+      lds_insert(skeys, svals, kHubGatherLg, a.C[j], g.weight(beg + e));
+    }
+    if (threadIdx.x == 0) na += (unsigned long long)(e1 - e0);
+    __syncthreads();
+    int32_t* gk = tbl_keys_of(h, p);
+    double* gv = tbl_vals_of(h, p);
+    const int lg = tbl_lg(h, p);
+    for (int s = threadIdx.x; s < TS; s += kBlock) {
+      const int32_t c = skeys[s];
+      if (c != kEmpty) {
+        glb_insert(gk, gv, lg, c, svals[s]);
+        skeys[s] = kEmpty;
+        svals[s] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && na) {
+    atomicAdd(&a.cnt[1], na);
+    if (PH == kRefine) atomicAdd(&a.cnt[7], na);
+  }
+}
+
+__global__ void k_hub_kid(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
+  for (int64_t p = h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += (int64_t)gridDim.x * blockDim.x) {
+    if (!h.active[p]) continue;
+    const int32_t i = h.items[p];
+    h.kid[p] = glb_lookup(tbl_keys_of(h, (int32_t)p), tbl_vals_of(h, (int32_t)p), tbl_lg(h, (int32_t)p), a.C[i]);
+  }
+}
+
+// Slice evaluation: best candidate of the slice's table slots (the slots are
+// cleared for the next use); the last slice of a hub reduces the partial
+// bests, applies the min-label rule and the sign test, and commits (fast
+// local-moving) or records the decision.
+template <class WT, int PH, bool DET>
+__global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t s0,
+                                                     int32_t s1) {
+  __shared__ double s_g[kBlock / kWave];
+  __shared__ i128 s_k[kBlock / kWave];
+  __shared__ int32_t s_c[kBlock / kWave];
+  __shared__ int s_last, s_take, s_bc;
+  unsigned long long nc = 0, nv = 0, nm = 0;
+  double dq = 0.0;
+  i128 dqk = 0;
+  for (int64_t t = s0 + (int64_t)blockIdx.x; t < s1; t += gridDim.x) {
+    const int2 task = h.slice_tasks[t];
+    const int32_t p = task.x;
+    if (!h.active[p]) continue;  // uniform
+    const int32_t i = h.items[p];
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
+    const Eval<DET> ev(a, h.kid[p], ki, a.Sig[d]);
+    int32_t* gk = tbl_keys_of(h, p);
+    double* gv = tbl_vals_of(h, p);
+    const int64_t ts = (int64_t)1 << tbl_lg(h, p);
+    const int64_t q0 = (int64_t)task.y * kHubSlice;
+    const int64_t q1 = (q0 + kHubSlice < ts) ? q0 + kHubSlice : ts;
+    int32_t bc = -1;
+    double bg = 0.0;
+    i128 bk = 0;
+    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
+      const int32_t c = glb_load_key(gk, (uint32_t)q);
+      if (c == kEmpty) continue;
+      if (c != d) {
+        ++nc;
+        ev(a, c, glb_load_val(gv, (uint32_t)q), a.Sig[c], bg, bk, bc);
+      }
+      gk[q] = kEmpty;
+      gv[q] = 0.0;
+    }
+    if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { s_g[w] = bg; s_k[w] = bk; s_c[w] = bc; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      bc = s_c[0]; bg = s_g[0]; bk = s_k[0];
+      for (int k = 1; k < kBlock / kWave; ++k) {
+        if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
+        else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
+      }
+      h.pb_g[t] = bg;
+      h.pb_k[t] = bk;
+      h.pb_c[t] = bc;
+      __threadfence();
+      const int nsl = h.slice_off[p + 1] - h.slice_off[p];
+      const int prev = atomicAdd(&h.done[p], 1);
+      s_last = (prev == nsl - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    if (s_last) {
+      if (threadIdx.x == 0) {
+        __threadfence();
+        const int32_t sb = h.slice_off[p], se = h.slice_off[p + 1];
+        bc = -1; bg = 0.0; bk = 0;
+        for (int32_t k = sb; k < se; ++k) {
+          const int32_t c2 = __hip_atomic_load(h.pb_c + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (DET) {
+            const unsigned long long* kw = (const unsigned long long*)(h.pb_k + k);
+            const unsigned long long lo = __hip_atomic_load(kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long hi = __hip_atomic_load(kw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const i128 k2 = make_i128((long long)hi, lo);
+            if (better_k(k2, c2, bk, bc)) { bk = k2; bc = c2; }
+          } else {
+            const double g2 = __hip_atomic_load(h.pb_g + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (better_f(g2, c2, bg, bc)) { bg = g2; bc = c2; }
+          }
+        }
+        h.done[p] = 0;
+        ++nv;
+        const bool take = accept<PH, DET>(a, d, bc, bg, bk);
+        s_take = take ? 1 : 0;
+        s_bc = bc;
+        if (take) {
+          if (PH == kMove && !DET) {
+            atomicAdd(&a.Sig[d], -ki);
+            atomicAdd(&a.Sig[bc], ki);
+            atomicSub(&a.size[d], 1);
+            atomicAdd(&a.size[bc], 1);
+            a.C[i] = bc;
+            dq += bg;
+            ++nm;
+          } else if (PH == kMove) {
+            a.target[i] = bc;
+            dqk += bk;
+          } else {
+            a.target[i] = bc;
+            a.targeted[bc] = 1;
+          }
+        }
+      }
+      __syncthreads();
+      if (PH == kMove && !DET && s_take) {
+        const int32_t beg = g.begin(i), deg = g.degree(i);
+        for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
+          const int32_t j = g.idx[beg + e];
+          if (j != i) a.flag[j] = 1;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // one thread per workgroup carries the counters
+  if (threadIdx.x == 0) {
+    if (nv) atomicAdd(&a.cnt[0], nv);
+    if (nm) atomicAdd(&a.cnt[3], nm);
+    if (DET) { if (dqk != 0) atomic_add_i128(a.dq128, dqk); }
+    else { if (dq != 0.0) atomicAdd(a.dq, dq); }
+  }
+  __shared__ unsigned long long red_u[16];
+  nc = block_sum<unsigned long long>(nc, red_u);
+  if (threadIdx.x == 0 && nc) atomicAdd(&a.cnt[2], nc);
+}
+
+template <class WT, int PH, bool DET>
+static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const HubArgs& h, int32_t h0,
+                         int32_t h1, int32_t c0, int32_t c1, int32_t s0, int32_t s1, int64_t* launches) {
+  const GraphView<WT> g = view<WT>(gd);
+  const int hb = grid_items(h1 - h0, kBlock, 1024);
+  hipLaunchKernelGGL((k_hub_prep<PH, DET>), dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
+  if (c1 > c0)
+    hipLaunchKernelGGL((k_hub_gather<WT, PH>), dim3(grid_items(c1 - c0, 1, 8192)), dim3(kBlock), 0, st, g, a, h, c0,
+                       c1);
+  hipLaunchKernelGGL(k_hub_kid, dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
+  if (s1 > s0)
+    hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 8192)), dim3(kBlock), 0, st, g, a, h,
+                       s0, s1);
+  *launches += 4;
+}
+
+void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
+                int32_t c0, int32_t c1, int32_t s0, int32_t s1, int phase, bool det, int64_t* launches) {
+  if (h1 <= h0) return;
+#define GVL_HUB(WT, PH, DET) hub_decide_t<WT, PH, DET>(st, g, a, h, h0, h1, c0, c1, s0, s1, launches)
+  if (g.w_double) {
+    if (phase == kMove) { if (det) GVL_HUB(double, kMove, true); else GVL_HUB(double, kMove, false); }
+    else { if (det) GVL_HUB(double, kRefine, true); else GVL_HUB(double, kRefine, false); }
+  } else {
+    if (phase == kMove) { if (det) GVL_HUB(float, kMove, true); else GVL_HUB(float, kMove, false); }
+    else { if (det) GVL_HUB(float, kRefine, true); else GVL_HUB(float, kRefine, false); }
+  }
+#undef GVL_HUB
+}
+
+// ------------------------------------------------------ row sums of hubs ---
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_hub_weights(GraphView<WT> g, HubArgs h, int32_t t0, int32_t t1, double* K,
+                                                        double* accW, int32_t* flags, int validate) {
+  __shared__ double red[16];
+  int bad_csr = 0, bad_w = 0, bad_sign = 0;
+  for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
+    const int2 task = h.chunk_tasks[t];
+    const int32_t i = h.items[task.x];
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t e0 = task.y * kHubChunk;
+    const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
+    double s = 0.0;
+    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      const double w = g.weight(beg + e);
+      if (validate) {
+        const int32_t j = g.idx[beg + e];
+        if (j < 0 || j >= g.n) bad_csr = 1;
+      }
+      if (!(w >= 1.0 && w <= 16777216.0 && w == floor(w))) bad_w = 1;
+      if (!(w > 0.0 && w < INFINITY)) bad_sign = 1;
+      s += w;
+    }
+    s = block_sum<double>(s, red);
+    if (threadIdx.x == 0) {
+      atomicAdd(&K[i], s);
+      atomicAdd(accW, s);
+    }
+  }
+  if (bad_csr) atomicOr(&flags[0], 1);
+  if (bad_w) atomicOr(&flags[1], 1);
+  if (bad_sign) atomicOr(&flags[2], 1);
+}
+
+void hub_weights(hipStream_t st, const GraphDesc& gd, const HubArgs& h, int32_t c0, int32_t c1, double* K,
+                 double* accW, int32_t* flags, int validate) {
+  if (c1 <= c0) return;
+  const int grid = grid_items(c1 - c0, 1, 8192);
+  if (gd.w_double)
+    hipLaunchKernelGGL(k_hub_weights<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), h, c0, c1, K, accW,
+                       flags, validate);
+  else
+    hipLaunchKernelGGL(k_hub_weights<float>, dim3(grid), dim3(kBlock), 0, st, view<float>(gd), h, c0, c1, K, accW,
+                       flags, validate);
+}
+
+// --------------------------------------------------- modularity of hub rows ---
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_hub_modularity(GraphView<WT> g, HubArgs h, int32_t t0, int32_t t1,
+                                                           const int32_t* C, double* tot, double* acc_d) {
+  __shared__ double red[16];
+  double s1 = 0.0;
+  for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
+    const int2 task = h.chunk_tasks[t];
+    const int32_t i = h.items[task.x];
+    const int32_t beg = g.begin(i), deg = g.degree(i), ci = C[i];
+    const int32_t e0 = task.y * kHubChunk;
+    const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
+    double k = 0.0;
+    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      const double w = g.weight(beg + e);
+      k += w;
+      if (C[g.idx[beg + e]] == ci) s1 += w;
+    }
+    k = block_sum<double>(k, red);
+    if (threadIdx.x == 0) atomicAdd(&tot[ci], k);
+  }
+  s1 = block_sum<double>(s1, red);
+  if (threadIdx.x == 0 && s1 != 0.0) atomicAdd(&acc_d[0], s1);
+}
+
+void hub_modularity(hipStream_t st, const GraphDesc& gd, const HubArgs& h, int32_t c0, int32_t c1, const int32_t* C,
+                    double* tot, double* acc_d) {
+  if (c1 <= c0) return;
+  const int grid = grid_items(c1 - c0, 1, 8192);
+  if (gd.w_double)
+    hipLaunchKernelGGL(k_hub_modularity<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), h, c0, c1, C, tot,
+                       acc_d);
+  else
+    hipLaunchKernelGGL(k_hub_modularity<float>, dim3(grid), dim3(kBlock), 0, st, view<float>(gd), h, c0, c1, C, tot,
+                       acc_d);
+}
+
+// ------------------------------------------------ giant community rows ---
+template <class WT>
+__global__ void k_member_degrees(GraphView<WT> g, const int32_t* cv, int32_t* mdeg) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += (int64_t)gridDim.x * blockDim.x)
+    mdeg[k] = g.degree(cv[k]);
+}
+void member_degrees(hipStream_t st, const GraphDesc& gd, const int32_t* cv, int64_t n, int32_t* mdeg) {
+  if (n > 0) hipLaunchKernelGGL(k_member_degrees<float>, dim3(grid_items(n, kBlock, 16384)), dim3(kBlock), 0, st,
+                                view<float>(gd), cv, mdeg);
+}
+
+// Chunk gather over the concatenated member rows of community c: arcs
+// [apre[coff[c]] + chunk * kHubChunk, ...) of the community-vertex order.
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs a, HubArgs h, int32_t t0,
+                                                        int32_t t1) {
+  constexpr int TS = 1 << kHubGatherLg;
+  constexpr int PER = kHubChunk / kBlock;  // arcs per thread
+  __shared__ int32_t skeys[TS];
+  __shared__ double svals[TS];
+  for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
+  __syncthreads();
+  unsigned long long na = 0;
+  for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
+    const int2 task = h.chunk_tasks[t];
+    const int32_t p = task.x;
+    const int32_t c = h.items[p];
+    const int32_t mb = a.coff[c], me = a.coff[c + 1];
+    const int64_t cend = h.apre[me];
+    const int64_t A0 = (int64_t)h.apre[mb] + (int64_t)task.y * kHubChunk;
+    int64_t pos = A0 + (int64_t)threadIdx.x * PER;
+    int64_t end = pos + PER;
+    if (end > cend) end = cend;
+    if (pos < end) {
+      // member k with apre[k] <= pos < apre[k+1]
+      int32_t lo = mb, hi = me;  // invariant: apre[lo] <= pos < apre[hi]
+      while (hi - lo > 1) {
+        const int32_t mid = lo + (hi - lo) / 2;
+        if (h.apre[mid] <= pos) lo = mid; else hi = mid;
+      }
+      int32_t k = lo;
+      while (pos < end) {
+        const int32_t i = a.cv[k];
+        const int32_t beg = g.begin(i);
+        const int64_t r0 = pos - h.apre[k];
+        int64_t take = (int64_t)h.apre[k + 1] - pos;
+        if (take > end - pos) take = end - pos;
+        for (int64_t x = 0; x < take; ++x) {
+          const int64_t e = beg + r0 + x;
+          lds_insert(skeys, svals, kHubGatherLg, a.lab[g.idx[e]], g.weight(e));
+        }
+        na += (unsigned long long)take;
+        pos += take;
+        ++k;
+      }
+    }
+    __syncthreads();
+    int32_t* gk = tbl_keys_of(h, p);
+    double* gv = tbl_vals_of(h, p);
+    const int lg = tbl_lg(h, p);
+    for (int s = threadIdx.x; s < TS; s += kBlock) {
+      const int32_t key = skeys[s];
+      if (key != kEmpty) {
+        glb_insert(gk, gv, lg, key, svals[s]);
+        skeys[s] = kEmpty;
+        svals[s] = 0.0;
+      }
+    }
+    __syncthreads();
+  }
+  __shared__ unsigned long long red_u[16];
+  na = block_sum<unsigned long long>(na, red_u);
+  if (threadIdx.x == 0 && na) atomicAdd(&a.cnt[5], na);
+}
+
+// Slice emit: append the slice's (d, H[d]) pairs to row c (ydeg[c] is the
+// row cursor, zeroed by the caller) and clear the slots.
+template <class WTout>
+__global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int32_t s0, int32_t s1) {
+  __shared__ int s_wsum[kBlock / kWave];
+  __shared__ int s_base;
+  WTout* yw = (WTout*)a.yw;
+  unsigned long long no = 0;
+  for (int64_t t = s0 + (int64_t)blockIdx.x; t < s1; t += gridDim.x) {
+    const int2 task = h.slice_tasks[t];
+    const int32_t p = task.x;
+    const int32_t c = h.items[p];
+    int32_t* gk = tbl_keys_of(h, p);
+    double* gv = tbl_vals_of(h, p);
+    const int64_t ts = (int64_t)1 << tbl_lg(h, p);
+    const int64_t q0 = (int64_t)task.y * kHubSlice;
+    const int64_t q1 = (q0 + kHubSlice < ts) ? q0 + kHubSlice : ts;
+    // kHubSlice / kBlock slots per thread, contiguous
+    constexpr int PER = kHubSlice / kBlock;
+    const int64_t my0 = q0 + (int64_t)threadIdx.x * PER;
+    int cnt = 0;
+    for (int64_t q = my0; q < my0 + PER && q < q1; ++q) cnt += (glb_load_key(gk, (uint32_t)q) != kEmpty);
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) s_wsum[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < kBlock / kWave; ++k) {
+      if (k < w) before += s_wsum[k];
+      total += s_wsum[k];
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(&a.ydeg[c], total) : 0;
+    __syncthreads();
+    int64_t pos = (int64_t)a.yoff[c] + s_base + before + (incl - cnt);
+    for (int64_t q = my0; q < my0 + PER && q < q1; ++q) {
+      const int32_t key = glb_load_key(gk, (uint32_t)q);
+      if (key == kEmpty) continue;
+      a.yidx[pos] = key;
+      yw[pos] = (WTout)glb_load_val(gv, (uint32_t)q);
+      ++pos;
+      gk[q] = kEmpty;
+      gv[q] = 0.0;
+    }
+    if (threadIdx.x == 0) no += (unsigned long long)total;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && no) atomicAdd(&a.cnt[6], no);
+}
+
+void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
+               int32_t s0, int32_t s1, int64_t* launches) {
+  if (c1 > c0) {
+    const int grid = grid_items(c1 - c0, 1, 8192);
+    if (gd.w_double)
+      hipLaunchKernelGGL(k_gagg_gather<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), a, h, c0, c1);
+    else
+      hipLaunchKernelGGL(k_gagg_gather<float>, dim3(grid), dim3(kBlock), 0, st, view<float>(gd), a, h, c0, c1);
+    ++*launches;
+  }
+  if (s1 > s0) {
+    const int grid = grid_items(s1 - s0, 1, 8192);
+    if (a.yw_double) hipLaunchKernelGGL(k_gagg_emit<double>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
+    else hipLaunchKernelGGL(k_gagg_emit<float>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
+    ++*launches;
+  }
+}
+
+}  // namespace gvl

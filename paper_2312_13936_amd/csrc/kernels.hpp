@@ -1,0 +1,236 @@
+// Host-side launch interface of the gvl kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gvl {
+
+typedef __int128 i128_t;
+
+constexpr int32_t kEmpty = -1;        // empty hash-table slot
+enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (Alg. 3)
+
+// Degree bins (vertex scan) and capacity bins (aggregation rows).  A vertex
+// of degree d (or a community whose member arcs total d) goes to the first
+// bin with d <= kBinMax[b]; d == 0 is never binned.  Bins 0-4 map a group of
+// kBinLanes[b] lanes of one wavefront to each item with an LDS hash table of
+// 2^kBinLg[b] slots; bin 5 maps a 256-thread workgroup with an LDS table;
+// bin 6 (hubs / giant communities) a workgroup with a global-memory table.
+constexpr int kNumBins = 7;
+constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 0x7fffffff};
+constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 256};
+constexpr int kBinLg[kNumBins] = {3, 4, 5, 6, 8, 11, 0};
+constexpr int kHubBin = kNumBins - 1;
+
+// Local-moving and refinement visit the vertices in S pseudo-random groups
+// (sub-sweeps); the bin lists are laid out group-major so that every
+// (group, bin) segment is contiguous.
+constexpr int kMaxGroups = 64;
+
+// List layout: for every group its bins 0..kHubBin-1 (group-major), then the
+// hub bin of every group, so that all hubs form one region [H0, H0 + H).
+struct BinInfo {
+  int32_t S;                               // groups (1 for aggregation)
+  int32_t count[kMaxGroups][kNumBins];
+  int32_t start[kMaxGroups][kNumBins];
+  int32_t gstart[kMaxGroups + 1];          // non-hub items of group g: [gstart[g], gend[g])
+  int32_t gend[kMaxGroups];
+  int32_t H0, H;                           // hub region
+  int32_t binned;                          // items with at least one arc
+  int32_t maxsize[kNumBins];
+};
+
+// Device-side binning counters: counts[g * kNumBins + b], then maxsize[b].
+struct BinBuf {
+  int32_t counts[kMaxGroups * kNumBins];
+  int32_t maxsize[kNumBins];
+  int32_t cursors[kMaxGroups * kNumBins];
+  int32_t pad;
+};
+
+// State read and written by the local-moving / refinement decision kernels.
+struct ScanArgs {
+  int32_t* C;               // community of each vertex (C')
+  const int32_t* CB;        // community bound (C'_B), refinement only
+  double* Sig;              // total weight of each community (Sigma')
+  int32_t* size;            // vertices in each community
+  const double* K;          // weighted degree of each vertex (K')
+  uint8_t* flag;            // local-moving: 1 = unprocessed
+  int32_t* target;          // synchronous decisions: chosen community or -1
+  uint8_t* targeted;        // refinement: community chosen as a target this sweep
+  double inv_m;             // 1/m = 2/W
+  double gk_scale;          // 2 gamma / W^2
+  long long W;              // exact total weight (deterministic mode)
+  long long p;              // resolution numerator, gamma = p / 65536 (deterministic mode)
+  double* dq;               // fast mode: sum of the gains of the moves made
+  unsigned long long* dq128;  // deterministic mode: exact int128 sum of move keys (lo, hi)
+  unsigned long long* cnt;  // [0] vertices scanned, [1] arcs, [2] candidates, [3] moves,
+                            // [7] arcs scanned by refinement
+  int32_t* tbl_keys;        // global hash tables for the hub bin
+  double* tbl_vals;
+  int64_t tbl_slot;         // slots per workgroup table
+};
+
+// Hub path (vertices or communities with more than kBinMax[5] arcs).  Their
+// arcs are cut into chunks of kHubChunk; each chunk is pre-aggregated in an
+// LDS table by one workgroup and merged into the item's global table (Alg. 2
+// scanCommunities / Alg. 4 row accumulation), which is then read back in
+// slices of kHubSlice slots by several workgroups.  Global tables hold
+// max(1024, next_pow2(2 min(arcs, |V'|))) slots, allocated in units of 1024.
+constexpr int kHubChunk = 2048;
+constexpr int kHubGatherLg = 12;      // LDS pre-aggregation table: 4096 slots
+constexpr int kHubSlice = 8192;
+constexpr int kTblUnit = 1024;
+
+struct HubArgs {
+  const int32_t* items;       // hub vertex (or giant community) of each hub index p
+  const int32_t* chunk_off;   // [H+1] first chunk task of p
+  const int32_t* tbl_off;     // [H+1] table offset of p in units of kTblUnit
+  const int32_t* slice_off;   // [H+1] first slice task of p
+  const int2* chunk_tasks;    // (p, chunk)
+  const int2* slice_tasks;    // (p, slice)
+  int32_t* active;            // [H] item takes part in this launch
+  double* kid;                // [H] weight of a hub's arcs to its own community
+  int32_t* done;              // [H] slices finished (last one reduces)
+  double* pb_g;               // per slice task: best gain
+  i128_t* pb_k;               // per slice task: best exact key
+  int32_t* pb_c;              // per slice task: best community
+  int32_t* tbl_keys;          // table region
+  double* tbl_vals;
+  int64_t tbase;              // region offset of the current batch (slots)
+  const int32_t* apre;        // aggregation: arc prefix over the community-vertex list
+};
+
+// Raw graph description passed to launchers (weights float or double).
+struct GraphDesc {
+  int64_t n;
+  const int32_t* off;
+  const int32_t* deg;   // nullptr: plain CSR
+  const int32_t* idx;
+  const void* w;        // nullptr: unit weights
+  bool w_double;
+};
+
+// Arguments of the aggregation row kernels (Alg. 4, lines building G'').
+struct AggArgs {
+  const int32_t* lab;    // renumbered refined label of each vertex (super-vertex id)
+  const int32_t* coff;   // community-vertex CSR offsets [ncom + 1]
+  const int32_t* cv;     // community-vertex CSR members
+  const int32_t* yoff;   // super-vertex row offsets (holey) [ncom + 1]
+  int32_t* ydeg;         // filled length of each super-vertex row
+  int32_t* yidx;
+  void* yw;              // float or double
+  bool yw_double;
+  unsigned long long* cnt;  // [4] vertices, [5] arcs read, [6] arcs written
+  int32_t* tbl_keys;
+  double* tbl_vals;
+  int64_t tbl_slot;
+  int64_t ncom;
+};
+
+// ---- scan kernels (k_scan_move.hip, k_scan_refine.hip); one call per group
+// `list` is the whole bin list; count/start are the group's bin segments.
+void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
+                        const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
+                        int64_t* launches);
+// Apply the recorded moves of the vertices list[0..count).
+void launch_commit_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
+                        int32_t count);
+void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
+                          const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
+                          int64_t* launches);
+// Apply the recorded merges of list[0..count).
+void launch_commit_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
+                          int32_t count);
+// Clear target / targeted of list[0..count): only after every commit of the
+// group has read the targeted flags.
+void launch_refine_cleanup(hipStream_t st, const ScanArgs& a, const int32_t* list, int32_t count);
+
+// ---- aggregation (k_aggregate.hip)
+void launch_agg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const int32_t* list,
+                     const int32_t* count, const int32_t* start, int grid_cap, int hub_grid,
+                     int64_t* launches);
+
+// ---- hub path (k_hub.hip)
+// Per-hub sizes: nchunk, table units and nslice written to chunk_off /
+// tbl_off / slice_off[p] (exclusive-scanned by the caller).
+void hub_setup(hipStream_t st, const int32_t* off, const int32_t* deg, const int32_t* items, int32_t H,
+               int64_t n, int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off);
+void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_t* slice_off, int2* chunk_tasks,
+               int2* slice_tasks);
+// One batch [h0, h1) of one group: eligibility snapshot, gather, own-community
+// weight, evaluation (+ commit in fast local-moving).
+void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
+                int32_t c0, int32_t c1, int32_t s0, int32_t s1, int phase, bool det, int64_t* launches);
+// K[i] += sums of the chunks of hub rows (K[i] of hubs zeroed by the caller).
+void hub_weights(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_t c0, int32_t c1, double* K,
+                 double* accW, int32_t* flags, int validate);
+// Modularity partial sums of hub rows: tot[C[i]] += K part, acc_d[0] += sigma part.
+void hub_modularity(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_t c0, int32_t c1,
+                    const int32_t* C, double* tot, double* acc_d);
+// Aggregation of giant communities.
+void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom,
+                int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off);
+void member_degrees(hipStream_t st, const GraphDesc& g, const int32_t* cv, int64_t n, int32_t* mdeg);
+void gagg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
+               int32_t s0, int32_t s1, int64_t* launches);
+
+// ---- primitives (k_prims.hip)
+int scan_tiles(int64_t n);  // number of tiles used by exclusive_scan
+// In-place exclusive scan of int32 data[0..n); data[n] receives the total.
+// tmp needs scan_tiles(n) + 1 int32 entries.
+void exclusive_scan(hipStream_t st, int32_t* data, int64_t n, int32_t* tmp);
+void fill_i32(hipStream_t st, int32_t* p, int32_t v, int64_t n);
+void fill_u8(hipStream_t st, uint8_t* p, uint8_t v, int64_t n);
+void fill_f64(hipStream_t st, double* p, double v, int64_t n);
+void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64_t n);
+void iota_i32(hipStream_t st, int32_t* p, int64_t n);
+void copy_i32(hipStream_t st, int32_t* dst, const int32_t* src, int64_t n);
+void copy_f64(hipStream_t st, double* dst, const double* src, int64_t n);
+void set_size_one(hipStream_t st, int32_t* size, int64_t n);
+
+// K[i] = row sum (self-loop once); *accW += W.  flags[0] |= bad CSR
+// (validate only), flags[1] |= weight not an integer in [1, 2^24],
+// flags[2] |= weight not positive and finite.
+// Rows longer than kBinMax[kHubBin - 1] are skipped (K = 0): the hub path
+// adds them (hub_weights).
+void vertex_weights(hipStream_t st, const GraphDesc& g, int64_t m, double* K, double* accW,
+                    int32_t* flags, int validate);
+// Sig[C[i]] += K[i]; size[C[i]] += 1 (Sig, size zeroed by the caller).
+void community_totals(hipStream_t st, const int32_t* C, const double* K, double* Sig,
+                      int32_t* size, int64_t n);
+// Degree binning into S groups: bin_count fills bb->counts / bb->maxsize,
+// bin_scatter places item i at bb->cursors[group(i) * kNumBins + bin(i)]++.
+void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, BinBuf* bb);
+void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, BinBuf* bb,
+                 int32_t* list);
+// used[c] = 1 for every label c in C[0..n) (used zeroed by the caller).
+void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used);
+// top[v] = newid[C[top[v]]]  (first = 1: top[v] = newid[C[v]]).
+void lookup_top(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, const int32_t* newid,
+                bool first);
+// top[v] = C[top[v]] (or C[v] when first).
+void lookup_raw(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, bool first);
+// lab[i] = newid[C[i]]; rank[i] = atomic slot in cnt[lab]; cap[lab] += degree(i).
+void agg_count(hipStream_t st, const GraphDesc& g, const int32_t* C, const int32_t* newid,
+               int32_t* lab, int32_t* rank, int32_t* cnt, int32_t* cap);
+void agg_fill(hipStream_t st, const int32_t* lab, const int32_t* rank, const int32_t* coff, int64_t n,
+              int32_t* cv);
+// start[lab[i]] = brank[CB[i]] (move-based labels of super-vertices).
+void next_labels(hipStream_t st, const int32_t* lab, const int32_t* CB, const int32_t* brank,
+                 int64_t n, int32_t* start);
+// Canonical relabelling by first occurrence over v = 0..N-1.
+void first_occurrence(hipStream_t st, const int32_t* top, int64_t N, int32_t* first);
+void first_flags(hipStream_t st, const int32_t* top, const int32_t* first, int64_t N, int32_t* flags);
+void apply_canonical(hipStream_t st, int32_t* top, const int32_t* first, const int32_t* scan, int64_t N);
+// Modularity (Eq. 1): S1 = sum of intra-community arc weights (acc_d[0]),
+// tot[c] += K_i; then S2 = sum tot[c]^2 (exact int128 into acc_u[0..1] when
+// integral, else double into acc_d[1]).  Hub rows are left to hub_modularity.
+void modularity_partial(hipStream_t st, const GraphDesc& g, const int32_t* C, double* tot,
+                        double* acc_d);
+void check_offsets(hipStream_t st, const int32_t* off, int64_t n, int64_t m, int32_t* flags);
+void modularity_squares(hipStream_t st, const double* tot, int64_t n, bool integral, double* acc_d,
+                        unsigned long long* acc_u);
+
+}  // namespace gvl

@@ -1,0 +1,400 @@
+// Neighbour-community scan: the decision kernels shared by local-moving
+// (Alg. 2, scanCommunities) and refinement (Alg. 3, scanBounded), and the
+// commit kernel of the synchronous variants.
+//
+// For a vertex i the scan accumulates H[C[j]] += w_ij over the arcs of i
+// (j != i; refinement also requires CB[j] == CB[i]), evaluates the
+// delta-modularity of Eq. 2 for every community in H other than d = C[i],
+// and picks the best one (largest gain, lowest id on ties).
+//   fast mode:  gain = (K_ic - K_id) / m - gamma K_i (K_i + Sigma_c - Sigma_d) / (2 m^2)  (FP64)
+//   det mode:   key  = 2^16 W (K_ic - K_id) - p K_i (K_i + Sigma_c - Sigma_d)             (int128)
+//               with gamma = p / 2^16, so that gain = 2 key / (2^16 W^2) exactly.
+// Local-moving in fast mode commits a move at once (asynchronous updates,
+// Sec. 4.1): Sigma and sizes by atomics, C[i] by a plain store, neighbours
+// marked unprocessed.  Deterministic local-moving and refinement record the
+// choice in target[] and a separate commit kernel applies it.
+//
+// Singleton-to-singleton moves go only towards the lower community id
+// (min-label rule), which stops pairs of singletons from swapping.
+#pragma once
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace gvl {
+
+template <int PH, bool DET>
+struct Decide {
+  // Returns true if vertex i is to be scanned in this launch.
+  __device__ static __forceinline__ bool eligible(const ScanArgs& a, int32_t i) {
+    if (PH == kMove) return a.flag[i] != 0;
+    return a.size[a.C[i]] == 1 && a.K[i] > 0.0;
+  }
+};
+
+// Accumulators of one thread, reduced once per workgroup at kernel end.
+struct Acc {
+  double dq = 0.0;
+  i128 dqk = 0;
+  unsigned long long nv = 0, na = 0, nc = 0, nm = 0;
+};
+
+template <int PH, bool DET>
+__device__ __forceinline__ void flush_acc(const ScanArgs& a, Acc& acc) {
+  __shared__ double red_d[16];
+  __shared__ unsigned long long red_u[16];
+  __shared__ i128 red_k[16];
+  unsigned long long nv = block_sum<unsigned long long>(acc.nv, red_u);
+  unsigned long long na = block_sum<unsigned long long>(acc.na, red_u);
+  unsigned long long nc = block_sum<unsigned long long>(acc.nc, red_u);
+  unsigned long long nm = block_sum<unsigned long long>(acc.nm, red_u);
+  if (DET) {
+    i128 k = block_sum_i128(acc.dqk, red_k);
+    if (threadIdx.x == 0 && k != 0) atomic_add_i128(a.dq128, k);
+  } else {
+    double d = block_sum<double>(acc.dq, red_d);
+    if (threadIdx.x == 0 && d != 0.0) atomicAdd(a.dq, d);
+  }
+  if (threadIdx.x == 0) {
+    if (nv) atomicAdd(&a.cnt[0], nv);
+    if (na) atomicAdd(&a.cnt[1], na);
+    if (PH == kRefine && na) atomicAdd(&a.cnt[7], na);
+    if (nc) atomicAdd(&a.cnt[2], nc);
+    if (nm) atomicAdd(&a.cnt[3], nm);
+  }
+}
+
+// Gain of one candidate; updates the running best.
+template <bool DET>
+struct Eval {
+  double kid, ki, sd, gk;
+  long long kidi, kii, sdi;
+  i128 A, B;
+  __device__ __forceinline__ Eval(const ScanArgs& a, double kid_, double ki_, double sd_) {
+    kid = kid_; ki = ki_; sd = sd_;
+    gk = a.gk_scale * ki_;
+    kidi = (long long)kid_; kii = (long long)ki_; sdi = (long long)sd_;
+    A = (i128)65536 * (i128)a.W;
+    B = (i128)a.p * (i128)kii;
+  }
+  __device__ __forceinline__ void operator()(const ScanArgs& a, int32_t c, double kic, double sc,
+                                             double& bg, i128& bk, int32_t& bc) const {
+    if (DET) {
+      const i128 k = A * (i128)((long long)kic - kidi) - B * (i128)(kii + (long long)sc - sdi);
+      if (better_k(k, c, bk, bc)) { bk = k; bc = c; }
+    } else {
+      const double x = (kic - kid) * a.inv_m - gk * (ki + sc - sd);
+      if (better_f(x, c, bg, bc)) { bg = x; bc = c; }
+    }
+  }
+};
+
+// After the argmax: apply the min-label rule and the sign test.
+template <int PH, bool DET>
+__device__ __forceinline__ bool accept(const ScanArgs& a, int32_t d, int32_t bc, double bg, i128 bk) {
+  if (bc < 0) return false;
+  if (DET ? !(bk > 0) : !(bg > 0.0)) return false;
+  if (PH == kMove) {
+    if (a.size[d] == 1 && a.size[bc] == 1 && bc > d) return false;
+  } else {
+    if (a.size[bc] == 1 && bc > d) return false;
+  }
+  return true;
+}
+
+// ------------------------------------------------ group of G lanes per vertex ---
+template <int G, int LG, class WT, int PH, bool DET>
+__global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanArgs a,
+                                                         const int32_t* __restrict__ list,
+                                                         int32_t count) {
+  constexpr int TS = 1 << LG;
+  constexpr int GPB = kBlock / G;
+  __shared__ int32_t skeys[GPB * TS];
+  __shared__ double svals[GPB * TS];
+  const int gl = threadIdx.x % G;
+  const int gb = threadIdx.x / G;
+  int32_t* keys = skeys + gb * TS;
+  double* vals = svals + gb * TS;
+  for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
+  wave_sync();
+  Acc acc;
+  for (int64_t v = (int64_t)blockIdx.x * GPB + gb; v < count; v += (int64_t)gridDim.x * GPB) {
+    const int32_t i = list[v];
+    // One lane reads the (possibly concurrently updated) eligibility state.
+    int ok = (gl == 0) ? (int)Decide<PH, DET>::eligible(a, i) : 0;
+    ok = __shfl(ok, 0, G);
+    if (!ok) continue;
+    if (PH == kMove && gl == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    for (int32_t e = gl; e < deg; e += G) {
+      const int32_t j = g.idx[beg + e];
+      if (j == i) continue;
+      if (PH == kRefine && a.CB[j] != bi) continue;
+      lds_insert(keys, vals, LG, a.C[j], g.weight(beg + e));
+    }
+    wave_sync();
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
+    const Eval<DET> ev(a, lds_lookup(keys, vals, LG, d), ki, a.Sig[d]);
+    int32_t bc = -1;
+    double bg = 0.0;
+    i128 bk = 0;
+    for (int s = gl; s < TS; s += G) {
+      const int32_t c = keys[s];
+      if (c == kEmpty || c == d) continue;
+      ++acc.nc;
+      ev(a, c, vals[s], a.Sig[c], bg, bk, bc);
+    }
+    if (DET) argmax_k<G>(bk, bc); else argmax_f<G>(bg, bc);
+    wave_sync();
+    for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
+    wave_sync();
+    if (gl == 0) { ++acc.nv; acc.na += (unsigned long long)deg; }
+    int take = (gl == 0) ? (int)accept<PH, DET>(a, d, bc, bg, bk) : 0;
+    take = __shfl(take, 0, G);
+    if (!take) continue;
+    if (PH == kMove && !DET) {
+      if (gl == 0) {
+        atomicAdd(&a.Sig[d], -ki);
+        atomicAdd(&a.Sig[bc], ki);
+        atomicSub(&a.size[d], 1);
+        atomicAdd(&a.size[bc], 1);
+        a.C[i] = bc;
+        acc.dq += bg;
+        ++acc.nm;
+      }
+      for (int32_t e = gl; e < deg; e += G) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i) a.flag[j] = 1;
+      }
+    } else if (PH == kMove) {
+      if (gl == 0) { a.target[i] = bc; acc.dqk += bk; }
+    } else {
+      if (gl == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
+    }
+  }
+  flush_acc<PH, DET>(a, acc);
+}
+
+// ------------------------------------------- one workgroup per (hub) vertex ---
+// LG > 0: LDS table of 2^LG slots.  LG == 0: global-memory table of
+// next_pow2(2 deg) slots inside this workgroup's slice of the table region.
+template <int LG, class WT, int PH, bool DET>
+__global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanArgs a,
+                                                         const int32_t* __restrict__ list,
+                                                         int32_t count) {
+  constexpr bool GLB = (LG == 0);
+  constexpr int TS = GLB ? 1 : (1 << LG);
+  __shared__ int32_t skeys[TS];
+  __shared__ double svals[TS];
+  __shared__ double s_g[kBlock / kWave];
+  __shared__ i128 s_k[kBlock / kWave];
+  __shared__ int32_t s_c[kBlock / kWave];
+  __shared__ int s_flag, s_take;
+  int32_t* keys = GLB ? a.tbl_keys + (int64_t)blockIdx.x * a.tbl_slot : skeys;
+  double* vals = GLB ? a.tbl_vals + (int64_t)blockIdx.x * a.tbl_slot : svals;
+  if (!GLB) {
+    for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+    __syncthreads();
+  }
+  Acc acc;
+  for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
+    const int32_t i = list[v];
+    if (threadIdx.x == 0) s_flag = (int)Decide<PH, DET>::eligible(a, i);
+    __syncthreads();
+    const int ok = s_flag;
+    __syncthreads();
+    if (!ok) continue;  // uniform over the workgroup
+    if (PH == kMove && threadIdx.x == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    // distinct neighbour communities <= min(deg, n): the table slice holds
+    // next_pow2(2 min(max hub degree, n)) slots
+    const int lg = GLB ? ceil_log2(2 * ((int64_t)deg < g.n ? (int64_t)deg : g.n)) : LG;
+    const int ts = 1 << lg;
+    if (GLB) {
+      for (int s = threadIdx.x; s < ts; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+      __syncthreads();
+    }
+    for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
+      const int32_t j = g.idx[beg + e];
+      if (j == i) continue;
+      if (PH == kRefine && a.CB[j] != bi) continue;
+      if (GLB) glb_insert(keys, vals, lg, a.C[j], g.weight(beg + e));
+      else lds_insert(keys, vals, lg, a.C[j], g.weight(beg + e));
+    }
+    __syncthreads();
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
+    const double kid = GLB ? glb_lookup(keys, vals, lg, d) : lds_lookup(keys, vals, lg, d);
+    const Eval<DET> ev(a, kid, ki, a.Sig[d]);
+    int32_t bc = -1;
+    double bg = 0.0;
+    i128 bk = 0;
+    for (int s = threadIdx.x; s < ts; s += kBlock) {
+      const int32_t c = GLB ? glb_load_key(keys, s) : keys[s];
+      if (c == kEmpty || c == d) continue;
+      ++acc.nc;
+      ev(a, c, GLB ? glb_load_val(vals, s) : vals[s], a.Sig[c], bg, bk, bc);
+    }
+    if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) { s_g[w] = bg; s_k[w] = bk; s_c[w] = bc; }
+    __syncthreads();
+    bc = s_c[0]; bg = s_g[0]; bk = s_k[0];
+    for (int k = 1; k < kBlock / kWave; ++k) {
+      if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
+      else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
+    }
+    if (!GLB) for (int s = threadIdx.x; s < ts; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+    if (threadIdx.x == 0) {
+      ++acc.nv;
+      acc.na += (unsigned long long)deg;
+      s_take = (int)accept<PH, DET>(a, d, bc, bg, bk);
+    }
+    __syncthreads();  // table and s_* reads done; s_take published
+    const int take = s_take;
+    if (!take) continue;
+    if (PH == kMove && !DET) {
+      if (threadIdx.x == 0) {
+        atomicAdd(&a.Sig[d], -ki);
+        atomicAdd(&a.Sig[bc], ki);
+        atomicSub(&a.size[d], 1);
+        atomicAdd(&a.size[bc], 1);
+        a.C[i] = bc;
+        acc.dq += bg;
+        ++acc.nm;
+      }
+      for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i) a.flag[j] = 1;
+      }
+    } else if (PH == kMove) {
+      if (threadIdx.x == 0) { a.target[i] = bc; acc.dqk += bk; }
+    } else {
+      if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
+    }
+  }
+  flush_acc<PH, DET>(a, acc);
+}
+
+// ------------------------------------------------------------- commit ---
+// Applies the recorded synchronous decisions of the vertices list[0..count)
+// (one group).  Refinement: vertex i moves only if its own community was not
+// chosen as a target in this group.  Local-moving: every recorded move
+// applies and the neighbours of movers are marked unprocessed (one
+// wavefront walks each mover's row).
+template <class WT, int PH>
+__global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
+                                                   const int32_t* __restrict__ list, int32_t count) {
+  __shared__ unsigned long long red_u[16];
+  unsigned long long nm = 0;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = base + threadIdx.x;
+    const int32_t i = (k < count) ? list[k] : 0;
+    int32_t t = -1;
+    if (k < count) t = a.target[i];
+    bool mv = t >= 0;
+    if (mv) {
+      if (PH == kMove) a.target[i] = -1;
+      const int32_t d = a.C[i];
+      if (PH == kRefine && a.targeted[d]) mv = false;
+      if (mv) {
+        const double ki = a.K[i];
+        atomicAdd(&a.Sig[d], -ki);
+        atomicAdd(&a.Sig[t], ki);
+        atomicSub(&a.size[d], 1);
+        atomicAdd(&a.size[t], 1);
+        a.C[i] = t;
+        ++nm;
+      }
+    }
+    if (PH == kMove) {
+      u64 mask = __ballot(mv);
+      while (mask) {
+        const int l = __ffsll((unsigned long long)mask) - 1;
+        mask &= mask - 1;
+        const int32_t ii = __shfl(i, l);
+        const int32_t beg = g.begin(ii), deg = g.degree(ii);
+        for (int32_t e = lane_id(); e < deg; e += kWave) {
+          const int32_t j = g.idx[beg + e];
+          if (j != ii) a.flag[j] = 1;
+        }
+      }
+    }
+  }
+  nm = block_sum<unsigned long long>(nm, red_u);
+  if (threadIdx.x == 0 && nm) atomicAdd(&a.cnt[3], nm);
+}
+
+// Refinement: forget the group's targets once every commit has read them.
+template <int PH>
+__global__ __launch_bounds__(kBlock) void k_refine_cleanup(ScanArgs a, const int32_t* __restrict__ list,
+                                                           int32_t count) {
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < count; k += (int64_t)gridDim.x * kBlock) {
+    const int32_t i = list[k];
+    const int32_t t = a.target[i];
+    if (t >= 0) {
+      a.targeted[t] = 0;
+      a.target[i] = -1;
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers ---
+template <class WT>
+inline GraphView<WT> view(const GraphDesc& g) {
+  GraphView<WT> v;
+  v.n = g.n; v.off = g.off; v.deg = g.deg; v.idx = g.idx; v.w = (const WT*)g.w;
+  return v;
+}
+
+inline int grid_for(int64_t items, int per_block, int cap) {
+  int64_t b = (items + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+template <class WT, int PH, bool DET>
+void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list,
+                 const int32_t* count, const int32_t* start, int grid_cap, int hub_grid, int64_t* launches) {
+  const GraphView<WT> g = view<WT>(gd);
+#define GVL_GROUP_BIN(B, G, LG)                                                                 \
+  if (count[B] > 0) {                                                                           \
+    const int grid = grid_for(count[B], kBlock / (G), grid_cap);                                \
+    hipLaunchKernelGGL((k_decide_group<G, LG, WT, PH, DET>), dim3(grid), dim3(kBlock), 0, st, g, \
+                       a, list + start[B], count[B]);                                           \
+    ++*launches;                                                                                \
+  }
+  GVL_GROUP_BIN(0, 4, 3)
+  GVL_GROUP_BIN(1, 8, 4)
+  GVL_GROUP_BIN(2, 16, 5)
+  GVL_GROUP_BIN(3, 32, 6)
+  GVL_GROUP_BIN(4, 64, 8)
+#undef GVL_GROUP_BIN
+  if (count[5] > 0) {
+    const int grid = grid_for(count[5], 1, grid_cap);
+    hipLaunchKernelGGL((k_decide_block<11, WT, PH, DET>), dim3(grid), dim3(kBlock), 0, st, g, a,
+                       list + start[5], count[5]);
+    ++*launches;
+  }
+  (void)hub_grid;  // the hub bin goes through the chunked hub path
+}
+
+template <class WT, int PH>
+void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count) {
+  if (count <= 0) return;
+  const GraphView<WT> g = view<WT>(gd);
+  const int grid = grid_for(count, kBlock, 8192);
+  hipLaunchKernelGGL((k_commit<WT, PH>), dim3(grid), dim3(kBlock), 0, st, g, a, list, count);
+}
+
+inline void cleanup_list(hipStream_t st, const ScanArgs& a, const int32_t* list, int32_t count) {
+  if (count <= 0) return;
+  const int grid = grid_for(count, kBlock, 8192);
+  hipLaunchKernelGGL((k_refine_cleanup<kRefine>), dim3(grid), dim3(kBlock), 0, st, a, list, count);
+}
+
+}  // namespace gvl
