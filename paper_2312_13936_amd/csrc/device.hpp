@@ -36,6 +36,10 @@ struct GraphView {
 // ------------------------------------------------------------ wave helpers ---
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
 
+// This workgroup's copy of the counters / sums (see kCntSlots).
+__device__ __forceinline__ int cslot() { return (int)(blockIdx.x & (kCntSlots - 1)); }
+__device__ __forceinline__ unsigned long long* cnt_of(unsigned long long* cnt) { return cnt + 8 * cslot(); }
+
 // Orders the LDS traffic of one wavefront: every lane's earlier LDS
 // operations complete before any lane's later ones.
 __device__ __forceinline__ void wave_sync() {
@@ -155,6 +159,20 @@ __device__ __forceinline__ void glb_insert(int32_t* keys, double* vals, int lg, 
   while (true) {
     int32_t old = atomicCAS(&keys[h], kEmpty, c);
     if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return; }
+    h = (h + 1u) & mask;
+  }
+}
+
+// As glb_insert; returns the slot if this call created the key, else -1.
+__device__ __forceinline__ int64_t glb_insert_new(int32_t* keys, double* vals, int lg, int32_t c, double w) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = hslot(c, lg);
+  while (true) {
+    int32_t old = atomicCAS(&keys[h], kEmpty, c);
+    if (old == kEmpty || old == c) {
+      atomicAdd(&vals[h], w);
+      return old == kEmpty ? (int64_t)h : -1;
+    }
     h = (h + 1u) & mask;
   }
 }

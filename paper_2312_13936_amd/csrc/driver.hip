@@ -26,9 +26,9 @@ namespace gvl {
 
 // Scalars shared between the device and one pinned host mirror.
 struct Scalars {
-  double dq;                        // fast: summed move gains of an iteration
-  unsigned long long dq128[2];      // det: exact summed move keys (lo, hi)
-  unsigned long long cnt[8];        // kernel work counters (cumulative)
+  double dq[kCntSlots];                        // fast: summed move gains of an iteration
+  unsigned long long dq128[kCntSlots][2];      // det: exact summed move keys (lo, hi)
+  unsigned long long cnt[kCntSlots][8];        // kernel work counters (cumulative)
   int32_t flags[4];                 // input checks
   double accW;                      // total weight
   double acc_d[2];                  // modularity: S1, S2 (floating)
@@ -56,7 +56,7 @@ struct Workspace {
   double* tbl_vals;
   int64_t tbl_entries;
   // hub path
-  int32_t *hp_chunk, *hp_tbl, *hp_slice, *hp_active, *hp_done, *apre;
+  int32_t *hp_chunk, *hp_tbl, *hp_slice, *hp_active, *hp_done, *hp_lcnt, *apre, *tbl_list;
   double* hp_kid;
   int2 *chunk_tasks, *slice_tasks;
   double* pb_g;
@@ -114,6 +114,8 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base) {
   w.hp_slice = (int32_t*)take(4 * (N + 1));
   w.hp_active = (int32_t*)take(4 * N);
   w.hp_done = (int32_t*)take(4 * N);
+  w.hp_lcnt = (int32_t*)take(4 * N);
+  w.tbl_list = (int32_t*)take(4 * (size_t)w.tbl_entries);
   w.apre = (int32_t*)take(4 * (N + 1));
   w.hp_kid = (double*)take(8 * N);
   // chunk tasks <= H + M / kHubChunk; slice tasks <= H + M / (kHubSlice / 4)
@@ -125,6 +127,12 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base) {
   w.pb_c = (int32_t*)take(4 * (size_t)w.max_tasks);
   w.bytes = o;
   return w;
+}
+
+static unsigned long long counter(const Scalars* h, int k) {
+  unsigned long long s = 0;
+  for (int j = 0; j < kCntSlots; ++j) s += h->cnt[j][k];
+  return s;
 }
 
 // Deterministic int128 -> double: hi * 2^64 + lo (one rounding in the add).
@@ -316,6 +324,7 @@ HubArgs hub_args(Workspace& ws, const BinInfo& bins) {
   h.active = ws.hp_active; h.kid = ws.hp_kid; h.done = ws.hp_done;
   h.pb_g = ws.pb_g; h.pb_k = ws.pb_k; h.pb_c = ws.pb_c;
   h.tbl_keys = ws.tbl_keys; h.tbl_vals = ws.tbl_vals;
+  h.tbl_list = ws.tbl_list; h.lcnt = ws.hp_lcnt;
   h.apre = ws.apre;
   return h;
 }
@@ -556,6 +565,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   int h = tm.begin(kEvOther);
   fill_u64(st, (unsigned long long*)ws.sc, 0ull, sizeof(Scalars) / 8);
   fill_i32(st, ws.hp_done, 0, n);
+  fill_i32(st, ws.hp_lcnt, 0, n);
   if (opt->validate) {
     check_offsets(st, d_off, n, m, ws.sc->flags);
     s = readback(ctx, ws.sc);
@@ -567,10 +577,11 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
   a.target = ws.target; a.targeted = ws.targeted;
-  a.dq = &ws.sc->dq; a.dq128 = ws.sc->dq128; a.cnt = ws.sc->cnt;
+  a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.tbl_keys = ws.tbl_keys; a.tbl_vals = ws.tbl_vals;
 
-  const int grid_cap = 256 * 16;
+  // grids are capped near the number of resident workgroups (256 CUs x 8)
+  const int grid_cap = 2048;
   GraphDesc cur = input;
   int buf = 0;
   double tau = opt->tolerance;
@@ -626,9 +637,9 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     }
     if (pass < GVL_MAX_PASS_STATS) {
       S->nv[pass] = nn;
-      S->ne[pass] = (pass == 0) ? m : (int64_t)(ctx->host->cnt[6] - out_before);
+      S->ne[pass] = (pass == 0) ? m : (int64_t)(counter(ctx->host, 6) - out_before);
     }
-    out_before = ctx->host->cnt[6];
+    out_before = counter(ctx->host, 6);
     if (pass > 0) {
       copy_i32(st, ws.C, ws.start, nn);
       fill_f64(st, ws.Sig, 0.0, nn);
@@ -680,7 +691,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     int32_t iters = 0;
     bool first_conv = false;
     for (int32_t it = 0; it < opt->max_iterations; ++it) {
-      fill_u64(st, (unsigned long long*)&ws.sc->dq, 0ull, 3);
+      fill_u64(st, (unsigned long long*)ws.sc->dq, 0ull, 3 * kCntSlots);
       int hk = det ? -1 : tm.begin(kEvScanMoveK);
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         if (det) hk = tm.begin(kEvScanMoveK);
@@ -694,15 +705,19 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
       ++iters;
-      const unsigned long long mv = ctx->host->cnt[3] - moves_before;
-      moves_before = ctx->host->cnt[3];
+      const unsigned long long mv = counter(ctx->host, 3) - moves_before;
+      moves_before = counter(ctx->host, 3);
       pd.movers.push_back((int64_t)mv);
       double dq;
       if (det) {
-        dq = i128_to_double(ctx->host->dq128[0], ctx->host->dq128[1]) * 2.0 /
+        unsigned __int128 sum = 0;
+        for (int k = 0; k < kCntSlots; ++k)
+          sum += ((unsigned __int128)ctx->host->dq128[k][1] << 64) | ctx->host->dq128[k][0];
+        dq = i128_to_double((unsigned long long)sum, (unsigned long long)(sum >> 64)) * 2.0 /
              (65536.0 * (double)Wi * (double)Wi);
       } else {
-        dq = ctx->host->dq;
+        dq = 0.0;
+        for (int k = 0; k < kCntSlots; ++k) dq += ctx->host->dq[k];
       }
       if (dq <= tau) {
         if (it == 0) first_conv = true;
@@ -729,8 +744,8 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
       ++sweeps;
-      const unsigned long long mv = ctx->host->cnt[3] - moves_before;
-      moves_before = ctx->host->cnt[3];
+      const unsigned long long mv = counter(ctx->host, 3) - moves_before;
+      moves_before = counter(ctx->host, 3);
       pd.refine_movers.push_back((int64_t)mv);
       refine_moved += (int64_t)mv;
       if (mv == 0) break;
@@ -794,7 +809,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       AggArgs g;
       memset(&g, 0, sizeof(g));
       g.lab = ws.lab; g.coff = ws.cnt; g.cv = ws.cv; g.yoff = yoff; g.ydeg = ydeg;
-      g.yidx = ws.idx[nb]; g.yw = ws.w[nb]; g.yw_double = det; g.cnt = ws.sc->cnt;
+      g.yidx = ws.idx[nb]; g.yw = ws.w[nb]; g.yw_double = det; g.cnt = &ws.sc->cnt[0][0];
       g.tbl_keys = ws.tbl_keys; g.tbl_vals = ws.tbl_vals; g.ncom = ncom;
       const int hk = tm.begin(kEvAggK);
       launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], grid_cap, 0, &S->agg_launches);
@@ -838,14 +853,14 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   if (s != GVL_OK) return s;
   tm.end(h);
   HIP_TRY(hipStreamSynchronize(st));
-  S->scan_vertices = (int64_t)ctx->host->cnt[0];
-  S->scan_arcs = (int64_t)ctx->host->cnt[1];
-  S->scan_candidates = (int64_t)ctx->host->cnt[2];
-  S->scan_moves = (int64_t)ctx->host->cnt[3];
-  S->agg_vertices = (int64_t)ctx->host->cnt[4];
-  S->agg_arcs = (int64_t)ctx->host->cnt[5];
-  S->agg_out_arcs = (int64_t)ctx->host->cnt[6];
-  S->scan_refine_arcs = (int64_t)ctx->host->cnt[7];
+  S->scan_vertices = (int64_t)counter(ctx->host, 0);
+  S->scan_arcs = (int64_t)counter(ctx->host, 1);
+  S->scan_candidates = (int64_t)counter(ctx->host, 2);
+  S->scan_moves = (int64_t)counter(ctx->host, 3);
+  S->agg_vertices = (int64_t)counter(ctx->host, 4);
+  S->agg_arcs = (int64_t)counter(ctx->host, 5);
+  S->agg_out_arcs = (int64_t)counter(ctx->host, 6);
+  S->scan_refine_arcs = (int64_t)counter(ctx->host, 7);
   if (tm.on) {
     double ms[kEvClasses];
     tm.totals(ms);

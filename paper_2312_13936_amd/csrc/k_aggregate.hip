@@ -92,9 +92,9 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
   na = block_sum<unsigned long long>(na, red_u);
   no = block_sum<unsigned long long>(no, red_u);
   if (threadIdx.x == 0) {
-    if (nv) atomicAdd(&a.cnt[4], nv);
-    if (na) atomicAdd(&a.cnt[5], na);
-    if (no) atomicAdd(&a.cnt[6], no);
+    if (nv) atomicAdd(&cnt_of(a.cnt)[4], nv);
+    if (na) atomicAdd(&cnt_of(a.cnt)[5], na);
+    if (no) atomicAdd(&cnt_of(a.cnt)[6], no);
   }
 }
 
@@ -198,9 +198,9 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
   na = block_sum<unsigned long long>(na, red_u);
   no = block_sum<unsigned long long>(no, red_u);
   if (threadIdx.x == 0) {
-    if (nv) atomicAdd(&a.cnt[4], nv);
-    if (na) atomicAdd(&a.cnt[5], na);
-    if (no) atomicAdd(&a.cnt[6], no);
+    if (nv) atomicAdd(&cnt_of(a.cnt)[4], nv);
+    if (na) atomicAdd(&cnt_of(a.cnt)[5], na);
+    if (no) atomicAdd(&cnt_of(a.cnt)[6], no);
   }
 }
 

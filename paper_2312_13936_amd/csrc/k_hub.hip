@@ -34,6 +34,9 @@ __device__ __forceinline__ int32_t* tbl_keys_of(const HubArgs& h, int32_t p) {
 __device__ __forceinline__ double* tbl_vals_of(const HubArgs& h, int32_t p) {
   return h.tbl_vals + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
 }
+__device__ __forceinline__ int32_t* tbl_list_of(const HubArgs& h, int32_t p) {
+  return h.tbl_list + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
+}
 __device__ __forceinline__ int tbl_lg(const HubArgs& h, int32_t p) {
   return ceil_log2((int64_t)(h.tbl_off[p + 1] - h.tbl_off[p]) * kTblUnit);
 }
@@ -100,6 +103,35 @@ __global__ void k_hub_prep(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
   }
 }
 
+// Merge the LDS pre-aggregation table of one chunk into item p's global
+// table; the slots of keys new to the global table are appended to p's
+// occupied-slot list (one reservation per workgroup).  Leaves the LDS table
+// empty.
+__device__ __forceinline__ void flush_chunk(const HubArgs& h, int32_t p, int32_t* skeys, double* svals,
+                                            int32_t* snew, int* s_nnew, int* s_base) {
+  constexpr int TS = 1 << kHubGatherLg;
+  int32_t* gk = tbl_keys_of(h, p);
+  double* gv = tbl_vals_of(h, p);
+  const int lg = tbl_lg(h, p);
+  if (threadIdx.x == 0) *s_nnew = 0;
+  __syncthreads();
+  for (int s = threadIdx.x; s < TS; s += kBlock) {
+    const int32_t c = skeys[s];
+    if (c != kEmpty) {
+      const int64_t slot = glb_insert_new(gk, gv, lg, c, svals[s]);
+      if (slot >= 0) snew[atomicAdd(s_nnew, 1)] = (int32_t)slot;
+      skeys[s] = kEmpty;
+      svals[s] = 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *s_base = *s_nnew ? atomicAdd(&h.lcnt[p], *s_nnew) : 0;
+  __syncthreads();
+  int32_t* lst = tbl_list_of(h, p);
+  for (int k = threadIdx.x; k < *s_nnew; k += kBlock) lst[*s_base + k] = snew[k];
+  __syncthreads();
+}
+
 // Chunk gather: H_chunk[C[j]] += w over the chunk's arcs (j != i; in
 // refinement only j inside i's bound), merged into the hub's global table.
 template <class WT, int PH>
@@ -108,6 +140,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
   constexpr int TS = 1 << kHubGatherLg;
   __shared__ int32_t skeys[TS];
   __shared__ double svals[TS];
+  __shared__ int32_t snew[kHubChunk];
+  __shared__ int s_nnew, s_base;
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -128,22 +162,11 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
     }
     if (threadIdx.x == 0) na += (unsigned long long)(e1 - e0);
     __syncthreads();
-    int32_t* gk = tbl_keys_of(h, p);
-    double* gv = tbl_vals_of(h, p);
-    const int lg = tbl_lg(h, p);
-    for (int s = threadIdx.x; s < TS; s += kBlock) {
-      const int32_t c = skeys[s];
-      if (c != kEmpty) {
-        glb_insert(gk, gv, lg, c, svals[s]);
-        skeys[s] = kEmpty;
-        svals[s] = 0.0;
-      }
-    }
-    __syncthreads();
+    flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
   }
   if (threadIdx.x == 0 && na) {
-    atomicAdd(&a.cnt[1], na);
-    if (PH == kRefine) atomicAdd(&a.cnt[7], na);
+    atomicAdd(&cnt_of(a.cnt)[1], na);
+    if (PH == kRefine) atomicAdd(&cnt_of(a.cnt)[7], na);
   }
 }
 
@@ -155,17 +178,17 @@ __global__ void k_hub_kid(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
   }
 }
 
-// Slice evaluation: best candidate of the slice's table slots (the slots are
-// cleared for the next use); the last slice of a hub reduces the partial
-// bests, applies the min-label rule and the sign test, and commits (fast
-// local-moving) or records the decision.
+// Slice evaluation: best candidate among the slice's entries of the hub's
+// occupied-slot list (the slots are cleared for the next use); the last
+// slice of a hub reduces the partial bests, applies the min-label rule and
+// the sign test, and commits (fast local-moving) or records the decision.
 template <class WT, int PH, bool DET>
 __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t s0,
                                                      int32_t s1) {
   __shared__ double s_g[kBlock / kWave];
   __shared__ i128 s_k[kBlock / kWave];
   __shared__ int32_t s_c[kBlock / kWave];
-  __shared__ int s_last, s_take, s_bc;
+  __shared__ int s_last, s_take;
   unsigned long long nc = 0, nv = 0, nm = 0;
   double dq = 0.0;
   i128 dqk = 0;
@@ -179,32 +202,31 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     const Eval<DET> ev(a, h.kid[p], ki, a.Sig[d]);
     int32_t* gk = tbl_keys_of(h, p);
     double* gv = tbl_vals_of(h, p);
+    const int32_t* lst = tbl_list_of(h, p);
+    const int32_t len = h.lcnt[p];
     const int64_t ts = (int64_t)1 << tbl_lg(h, p);
+    // dense tables are scanned slot by slot (coalesced), sparse ones through
+    // their occupied-slot list; slice sl covers kHubSlice slots or entries
+    const bool dense = (int64_t)len * 8 > ts;
+    const int64_t lim = dense ? ts : len;
     const int64_t q0 = (int64_t)task.y * kHubSlice;
-    const int64_t q1 = (q0 + kHubSlice < ts) ? q0 + kHubSlice : ts;
+    const int64_t q1 = (lim - q0 < kHubSlice) ? lim : q0 + kHubSlice;
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
     for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
-      const int32_t c = glb_load_key(gk, (uint32_t)q);
+      const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
+      const int32_t c = glb_load_key(gk, slot);
       if (c == kEmpty) continue;
       if (c != d) {
         ++nc;
-        ev(a, c, glb_load_val(gv, (uint32_t)q), a.Sig[c], bg, bk, bc);
+        ev(a, c, glb_load_val(gv, slot), a.Sig[c], bg, bk, bc);
       }
-      gk[q] = kEmpty;
-      gv[q] = 0.0;
+      gk[slot] = kEmpty;
+      gv[slot] = 0.0;
     }
-    if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) { s_g[w] = bg; s_k[w] = bk; s_c[w] = bc; }
-    __syncthreads();
+    block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     if (threadIdx.x == 0) {
-      bc = s_c[0]; bg = s_g[0]; bk = s_k[0];
-      for (int k = 1; k < kBlock / kWave; ++k) {
-        if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
-        else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
-      }
       h.pb_g[t] = bg;
       h.pb_k[t] = bk;
       h.pb_c[t] = bc;
@@ -215,28 +237,29 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     }
     __syncthreads();
     if (s_last) {
-      if (threadIdx.x == 0) {
-        __threadfence();
-        const int32_t sb = h.slice_off[p], se = h.slice_off[p + 1];
-        bc = -1; bg = 0.0; bk = 0;
-        for (int32_t k = sb; k < se; ++k) {
-          const int32_t c2 = __hip_atomic_load(h.pb_c + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          if (DET) {
-            const unsigned long long* kw = (const unsigned long long*)(h.pb_k + k);
-            const unsigned long long lo = __hip_atomic_load(kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned long long hi = __hip_atomic_load(kw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const i128 k2 = make_i128((long long)hi, lo);
-            if (better_k(k2, c2, bk, bc)) { bk = k2; bc = c2; }
-          } else {
-            const double g2 = __hip_atomic_load(h.pb_g + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (better_f(g2, c2, bg, bc)) { bg = g2; bc = c2; }
-          }
+      __threadfence();
+      const int32_t sb = h.slice_off[p], se = h.slice_off[p + 1];
+      bc = -1; bg = 0.0; bk = 0;
+      for (int32_t k = sb + (int32_t)threadIdx.x; k < se; k += kBlock) {
+        const int32_t c2 = __hip_atomic_load(h.pb_c + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (DET) {
+          const unsigned long long* kw = (const unsigned long long*)(h.pb_k + k);
+          const unsigned long long lo = __hip_atomic_load(kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const unsigned long long hi = __hip_atomic_load(kw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          const i128 k2 = make_i128((long long)hi, lo);
+          if (better_k(k2, c2, bk, bc)) { bk = k2; bc = c2; }
+        } else {
+          const double g2 = __hip_atomic_load(h.pb_g + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (better_f(g2, c2, bg, bc)) { bg = g2; bc = c2; }
         }
+      }
+      block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
+      if (threadIdx.x == 0) {
         h.done[p] = 0;
+        h.lcnt[p] = 0;
         ++nv;
         const bool take = accept<PH, DET>(a, d, bc, bg, bk);
         s_take = take ? 1 : 0;
-        s_bc = bc;
         if (take) {
           if (PH == kMove && !DET) {
             atomicAdd(&a.Sig[d], -ki);
@@ -268,14 +291,14 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
   }
   // one thread per workgroup carries the counters
   if (threadIdx.x == 0) {
-    if (nv) atomicAdd(&a.cnt[0], nv);
-    if (nm) atomicAdd(&a.cnt[3], nm);
-    if (DET) { if (dqk != 0) atomic_add_i128(a.dq128, dqk); }
-    else { if (dq != 0.0) atomicAdd(a.dq, dq); }
+    if (nv) atomicAdd(&cnt_of(a.cnt)[0], nv);
+    if (nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
+    if (DET) { if (dqk != 0) atomic_add_i128(a.dq128 + 2 * cslot(), dqk); }
+    else { if (dq != 0.0) atomicAdd(a.dq + cslot(), dq); }
   }
   __shared__ unsigned long long red_u[16];
   nc = block_sum<unsigned long long>(nc, red_u);
-  if (threadIdx.x == 0 && nc) atomicAdd(&a.cnt[2], nc);
+  if (threadIdx.x == 0 && nc) atomicAdd(&cnt_of(a.cnt)[2], nc);
 }
 
 template <class WT, int PH, bool DET>
@@ -285,11 +308,11 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
   const int hb = grid_items(h1 - h0, kBlock, 1024);
   hipLaunchKernelGGL((k_hub_prep<PH, DET>), dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
   if (c1 > c0)
-    hipLaunchKernelGGL((k_hub_gather<WT, PH>), dim3(grid_items(c1 - c0, 1, 8192)), dim3(kBlock), 0, st, g, a, h, c0,
+    hipLaunchKernelGGL((k_hub_gather<WT, PH>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g, a, h, c0,
                        c1);
   hipLaunchKernelGGL(k_hub_kid, dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
   if (s1 > s0)
-    hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 8192)), dim3(kBlock), 0, st, g, a, h,
+    hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a, h,
                        s0, s1);
   *launches += 4;
 }
@@ -345,7 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_weights(GraphView<WT> g, HubArgs
 void hub_weights(hipStream_t st, const GraphDesc& gd, const HubArgs& h, int32_t c0, int32_t c1, double* K,
                  double* accW, int32_t* flags, int validate) {
   if (c1 <= c0) return;
-  const int grid = grid_items(c1 - c0, 1, 8192);
+  const int grid = grid_items(c1 - c0, 1, 2048);
   if (gd.w_double)
     hipLaunchKernelGGL(k_hub_weights<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), h, c0, c1, K, accW,
                        flags, validate);
@@ -382,7 +405,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_modularity(GraphView<WT> g, HubA
 void hub_modularity(hipStream_t st, const GraphDesc& gd, const HubArgs& h, int32_t c0, int32_t c1, const int32_t* C,
                     double* tot, double* acc_d) {
   if (c1 <= c0) return;
-  const int grid = grid_items(c1 - c0, 1, 8192);
+  const int grid = grid_items(c1 - c0, 1, 2048);
   if (gd.w_double)
     hipLaunchKernelGGL(k_hub_modularity<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), h, c0, c1, C, tot,
                        acc_d);
@@ -411,6 +434,8 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
   constexpr int PER = kHubChunk / kBlock;  // arcs per thread
   __shared__ int32_t skeys[TS];
   __shared__ double svals[TS];
+  __shared__ int32_t snew[kHubChunk];
+  __shared__ int s_nnew, s_base;
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -448,26 +473,16 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
       }
     }
     __syncthreads();
-    int32_t* gk = tbl_keys_of(h, p);
-    double* gv = tbl_vals_of(h, p);
-    const int lg = tbl_lg(h, p);
-    for (int s = threadIdx.x; s < TS; s += kBlock) {
-      const int32_t key = skeys[s];
-      if (key != kEmpty) {
-        glb_insert(gk, gv, lg, key, svals[s]);
-        skeys[s] = kEmpty;
-        svals[s] = 0.0;
-      }
-    }
-    __syncthreads();
+    flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
   }
   __shared__ unsigned long long red_u[16];
   na = block_sum<unsigned long long>(na, red_u);
-  if (threadIdx.x == 0 && na) atomicAdd(&a.cnt[5], na);
+  if (threadIdx.x == 0 && na) atomicAdd(&cnt_of(a.cnt)[5], na);
 }
 
-// Slice emit: append the slice's (d, H[d]) pairs to row c (ydeg[c] is the
-// row cursor, zeroed by the caller) and clear the slots.
+// Slice emit: append the slice's entries of the community's occupied-slot
+// list, (d, H[d]), to row c (ydeg[c] is the row cursor, zeroed by the
+// caller) and clear the slots; the last slice resets the list.
 template <class WTout>
 __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int32_t s0, int32_t s1) {
   __shared__ int s_wsum[kBlock / kWave];
@@ -480,14 +495,23 @@ __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int3
     const int32_t c = h.items[p];
     int32_t* gk = tbl_keys_of(h, p);
     double* gv = tbl_vals_of(h, p);
+    const int32_t* lst = tbl_list_of(h, p);
+    const int32_t len = h.lcnt[p];
     const int64_t ts = (int64_t)1 << tbl_lg(h, p);
+    const bool dense = (int64_t)len * 8 > ts;
+    const int64_t lim = dense ? ts : len;
     const int64_t q0 = (int64_t)task.y * kHubSlice;
-    const int64_t q1 = (q0 + kHubSlice < ts) ? q0 + kHubSlice : ts;
-    // kHubSlice / kBlock slots per thread, contiguous
+    const int64_t q1 = (lim - q0 < kHubSlice) ? lim : q0 + kHubSlice;
+    // kHubSlice / kBlock consecutive positions per thread
     constexpr int PER = kHubSlice / kBlock;
     const int64_t my0 = q0 + (int64_t)threadIdx.x * PER;
+    const int64_t my1 = (my0 + PER < q1) ? my0 + PER : q1;
     int cnt = 0;
-    for (int64_t q = my0; q < my0 + PER && q < q1; ++q) cnt += (glb_load_key(gk, (uint32_t)q) != kEmpty);
+    if (dense) {
+      for (int64_t q = my0; q < my1; ++q) cnt += (glb_load_key(gk, (uint32_t)q) != kEmpty);
+    } else {
+      cnt = my1 > my0 ? (int)(my1 - my0) : 0;
+    }
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < kWave; o <<= 1) {
@@ -505,25 +529,35 @@ __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int3
     if (threadIdx.x == 0) s_base = total ? atomicAdd(&a.ydeg[c], total) : 0;
     __syncthreads();
     int64_t pos = (int64_t)a.yoff[c] + s_base + before + (incl - cnt);
-    for (int64_t q = my0; q < my0 + PER && q < q1; ++q) {
-      const int32_t key = glb_load_key(gk, (uint32_t)q);
+    for (int64_t q = my0; q < my1; ++q) {
+      const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
+      const int32_t key = glb_load_key(gk, slot);
       if (key == kEmpty) continue;
       a.yidx[pos] = key;
-      yw[pos] = (WTout)glb_load_val(gv, (uint32_t)q);
+      yw[pos] = (WTout)glb_load_val(gv, slot);
       ++pos;
-      gk[q] = kEmpty;
-      gv[q] = 0.0;
+      gk[slot] = kEmpty;
+      gv[slot] = 0.0;
     }
-    if (threadIdx.x == 0) no += (unsigned long long)total;
+    __syncthreads();  // every thread's reads and clears of this slice are done
+    if (threadIdx.x == 0) {
+      no += (unsigned long long)total;
+      __threadfence();
+      const int nsl = h.slice_off[p + 1] - h.slice_off[p];
+      if (atomicAdd(&h.done[p], 1) == nsl - 1) {
+        h.done[p] = 0;
+        h.lcnt[p] = 0;
+      }
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && no) atomicAdd(&a.cnt[6], no);
+  if (threadIdx.x == 0 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
 }
 
 void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
                int32_t s0, int32_t s1, int64_t* launches) {
   if (c1 > c0) {
-    const int grid = grid_items(c1 - c0, 1, 8192);
+    const int grid = grid_items(c1 - c0, 1, 2048);
     if (gd.w_double)
       hipLaunchKernelGGL(k_gagg_gather<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), a, h, c0, c1);
     else
@@ -531,7 +565,7 @@ void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubA
     ++*launches;
   }
   if (s1 > s0) {
-    const int grid = grid_items(s1 - s0, 1, 8192);
+    const int grid = grid_items(s1 - s0, 1, 2048);
     if (a.yw_double) hipLaunchKernelGGL(k_gagg_emit<double>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
     else hipLaunchKernelGGL(k_gagg_emit<float>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
     ++*launches;

@@ -116,11 +116,11 @@ void vertex_weights(hipStream_t st, const GraphDesc& gd, int64_t m, double* K, d
   if (gd.n <= 0) return;
   if (gd.w_double) {
     GraphView<double> g{gd.n, gd.off, gd.deg, gd.idx, (const double*)gd.w};
-    hipLaunchKernelGGL(k_vertex_weights<double>, dim3(grid_n(gd.n, kBlock, 8192)), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_vertex_weights<double>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st,
                        g, m, K, accW, flags, validate);
   } else {
     GraphView<float> g{gd.n, gd.off, gd.deg, gd.idx, (const float*)gd.w};
-    hipLaunchKernelGGL(k_vertex_weights<float>, dim3(grid_n(gd.n, kBlock, 8192)), dim3(kBlock), 0, st,
+    hipLaunchKernelGGL(k_vertex_weights<float>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st,
                        g, m, K, accW, flags, validate);
   }
 }
@@ -464,11 +464,11 @@ void modularity_partial(hipStream_t st, const GraphDesc& gd, const int32_t* C, d
   if (gd.n <= 0) return;
   if (gd.w_double) {
     GraphView<double> g{gd.n, gd.off, gd.deg, gd.idx, (const double*)gd.w};
-    hipLaunchKernelGGL(k_mod_partial<double>, dim3(grid_n(gd.n, kBlock, 8192)), dim3(kBlock), 0, st, g, C,
+    hipLaunchKernelGGL(k_mod_partial<double>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st, g, C,
                        tot, acc_d);
   } else {
     GraphView<float> g{gd.n, gd.off, gd.deg, gd.idx, (const float*)gd.w};
-    hipLaunchKernelGGL(k_mod_partial<float>, dim3(grid_n(gd.n, kBlock, 8192)), dim3(kBlock), 0, st, g, C,
+    hipLaunchKernelGGL(k_mod_partial<float>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st, g, C,
                        tot, acc_d);
   }
 }

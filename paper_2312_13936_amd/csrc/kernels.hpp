@@ -9,6 +9,10 @@ namespace gvl {
 typedef __int128 i128_t;
 
 constexpr int32_t kEmpty = -1;        // empty hash-table slot
+// Work counters and iteration sums are kept in kCntSlots copies indexed by
+// workgroup id, so that thousands of workgroups do not serialise on one
+// address; the host adds the copies up.
+constexpr int kCntSlots = 64;
 enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (Alg. 3)
 
 // Degree bins (vertex scan) and capacity bins (aggregation rows).  A vertex
@@ -63,10 +67,10 @@ struct ScanArgs {
   double gk_scale;          // 2 gamma / W^2
   long long W;              // exact total weight (deterministic mode)
   long long p;              // resolution numerator, gamma = p / 65536 (deterministic mode)
-  double* dq;               // fast mode: sum of the gains of the moves made
-  unsigned long long* dq128;  // deterministic mode: exact int128 sum of move keys (lo, hi)
-  unsigned long long* cnt;  // [0] vertices scanned, [1] arcs, [2] candidates, [3] moves,
-                            // [7] arcs scanned by refinement
+  double* dq;               // fast mode: sum of the gains of the moves made [kCntSlots]
+  unsigned long long* dq128;  // deterministic mode: exact int128 sums of move keys [kCntSlots][lo, hi]
+  unsigned long long* cnt;  // [kCntSlots][8]: [0] vertices scanned, [1] arcs, [2] candidates,
+                            // [3] moves, [4..6] aggregation, [7] arcs scanned by refinement
   int32_t* tbl_keys;        // global hash tables for the hub bin
   double* tbl_vals;
   int64_t tbl_slot;         // slots per workgroup table
@@ -98,6 +102,8 @@ struct HubArgs {
   int32_t* pb_c;              // per slice task: best community
   int32_t* tbl_keys;          // table region
   double* tbl_vals;
+  int32_t* tbl_list;          // occupied slots of each item's table, at the item's table offset
+  int32_t* lcnt;              // [H] length of each item's occupied-slot list
   int64_t tbase;              // region offset of the current batch (slots)
   const int32_t* apre;        // aggregation: arc prefix over the community-vertex list
 };
@@ -122,7 +128,7 @@ struct AggArgs {
   int32_t* yidx;
   void* yw;              // float or double
   bool yw_double;
-  unsigned long long* cnt;  // [4] vertices, [5] arcs read, [6] arcs written
+  unsigned long long* cnt;  // [kCntSlots][8]: [4] vertices, [5] arcs read, [6] arcs written
   int32_t* tbl_keys;
   double* tbl_vals;
   int64_t tbl_slot;

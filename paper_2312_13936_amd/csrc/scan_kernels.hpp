@@ -50,17 +50,17 @@ __device__ __forceinline__ void flush_acc(const ScanArgs& a, Acc& acc) {
   unsigned long long nm = block_sum<unsigned long long>(acc.nm, red_u);
   if (DET) {
     i128 k = block_sum_i128(acc.dqk, red_k);
-    if (threadIdx.x == 0 && k != 0) atomic_add_i128(a.dq128, k);
+    if (threadIdx.x == 0 && k != 0) atomic_add_i128(a.dq128 + 2 * cslot(), k);
   } else {
     double d = block_sum<double>(acc.dq, red_d);
-    if (threadIdx.x == 0 && d != 0.0) atomicAdd(a.dq, d);
+    if (threadIdx.x == 0 && d != 0.0) atomicAdd(a.dq + cslot(), d);
   }
   if (threadIdx.x == 0) {
-    if (nv) atomicAdd(&a.cnt[0], nv);
-    if (na) atomicAdd(&a.cnt[1], na);
-    if (PH == kRefine && na) atomicAdd(&a.cnt[7], na);
-    if (nc) atomicAdd(&a.cnt[2], nc);
-    if (nm) atomicAdd(&a.cnt[3], nm);
+    if (nv) atomicAdd(&cnt_of(a.cnt)[0], nv);
+    if (na) atomicAdd(&cnt_of(a.cnt)[1], na);
+    if (PH == kRefine && na) atomicAdd(&cnt_of(a.cnt)[7], na);
+    if (nc) atomicAdd(&cnt_of(a.cnt)[2], nc);
+    if (nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
   }
 }
 
@@ -88,6 +88,22 @@ struct Eval {
     }
   }
 };
+
+// Workgroup argmax of (gain or key, id); the result is valid in every thread.
+template <bool DET>
+__device__ __forceinline__ void block_argmax(double& bg, i128& bk, int32_t& bc, double* s_g, i128* s_k,
+                                             int32_t* s_c) {
+  if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) { s_g[w] = bg; s_k[w] = bk; s_c[w] = bc; }
+  __syncthreads();
+  bc = s_c[0]; bg = s_g[0]; bk = s_k[0];
+  for (int k = 1; k < kBlock / kWave; ++k) {
+    if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
+    else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
+  }
+}
 
 // After the argmax: apply the min-label rule and the sign test.
 template <int PH, bool DET>
@@ -127,28 +143,34 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
     if (PH == kMove && gl == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
     const int32_t beg = g.begin(i), deg = g.degree(i);
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    // table of next_pow2(2 deg) <= TS slots: at most deg distinct keys
+    const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
+    const int ts = 1 << lg;
     for (int32_t e = gl; e < deg; e += G) {
       const int32_t j = g.idx[beg + e];
       if (j == i) continue;
       if (PH == kRefine && a.CB[j] != bi) continue;
-      lds_insert(keys, vals, LG, a.C[j], g.weight(beg + e));
+      lds_insert(keys, vals, lg, a.C[j], g.weight(beg + e));
     }
     wave_sync();
     const int32_t d = a.C[i];
     const double ki = a.K[i];
-    const Eval<DET> ev(a, lds_lookup(keys, vals, LG, d), ki, a.Sig[d]);
+    const Eval<DET> ev(a, lds_lookup(keys, vals, lg, d), ki, a.Sig[d]);
+    wave_sync();  // the lookup of d is done before slots are cleared
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    for (int s = gl; s < TS; s += G) {
+    for (int s = gl; s < ts; s += G) {
       const int32_t c = keys[s];
-      if (c == kEmpty || c == d) continue;
-      ++acc.nc;
-      ev(a, c, vals[s], a.Sig[c], bg, bk, bc);
+      if (c == kEmpty) continue;
+      if (c != d) {
+        ++acc.nc;
+        ev(a, c, vals[s], a.Sig[c], bg, bk, bc);
+      }
+      keys[s] = kEmpty;
+      vals[s] = 0.0;
     }
     if (DET) argmax_k<G>(bk, bc); else argmax_f<G>(bg, bc);
-    wave_sync();
-    for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
     wave_sync();
     if (gl == 0) { ++acc.nv; acc.na += (unsigned long long)deg; }
     int take = (gl == 0) ? (int)accept<PH, DET>(a, d, bc, bg, bk) : 0;
@@ -211,7 +233,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
     // distinct neighbour communities <= min(deg, n): the table slice holds
     // next_pow2(2 min(max hub degree, n)) slots
-    const int lg = GLB ? ceil_log2(2 * ((int64_t)deg < g.n ? (int64_t)deg : g.n)) : LG;
+    const int lg = GLB ? ceil_log2(2 * ((int64_t)deg < g.n ? (int64_t)deg : g.n))
+                       : min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
     if (GLB) {
       for (int s = threadIdx.x; s < ts; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
@@ -229,14 +252,18 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     const double ki = a.K[i];
     const double kid = GLB ? glb_lookup(keys, vals, lg, d) : lds_lookup(keys, vals, lg, d);
     const Eval<DET> ev(a, kid, ki, a.Sig[d]);
+    __syncthreads();  // the lookup of d is done before slots are cleared
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
     for (int s = threadIdx.x; s < ts; s += kBlock) {
       const int32_t c = GLB ? glb_load_key(keys, s) : keys[s];
-      if (c == kEmpty || c == d) continue;
-      ++acc.nc;
-      ev(a, c, GLB ? glb_load_val(vals, s) : vals[s], a.Sig[c], bg, bk, bc);
+      if (c == kEmpty) continue;
+      if (c != d) {
+        ++acc.nc;
+        ev(a, c, GLB ? glb_load_val(vals, s) : vals[s], a.Sig[c], bg, bk, bc);
+      }
+      if (!GLB) { keys[s] = kEmpty; vals[s] = 0.0; }
     }
     if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
     const int w = threadIdx.x / kWave;
@@ -247,7 +274,6 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
       if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
       else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
     }
-    if (!GLB) for (int s = threadIdx.x; s < ts; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
     if (threadIdx.x == 0) {
       ++acc.nv;
       acc.na += (unsigned long long)deg;
@@ -325,7 +351,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
     }
   }
   nm = block_sum<unsigned long long>(nm, red_u);
-  if (threadIdx.x == 0 && nm) atomicAdd(&a.cnt[3], nm);
+  if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
 }
 
 // Refinement: forget the group's targets once every commit has read them.
@@ -387,13 +413,13 @@ template <class WT, int PH>
 void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count) {
   if (count <= 0) return;
   const GraphView<WT> g = view<WT>(gd);
-  const int grid = grid_for(count, kBlock, 8192);
+  const int grid = grid_for(count, kBlock, 2048);
   hipLaunchKernelGGL((k_commit<WT, PH>), dim3(grid), dim3(kBlock), 0, st, g, a, list, count);
 }
 
 inline void cleanup_list(hipStream_t st, const ScanArgs& a, const int32_t* list, int32_t count) {
   if (count <= 0) return;
-  const int grid = grid_for(count, kBlock, 8192);
+  const int grid = grid_for(count, kBlock, 2048);
   hipLaunchKernelGGL((k_refine_cleanup<kRefine>), dim3(grid), dim3(kBlock), 0, st, a, list, count);
 }
 
