@@ -84,12 +84,219 @@ def cpu_baseline(scale: int):
             "seconds": dt}
 
 
+# --------------------------------------------------------- batch and serving ---
+
+def gen_many(specs, threads=16):
+    """Generate LFR-style graphs in parallel host threads (the generator
+    releases the GIL); specs = [(n, avg_deg, mu, seed)]."""
+    import concurrent.futures as cf
+    import gen
+    with cf.ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(lambda s: gen.lfr(int(s[0]), avg_deg=s[1], mu=s[2], seed=s[3]), specs))
+
+
+def lfr_batch_specs(count):
+    """Batch recipe: vertex counts log-uniform on [1k, 200k] (seed 4096),
+    power-law degrees (exponent 2.5, mean 12), power-law community sizes
+    (exponent 1.5), mixing 0.3, unit weights; graph k uses seed 1000 + k."""
+    import gen
+    sizes = gen.lfr_sizes(count, 1000, 200000, 4096)
+    return [(int(n), 12.0, 0.3, 1000 + k) for k, n in enumerate(sizes)]
+
+
+def lfr_serve_specs(pool):
+    """Serving pool recipe: vertex counts log-uniform on [10k, 5M] (seed 5000),
+    mean degree 16, mixing uniform on [0.1, 0.5] (seed 5001), graph k uses
+    seed 5000 + k."""
+    import numpy as np
+    import gen
+    sizes = gen.lfr_sizes(pool, 10000, 5000000, 5000)
+    mus = np.random.default_rng(5001).uniform(0.1, 0.5, pool)
+    return [(int(n), 16.0, float(mu), 5000 + k) for k, (n, mu) in enumerate(zip(sizes, mus))]
+
+
+def upload(graphs):
+    import torch
+    dev = torch.device("cuda", 0)
+    out = []
+    for g in graphs:
+        out.append((torch.from_numpy(g.offsets).to(dev), torch.from_numpy(g.indices).to(dev),
+                    torch.from_numpy(g.weights).to(dev)))
+    torch.cuda.synchronize()
+    return out
+
+
+def bench_batch(args, mode):
+    """Batched Leiden over many graphs against the plain path (one
+    gvl_leiden call per graph, one after the other) on the same graphs."""
+    import numpy as np
+    import torch
+    import paper_2312_13936_amd as gvl
+    t0 = time.perf_counter()
+    specs = lfr_batch_specs(args.graphs)
+    graphs = gen_many(specs)
+    arcs = sum(g.m for g in graphs)
+    log("generated %d LFR-style graphs: %d vertices, %d arcs in %.1fs" % (
+        len(graphs), sum(g.n for g in graphs), arcs, time.perf_counter() - t0))
+    tens = upload(graphs)
+    mems = [torch.empty(max(g.n, 1), dtype=torch.int32, device="cuda") for g in graphs]
+    descs = [gvl.graph_desc(o, i, w, m) for (o, i, w), m in zip(tens, mems)]
+    eng = gvl.Leiden(0)
+    opt = eng.options(mode)
+    # plain path: one launch sequence per graph on a seeded subset
+    rng = np.random.default_rng(77)
+    sub = sorted(rng.choice(len(graphs), min(args.plain_graphs, len(graphs)), replace=False).tolist())
+    plain_q = {}
+    for k in sub[:4]:  # warm-up
+        eng.run(*tens[k], 1.0, opt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in sub:
+        plain_q[k] = eng.run(*tens[k], 1.0, opt).modularity
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    plain_arcs = sum(graphs[k].m for k in sub)
+    log("plain: %d graphs in %.2fs (%.1f graphs/s)" % (len(sub), plain_s, len(sub) / plain_s))
+    wsb = gvl.gvl_batch_workspace_bytes(descs, opt, args.lanes)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    times, qs = [], None
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        code, qs, sts = gvl.gvl_leiden_batch(eng.ctx, descs, opt, args.lanes, ws.data_ptr(), wsb)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        if code != 0:
+            raise RuntimeError("batch failed: %s" % sorted(set(sts)))
+        log("batch step %d: %.2fs (%.1f graphs/s)" % (k, dt, len(graphs) / dt))
+        if k >= args.warmup:
+            times.append(dt)
+    total = sum(times)
+    bq = np.array([qs[k] for k in sub])
+    pq = np.array([plain_q[k] for k in sub])
+    batched_gps = len(graphs) * len(times) / total
+    plain_gps = len(sub) / plain_s
+    eng.close()
+    return {
+        "metric": METRIC, "value": batched_gps, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * total / len(times), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%d LFR-style graphs, vertices log-uniform on [1k, 200k], degree exponent 2.5, "
+                               "mean degree 12, community-size exponent 1.5, mixing 0.3, unit weights"
+                               % len(graphs),
+                   "vertices": sum(g.n for g in graphs), "arcs": arcs, "mode": args.mode, "lanes": args.lanes,
+                   "parallelism": "single GPU"},
+        "batched_graphs_per_s": batched_gps, "batched_edges_per_s": arcs * len(times) / total,
+        "plain_graphs_per_s": plain_gps, "plain_edges_per_s": plain_arcs / plain_s,
+        "plain_sample": "%d of the %d graphs (seeded), one gvl_leiden call after another" % (len(sub), len(graphs)),
+        "speedup_vs_plain": batched_gps / plain_gps,
+        "modularity_mean": float(np.mean(qs)),
+        "modularity_max_abs_diff_vs_plain": float(np.max(np.abs(bq - pq))),
+    }
+
+
+def bench_serve(args, mode):
+    """Serving loop: Poisson arrivals of LFR-style requests drawn from a pool
+    at 0.8 x the plain path's one-at-a-time service rate."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_2312_13936_amd as gvl
+    t0 = time.perf_counter()
+    specs = lfr_serve_specs(args.pool)
+    graphs = gen_many(specs)
+    log("generated pool of %d graphs: %d arcs in %.1fs" % (len(graphs), sum(g.m for g in graphs),
+                                                          time.perf_counter() - t0))
+    tens = upload(graphs)
+    eng = gvl.Leiden(0)
+    opt = eng.options(mode)
+    eng.run(*tens[0], 1.0, opt)
+    solo_t, solo_q = [], []
+    for k in range(len(graphs)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        solo_q.append(eng.run(*tens[k], 1.0, opt).modularity)
+        torch.cuda.synchronize()
+        solo_t.append(time.perf_counter() - t1)
+    eng.close()
+    eng.ws = None
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5000)
+    req = rng.integers(0, len(graphs), args.requests)
+    mean_service = float(np.mean([solo_t[k] for k in req]))
+    qps = args.load / mean_service
+    arrivals = np.cumsum(rng.exponential(1.0 / qps, args.requests))
+    log("plain service %.1f ms mean -> %.1f requests/s offered" % (1e3 * mean_service, qps))
+    # one output membership per request (requests for the same pool graph may overlap)
+    starts = np.concatenate([[0], np.cumsum([max(graphs[k].n, 1) for k in req])])
+    out_all = torch.empty(int(starts[-1]), dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    arena_bytes = int(free * 0.8) & ~255
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    srv = gvl.Server(arena, args.lanes, opt)
+    tickets = [None] * args.requests
+    done = [None] * args.requests
+    ready = [threading.Event() for _ in range(args.requests)]
+
+    def collector():
+        for r in range(args.requests):
+            ready[r].wait()
+            info = srv.wait(tickets[r], 600000)
+            done[r] = (time.perf_counter(), info.latency_ms, info.queue_ms, info.modularity, info.result)
+            srv.release(tickets[r])
+            if r % 200 == 199:
+                log("served %d/%d" % (r + 1, args.requests))
+
+    th = threading.Thread(target=collector)
+    th.start()
+    start = time.perf_counter()
+    for r in range(args.requests):
+        delay = start + arrivals[r] - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        o, i, w = tens[req[r]]
+        tickets[r] = srv.submit(o, i, w, out_all[int(starts[r]):int(starts[r + 1])])
+        ready[r].set()
+    th.join()
+    wall = max(d[0] for d in done) - start
+    st = srv.stats()
+    srv.close()
+    lat = np.array([d[1] for d in done])
+    dq = np.array([abs(done[r][3] - solo_q[req[r]]) for r in range(args.requests)])
+    arcs = sum(graphs[k].m for k in req)
+    return {
+        "metric": METRIC, "value": float(np.percentile(lat, 99)), "unit": "ms (p99 latency)", "n_gpus": 1,
+        "steps": args.requests, "warmup": 0, "ms_per_step": 1e3 * wall / args.requests, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%d requests, Poisson arrivals at %.2f x the plain service rate (%.2f req/s), "
+                               "drawn from a pool of %d LFR-style graphs: vertices log-uniform on [10k, 5M], "
+                               "degree exponent 2.5, mean degree 16, mixing U[0.1, 0.5], unit weights, "
+                               "resolution 1" % (args.requests, args.load, qps, len(graphs)),
+                   "mode": args.mode, "lanes": args.lanes, "arena_bytes": arena_bytes,
+                   "parallelism": "single GPU"},
+        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+        "mean_ms": float(np.mean(lat)), "edges_per_s": arcs / wall, "requests_per_s": args.requests / wall,
+        "plain_mean_service_ms": 1e3 * mean_service, "max_running": int(st.max_running),
+        "arena_peak_bytes": int(st.arena_peak), "failed": int(sum(1 for d in done if d[4] != 0)),
+        "modularity_max_abs_diff_vs_alone": float(dq.max()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat-s24", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="rmat-s24", choices=sorted(WORKLOADS) + ["lfr-batch", "lfr-serve"])
+    ap.add_argument("--graphs", type=int, default=4096, help="lfr-batch: number of graphs")
+    ap.add_argument("--plain-graphs", type=int, default=512, help="lfr-batch: graphs timed on the plain path")
+    ap.add_argument("--lanes", type=int, default=8, help="lfr-batch / lfr-serve: concurrent lanes")
+    ap.add_argument("--pool", type=int, default=64, help="lfr-serve: distinct graphs in the request pool")
+    ap.add_argument("--requests", type=int, default=2000, help="lfr-serve: number of requests")
+    ap.add_argument("--load", type=float, default=0.8, help="lfr-serve: offered load / plain service rate")
     ap.add_argument("--mode", default="fast", choices=["fast", "det"])
     ap.add_argument("--subsweeps", type=int, default=0, help="0 = library default")
     ap.add_argument("--cpu-sample-scale", type=int, default=20)
@@ -104,6 +311,12 @@ def main():
     import numpy as np
     import torch
     import paper_2312_13936_amd as gvl
+
+    if args.workload in ("lfr-batch", "lfr-serve"):
+        mode = gvl.GVL_MODE_DET if args.mode == "det" else gvl.GVL_MODE_FAST
+        out = bench_batch(args, mode) if args.workload == "lfr-batch" else bench_serve(args, mode)
+        print(json.dumps(out), flush=True)
+        return
 
     w = WORKLOADS[args.workload]
     t0 = time.perf_counter()

@@ -55,7 +55,9 @@ def _load():
                                  ctypes.c_int32, ctypes.c_uint64, P]
         lib.gen_from_edges.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, P]
-        for f in (lib.gen_planted, lib.gen_rmat, lib.gen_grid, lib.gen_from_edges):
+        lib.gen_lfr.argtypes = [ctypes.c_int64, ctypes.c_double, ctypes.c_int64, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_int64, ctypes.c_int64, ctypes.c_uint64, P]
+        for f in (lib.gen_planted, lib.gen_rmat, lib.gen_grid, lib.gen_from_edges, lib.gen_lfr):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -114,6 +116,24 @@ def grid(rows: int = 4096, cols: int = 4096, drop: float = 0.1, diag_frac: float
          wmax: int = 100, seed: int = 3) -> Graph:
     """Lattice with dropped edges, diagonal shortcuts and integer weights in [1, wmax]."""
     return _call("gen_grid", (rows, cols, drop, diag_frac, wmax, seed), "grid-%dx%d" % (rows, cols))
+
+
+def lfr(n: int, avg_deg: float = 12.0, tau1: float = 2.5, tau2: float = 1.5, mu: float = 0.3,
+        kmax: int = 0, cmin: int = 20, cmax: int = 0, seed: int = 1000) -> Graph:
+    """LFR-style graph: power-law degrees and community sizes, mixing mu,
+    unit weights (truth = planted community).  Defaults: kmax = min(4 sqrt(n),
+    n/10), community sizes on [20, max(20, n/10)]."""
+    if kmax <= 0:
+        kmax = max(2, min(int(4 * n ** 0.5), n // 10))
+    if cmax <= 0:
+        cmax = max(cmin, n // 10)
+    return _call("gen_lfr", (n, avg_deg, kmax, tau1, tau2, mu, cmin, cmax, seed), "lfr-%d-%d" % (n, seed))
+
+
+def lfr_sizes(count: int, lo: int, hi: int, seed: int):
+    """Vertex counts log-uniform on [lo, hi] (seeded)."""
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.uniform(np.log(lo), np.log(hi), count)).astype(np.int64)
 
 
 def from_edges(n: int, edges, weights=None, name: str = "edges") -> Graph:

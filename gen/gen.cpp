@@ -264,6 +264,93 @@ int gen_grid(int32_t rows, int32_t cols, double drop, double diag_frac, int32_t 
   return build_csr(n, edges, out);
 }
 
+// LFR-style benchmark graph (Lancichinetti, Fortunato, Radicchi 2008),
+// simplified: degrees from a power law with exponent tau1 on
+// [kmin, kmax] (kmin chosen so that the mean is close to avg_deg);
+// community sizes from a power law with exponent tau2 on [cmin, cmax]
+// until they cover n; vertices assigned to communities in a shuffled order;
+// each vertex's stubs split into round((1 - mu) k) internal and the rest
+// external; stubs paired uniformly at random inside each community
+// (internal) and over the whole graph (external); self-loops and duplicate
+// edges dropped.  Unit weights; truth[] holds the planted community.
+namespace {
+int64_t discrete_powerlaw(u64 s, u64 k, const std::vector<double>& cdf, int64_t lo) {
+  const double u = unif(s, k) * cdf.back();
+  return lo + (int64_t)(std::lower_bound(cdf.begin(), cdf.end(), u) - cdf.begin());
+}
+std::vector<double> powerlaw_cdf(int64_t lo, int64_t hi, double tau) {
+  std::vector<double> cdf;
+  double acc = 0.0;
+  for (int64_t k = lo; k <= hi; ++k) { acc += std::pow((double)k, -tau); cdf.push_back(acc); }
+  return cdf;
+}
+double powerlaw_mean(int64_t lo, int64_t hi, double tau) {
+  double a = 0.0, b = 0.0;
+  for (int64_t k = lo; k <= hi; ++k) { double p = std::pow((double)k, -tau); a += p * k; b += p; }
+  return a / b;
+}
+void shuffle(std::vector<int32_t>& v, u64 s) {
+  for (int64_t i = (int64_t)v.size() - 1; i > 0; --i) std::swap(v[i], v[(int64_t)(draw(s, (u64)i) % (u64)(i + 1))]);
+}
+}  // namespace
+
+extern "C" int gen_lfr(int64_t n, double avg_deg, int64_t kmax, double tau1, double tau2, double mu, int64_t cmin,
+                       int64_t cmax, uint64_t seed, gen_graph* out) {
+  memset(out, 0, sizeof(*out));
+  if (n < 2 || avg_deg <= 0 || kmax < 1 || cmin < 1 || cmax < cmin || mu < 0 || mu > 1) return -1;
+  kmax = std::min<int64_t>(kmax, n - 1);
+  cmax = std::min<int64_t>(cmax, n);
+  cmin = std::min<int64_t>(cmin, cmax);
+  const u64 s_deg = stream(seed, 31), s_com = stream(seed, 32), s_ord = stream(seed, 33), s_in = stream(seed, 34),
+            s_ex = stream(seed, 35);
+  int64_t kmin = 1;
+  while (kmin < kmax && powerlaw_mean(kmin + 1, kmax, tau1) <= avg_deg) ++kmin;
+  std::vector<double> dcdf = powerlaw_cdf(kmin, kmax, tau1);
+  std::vector<int64_t> deg(n);
+  for (int64_t i = 0; i < n; ++i) deg[i] = discrete_powerlaw(s_deg, (u64)i, dcdf, kmin);
+  // community sizes
+  std::vector<double> ccdf = powerlaw_cdf(cmin, cmax, tau2);
+  std::vector<int64_t> csize;
+  int64_t covered = 0;
+  for (u64 t = 0; covered < n; ++t) {
+    int64_t c = discrete_powerlaw(s_com, t, ccdf, cmin);
+    if (covered + c > n) c = n - covered;
+    csize.push_back(c);
+    covered += c;
+  }
+  // assignment: shuffled vertex order fills communities in turn
+  std::vector<int32_t> order(n);
+  for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+  shuffle(order, s_ord);
+  std::vector<int32_t> com(n);
+  std::vector<std::vector<int32_t>> members(csize.size());
+  int64_t pos = 0;
+  for (size_t c = 0; c < csize.size(); ++c)
+    for (int64_t k = 0; k < csize[c]; ++k) { com[order[pos]] = (int32_t)c; members[c].push_back(order[pos]); ++pos; }
+  std::vector<Edge> edges;
+  std::vector<int32_t> ext;
+  for (size_t c = 0; c < members.size(); ++c) {
+    std::vector<int32_t> stubs;
+    for (int32_t v : members[c]) {
+      int64_t kin = (int64_t)llround((1.0 - mu) * (double)deg[v]);
+      kin = std::min<int64_t>(kin, (int64_t)members[c].size() - 1);
+      for (int64_t k = 0; k < kin; ++k) stubs.push_back(v);
+      for (int64_t k = kin; k < deg[v]; ++k) ext.push_back(v);
+    }
+    shuffle(stubs, stream(s_in, (u64)c));
+    for (size_t k = 0; k + 1 < stubs.size(); k += 2)
+      if (stubs[k] != stubs[k + 1]) edges.push_back({stubs[k], stubs[k + 1], 1.0f});
+  }
+  shuffle(ext, s_ex);
+  for (size_t k = 0; k + 1 < ext.size(); k += 2)
+    if (ext[k] != ext[k + 1]) edges.push_back({ext[k], ext[k + 1], 1.0f});
+  int rc = build_csr(n, edges, out);
+  if (rc) return rc;
+  out->truth = (int32_t*)malloc(sizeof(int32_t) * n);
+  memcpy(out->truth, com.data(), sizeof(int32_t) * n);
+  return 0;
+}
+
 // Symmetric CSR from an explicit undirected edge list (for small test
 // graphs).  Self-loops are kept once, duplicates merged by summing.
 int gen_from_edges(int64_t n, int64_t ne, const int32_t* us, const int32_t* vs,

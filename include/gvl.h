@@ -39,7 +39,9 @@ typedef enum {
   GVL_E_NONINTEGER_WEIGHT = -4, /* deterministic mode: weight not an integer in [1, 2^24] or total > 2^40 */
   GVL_E_RESOLUTION = -5,        /* resolution < 0, or (deterministic mode) not p / 65536 with p <= 2^24 */
   GVL_E_WORKSPACE = -6,         /* workspace null or smaller than gvl_workspace_bytes */
-  GVL_E_HIP = -8                /* a HIP runtime call failed */
+  GVL_E_HIP = -8,               /* a HIP runtime call failed */
+  GVL_E_BUSY = -9,              /* serving: request not in a state that allows the call */
+  GVL_E_BATCH = -10             /* batch: at least one graph failed (see its status) */
 } gvl_status;
 
 enum { GVL_MODE_FAST = 0, GVL_MODE_DET = 1 };
@@ -149,6 +151,77 @@ gvl_status gvl_debug_export_pass(gvl_ctx_t ctx, int32_t pass, int32_t* bound, in
 /* Movers per local-moving iteration / refinement sweep of pass p (debug_trace = 1). */
 gvl_status gvl_debug_pass_movers(gvl_ctx_t ctx, int32_t pass, int64_t* movers, int32_t max_it,
                                  int64_t* refine_movers, int32_t max_sw);
+
+/* ------------------------------------------------------------------------
+ * Batched and served Leiden (many independent graphs on one GPU).
+ *
+ * Both run gvl_leiden for every graph on a pool of `lanes` concurrent HIP
+ * streams (one host worker thread, one context and one workspace slice per
+ * lane), so each graph gets exactly the result it gets alone: bit-identical
+ * in deterministic mode, the same algorithm in fast mode.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  int64_t n, m;                 /* as for gvl_leiden */
+  const int32_t* d_offsets;
+  const int32_t* d_indices;
+  const float* d_weights;       /* NULL: unit weights */
+  double resolution;
+  int32_t* d_membership;        /* output int32[n] (device, caller-owned) */
+} gvl_graph_desc;
+
+/* Device workspace for gvl_leiden_batch: lanes x the largest per-graph
+ * workspace. */
+gvl_status gvl_batch_workspace_bytes(int32_t num_graphs, const gvl_graph_desc* graphs, const gvl_options* opt,
+                                     int32_t lanes, size_t* bytes);
+/* Leiden on every graph; waits for all.  Work already queued on ctx's stream
+ * (e.g. uploads of the inputs) completes before any lane starts.
+ * modularities: host double[num_graphs]; statuses: host, nullable.  Returns
+ * GVL_E_BATCH if any graph failed, the others are still computed. */
+gvl_status gvl_leiden_batch(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_desc* graphs, const gvl_options* opt,
+                            int32_t lanes, void* d_workspace, size_t workspace_bytes, double* modularities,
+                            gvl_status* statuses);
+
+/* Serving with continuous admission.  The caller gives a device arena; a
+ * running request holds gvl_workspace_bytes(n, m) of it (rounded up to 256),
+ * returned when it completes.  Requests wait in arrival order; a free lane
+ * takes the oldest one whose workspace fits in the free arena; one that later
+ * requests overtook 64 times is admitted before any other.  The input graph
+ * must be fully written (its producing stream synchronised) before
+ * submission, and it and the output membership must stay valid until the
+ * request is done; the membership is complete once a wait or poll reports
+ * GVL_REQ_DONE.  All calls are thread safe.  Errors: GVL_E_INVALID_ARG for a
+ * null handle, unknown ticket or bad argument; GVL_E_HIP if a lane cannot be
+ * created. */
+typedef struct gvl_server* gvl_server_t;
+enum { GVL_REQ_PENDING = 0, GVL_REQ_RUNNING = 1, GVL_REQ_DONE = 2, GVL_REQ_CANCELLED = 3 };
+typedef struct {
+  int32_t state;                /* GVL_REQ_* */
+  gvl_status result;            /* status of the run (valid when done) */
+  double modularity;
+  double latency_ms;            /* submission -> completion (host steady clock) */
+  double queue_ms;              /* submission -> start */
+} gvl_request_info;
+typedef struct {
+  int64_t completed, pending, running, max_running;
+  size_t arena_bytes, arena_used, arena_peak;
+} gvl_server_info;
+
+gvl_status gvl_server_create(gvl_server_t* srv, int device, int32_t lanes, const gvl_options* opt, void* d_arena,
+                             size_t arena_bytes);
+/* GVL_E_WORKSPACE if the request can never fit into the arena. */
+gvl_status gvl_server_submit(gvl_server_t srv, const gvl_graph_desc* graph, uint64_t* ticket);
+gvl_status gvl_server_poll(gvl_server_t srv, uint64_t ticket, gvl_request_info* info);
+/* Blocks until the request is done or cancelled, or timeout_ms passes
+ * (then GVL_E_BUSY with the current state in info); timeout_ms < 0 waits
+ * without limit. */
+gvl_status gvl_server_wait(gvl_server_t srv, uint64_t ticket, int64_t timeout_ms, gvl_request_info* info);
+/* Only a request that is still waiting can be cancelled (else GVL_E_BUSY). */
+gvl_status gvl_server_cancel(gvl_server_t srv, uint64_t ticket);
+/* Forgets a finished or cancelled request (GVL_E_BUSY while it waits or runs). */
+gvl_status gvl_server_release(gvl_server_t srv, uint64_t ticket);
+gvl_status gvl_server_stats(gvl_server_t srv, gvl_server_info* info);
+/* Finishes running requests, cancels waiting ones, joins the workers. */
+gvl_status gvl_server_destroy(gvl_server_t srv);
 
 const char* gvl_status_string(gvl_status s);
 

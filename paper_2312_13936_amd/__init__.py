@@ -25,7 +25,9 @@ GVL_MODE_DET = 1
 GVL_MAX_PASS_STATS = 64
 
 STATUS = {0: "GVL_OK", -1: "GVL_E_INVALID_ARG", -2: "GVL_E_BAD_CSR", -4: "GVL_E_NONINTEGER_WEIGHT",
-          -5: "GVL_E_RESOLUTION", -6: "GVL_E_WORKSPACE", -8: "GVL_E_HIP"}
+          -5: "GVL_E_RESOLUTION", -6: "GVL_E_WORKSPACE", -8: "GVL_E_HIP", -9: "GVL_E_BUSY", -10: "GVL_E_BATCH"}
+
+GVL_REQ_PENDING, GVL_REQ_RUNNING, GVL_REQ_DONE, GVL_REQ_CANCELLED = 0, 1, 2, 3
 
 
 class GvlError(RuntimeError):
@@ -63,9 +65,28 @@ class gvl_stats(ctypes.Structure):
                 ("scan_refine_arcs", ctypes.c_int64), ("ms_scan_move_kernels", ctypes.c_double)]
 
 
+class gvl_graph_desc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("d_offsets", ctypes.c_void_p),
+                ("d_indices", ctypes.c_void_p), ("d_weights", ctypes.c_void_p), ("resolution", ctypes.c_double),
+                ("d_membership", ctypes.c_void_p)]
+
+
+class gvl_request_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("result", ctypes.c_int32), ("modularity", ctypes.c_double),
+                ("latency_ms", ctypes.c_double), ("queue_ms", ctypes.c_double)]
+
+
+class gvl_server_info(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_int64), ("pending", ctypes.c_int64), ("running", ctypes.c_int64),
+                ("max_running", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+                ("arena_peak", ctypes.c_size_t)]
+
+
 EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
            "gvl_modularity", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
-           "gvl_status_string"]
+           "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_server_create", "gvl_server_submit",
+           "gvl_server_poll", "gvl_server_wait", "gvl_server_cancel", "gvl_server_release", "gvl_server_stats",
+           "gvl_server_destroy", "gvl_status_string"]
 
 _lib = None
 
@@ -89,6 +110,18 @@ def load_library(path: str = LIB_PATH):
     lib.gvl_debug_pass_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.gvl_debug_export_pass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     lib.gvl_debug_pass_movers.argtypes = [vp, i32, vp, i32, vp, i32]
+    GD = ctypes.POINTER(gvl_graph_desc)
+    lib.gvl_batch_workspace_bytes.argtypes = [i32, GD, ctypes.POINTER(gvl_options), i32, ctypes.POINTER(sz)]
+    lib.gvl_leiden_batch.argtypes = [vp, i32, GD, ctypes.POINTER(gvl_options), i32, vp, sz,
+                                     ctypes.POINTER(dbl), ctypes.POINTER(i32)]
+    lib.gvl_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32, ctypes.POINTER(gvl_options), vp, sz]
+    lib.gvl_server_submit.argtypes = [vp, GD, ctypes.POINTER(ctypes.c_uint64)]
+    lib.gvl_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(gvl_request_info)]
+    lib.gvl_server_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(gvl_request_info)]
+    lib.gvl_server_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.gvl_server_release.argtypes = [vp, ctypes.c_uint64]
+    lib.gvl_server_stats.argtypes = [vp, ctypes.POINTER(gvl_server_info)]
+    lib.gvl_server_destroy.argtypes = [vp]
     for f in EXPORTS[:-1]:
         getattr(lib, f).restype = ctypes.c_int
     lib.gvl_status_string.argtypes = [ctypes.c_int]
@@ -173,6 +206,70 @@ def gvl_debug_pass_movers(ctx, p: int, max_it: int = 64, max_sw: int = 64):
     _check(load_library().gvl_debug_pass_movers(ctx, p, mv.ctypes.data, max_it, rmv.ctypes.data, max_sw),
            "gvl_debug_pass_movers")
     return mv[mv >= 0].tolist(), rmv[rmv >= 0].tolist()
+
+
+def gvl_batch_workspace_bytes(graphs, opt: gvl_options, lanes: int) -> int:
+    arr = (gvl_graph_desc * max(len(graphs), 1))(*graphs)
+    b = ctypes.c_size_t(0)
+    _check(load_library().gvl_batch_workspace_bytes(len(graphs), arr, ctypes.byref(opt), lanes, ctypes.byref(b)),
+           "gvl_batch_workspace_bytes")
+    return int(b.value)
+
+
+def gvl_leiden_batch(ctx, graphs, opt: gvl_options, lanes: int, d_workspace, workspace_bytes):
+    """Returns (status, modularities[num], statuses[num]); status GVL_E_BATCH means some graphs failed."""
+    num = len(graphs)
+    arr = (gvl_graph_desc * max(num, 1))(*graphs)
+    qs = (ctypes.c_double * max(num, 1))()
+    sts = (ctypes.c_int32 * max(num, 1))()
+    code = load_library().gvl_leiden_batch(ctx, num, arr, ctypes.byref(opt), lanes, d_workspace, workspace_bytes,
+                                           qs, sts)
+    if code not in (0, -10):
+        _check(code, "gvl_leiden_batch")
+    return code, list(qs)[:num], list(sts)[:num]
+
+
+def gvl_server_create(device: int, lanes: int, opt: gvl_options, d_arena, arena_bytes: int):
+    h = ctypes.c_void_p()
+    _check(load_library().gvl_server_create(ctypes.byref(h), device, lanes, ctypes.byref(opt), d_arena, arena_bytes),
+           "gvl_server_create")
+    return h
+
+
+def gvl_server_submit(srv, graph: gvl_graph_desc) -> int:
+    t = ctypes.c_uint64(0)
+    _check(load_library().gvl_server_submit(srv, ctypes.byref(graph), ctypes.byref(t)), "gvl_server_submit")
+    return int(t.value)
+
+
+def gvl_server_poll(srv, ticket: int) -> gvl_request_info:
+    info = gvl_request_info()
+    _check(load_library().gvl_server_poll(srv, ticket, ctypes.byref(info)), "gvl_server_poll")
+    return info
+
+
+def gvl_server_wait(srv, ticket: int, timeout_ms: int = -1) -> gvl_request_info:
+    info = gvl_request_info()
+    _check(load_library().gvl_server_wait(srv, ticket, timeout_ms, ctypes.byref(info)), "gvl_server_wait")
+    return info
+
+
+def gvl_server_cancel(srv, ticket: int) -> None:
+    _check(load_library().gvl_server_cancel(srv, ticket), "gvl_server_cancel")
+
+
+def gvl_server_release(srv, ticket: int) -> None:
+    _check(load_library().gvl_server_release(srv, ticket), "gvl_server_release")
+
+
+def gvl_server_stats(srv) -> gvl_server_info:
+    info = gvl_server_info()
+    _check(load_library().gvl_server_stats(srv, ctypes.byref(info)), "gvl_server_stats")
+    return info
+
+
+def gvl_server_destroy(srv) -> None:
+    _check(load_library().gvl_server_destroy(srv), "gvl_server_destroy")
 
 
 def gvl_status_string(code: int) -> str:
@@ -264,3 +361,55 @@ def leiden(offsets, indices, weights=None, resolution: float = 1.0, mode: int = 
         return r.membership, r.modularity, r.stats
     finally:
         eng.close()
+
+
+def graph_desc(offsets, indices, weights, membership, resolution: float = 1.0) -> gvl_graph_desc:
+    """Descriptor of one graph held in device tensors (int32 offsets/indices, float32 weights or None)."""
+    return gvl_graph_desc(offsets.numel() - 1, indices.numel(), offsets.data_ptr(),
+                          indices.data_ptr() if indices.numel() else None,
+                          None if weights is None else weights.data_ptr(), float(resolution),
+                          None if membership is None else membership.data_ptr())
+
+
+class Server:
+    """Continuous-batching Leiden server over a device arena (a torch uint8
+    tensor) that holds the workspaces of running requests.
+
+    Inputs must be fully written before ``submit`` (synchronise the stream
+    that produced them); the membership tensor is complete once ``wait``
+    or ``poll`` reports GVL_REQ_DONE.
+    """
+
+    def __init__(self, arena, lanes: int = 4, opt: Optional[gvl_options] = None):
+        self.arena = arena
+        opt = opt if opt is not None else Leiden.options()
+        self.srv = gvl_server_create(arena.device.index or 0, lanes, opt, arena.data_ptr(), arena.numel())
+
+    def submit(self, offsets, indices, weights, membership, resolution: float = 1.0) -> int:
+        return gvl_server_submit(self.srv, graph_desc(offsets, indices, weights, membership, resolution))
+
+    def poll(self, ticket: int) -> gvl_request_info:
+        return gvl_server_poll(self.srv, ticket)
+
+    def wait(self, ticket: int, timeout_ms: int = -1) -> gvl_request_info:
+        return gvl_server_wait(self.srv, ticket, timeout_ms)
+
+    def cancel(self, ticket: int) -> None:
+        gvl_server_cancel(self.srv, ticket)
+
+    def release(self, ticket: int) -> None:
+        gvl_server_release(self.srv, ticket)
+
+    def stats(self) -> gvl_server_info:
+        return gvl_server_stats(self.srv)
+
+    def close(self) -> None:
+        if self.srv is not None:
+            gvl_server_destroy(self.srv)
+            self.srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

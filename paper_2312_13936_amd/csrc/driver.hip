@@ -442,6 +442,8 @@ extern "C" {
 
 const char* gvl_status_string(gvl_status s) {
   switch (s) {
+    case GVL_E_BUSY: return "request busy";
+    case GVL_E_BATCH: return "some graphs of the batch failed";
     case GVL_OK: return "ok";
     case GVL_E_INVALID_ARG: return "invalid argument";
     case GVL_E_BAD_CSR: return "malformed CSR input";
@@ -910,3 +912,6 @@ gvl_status gvl_debug_pass_movers(gvl_ctx_t ctx, int32_t pass, int64_t* movers, i
 }
 
 }  // extern "C"
+
+// Stream of a context (used by the batch runner, same library).
+hipStream_t gvl_context_stream(gvl_ctx_t ctx) { return ctx ? ctx->stream : nullptr; }

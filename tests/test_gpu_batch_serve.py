@@ -1,0 +1,282 @@
+"""GPU tests of batched and served Leiden (many independent graphs on one GPU).
+
+Every graph of a batch, and every request of a served mix, must get the
+result it gets alone: bit-identical membership and modularity in
+deterministic mode (and identical to the oracle's det-sync run), the fast
+mode's quality bar in fast mode.  The server must respect its HBM arena,
+admit requests as memory frees up, overlap requests on the device, reject a
+request that can never fit and cancel one that still waits.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2312_13936_amd as gvl  # noqa: E402
+from test_gpu_parity import relabel  # noqa: E402
+
+FAST_TOL = 1e-3
+# On graphs of a few thousand vertices the sequential oracle's own modularity
+# spreads by up to ~3e-3 across vertex numberings, so a single fast-mode run
+# is held to the 1e-3 bar on the mean over a mix, and each graph to 5e-3.
+FAST_TOL_ONE = 5e-3
+
+
+def lfr_mix(count, lo, hi, seed, mu=0.3, avg_deg=12.0):
+    sizes = gen.lfr_sizes(count, lo, hi, seed)
+    return [gen.lfr(int(n), avg_deg=avg_deg, mu=mu, seed=seed * 1000 + k) for k, n in enumerate(sizes)]
+
+
+def dev(g):
+    d = torch.device("cuda", 0)
+    off = torch.from_numpy(g.offsets.astype(np.int32)).to(d)
+    idx = torch.from_numpy(g.indices.astype(np.int32)).to(d)
+    w = torch.from_numpy(g.weights.astype(np.float32)).to(d)
+    return off, idx, w
+
+
+@pytest.fixture(scope="module")
+def eng():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    e = gvl.Leiden(0)
+    yield e
+    e.close()
+
+
+def solo(eng, g, mode):
+    off, idx, w = dev(g)
+    r = eng.run(off, idx, w, 1.0, eng.options(mode))
+    torch.cuda.synchronize()
+    return r.membership.cpu().numpy(), r.modularity
+
+
+def batch_graphs():
+    gs = lfr_mix(18, 1000, 30000, seed=7)
+    gs += [gen.ring_of_cliques(10, 5), gen.from_edges(2000, [(0, i) for i in range(1, 2000)]),
+           gen.from_edges(500, [(i, i + 1) for i in range(499)]), gen.rmat(12, 16, seed=2),
+           gen.from_edges(7, [])]
+    return gs
+
+
+def run_batch(eng, gs, mode, lanes, corrupt=None):
+    tensors = [dev(g) for g in gs]
+    mems = [torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda") for g in gs]
+    if corrupt is not None:  # a decreasing offset makes that graph's CSR invalid
+        tensors[corrupt][0][1] = tensors[corrupt][0][-1] + 1
+    descs = [gvl.graph_desc(o, i, w, mm) for (o, i, w), mm in zip(tensors, mems)]
+    opt = eng.options(mode)
+    wsb = gvl.gvl_batch_workspace_bytes(descs, opt, lanes)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    code, qs, sts = gvl.gvl_leiden_batch(eng.ctx, descs, opt, lanes, ws.data_ptr(), wsb)
+    torch.cuda.synchronize()
+    return code, [m[:g.n].cpu().numpy() for m, g in zip(mems, gs)], qs, sts
+
+
+@pytest.mark.parametrize("lanes", [1, 4, 8])
+def test_batch_det_matches_solo_and_oracle(eng, lanes):
+    gs = batch_graphs()
+    print("batch det: %d graphs, %d lanes" % (len(gs), lanes), flush=True)
+    code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_DET, lanes)
+    assert code == 0 and all(s == 0 for s in sts)
+    for g, mem, q in zip(gs, mems, qs):
+        m1, q1 = solo(eng, g, gvl.GVL_MODE_DET)
+        assert np.array_equal(mem, m1), g.name
+        assert q == q1, g.name
+        if lanes == 4:
+            o = oracle.leiden(g, mode=oracle.DET_SYNC)
+            assert np.array_equal(mem, o.membership), g.name
+            assert q == o.q, g.name
+
+
+def check_fast_mix(gs, mems, qs):
+    """Fast-mode bar over a mix: every result reports Eq. 1 of its membership
+    and has no disconnected community; the mean modularity is within 1e-3 of
+    the mean of the sequential oracle (over the given and two renumbered
+    orders); each graph is within 5e-3 of the oracle's lowest."""
+    diffs = []
+    for g, mem, q in zip(gs, mems, qs):
+        assert q == oracle.modularity(g, mem), g.name
+        assert oracle.disconnected(g, mem) == 0, g.name
+        if g.m == 0:
+            continue
+        qref = [oracle.leiden(g, mode=oracle.SEQ_ASYNC).q]
+        qref += [oracle.leiden(relabel(g, s), mode=oracle.SEQ_ASYNC).q for s in range(2)]
+        assert q >= min(qref) - FAST_TOL_ONE, "%s: fast Q %.6f vs oracle %.6f" % (g.name, q, min(qref))
+        diffs.append(q - float(np.mean(qref)))
+    assert np.mean(diffs) >= -FAST_TOL, "mean fast-mode Q %.6f below the oracle's" % np.mean(diffs)
+
+
+def test_batch_fast_quality(eng):
+    gs = batch_graphs()
+    print("batch fast: %d graphs" % len(gs), flush=True)
+    code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_FAST, 6)
+    assert code == 0
+    check_fast_mix(gs, mems, qs)
+
+
+def test_batch_bad_graph_in_mix(eng):
+    gs = batch_graphs()[:8]
+    code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_DET, 4, corrupt=3)
+    assert code == -10  # GVL_E_BATCH
+    assert sts[3] == -2 and all(s == 0 for k, s in enumerate(sts) if k != 3)
+    for k, g in enumerate(gs):
+        if k != 3:
+            assert np.array_equal(mems[k], solo(eng, g, gvl.GVL_MODE_DET)[0]), g.name
+
+
+def test_batch_workspace_checks(eng):
+    gs = batch_graphs()[:3]
+    tensors = [dev(g) for g in gs]
+    mems = [torch.empty(g.n, dtype=torch.int32, device="cuda") for g in gs]
+    descs = [gvl.graph_desc(o, i, w, mm) for (o, i, w), mm in zip(tensors, mems)]
+    opt = eng.options(gvl.GVL_MODE_DET)
+    wsb = gvl.gvl_batch_workspace_bytes(descs, opt, 2)
+    assert wsb == 2 * max(-(-gvl.gvl_workspace_bytes(g.n, g.m, opt) // 256) * 256 for g in gs)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gvl.GvlError) as e:
+        gvl.gvl_leiden_batch(eng.ctx, descs, opt, 2, ws.data_ptr(), wsb - 1)
+    assert e.value.code == -6
+    code, qs, sts = gvl.gvl_leiden_batch(eng.ctx, [], opt, 2, ws.data_ptr(), wsb)
+    assert code == 0 and qs == []
+
+
+# ------------------------------------------------------------------ serving ---
+
+WAIT_MS = 60000  # a request that is not done by then fails the test (GVL_E_BUSY)
+
+
+def footprint(g, opt):
+    return -(-gvl.gvl_workspace_bytes(g.n, g.m, opt) // 256) * 256
+
+
+def serve(gs, tensors, mode, lanes, arena_bytes, alone):
+    opt = gvl.Leiden.options(mode)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    mems = [torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda") for g in gs]
+    torch.cuda.synchronize()
+    srv = gvl.Server(arena, lanes, opt)
+    out = []
+    try:
+        if alone:
+            for g, (o, i, w), mm in zip(gs, tensors, mems):
+                t = srv.submit(o, i, w, mm)
+                info = srv.wait(t, WAIT_MS)
+                assert info.state == gvl.GVL_REQ_DONE and info.result == 0
+                out.append((mm[:g.n].cpu().numpy(), info.modularity))
+                srv.release(t)
+        else:
+            tickets = [srv.submit(o, i, w, mm) for (o, i, w), mm in zip(tensors, mems)]
+            for g, t, mm in zip(gs, tickets, mems):
+                info = srv.wait(t, WAIT_MS)
+                assert info.state == gvl.GVL_REQ_DONE and info.result == 0
+                assert info.latency_ms >= info.queue_ms >= 0
+                out.append((mm[:g.n].cpu().numpy(), info.modularity))
+                srv.release(t)
+        st = srv.stats()
+    finally:
+        srv.close()
+    return out, st
+
+
+def test_serve_alone_vs_mix_det(eng):
+    gs = lfr_mix(16, 2000, 60000, seed=11, avg_deg=16.0)
+    tensors = [dev(g) for g in gs]
+    opt = gvl.Leiden.options(gvl.GVL_MODE_DET)
+    arena = 8 * max(footprint(g, opt) for g in gs)
+    print("serve det: %d requests, arena %d MB" % (len(gs), arena >> 20), flush=True)
+    alone, _ = serve(gs, tensors, gvl.GVL_MODE_DET, 4, arena, alone=True)
+    mix, st = serve(gs, tensors, gvl.GVL_MODE_DET, 4, arena, alone=False)
+    for g, (m1, q1), (m2, q2) in zip(gs, alone, mix):
+        assert np.array_equal(m1, m2), g.name
+        assert q1 == q2, g.name
+    for g, (m, q) in zip(gs[:6], mix[:6]):
+        o = oracle.leiden(g, mode=oracle.DET_SYNC)
+        assert np.array_equal(m, o.membership) and q == o.q, g.name
+    assert st.completed == len(gs) and st.pending == 0 and st.running == 0
+    assert st.max_running >= 2  # requests overlapped on the device
+    assert st.arena_peak <= st.arena_bytes and st.arena_used == 0
+
+
+def test_serve_mix_fast_quality(eng):
+    gs = lfr_mix(10, 2000, 40000, seed=12, avg_deg=16.0)
+    tensors = [dev(g) for g in gs]
+    opt = gvl.Leiden.options(gvl.GVL_MODE_FAST)
+    arena = 6 * max(footprint(g, opt) for g in gs)
+    print("serve fast: %d requests" % len(gs), flush=True)
+    alone, _ = serve(gs, tensors, gvl.GVL_MODE_FAST, 4, arena, alone=True)
+    mix, st = serve(gs, tensors, gvl.GVL_MODE_FAST, 4, arena, alone=False)
+    check_fast_mix(gs, [m for m, _ in mix], [q for _, q in mix])
+    # fast mode commits moves asynchronously, so a result may differ between
+    # runs, alone or in the mix; its modularity stays within the same bar
+    dq = np.array([q2 - q1 for (_, q1), (_, q2) in zip(alone, mix)])
+    assert np.all(np.abs(dq) <= FAST_TOL_ONE) and abs(dq.mean()) <= FAST_TOL, dq
+
+
+def test_serve_admission_by_footprint(eng):
+    # an arena that holds two of these workspaces at a time: the rest wait
+    # and are admitted as earlier requests finish
+    gs = lfr_mix(8, 20000, 30000, seed=13)
+    tensors = [dev(g) for g in gs]
+    opt = gvl.Leiden.options(gvl.GVL_MODE_DET)
+    fp = max(footprint(g, opt) for g in gs)
+    print("serve admission: arena %.1f workspaces" % 2.5, flush=True)
+    mix, st = serve(gs, tensors, gvl.GVL_MODE_DET, 4, 2 * fp + fp // 2, alone=False)
+    assert st.max_running <= 2
+    assert st.arena_peak <= st.arena_bytes
+    for g, (m, q) in zip(gs, mix):
+        m1, q1 = solo(eng, g, gvl.GVL_MODE_DET)
+        assert np.array_equal(m, m1) and q == q1, g.name
+
+
+def test_serve_errors_and_cancel(eng):
+    big = gen.lfr(60000, seed=21)
+    small = gen.lfr(3000, seed=22)
+    tb, ts = dev(big), dev(small)
+    mb = torch.empty(big.n, dtype=torch.int32, device="cuda")
+    ms = [torch.empty(small.n, dtype=torch.int32, device="cuda") for _ in range(2)]
+    opt = gvl.Leiden.options(gvl.GVL_MODE_DET)
+    arena = torch.empty(footprint(big, opt) + 4096, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    print("serve errors and cancel", flush=True)
+    srv = gvl.Server(arena, 1, opt)
+    try:
+        # a request whose workspace can never fit is refused at submission
+        huge = gvl.gvl_graph_desc(big.n * 4, big.m * 4, tb[0].data_ptr(), tb[1].data_ptr(), tb[2].data_ptr(), 1.0,
+                                  mb.data_ptr())
+        with pytest.raises(gvl.GvlError) as e:
+            gvl.gvl_server_submit(srv.srv, huge)
+        assert e.value.code == -6
+        nomem = gvl.gvl_graph_desc(small.n, small.m, ts[0].data_ptr(), ts[1].data_ptr(), None, 1.0, None)
+        with pytest.raises(gvl.GvlError) as e:
+            gvl.gvl_server_submit(srv.srv, nomem)
+        assert e.value.code == -1
+        t1 = srv.submit(*tb, mb)
+        t2 = srv.submit(*ts, ms[0])
+        t3 = srv.submit(*ts, ms[1])
+        # one lane: t3 still waits unless t1 and t2 have both finished already
+        try:
+            srv.cancel(t3)
+            cancelled = True
+        except gvl.GvlError as e:
+            assert e.code == -9
+            cancelled = False
+        i1, i2, i3 = srv.wait(t1, WAIT_MS), srv.wait(t2, WAIT_MS), srv.wait(t3, WAIT_MS)
+        assert i1.state == gvl.GVL_REQ_DONE and i2.state == gvl.GVL_REQ_DONE
+        assert i3.state == (gvl.GVL_REQ_CANCELLED if cancelled else gvl.GVL_REQ_DONE)
+        with pytest.raises(gvl.GvlError) as e:
+            srv.cancel(t1)  # already done
+        assert e.value.code == -9
+        assert np.array_equal(mb.cpu().numpy(), solo(eng, big, gvl.GVL_MODE_DET)[0])
+        assert np.array_equal(ms[0].cpu().numpy(), solo(eng, small, gvl.GVL_MODE_DET)[0])
+        for t in (t1, t2, t3):
+            srv.release(t)
+        with pytest.raises(gvl.GvlError) as e:
+            srv.poll(t1)  # released
+        assert e.value.code == -1
+        assert srv.stats().arena_used == 0
+    finally:
+        srv.close()
