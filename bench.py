@@ -23,6 +23,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Leiden edges/s at matched modularity; batched graphs/s vs plain; p99 latency"
+# rocprofv3 FETCH_SIZE / WRITE_SIZE of one step of the default workload (fast
+# mode), valid while the kernel sources are unchanged
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "leiden_rmat_s24_fast_counters.md")
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -301,6 +304,9 @@ def main():
     ap.add_argument("--subsweeps", type=int, default=0, help="0 = library default")
     ap.add_argument("--cpu-sample-scale", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed region "
+                         "(a kernel of known traffic for scaling profiler byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -328,6 +334,14 @@ def main():
     wt = torch.from_numpy(g.weights).to(dev)
     torch.cuda.synchronize()
 
+    if args.copy_calibration_mib:
+        nb = args.copy_calibration_mib << 20
+        src = torch.ones(nb, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: %d bytes read, %d bytes written" % (nb, nb))
+        del src, dst
     eng = gvl.Leiden(0)
     mode = gvl.GVL_MODE_DET if args.mode == "det" else gvl.GVL_MODE_FAST
     kw = dict(profile=1)
@@ -354,6 +368,12 @@ def main():
     total = time.perf_counter() - t_all
     ms_per_step = 1e3 * total / args.steps
     value = g.m / (total / args.steps)
+
+    from paper_2312_13936_amd.profile_summary import recorded_traffic
+    rec = recorded_traffic(COUNTERS_FILE) if (args.workload == "rmat-s24" and args.mode == "fast") else None
+
+    def traffic(cls):
+        return None if rec is None else rec[cls + "_fetch_bytes"] + rec[cls + "_write_bytes"]
 
     # roofline of the dominant kernel class (neighbour-community scan)
     sb = sum(scan_bytes(s) for s in stats)
@@ -390,11 +410,13 @@ def main():
         "phases": phase,
         "roofline": {"bound": "hbm", "kernel": "neighbour-community scan (k_decide_*: local-moving + refinement)",
                      "achieved": scan_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": scan_gbs / HBM_PEAK_GBS, "traffic": None,
+                     "frac": scan_gbs / HBM_PEAK_GBS, "traffic": traffic("scan"),
+                     "traffic_unit": "bytes per step (fetched + written, rocprofv3 counters)",
                      "algorithmic_bytes_per_step": sb / len(stats),
                      "kernel_ms_per_step": sms / len(stats)},
         "roofline_aggregation": {"bound": "hbm", "kernel": "super-vertex rows (k_agg_*)", "achieved": agg_gbs,
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": agg_gbs / HBM_PEAK_GBS,
+                                 "traffic": traffic("agg"),
                                  "algorithmic_bytes_per_step": ab / len(stats),
                                  "kernel_ms_per_step": ams / len(stats)},
         "cpu_baseline": None,

@@ -60,13 +60,18 @@ typedef struct {
   double aggregation_tolerance;  /* stop when |Gamma| / |V'| exceeds this (Alg. 1) */
   int32_t max_iterations;        /* cap on local-moving iterations per pass */
   int32_t max_passes;            /* cap on passes */
-  int32_t refine_sweeps;         /* cap on synchronous refinement sweeps per pass */
+  int32_t refine_sweeps;         /* cap on synchronous refinement sweeps per pass; sweeps stop
+                                    early once one moves no vertex (1 = the single sweep of Alg. 3) */
   int32_t subsweeps;             /* S <= 64: local-moving and refinement visit the vertices in S
                                     pseudo-random groups in turn (sub-sweeps) */
   int32_t validate;              /* 0: none; 1: CSR bounds and weight checks on the device */
   int32_t profile;               /* 1: time every kernel class with HIP events (fills gvl_stats ms_*) */
   int32_t debug_trace;           /* 1: keep per-pass labels and super-vertex CSRs for gvl_debug_* */
-  int32_t reserved[7];
+  int32_t sync_moves;            /* fast mode local-moving: 0 commits every move at once
+                                    (asynchronous); bit 0 (rows of <= 128 arcs) and bit 1 (longer
+                                    rows) instead decide the group on one snapshot and commit it
+                                    afterwards (the deterministic schedule, FP64 gains) */
+  int32_t reserved[6];
 } gvl_options;
 
 #define GVL_MAX_PASS_STATS 64

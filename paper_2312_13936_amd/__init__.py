@@ -42,7 +42,8 @@ class gvl_options(ctypes.Structure):
                 ("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
-                ("debug_trace", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+                ("debug_trace", ctypes.c_int32), ("sync_moves", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 _P = GVL_MAX_PASS_STATS

@@ -140,6 +140,32 @@ __device__ __forceinline__ void lds_insert(int32_t* keys, double* vals, int lg, 
   }
 }
 
+// As lds_insert, but gives up after probing every slot once (full table):
+// returns false then.
+__device__ __forceinline__ bool lds_insert_bounded(int32_t* keys, double* vals, int lg, int32_t c, double w) {
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t h = hslot(c, lg);
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    int32_t k = keys[h];
+    if (k == c) { atomicAdd(&vals[h], w); return true; }
+    if (k == kEmpty) {
+      int32_t old = atomicCAS(&keys[h], kEmpty, c);
+      if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return true; }
+    }
+    h = (h + 1u) & mask;
+  }
+  return false;
+}
+
+// Partition hash of a community id for wide rows (Wellons' "lowbias32"
+// integer mixer); independent of hslot, which takes the high bits of a
+// multiplicative hash.
+__device__ __forceinline__ uint32_t wide_part(int32_t c) {
+  uint32_t h = (uint32_t)c;
+  h ^= h >> 16; h *= 0x7feb352du; h ^= h >> 15; h *= 0x846ca68bu; h ^= h >> 16;
+  return h;
+}
+
 __device__ __forceinline__ double lds_lookup(const int32_t* keys, const double* vals, int lg, int32_t c) {
   const uint32_t mask = (1u << lg) - 1u;
   uint32_t h = hslot(c, lg);
@@ -193,6 +219,27 @@ __device__ __forceinline__ double glb_lookup(const int32_t* keys, const double* 
     if (k == kEmpty) return 0.0;
     h = (h + 1u) & mask;
   }
+}
+
+// p[key] += v for every active lane.  Lanes of the wavefront that share the
+// key of the first remaining active lane are summed into one atomic (two
+// rounds), which takes the load off the address of a giant community; the
+// rest add one by one.  Must be reached by the whole wavefront.
+template <class T>
+__device__ __forceinline__ void atomic_add_keyed(T* p, int32_t key, T v, bool active) {
+  u64 rem = __ballot(active);
+#pragma unroll
+  for (int round = 0; round < 2; ++round) {
+    if (!rem) break;
+    const int leader = __ffsll((unsigned long long)rem) - 1;
+    const int32_t k0 = __shfl(key, leader);
+    const bool mine = ((rem >> lane_id()) & 1) && key == k0;
+    const u64 m = __ballot(mine);
+    const T part = sum_xor<kWave>(mine ? v : T(0));
+    if (lane_id() == leader) atomicAdd(&p[k0], part);
+    rem &= ~m;
+  }
+  if ((rem >> lane_id()) & 1) atomicAdd(&p[key], v);
 }
 
 // Sub-sweep group of vertex i: MurmurHash3's 32-bit finalizer of i, mod S.

@@ -63,6 +63,12 @@ struct Workspace {
   i128_t* pb_k;
   int32_t* pb_c;
   int64_t max_tasks;
+  // wide rows
+  double* wd_g;
+  i128_t* wd_k;
+  int32_t *wd_c, *wd_ok, *wd_done;
+  int64_t max_wide;
+
   Scalars* sc;
   BinBuf* bb;
   size_t bytes;
@@ -125,6 +131,14 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base) {
   w.pb_g = (double*)take(8 * (size_t)w.max_tasks);
   w.pb_k = (i128_t*)take(16 * (size_t)w.max_tasks);
   w.pb_c = (int32_t*)take(4 * (size_t)w.max_tasks);
+  // vertices of the wide bins: degree > kBinMax[5]
+  w.max_wide = std::min<int64_t>((int64_t)N, (int64_t)M / (kBinMax[5] + 1) + 1);
+  const size_t wq = (size_t)w.max_wide * kWideMaxParts;
+  w.wd_g = (double*)take(8 * wq);
+  w.wd_k = (i128_t*)take(16 * wq);
+  w.wd_c = (int32_t*)take(4 * wq);
+  w.wd_ok = (int32_t*)take(4 * wq);
+  w.wd_done = (int32_t*)take(4 * (size_t)w.max_wide);
   w.bytes = o;
   return w;
 }
@@ -225,10 +239,10 @@ gvl_status readback(gvl_ctx* ctx, Scalars* dev) {
 // `list`: bins 0..kHubBin-1 of every group (group-major), then the hub bin
 // of every group in group order.
 gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int32_t* deg, int64_t n, int S,
-                     BinInfo& bins) {
+                     bool wide, BinInfo& bins) {
   hipStream_t st = ctx->stream;
   fill_i32(st, (int32_t*)ws.bb, 0, (int64_t)(sizeof(BinBuf) / sizeof(int32_t)));
-  bin_count(st, off, deg, n, S, ws.bb);
+  bin_count(st, off, deg, n, S, wide, ws.bb);
   HIP_TRY(hipMemcpyAsync(ctx->hbins, ws.bb, sizeof(BinBuf), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   bins.S = S;
@@ -256,7 +270,7 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
   for (int b = 0; b < kNumBins; ++b) bins.maxsize[b] = ctx->hbins->maxsize[b];
   HIP_TRY(hipMemcpyAsync(ws.bb->cursors, ctx->hbins->cursors, sizeof(int32_t) * S * kNumBins,
                          hipMemcpyHostToDevice, st));
-  bin_scatter(st, off, deg, n, S, ws.bb, ws.list);
+  bin_scatter(st, off, deg, n, S, wide, ws.bb, ws.list);
   return GVL_OK;
 }
 
@@ -400,7 +414,7 @@ gvl_status modularity_device(gvl_ctx* ctx, Workspace& ws, const GraphDesc& in, c
                              double W, bool integral, double gamma, double* q) {
   hipStream_t st = ctx->stream;
   BinInfo bins;
-  gvl_status s = make_bins(ctx, ws, in.off, in.deg, in.n, 1, bins);
+  gvl_status s = make_bins(ctx, ws, in.off, in.deg, in.n, 1, true, bins);
   if (s != GVL_OK) return s;
   HubPlan plan;
   s = build_hub_plan(ctx, ws, bins, false, in, nullptr, 0, plan);
@@ -525,7 +539,7 @@ gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_
   if (s != GVL_OK) return s;
   if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
   BinInfo bins;
-  s = make_bins(ctx, ws, d_off, nullptr, n, 1, bins);
+  s = make_bins(ctx, ws, d_off, nullptr, n, 1, true, bins);
   if (s != GVL_OK) return s;
   HubPlan plan;
   s = build_hub_plan(ctx, ws, bins, false, in, nullptr, 0, plan);
@@ -568,6 +582,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   fill_u64(st, (unsigned long long*)ws.sc, 0ull, sizeof(Scalars) / 8);
   fill_i32(st, ws.hp_done, 0, n);
   fill_i32(st, ws.hp_lcnt, 0, n);
+  fill_i32(st, ws.wd_done, 0, ws.max_wide);
   if (opt->validate) {
     check_offsets(st, d_off, n, m, ws.sc->flags);
     s = readback(ctx, ws.sc);
@@ -581,6 +596,9 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.tbl_keys = ws.tbl_keys; a.tbl_vals = ws.tbl_vals;
+  a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
+  const bool sync_mv = det || opt->sync_moves != 0;
+  a.sync_moves = det ? 3 : (opt->sync_moves & 3);
 
   // grids are capped near the number of resident workgroups (256 CUs x 8)
   const int grid_cap = 2048;
@@ -604,7 +622,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     // ---- 1. degree bins, hub plan, vertex weights K', initial labels
     h = tm.begin(kEvOther);
     BinInfo bins;
-    s = make_bins(ctx, ws, cur.off, cur.deg, nn, opt->subsweeps, bins);
+    s = make_bins(ctx, ws, cur.off, cur.deg, nn, opt->subsweeps, true, bins);
     if (s != GVL_OK) return s;
     HubPlan plan;
     s = build_hub_plan(ctx, ws, bins, false, cur, nullptr, 0, plan);
@@ -626,7 +644,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         p = (long long)pd_;
       }
       if (Wd == 0.0) {
-        iota_i32(st, top, n);
+        iota_i32(st, d_membership, n);
         HIP_TRY(hipStreamSynchronize(st));
         S->termination = 3;
         S->num_communities = n;
@@ -678,8 +696,11 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       const int32_t* l1 = ws.list + bins.start[grp][kHubBin];
       const int32_t n1 = bins.count[grp][kHubBin];
       if (phase == kMove) {
-        launch_commit_move(st, cur, a, l0, n0);
-        launch_commit_move(st, cur, a, l1, n1);
+        // rows of at most kBinMax[4] arcs, longer rows, hubs
+        const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];
+        launch_commit_move(st, cur, a, l0, n0s, false);
+        launch_commit_move(st, cur, a, l0 + n0s, n0 - n0s, true);
+        launch_commit_move(st, cur, a, l1, n1, true);
       } else {
         launch_commit_refine(st, cur, a, l0, n0);
         launch_commit_refine(st, cur, a, l1, n1);
@@ -694,16 +715,16 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     bool first_conv = false;
     for (int32_t it = 0; it < opt->max_iterations; ++it) {
       fill_u64(st, (unsigned long long*)ws.sc->dq, 0ull, 3 * kCntSlots);
-      int hk = det ? -1 : tm.begin(kEvScanMoveK);
+      int hk = sync_mv ? -1 : tm.begin(kEvScanMoveK);
       for (int32_t grp = 0; grp < bins.S; ++grp) {
-        if (det) hk = tm.begin(kEvScanMoveK);
+        if (sync_mv) hk = tm.begin(kEvScanMoveK);
         decide_group(grp, kMove);
-        if (det) {
+        if (sync_mv) {
           tm.end(hk);
           commit_group(grp, kMove);
         }
       }
-      if (!det) tm.end(hk);
+      if (!sync_mv) tm.end(hk);
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
       ++iters;
@@ -803,7 +824,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       agg_fill(st, ws.lab, ws.rank, ws.cnt, nn, ws.cv);
       fill_i32(st, ydeg, 0, ncom);
       BinInfo cb;
-      s = make_bins(ctx, ws, yoff, nullptr, ncom, 1, cb);
+      s = make_bins(ctx, ws, yoff, nullptr, ncom, 1, false, cb);
       if (s != GVL_OK) return s;
       HubPlan gp;
       s = build_hub_plan(ctx, ws, cb, true, cur, yoff, ncom, gp);

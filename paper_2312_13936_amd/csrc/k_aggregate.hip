@@ -38,6 +38,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
   for (int64_t v = (int64_t)blockIdx.x * GPB + gb; v < count; v += (int64_t)gridDim.x * GPB) {
     const int32_t c = list[v];
     const int32_t mb = a.coff[c], me = a.coff[c + 1];
+    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
     // members with short rows: one lane each
     for (int32_t k = mb + gl; k < me; k += G) {
       const int32_t i = a.cv[k];
@@ -45,8 +46,11 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
       ++nv;
       if (deg >= G) continue;
       na += (unsigned long long)deg;
-      for (int32_t e = 0; e < deg; ++e)
-        lds_insert(keys, vals, LG, a.lab[g.idx[beg + e]], g.weight(beg + e));
+      for (int32_t e = 0; e < deg; ++e) {
+        const int32_t d = a.lab[g.idx[beg + e]];
+        if (d == c) self += g.weight(beg + e);
+        else lds_insert(keys, vals, LG, d, g.weight(beg + e));
+      }
     }
     // members with long rows: the whole group
     for (int32_t kb = mb; kb < me; kb += G) {
@@ -60,10 +64,16 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
         const int32_t ii = __shfl(i, q, G);
         const int32_t beg = g.begin(ii), deg = g.degree(ii);
         if (gl == 0) na += (unsigned long long)deg;
-        for (int32_t e = gl; e < deg; e += G)
-          lds_insert(keys, vals, LG, a.lab[g.idx[beg + e]], g.weight(beg + e));
+        for (int32_t e = gl; e < deg; e += G) {
+          const int32_t d = a.lab[g.idx[beg + e]];
+          if (d == c) self += g.weight(beg + e);
+          else lds_insert(keys, vals, LG, d, g.weight(beg + e));
+        }
       }
     }
+    self = sum_xor<G>(self);
+    wave_sync();
+    if (gl == 0 && self != 0.0) lds_insert(keys, vals, LG, c, self);
     wave_sync();
     // emit the row: group exclusive scan of per-lane occupied counts
     int cnt = 0;
@@ -110,6 +120,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
   __shared__ double svals[TS];
   __shared__ int s_wsum[kBlock / kWave];
   __shared__ unsigned long long red_u[16];
+  __shared__ double s_red[kBlock / kWave];
   int32_t* keys = GLB ? a.tbl_keys + (int64_t)blockIdx.x * a.tbl_slot : skeys;
   double* vals = GLB ? a.tbl_vals + (int64_t)blockIdx.x * a.tbl_slot : svals;
   WTout* yw = (WTout*)a.yw;
@@ -130,6 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
       __syncthreads();
     }
     const int ts = 1 << lg;
+    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
     for (int32_t kb = mb; kb < me; kb += kBlock) {
       const int32_t k = kb + threadIdx.x;
       const int32_t i = (k < me) ? a.cv[k] : 0;
@@ -140,7 +152,8 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
         na += (unsigned long long)deg;
         for (int32_t e = 0; e < deg; ++e) {
           const int32_t d = a.lab[g.idx[beg + e]];
-          if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
+          if (d == c) self += g.weight(beg + e);
+          else if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
           else lds_insert(keys, vals, lg, d, g.weight(beg + e));
         }
       }
@@ -153,10 +166,16 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
         if (lane_id() == 0) na += (unsigned long long)dg;
         for (int32_t e = lane_id(); e < dg; e += kWave) {
           const int32_t d = a.lab[g.idx[beg + e]];
-          if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
+          if (d == c) self += g.weight(beg + e);
+          else if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
           else lds_insert(keys, vals, lg, d, g.weight(beg + e));
         }
       }
+    }
+    self = block_sum<double>(self, s_red);
+    if (threadIdx.x == 0 && self != 0.0) {
+      if (GLB) glb_insert(keys, vals, lg, c, self);
+      else lds_insert(keys, vals, lg, c, self);
     }
     __syncthreads();
     // emit: block exclusive scan of per-thread occupied counts

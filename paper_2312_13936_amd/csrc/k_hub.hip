@@ -99,6 +99,7 @@ __global__ void k_hub_prep(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
     const int32_t i = h.items[p];
     const bool act = Decide<PH, DET>::eligible(a, i);
     h.active[p] = act ? 1 : 0;
+    h.kid[p] = 0.0;
     if (PH == kMove && act) a.flag[i] = 0;  // processed (Alg. 2 prune)
   }
 }
@@ -142,6 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
   __shared__ double svals[TS];
   __shared__ int32_t snew[kHubChunk];
   __shared__ int s_nnew, s_base;
+  __shared__ double s_red[kBlock / kWave];
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -154,27 +156,22 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
     const int32_t e0 = task.y * kHubChunk;
     const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
-    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      const int32_t j = g.idx[beg + e];
-      if (j == i) continue;
-      if (PH == kRefine && a.CB[j] != bi) continue;
-      lds_insert(skeys, svals, kHubGatherLg, a.C[j], g.weight(beg + e));
+    const int32_t d = a.C[i];
+    // arcs to the hub's own community are summed apart into kid[p]
+    double kid = scan_row<4, kBlock, PH>(g, a, i, beg, e1, e0 + threadIdx.x, d, bi, [&](int32_t c, double w) {
+      lds_insert(skeys, svals, kHubGatherLg, c, w);
+    });
+    kid = block_sum<double>(kid, s_red);
+    if (threadIdx.x == 0) {
+      na += (unsigned long long)(e1 - e0);
+      if (kid != 0.0) atomicAdd(&h.kid[p], kid);
     }
-    if (threadIdx.x == 0) na += (unsigned long long)(e1 - e0);
     __syncthreads();
     flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
   }
   if (threadIdx.x == 0 && na) {
     atomicAdd(&cnt_of(a.cnt)[1], na);
     if (PH == kRefine) atomicAdd(&cnt_of(a.cnt)[7], na);
-  }
-}
-
-__global__ void k_hub_kid(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
-  for (int64_t p = h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += (int64_t)gridDim.x * blockDim.x) {
-    if (!h.active[p]) continue;
-    const int32_t i = h.items[p];
-    h.kid[p] = glb_lookup(tbl_keys_of(h, (int32_t)p), tbl_vals_of(h, (int32_t)p), tbl_lg(h, (int32_t)p), a.C[i]);
   }
 }
 
@@ -261,7 +258,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
         const bool take = accept<PH, DET>(a, d, bc, bg, bk);
         s_take = take ? 1 : 0;
         if (take) {
-          if (PH == kMove && !DET) {
+          if (PH == kMove && !DET && !(a.sync_moves & 2)) {
             atomicAdd(&a.Sig[d], -ki);
             atomicAdd(&a.Sig[bc], ki);
             atomicSub(&a.size[d], 1);
@@ -271,7 +268,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
             ++nm;
           } else if (PH == kMove) {
             a.target[i] = bc;
-            dqk += bk;
+            if (DET) dqk += bk; else dq += bg;
           } else {
             a.target[i] = bc;
             a.targeted[bc] = 1;
@@ -279,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
         }
       }
       __syncthreads();
-      if (PH == kMove && !DET && s_take) {
+      if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) {
         const int32_t beg = g.begin(i), deg = g.degree(i);
         for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
           const int32_t j = g.idx[beg + e];
@@ -310,11 +307,10 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
   if (c1 > c0)
     hipLaunchKernelGGL((k_hub_gather<WT, PH>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g, a, h, c0,
                        c1);
-  hipLaunchKernelGGL(k_hub_kid, dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
   if (s1 > s0)
     hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a, h,
                        s0, s1);
-  *launches += 4;
+  *launches += 3;
 }
 
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
@@ -436,6 +432,7 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
   __shared__ double svals[TS];
   __shared__ int32_t snew[kHubChunk];
   __shared__ int s_nnew, s_base;
+  __shared__ double s_red[kBlock / kWave];
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -446,6 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     const int32_t mb = a.coff[c], me = a.coff[c + 1];
     const int64_t cend = h.apre[me];
     const int64_t A0 = (int64_t)h.apre[mb] + (int64_t)task.y * kHubChunk;
+    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
     int64_t pos = A0 + (int64_t)threadIdx.x * PER;
     int64_t end = pos + PER;
     if (end > cend) end = cend;
@@ -465,14 +463,17 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
         if (take > end - pos) take = end - pos;
         for (int64_t x = 0; x < take; ++x) {
           const int64_t e = beg + r0 + x;
-          lds_insert(skeys, svals, kHubGatherLg, a.lab[g.idx[e]], g.weight(e));
+          const int32_t dl = a.lab[g.idx[e]];
+          if (dl == c) self += g.weight(e);
+          else lds_insert(skeys, svals, kHubGatherLg, dl, g.weight(e));
         }
         na += (unsigned long long)take;
         pos += take;
         ++k;
       }
     }
-    __syncthreads();
+    self = block_sum<double>(self, s_red);
+    if (threadIdx.x == 0 && self != 0.0) lds_insert(skeys, svals, kHubGatherLg, c, self);
     flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
   }
   __shared__ unsigned long long red_u[16];

@@ -137,10 +137,12 @@ __global__ void k_check_offsets(const int32_t* off, int64_t n, int64_t m, int32_
 // ------------------------------------------------------- community totals ---
 __global__ void k_community_totals(const int32_t* C, const double* K, double* Sig, int32_t* size,
                                    int64_t n) {
-  GRID_STRIDE(i, n) {
-    const int32_t c = C[i];
-    atomicAdd(&Sig[c], K[i]);
-    atomicAdd(&size[c], 1);
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = base + threadIdx.x;
+    const bool ok = i < n;
+    const int32_t c = ok ? C[i] : 0;
+    atomic_add_keyed<double>(Sig, c, ok ? K[i] : 0.0, ok);
+    atomic_add_keyed<int32_t>(size, c, 1, ok);
   }
 }
 void community_totals(hipStream_t st, const int32_t* C, const double* K, double* Sig, int32_t* size,
@@ -149,12 +151,14 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
 }
 
 // ---------------------------------------------------------------- binning ---
-__device__ __forceinline__ int bin_of(int32_t d) {
+__device__ __forceinline__ int bin_of(int32_t d, bool wide) {
   if (d <= 0) return -1;
 #pragma unroll
-  for (int b = 0; b < kNumBins; ++b)
+  for (int b = 0; b < kNumBins; ++b) {
+    if (!wide && b == kWideBin0) return kHubBin;
     if (d <= kBinMax[b]) return b;
-  return kNumBins - 1;
+  }
+  return kHubBin;
 }
 
 __device__ __forceinline__ int32_t size_of(const int32_t* off, const int32_t* deg, int64_t i) {
@@ -164,7 +168,7 @@ __device__ __forceinline__ int32_t size_of(const int32_t* off, const int32_t* de
 // Binning key of item i: group_of(i, S) * kNumBins + bin(size).  Counts
 // per key and the largest size per bin go to bb.
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const int32_t* deg, int64_t n, int S,
-                                                      BinBuf* bb) {
+                                                      bool wide, BinBuf* bb) {
   __shared__ int32_t h[kMaxGroups * kNumBins], mx[kNumBins];
   const int nk = S * kNumBins;
   for (int k = threadIdx.x; k < nk; k += kBlock) h[k] = 0;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
   __syncthreads();
   GRID_STRIDE(i, n) {
     const int32_t d = size_of(off, deg, i);
-    const int b = bin_of(d);
+    const int b = bin_of(d, wide);
     if (b >= 0) {
       const int grp = (S > 1) ? group_of(i, S) : 0;
       atomicAdd(&h[grp * kNumBins + b], 1);
@@ -184,8 +188,9 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
     if (h[k]) atomicAdd(&bb->counts[k], h[k]);
   if (threadIdx.x < kNumBins && mx[threadIdx.x]) atomicMax(&bb->maxsize[threadIdx.x], mx[threadIdx.x]);
 }
-void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, BinBuf* bb) {
-  if (n > 0) hipLaunchKernelGGL(k_bin_count, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, st, off, deg, n, S, bb);
+void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb) {
+  if (n > 0)
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, st, off, deg, n, S, wide, bb);
 }
 
 // Each workgroup takes a contiguous chunk of items, reserves room per key
@@ -193,7 +198,7 @@ void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n
 // that rows of consecutive list entries sit close together in memory).
 constexpr int kBinChunk = 4096;
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, const int32_t* deg, int64_t n, int S,
-                                                        BinBuf* bb, int32_t* list) {
+                                                        bool wide, BinBuf* bb, int32_t* list) {
   __shared__ int32_t h[kMaxGroups * kNumBins], base[kMaxGroups * kNumBins];
   const int nk = S * kNumBins;
   for (int64_t c0 = (int64_t)blockIdx.x * kBinChunk; c0 < n; c0 += (int64_t)gridDim.x * kBinChunk) {
@@ -201,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     __syncthreads();
     const int64_t c1 = (c0 + kBinChunk < n) ? c0 + kBinChunk : n;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-      const int b = bin_of(size_of(off, deg, i));
+      const int b = bin_of(size_of(off, deg, i), wide);
       if (b >= 0) atomicAdd(&h[((S > 1) ? group_of(i, S) : 0) * kNumBins + b], 1);
     }
     __syncthreads();
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     }
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-      const int b = bin_of(size_of(off, deg, i));
+      const int b = bin_of(size_of(off, deg, i), wide);
       if (b >= 0) {
         const int k = ((S > 1) ? group_of(i, S) : 0) * kNumBins + b;
         list[base[k] + atomicAdd(&h[k], 1)] = (int32_t)i;
@@ -220,11 +225,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     __syncthreads();
   }
 }
-void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, BinBuf* bb,
+void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb,
                  int32_t* list) {
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_n(n, kBinChunk, 2048)), dim3(kBlock), 0, st, off, deg, n, S,
-                       bb, list);
+                       wide, bb, list);
 }
 
 // ---------------------------------------------------------- exclusive scan ---
@@ -452,10 +457,8 @@ __global__ __launch_bounds__(kBlock) void k_mod_partial(GraphView<WT> g, const i
       ps = sum_xor<kWave>(ps);
       if (lane_id() == q) { k = pk; sg = ps; }
     }
-    if (i < n) {
-      if (k != 0.0) atomicAdd(&tot[ci], k);
-      s1 += sg;
-    }
+    atomic_add_keyed<double>(tot, ci, k, i < n && k != 0.0);
+    if (i < n) s1 += sg;
   }
   const double t = block_sum<double>(s1, red);
   if (threadIdx.x == 0) atomicAdd(&acc_d[0], t);

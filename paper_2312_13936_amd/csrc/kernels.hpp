@@ -19,12 +19,19 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 // of degree d (or a community whose member arcs total d) goes to the first
 // bin with d <= kBinMax[b]; d == 0 is never binned.  Bins 0-4 map a group of
 // kBinLanes[b] lanes of one wavefront to each item with an LDS hash table of
-// 2^kBinLg[b] slots; bin 5 maps a 256-thread workgroup with an LDS table;
-// bin 6 (hubs / giant communities) a workgroup with a global-memory table.
-constexpr int kNumBins = 7;
-constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 0x7fffffff};
-constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 256};
-constexpr int kBinLg[kNumBins] = {3, 4, 5, 6, 8, 11, 0};
+// 2^kBinLg[b] slots; bin 5 maps a 256-thread workgroup with an LDS table.
+// Bins 6-8 ("wide" rows, vertex scan only) map 1, 2 or 4 workgroups of 1024
+// threads to a vertex, each with a 2^13-slot LDS table for one partition of
+// the neighbour communities; aggregation bins skip them (wide = false), so a
+// capacity above kBinMax[5] goes straight to the last bin.  The last bin
+// (hubs / giant communities) uses global-memory tables.
+constexpr int kNumBins = 10;
+constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 4096, 8192, 16384, 0x7fffffff};
+constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 1024, 2048, 4096, 256};
+constexpr int kBinLg[kNumBins] = {3, 4, 5, 6, 8, 11, 13, 13, 13, 0};
+constexpr int kWideBin0 = 6;       // first wide bin; bin kWideBin0 + k uses 2^k partitions
+constexpr int kWideClasses = 3;
+constexpr int kWideMaxParts = 1 << (kWideClasses - 1);
 constexpr int kHubBin = kNumBins - 1;
 
 // Local-moving and refinement visit the vertices in S pseudo-random groups
@@ -74,9 +81,19 @@ struct ScanArgs {
   int32_t* tbl_keys;        // global hash tables for the hub bin
   double* tbl_vals;
   int64_t tbl_slot;         // slots per workgroup table
+  // wide rows: partial bests of the partitions of each vertex of a launch
+  // ([vertex][kWideMaxParts]) and the partitions finished per vertex
+  double* wd_g;
+  i128_t* wd_k;
+  int32_t* wd_c;
+  int32_t* wd_ok;           // bit 0: eligible (partition 0), bit 1: table overflow
+  int32_t* wd_done;         // zero between launches
+  int32_t sync_moves;       // local-moving records decisions (committed per group) instead of
+                            // committing at once: bit 0 rows <= kBinMax[4], bit 1 longer rows
 };
 
-// Hub path (vertices or communities with more than kBinMax[5] arcs).  Their
+// Hub path (vertices with more than kBinMax[kHubBin - 1] arcs, communities
+// with more than kBinMax[5] member arcs).  Their
 // arcs are cut into chunks of kHubChunk; each chunk is pre-aggregated in an
 // LDS table by one workgroup and merged into the item's global table (Alg. 2
 // scanCommunities / Alg. 4 row accumulation), which is then read back in
@@ -140,9 +157,10 @@ struct AggArgs {
 void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
                         const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
                         int64_t* launches);
-// Apply the recorded moves of the vertices list[0..count).
+// Apply the recorded moves of the vertices list[0..count) and mark the
+// neighbours of movers (long_rows: one workgroup per vertex).
 void launch_commit_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        int32_t count);
+                        int32_t count, bool long_rows);
 void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
                           const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
                           int64_t* launches);
@@ -208,8 +226,9 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
                       int32_t* size, int64_t n);
 // Degree binning into S groups: bin_count fills bb->counts / bb->maxsize,
 // bin_scatter places item i at bb->cursors[group(i) * kNumBins + bin(i)]++.
-void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, BinBuf* bb);
-void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, BinBuf* bb,
+// wide = false leaves bins kWideBin0.. empty (aggregation capacities).
+void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb);
+void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb,
                  int32_t* list);
 // used[c] = 1 for every label c in C[0..n) (used zeroed by the caller).
 void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used);

@@ -11,8 +11,9 @@
 //               with gamma = p / 2^16, so that gain = 2 key / (2^16 W^2) exactly.
 // Local-moving in fast mode commits a move at once (asynchronous updates,
 // Sec. 4.1): Sigma and sizes by atomics, C[i] by a plain store, neighbours
-// marked unprocessed.  Deterministic local-moving and refinement record the
-// choice in target[] and a separate commit kernel applies it.
+// marked unprocessed.  Deterministic local-moving, fast local-moving with
+// sync_moves, and refinement record the choice in target[] and a separate
+// commit kernel applies it.
 //
 // Singleton-to-singleton moves go only towards the lower community id
 // (min-label rule), which stops pairs of singletons from swapping.
@@ -89,8 +90,9 @@ struct Eval {
   }
 };
 
-// Workgroup argmax of (gain or key, id); the result is valid in every thread.
-template <bool DET>
+// Workgroup argmax of (gain or key, id) over NW wavefronts; the result is
+// valid in every thread.
+template <bool DET, int NW = kBlock / kWave>
 __device__ __forceinline__ void block_argmax(double& bg, i128& bk, int32_t& bc, double* s_g, i128* s_k,
                                              int32_t* s_c) {
   if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
@@ -99,7 +101,7 @@ __device__ __forceinline__ void block_argmax(double& bg, i128& bk, int32_t& bc, 
   if (lane_id() == 0) { s_g[w] = bg; s_k[w] = bk; s_c[w] = bc; }
   __syncthreads();
   bc = s_c[0]; bg = s_g[0]; bk = s_k[0];
-  for (int k = 1; k < kBlock / kWave; ++k) {
+  for (int k = 1; k < NW; ++k) {
     if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
     else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
   }
@@ -116,6 +118,80 @@ __device__ __forceinline__ bool accept(const ScanArgs& a, int32_t d, int32_t bc,
     if (a.size[bc] == 1 && bc > d) return false;
   }
   return true;
+}
+
+// Largest degree of the bin served by groups of G lanes.
+constexpr int bin_max_for_lanes(int G) {
+  for (int b = 0; b < 5; ++b)
+    if (kBinLanes[b] == G) return kBinMax[b];
+  return G;
+}
+
+// Accumulates the arcs e0, e0 + NT, ... of row i: arcs to the vertex's own
+// community d are summed into the returned K_{i->d} (kept out of the table,
+// whose slot would otherwise take an atomic per intra-community arc), every
+// other neighbour community goes to ins(c, w).  U arcs per round, with their
+// index, weight, label (and bound) loads issued together.
+template <int U, int NT, int PH, class WT, class Ins>
+__device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArgs& a, int32_t i, int32_t beg,
+                                           int32_t deg, int32_t e0, int32_t d, int32_t bi, Ins ins) {
+  double kid = 0.0;
+  for (int32_t base = e0; base < deg; base += U * NT) {
+    int32_t j[U];
+    double w[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int32_t e = base + u * NT;
+      j[u] = (e < deg) ? g.idx[beg + e] : i;
+      w[u] = (e < deg) ? g.weight(beg + e) : 0.0;
+    }
+    int32_t c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = j[u] != i;
+      c[u] = ok ? a.C[j[u]] : kEmpty;
+      if (PH == kRefine) {
+        const int32_t b = ok ? a.CB[j[u]] : bi;
+        if (b != bi) c[u] = kEmpty;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (c[u] == kEmpty) continue;
+      if (c[u] == d) kid += w[u];
+      else ins(c[u], w[u]);
+    }
+  }
+  return kid;
+}
+
+// Evaluates the table slots s0, s0 + NT, ... < ts (no slot holds d) and
+// clears them; U slots per round with their Sigma loads issued together.
+template <int U, int NT, bool DET>
+__device__ __forceinline__ void eval_table(int32_t* keys, double* vals, int ts, int s0, const ScanArgs& a,
+                                           const Eval<DET>& ev, Acc& acc, double& bg, i128& bk, int32_t& bc) {
+  for (int base = s0; base < ts; base += U * NT) {
+    int32_t c[U];
+    double v[U], sg[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = base + u * NT;
+      c[u] = (s < ts) ? keys[s] : kEmpty;
+      v[u] = (c[u] != kEmpty) ? vals[s] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) sg[u] = (c[u] != kEmpty) ? a.Sig[c[u]] : 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int s = base + u * NT;
+      if (c[u] != kEmpty) {
+        ++acc.nc;
+        ev(a, c[u], v[u], sg[u], bg, bk, bc);
+        keys[s] = kEmpty;
+        vals[s] = 0.0;
+      }
+    }
+  }
 }
 
 // ------------------------------------------------ group of G lanes per vertex ---
@@ -143,40 +219,28 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
     if (PH == kMove && gl == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
     const int32_t beg = g.begin(i), deg = g.degree(i);
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
     // table of next_pow2(2 deg) <= TS slots: at most deg distinct keys
     const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
-    for (int32_t e = gl; e < deg; e += G) {
-      const int32_t j = g.idx[beg + e];
-      if (j == i) continue;
-      if (PH == kRefine && a.CB[j] != bi) continue;
-      lds_insert(keys, vals, lg, a.C[j], g.weight(beg + e));
-    }
+    constexpr int UA = (bin_max_for_lanes(G) + G - 1) / G;
+    double kid = scan_row<UA, G, PH>(g, a, i, beg, deg, gl, d, bi,
+                                     [&](int32_t c, double w) { lds_insert(keys, vals, lg, c, w); });
+    kid = sum_xor<G>(kid);
     wave_sync();
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
-    const Eval<DET> ev(a, lds_lookup(keys, vals, lg, d), ki, a.Sig[d]);
-    wave_sync();  // the lookup of d is done before slots are cleared
+    const Eval<DET> ev(a, kid, ki, a.Sig[d]);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    for (int s = gl; s < ts; s += G) {
-      const int32_t c = keys[s];
-      if (c == kEmpty) continue;
-      if (c != d) {
-        ++acc.nc;
-        ev(a, c, vals[s], a.Sig[c], bg, bk, bc);
-      }
-      keys[s] = kEmpty;
-      vals[s] = 0.0;
-    }
+    eval_table<TS / G, G, DET>(keys, vals, ts, gl, a, ev, acc, bg, bk, bc);
     if (DET) argmax_k<G>(bk, bc); else argmax_f<G>(bg, bc);
     wave_sync();
     if (gl == 0) { ++acc.nv; acc.na += (unsigned long long)deg; }
     int take = (gl == 0) ? (int)accept<PH, DET>(a, d, bc, bg, bk) : 0;
     take = __shfl(take, 0, G);
     if (!take) continue;
-    if (PH == kMove && !DET) {
+    if (PH == kMove && !DET && !(a.sync_moves & 1)) {
       if (gl == 0) {
         atomicAdd(&a.Sig[d], -ki);
         atomicAdd(&a.Sig[bc], ki);
@@ -191,7 +255,10 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
         if (j != i) a.flag[j] = 1;
       }
     } else if (PH == kMove) {
-      if (gl == 0) { a.target[i] = bc; acc.dqk += bk; }
+      if (gl == 0) {
+        a.target[i] = bc;
+        if (DET) acc.dqk += bk; else acc.dq += bg;
+      }
     } else {
       if (gl == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
     }
@@ -214,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
   __shared__ i128 s_k[kBlock / kWave];
   __shared__ int32_t s_c[kBlock / kWave];
   __shared__ int s_flag, s_take;
+  __shared__ double s_kid;
   int32_t* keys = GLB ? a.tbl_keys + (int64_t)blockIdx.x * a.tbl_slot : skeys;
   double* vals = GLB ? a.tbl_vals + (int64_t)blockIdx.x * a.tbl_slot : svals;
   if (!GLB) {
@@ -240,40 +308,31 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
       for (int s = threadIdx.x; s < ts; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
       __syncthreads();
     }
-    for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
-      const int32_t j = g.idx[beg + e];
-      if (j == i) continue;
-      if (PH == kRefine && a.CB[j] != bi) continue;
-      if (GLB) glb_insert(keys, vals, lg, a.C[j], g.weight(beg + e));
-      else lds_insert(keys, vals, lg, a.C[j], g.weight(beg + e));
-    }
-    __syncthreads();
     const int32_t d = a.C[i];
     const double ki = a.K[i];
-    const double kid = GLB ? glb_lookup(keys, vals, lg, d) : lds_lookup(keys, vals, lg, d);
-    const Eval<DET> ev(a, kid, ki, a.Sig[d]);
-    __syncthreads();  // the lookup of d is done before slots are cleared
+    double kid = scan_row<4, kBlock, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
+      if (GLB) glb_insert(keys, vals, lg, c, w);
+      else lds_insert(keys, vals, lg, c, w);
+    });
+    kid = block_sum<double>(kid, s_g);
+    if (threadIdx.x == 0) s_kid = kid;
+    __syncthreads();
+    const Eval<DET> ev(a, s_kid, ki, a.Sig[d]);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    for (int s = threadIdx.x; s < ts; s += kBlock) {
-      const int32_t c = GLB ? glb_load_key(keys, s) : keys[s];
-      if (c == kEmpty) continue;
-      if (c != d) {
+    if (GLB) {
+      for (int s = threadIdx.x; s < ts; s += kBlock) {
+        const int32_t c = glb_load_key(keys, s);
+        if (c == kEmpty) continue;
         ++acc.nc;
-        ev(a, c, GLB ? glb_load_val(vals, s) : vals[s], a.Sig[c], bg, bk, bc);
+        ev(a, c, glb_load_val(vals, s), a.Sig[c], bg, bk, bc);
       }
-      if (!GLB) { keys[s] = kEmpty; vals[s] = 0.0; }
+    } else {
+      eval_table<(TS / kBlock > 0 ? TS / kBlock : 1), kBlock, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk,
+                                                                   bc);
     }
-    if (DET) argmax_k<kWave>(bk, bc); else argmax_f<kWave>(bg, bc);
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == 0) { s_g[w] = bg; s_k[w] = bk; s_c[w] = bc; }
-    __syncthreads();
-    bc = s_c[0]; bg = s_g[0]; bk = s_k[0];
-    for (int k = 1; k < kBlock / kWave; ++k) {
-      if (DET) { if (better_k(s_k[k], s_c[k], bk, bc)) { bk = s_k[k]; bc = s_c[k]; } }
-      else { if (better_f(s_g[k], s_c[k], bg, bc)) { bg = s_g[k]; bc = s_c[k]; } }
-    }
+    block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     if (threadIdx.x == 0) {
       ++acc.nv;
       acc.na += (unsigned long long)deg;
@@ -282,7 +341,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     __syncthreads();  // table and s_* reads done; s_take published
     const int take = s_take;
     if (!take) continue;
-    if (PH == kMove && !DET) {
+    if (PH == kMove && !DET && !(a.sync_moves & 2)) {
       if (threadIdx.x == 0) {
         atomicAdd(&a.Sig[d], -ki);
         atomicAdd(&a.Sig[bc], ki);
@@ -297,9 +356,170 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
         if (j != i) a.flag[j] = 1;
       }
     } else if (PH == kMove) {
-      if (threadIdx.x == 0) { a.target[i] = bc; acc.dqk += bk; }
+      if (threadIdx.x == 0) {
+        a.target[i] = bc;
+        if (DET) acc.dqk += bk; else acc.dq += bg;
+      }
     } else {
       if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
+    }
+  }
+  flush_acc<PH, DET>(a, acc);
+}
+
+// ------------------------------------ wide rows: P workgroups per vertex ---
+// Vertices of the wide bins (kBinMax[5] < deg <= kBinMax[kHubBin - 1]).  The
+// P = 2^k workgroups of a vertex of wide class k each stream the whole row,
+// but accumulate only the neighbour communities c with wide_part(c) mod P
+// equal to their partition, in an LDS table of up to 2^13 slots, so no
+// global table or global atomics are needed.  K_{i->d} is a plain sum over
+// the row.  Every partition evaluates its own candidates; the last one to
+// finish reduces the partial bests and applies the decision.  Only partition
+// 0 tests (and, for local-moving, clears) the pruning flag: the others scan
+// regardless, and the decision follows partition 0.  A partition whose keys
+// overflow the table (more than 2^13 distinct; statistically out of reach
+// for rows of at most 2^12 P arcs) cancels the move of its vertex.
+constexpr int kWideThreads = 1024;
+constexpr int kWideLg = 13;
+
+struct WideLaunch {
+  int32_t count[kWideClasses];  // vertices of class k in this launch
+  int32_t start[kWideClasses];  // their offset in the list
+};
+
+template <class WT, int PH, bool DET>
+__global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, ScanArgs a,
+                                                              const int32_t* __restrict__ list, WideLaunch wl) {
+  constexpr int TS = 1 << kWideLg;
+  constexpr int NW = kWideThreads / kWave;
+  __shared__ int32_t keys[TS];
+  __shared__ double vals[TS];
+  __shared__ double s_g[NW];
+  __shared__ i128 s_k[NW];
+  __shared__ int32_t s_c[NW];
+  __shared__ double s_d[NW];
+  __shared__ int s_ok, s_ovf, s_last, s_take;
+  // task -> (class k, vertex r of the launch, partition)
+  int32_t b = blockIdx.x, r = 0;
+  int k = 0;
+  for (; k < kWideClasses - 1; ++k) {
+    const int32_t tk = wl.count[k] << k;
+    if (b < tk) break;
+    b -= tk;
+    r += wl.count[k];
+  }
+  const int P = 1 << k;
+  const int32_t vloc = b >> k;
+  const int part = b & (P - 1);
+  r += vloc;
+  const int32_t i = list[wl.start[k] + vloc];
+  const int32_t beg = g.begin(i), deg = g.degree(i);
+  const int lg = (P == 1) ? min(kWideLg, ceil_log2(2 * (int64_t)deg)) : kWideLg;
+  const int ts = 1 << lg;
+  for (int s = threadIdx.x; s < ts; s += kWideThreads) { keys[s] = kEmpty; vals[s] = 0.0; }
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    if (part == 0 || PH == kRefine) ok = (int)Decide<PH, DET>::eligible(a, i);
+    if (PH == kMove && part == 0 && ok) a.flag[i] = 0;  // processed (Alg. 2 prune)
+    s_ok = ok;
+    s_ovf = 0;
+  }
+  __syncthreads();
+  const int ok = s_ok;
+  Acc acc;
+  int32_t bc = -1;
+  double bg = 0.0;
+  i128 bk = 0;
+  const int32_t d = a.C[i];
+  const double ki = a.K[i];
+  if (ok) {  // uniform
+    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    double kid = scan_row<4, kWideThreads, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
+      if ((int)(wide_part(c) & (uint32_t)(P - 1)) != part) return;
+      if (!lds_insert_bounded(keys, vals, lg, c, w)) s_ovf = 1;
+    });
+    kid = block_sum<double>(kid, s_d);
+    if (threadIdx.x == 0) s_d[0] = kid;
+    __syncthreads();
+    kid = s_d[0];
+    const Eval<DET> ev(a, kid, ki, a.Sig[d]);
+    eval_table<TS / kWideThreads, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
+    block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
+  }
+  const int ovf = s_ovf;
+  int last = 1;
+  if (P > 1) {
+    if (threadIdx.x == 0) {
+      const int64_t q = (int64_t)r * kWideMaxParts + part;
+      a.wd_g[q] = bg;
+      a.wd_k[q] = bk;
+      a.wd_c[q] = bc;
+      a.wd_ok[q] = ok | (ovf << 1);
+      __threadfence();
+      const int prev = atomicAdd(&a.wd_done[r], 1);
+      s_last = (prev == P - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    last = s_last;
+  }
+  if (last) {  // uniform
+    int ok0 = ok, ovf_any = ovf;
+    if (P > 1) {
+      __threadfence();
+      if (threadIdx.x == 0) {
+        bc = -1; bg = 0.0; bk = 0;
+        for (int q2 = 0; q2 < P; ++q2) {
+          const int64_t q = (int64_t)r * kWideMaxParts + q2;
+          const int f = __hip_atomic_load(a.wd_ok + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (q2 == 0) ok0 = f & 1;
+          ovf_any |= (f >> 1) & 1;
+          const int32_t c2 = __hip_atomic_load(a.wd_c + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          if (DET) {
+            const unsigned long long* kw = (const unsigned long long*)(a.wd_k + q);
+            const unsigned long long lo = __hip_atomic_load(kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned long long hi = __hip_atomic_load(kw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const i128 k2 = make_i128((long long)hi, lo);
+            if (better_k(k2, c2, bk, bc)) { bk = k2; bc = c2; }
+          } else {
+            const double g2 = __hip_atomic_load(a.wd_g + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (better_f(g2, c2, bg, bc)) { bg = g2; bc = c2; }
+          }
+        }
+        a.wd_done[r] = 0;
+      }
+    }
+    if (threadIdx.x == 0) {
+      int take = 0;
+      if (ok0) {
+        ++acc.nv;
+        acc.na += (unsigned long long)deg;
+        take = (!ovf_any && accept<PH, DET>(a, d, bc, bg, bk)) ? 1 : 0;
+      }
+      if (take) {
+        if (PH == kMove && !DET && !(a.sync_moves & 2)) {
+          atomicAdd(&a.Sig[d], -ki);
+          atomicAdd(&a.Sig[bc], ki);
+          atomicSub(&a.size[d], 1);
+          atomicAdd(&a.size[bc], 1);
+          a.C[i] = bc;
+          acc.dq += bg;
+          ++acc.nm;
+        } else if (PH == kMove) {
+          a.target[i] = bc;
+          if (DET) acc.dqk += bk; else acc.dq += bg;
+        } else {
+          a.target[i] = bc;
+          a.targeted[bc] = 1;
+        }
+      }
+      s_take = take;
+    }
+    __syncthreads();
+    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) {
+      for (int32_t e = threadIdx.x; e < deg; e += kWideThreads) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i) a.flag[j] = 1;
+      }
     }
   }
   flush_acc<PH, DET>(a, acc);
@@ -351,6 +571,44 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
     }
   }
   nm = block_sum<unsigned long long>(nm, red_u);
+  if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
+}
+
+// Local-moving commit of vertices with long rows: one workgroup per vertex,
+// so that the neighbours of a mover are marked by the whole workgroup.
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_commit_rows(GraphView<WT> g, ScanArgs a,
+                                                        const int32_t* __restrict__ list, int32_t count) {
+  __shared__ int s_mv;
+  unsigned long long nm = 0;
+  for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
+    const int32_t i = list[k];
+    if (threadIdx.x == 0) {
+      const int32_t t = a.target[i];
+      s_mv = 0;
+      if (t >= 0) {
+        a.target[i] = -1;
+        const int32_t d = a.C[i];
+        const double ki = a.K[i];
+        atomicAdd(&a.Sig[d], -ki);
+        atomicAdd(&a.Sig[t], ki);
+        atomicSub(&a.size[d], 1);
+        atomicAdd(&a.size[t], 1);
+        a.C[i] = t;
+        ++nm;
+        s_mv = 1;
+      }
+    }
+    __syncthreads();
+    if (s_mv) {
+      const int32_t beg = g.begin(i), deg = g.degree(i);
+      for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i) a.flag[j] = 1;
+      }
+    }
+    __syncthreads();
+  }
   if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
 }
 
@@ -406,13 +664,31 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
                        list + start[5], count[5]);
     ++*launches;
   }
+  WideLaunch wl;
+  int64_t tasks = 0;
+  for (int k = 0; k < kWideClasses; ++k) {
+    wl.count[k] = count[kWideBin0 + k];
+    wl.start[k] = start[kWideBin0 + k];
+    tasks += (int64_t)wl.count[k] << k;
+  }
+  if (tasks > 0) {
+    hipLaunchKernelGGL((k_decide_wide<WT, PH, DET>), dim3((unsigned)tasks), dim3(kWideThreads), 0, st, g, a,
+                       list, wl);
+    ++*launches;
+  }
   (void)hub_grid;  // the hub bin goes through the chunked hub path
 }
 
 template <class WT, int PH>
-void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count) {
+void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count,
+                 bool long_rows = false) {
   if (count <= 0) return;
   const GraphView<WT> g = view<WT>(gd);
+  if (PH == kMove && long_rows) {
+    hipLaunchKernelGGL((k_commit_rows<WT>), dim3(grid_for(count, 1, 2048)), dim3(kBlock), 0, st, g, a, list,
+                       count);
+    return;
+  }
   const int grid = grid_for(count, kBlock, 2048);
   hipLaunchKernelGGL((k_commit<WT, PH>), dim3(grid), dim3(kBlock), 0, st, g, a, list, count);
 }

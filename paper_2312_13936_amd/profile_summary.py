@@ -1,0 +1,139 @@
+"""Summaries of rocprofv3 output for the profiles/ folder.
+
+    python -m paper_2312_13936_amd.profile_summary stats  <kernel_stats.csv> <bench.json> <out.md> <command>
+    python -m paper_2312_13936_amd.profile_summary counters <fetch.csv> <write.csv> <calib_bytes> <out.md> <command>
+
+`stats` writes the per-kernel time table of a `--kernel-trace --stats` run
+grouped into the scan and aggregation classes.  `counters` sums FETCH_SIZE
+and WRITE_SIZE (KiB per dispatch) over the dispatches of each class, scales
+each counter by what it reads for the device-to-device copy of
+`calib_bytes` bytes that the benchmark runs first, and records the result
+with a digest of the kernel sources; bench.py reports it as the roofline's
+`traffic` only while that digest matches the current sources.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import hashlib
+import json
+import os
+import re
+import sys
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SCAN = re.compile(r"k_decide_|k_hub_(prep|gather|eval)")
+AGG = re.compile(r"k_agg_(group|block)|k_gagg_|k_member_degrees")
+COPY = re.compile(r"copyBuffer|copy_kernel|CatArrayBatchedCopy|elementwise_kernel.*copy", re.I)
+
+
+def source_digest() -> str:
+    """sha256 (16 hex digits) over the HIP sources of libgvl.so."""
+    h = hashlib.sha256()
+    d = os.path.join(_HERE, "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            h.update(f.encode())
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name: str) -> str:
+    name = re.sub(r"gvl::", "", name)
+    name = re.sub(r"GraphView<([a-z]+)>", r"GV<\1>", name)
+    return name
+
+
+def stats(stats_csv, bench_json, out, command):
+    rows = list(csv.DictReader(open(stats_csv)))
+    bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
+    tot = sum(float(r["TotalDurationNs"]) for r in rows) / 1e6
+    cls = collections.defaultdict(float)
+    for r in rows:
+        ms = float(r["TotalDurationNs"]) / 1e6
+        if SCAN.search(r["Name"]):
+            cls["scan"] += ms
+        elif AGG.search(r["Name"]):
+            cls["agg"] += ms
+    ph = bench.get("phases", {})
+    lines = ["# Kernel time summary: %s" % bench["config"]["workload"], "",
+             "Command (from the repository root on the MI355X box):", "", "```", command, "```", "",
+             "One gvl_leiden call: %.1f ms wall, Q = %.4f, %d passes, %s mode." % (
+                 bench["ms_per_step"], bench["modularity"], bench["passes"], bench["config"]["mode"]), "",
+             "| kernel class | rocprofv3 total (ms) | HIP-event total in bench.py (ms) |", "|---|---|---|",
+             "| neighbour-community scan (`k_decide_*`, `k_hub_prep/gather/eval`) | %.1f | %.1f |" % (
+                 cls["scan"], ph.get("scan_kernels_ms", float("nan"))),
+             "| aggregation rows (`k_agg_*`, `k_gagg_*`, `k_member_degrees`) | %.1f | %.1f |" % (
+                 cls["agg"], ph.get("agg_kernels_ms", float("nan"))),
+             "| all kernels | %.1f | |" % tot, "",
+             "The HIP-event spans bracket every launch of a class and the short gaps between them.", "",
+             "| total ms | calls | avg us | % | kernel |", "|---|---|---|---|---|"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
+        lines.append("| %.2f | %s | %.1f | %.1f | `%s` |" % (
+            float(r["TotalDurationNs"]) / 1e6, r["Calls"], float(r["AverageNs"]) / 1e3, float(r["Percentage"]),
+            short(r["Name"])[:110]))
+    lines.append("")
+    lines.append("Kernel sources digest: %s" % source_digest())
+    open(out, "w").write("\n".join(lines) + "\n")
+
+
+def _sum(path, counter):
+    per = collections.defaultdict(float)
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] == counter:
+            per[r["Kernel_Name"]] += float(r["Counter_Value"])
+    return per
+
+
+def counters(fetch_csv, write_csv, calib_bytes, out, command):
+    calib_bytes = int(calib_bytes)
+    f = _sum(fetch_csv, "FETCH_SIZE")
+    w = _sum(write_csv, "WRITE_SIZE")
+    fc = [v for k, v in f.items() if COPY.search(k)]
+    wc = [v for k, v in w.items() if COPY.search(k)]
+    if not fc or not wc:
+        raise SystemExit("no copy kernel found for the calibration")
+    kf = calib_bytes / (max(fc) * 1024.0)   # bytes per counted KiB
+    kw = calib_bytes / (max(wc) * 1024.0)
+    res = {"digest": source_digest(), "calib_bytes": calib_bytes, "fetch_scale": kf, "write_scale": kw}
+    for name, rx in (("scan", SCAN), ("agg", AGG)):
+        fb = sum(v for k, v in f.items() if rx.search(k)) * 1024.0 * kf
+        wb = sum(v for k, v in w.items() if rx.search(k)) * 1024.0 * kw
+        res[name + "_fetch_bytes"] = fb
+        res[name + "_write_bytes"] = wb
+    lines = ["# HBM traffic of the Leiden kernel classes (rocprofv3 counters)", "",
+             "Commands (from the repository root on the MI355X box), one counter per run:", "", "```",
+             command, "```", "",
+             "FETCH_SIZE and WRITE_SIZE are summed over the dispatches of each class in one step and",
+             "scaled by what each counter reads for a device-to-device copy of %d bytes run first" % calib_bytes,
+             "(fetch x%.4f, write x%.4f per counted byte)." % (kf, kw), "",
+             "| class | fetched (GB) | written (GB) |", "|---|---|---|",
+             "| neighbour-community scan | %.2f | %.2f |" % (res["scan_fetch_bytes"] / 1e9,
+                                                             res["scan_write_bytes"] / 1e9),
+             "| aggregation rows | %.2f | %.2f |" % (res["agg_fetch_bytes"] / 1e9, res["agg_write_bytes"] / 1e9),
+             "", "counters-json: " + json.dumps(res), ""]
+    open(out, "w").write("\n".join(lines))
+
+
+def recorded_traffic(path):
+    """The counters-json record of a counters summary, or None if the file is
+    missing or the kernel sources changed since it was taken."""
+    try:
+        for line in open(path):
+            if line.startswith("counters-json: "):
+                rec = json.loads(line[len("counters-json: "):])
+                return rec if rec.get("digest") == source_digest() else None
+    except OSError:
+        return None
+    return None
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 6 and sys.argv[1] == "stats":
+        stats(*sys.argv[2:6])
+    elif len(sys.argv) >= 7 and sys.argv[1] == "counters":
+        counters(*sys.argv[2:7])
+    else:
+        print(__doc__)
+        sys.exit(2)

@@ -37,6 +37,7 @@ def _graphs():
         "star": lambda: gen.from_edges(2000, [(0, i) for i in range(1, 2000)]),
         "hub+cliques": lambda: _hub_graph(),
         "path": lambda: gen.from_edges(500, [(i, i + 1) for i in range(499)]),
+        "hubs-wide": lambda: _wide_hubs(),
     }
 
 
@@ -54,6 +55,25 @@ def _hub_graph():
     leaves = range(hub + 1, hub + 1 + 1500)
     edges += [(hub, v) for v in leaves]
     return gen.from_edges(hub + 1 + 1500, edges, name="hub+cliques")
+
+
+def _wide_hubs():
+    # 400 cliques of 20 plus 50000 leaves and five hubs of degree about
+    # 3000, 6000, 12000, 20000 and 40000: every wide class (1, 2 and 4
+    # partitions per vertex) and the global-table hub path.
+    rng = np.random.default_rng(31)
+    s, k, nl = 20, 400, 50000
+    edges = []
+    for q in range(k):
+        edges += gen.clique_edges(range(q * s, (q + 1) * s))
+    nc = s * k
+    hubs = [nc + nl + t for t in range(5)]
+    for h, deg in zip(hubs, (3000, 6000, 12000, 20000, 40000)):
+        inner = rng.choice(nc, 400, replace=False)
+        leaves = nc + rng.choice(nl, deg - 400, replace=False)
+        edges += [(h, int(v)) for v in np.concatenate([inner, leaves])]
+    edges += [(hubs[a], hubs[b]) for a in range(5) for b in range(a + 1, 5)]
+    return gen.from_edges(nc + nl + 5, edges, name="hubs-wide")
 
 
 GRAPHS = _graphs()
@@ -125,12 +145,16 @@ def relabel(g, seed):
 
 
 def oracle_reference_q(g, orders=4):
-    """Sequential oracle modularity: on the given numbering, and the lowest
-    over `orders` seeded renumberings of the same graph.  The sequential
-    algorithm depends on the vertex order, so on graphs with weak structure
-    its own spread across numberings exceeds 1e-3."""
+    """Oracle modularity: the sequential run on the given numbering, and the
+    lowest the oracle reaches over that numbering and `orders` seeded
+    renumberings, in either of its modes (sequential, group-synchronous).
+    Leiden's result depends on the visiting order, so on graphs with weak
+    structure (R-MAT, Q ~ 0.1) the oracle's own spread exceeds 1e-3."""
     q0 = oracle.leiden(g, mode=oracle.SEQ_ASYNC).q
-    qs = [q0] + [oracle.leiden(relabel(g, s), mode=oracle.SEQ_ASYNC).q for s in range(orders)]
+    qs = [q0, oracle.leiden(g, mode=oracle.DET_SYNC).q]
+    for s in range(orders):
+        h = relabel(g, s)
+        qs += [oracle.leiden(h, mode=oracle.SEQ_ASYNC).q, oracle.leiden(h, mode=oracle.DET_SYNC).q]
     return q0, min(qs)
 
 
@@ -145,6 +169,19 @@ def test_fast_mode_quality(eng, name):
     assert oracle.disconnected(g, mem) == 0
     _, first = np.unique(mem, return_index=True)
     assert np.all(np.diff(first) > 0) and mem[0] == 0  # first-occurrence labels
+
+
+@pytest.mark.parametrize("sync_moves", [1, 2, 3])
+@pytest.mark.parametrize("name", ["rmat-s14", "planted-C1", "hubs-wide", "grid200-w100"])
+def test_fast_mode_sync_moves(eng, name, sync_moves):
+    # local-moving that decides a group on one snapshot and commits it
+    # afterwards, for short rows (bit 0), long rows (bit 1) or both
+    g = graph(name)
+    mem, q, st = run(eng, g, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
+    q0, qmin = oracle_reference_q(g, orders=2)
+    assert q == oracle.modularity(g, mem)
+    assert q >= qmin - FAST_TOL, "fast Q %.6f vs oracle %.6f" % (q, qmin)
+    assert oracle.disconnected(g, mem) == 0
 
 
 @pytest.mark.parametrize("gamma", [0.5, 1.5, 0.25])
