@@ -130,8 +130,10 @@ def upload(graphs):
 
 
 def bench_batch(args, mode):
-    """Batched Leiden over many graphs against the plain path (one
-    gvl_leiden call per graph, one after the other) on the same graphs."""
+    """Batched Leiden over many graphs: the fused path (one union, one launch
+    sequence for all graphs) and, with --lanes > 0, the lane pool (one
+    gvl_leiden per graph on concurrent streams), against the plain path (one
+    gvl_leiden call per graph, one after the other) on a seeded subset."""
     import numpy as np
     import torch
     import paper_2312_13936_amd as gvl
@@ -159,41 +161,64 @@ def bench_batch(args, mode):
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - t1
     plain_arcs = sum(graphs[k].m for k in sub)
-    log("plain: %d graphs in %.2fs (%.1f graphs/s)" % (len(sub), plain_s, len(sub) / plain_s))
-    wsb = gvl.gvl_batch_workspace_bytes(descs, opt, args.lanes)
+    plain_gps = len(sub) / plain_s
+    log("plain: %d graphs in %.2fs (%.1f graphs/s)" % (len(sub), plain_s, plain_gps))
+    eng.ws = None
+    torch.cuda.empty_cache()
+    # fused path
+    wsb = gvl.gvl_fused_workspace_bytes(descs, opt)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    log("fused workspace %.1f GB" % (wsb / 1e9))
     times, qs = [], None
     for k in range(args.warmup + args.steps):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        code, qs, sts = gvl.gvl_leiden_batch(eng.ctx, descs, opt, args.lanes, ws.data_ptr(), wsb)
+        code, qs, sts = gvl.gvl_leiden_fused(eng.ctx, descs, opt, ws.data_ptr(), wsb)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t1
         if code != 0:
-            raise RuntimeError("batch failed: %s" % sorted(set(sts)))
-        log("batch step %d: %.2fs (%.1f graphs/s)" % (k, dt, len(graphs) / dt))
+            raise RuntimeError("fused batch failed: %s" % sorted(set(sts)))
+        log("fused step %d: %.2fs (%.1f graphs/s)" % (k, dt, len(graphs) / dt))
         if k >= args.warmup:
             times.append(dt)
+    del ws
+    torch.cuda.empty_cache()
     total = sum(times)
+    fused_gps = len(graphs) * len(times) / total
+    fq = np.array(qs)
+    lanes = None
+    if args.lanes > 0:
+        wsb = gvl.gvl_batch_workspace_bytes(descs, opt, args.lanes)
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        code, lq, sts = gvl.gvl_leiden_batch(eng.ctx, descs, opt, args.lanes, ws.data_ptr(), wsb)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        log("lanes (%d): %.2fs (%.1f graphs/s)" % (args.lanes, dt, len(graphs) / dt))
+        lanes = {"lanes": args.lanes, "graphs_per_s": len(graphs) / dt, "edges_per_s": arcs / dt,
+                 "modularity_mean": float(np.mean(lq))}
+        del ws
+    eng.close()
     bq = np.array([qs[k] for k in sub])
     pq = np.array([plain_q[k] for k in sub])
-    batched_gps = len(graphs) * len(times) / total
-    plain_gps = len(sub) / plain_s
-    eng.close()
     return {
-        "metric": METRIC, "value": batched_gps, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
+        "metric": METRIC, "value": fused_gps, "unit": "graphs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * total / len(times), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "%d LFR-style graphs, vertices log-uniform on [1k, 200k], degree exponent 2.5, "
                                "mean degree 12, community-size exponent 1.5, mixing 0.3, unit weights"
                                % len(graphs),
-                   "vertices": sum(g.n for g in graphs), "arcs": arcs, "mode": args.mode, "lanes": args.lanes,
+                   "vertices": sum(g.n for g in graphs), "arcs": arcs, "mode": args.mode, "path": "fused",
                    "parallelism": "single GPU"},
-        "batched_graphs_per_s": batched_gps, "batched_edges_per_s": arcs * len(times) / total,
+        "batched_graphs_per_s": fused_gps, "batched_edges_per_s": arcs * len(times) / total,
         "plain_graphs_per_s": plain_gps, "plain_edges_per_s": plain_arcs / plain_s,
         "plain_sample": "%d of the %d graphs (seeded), one gvl_leiden call after another" % (len(sub), len(graphs)),
-        "speedup_vs_plain": batched_gps / plain_gps,
-        "modularity_mean": float(np.mean(qs)),
+        "speedup_vs_plain": fused_gps / plain_gps,
+        "lane_pool": lanes,
+        "modularity_mean": float(np.mean(fq)),
+        "modularity_mean_plain_sample": float(np.mean(pq)),
+        "modularity_mean_fused_sample": float(np.mean(bq)),
         "modularity_max_abs_diff_vs_plain": float(np.max(np.abs(bq - pq))),
     }
 
@@ -239,7 +264,7 @@ def bench_serve(args, mode):
     arena_bytes = int(free * 0.8) & ~255
     arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
     torch.cuda.synchronize()
-    srv = gvl.Server(arena, args.lanes, opt)
+    srv = gvl.Server(arena, args.lanes or 4, opt)
     tickets = [None] * args.requests
     done = [None] * args.requests
     ready = [threading.Event() for _ in range(args.requests)]
@@ -278,7 +303,7 @@ def bench_serve(args, mode):
                                "drawn from a pool of %d LFR-style graphs: vertices log-uniform on [10k, 5M], "
                                "degree exponent 2.5, mean degree 16, mixing U[0.1, 0.5], unit weights, "
                                "resolution 1" % (args.requests, args.load, qps, len(graphs)),
-                   "mode": args.mode, "lanes": args.lanes, "arena_bytes": arena_bytes,
+                   "mode": args.mode, "lanes": args.lanes or 4, "arena_bytes": arena_bytes,
                    "parallelism": "single GPU"},
         "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
         "mean_ms": float(np.mean(lat)), "edges_per_s": arcs / wall, "requests_per_s": args.requests / wall,
@@ -296,7 +321,8 @@ def main():
     ap.add_argument("--workload", default="rmat-s24", choices=sorted(WORKLOADS) + ["lfr-batch", "lfr-serve"])
     ap.add_argument("--graphs", type=int, default=4096, help="lfr-batch: number of graphs")
     ap.add_argument("--plain-graphs", type=int, default=512, help="lfr-batch: graphs timed on the plain path")
-    ap.add_argument("--lanes", type=int, default=8, help="lfr-batch / lfr-serve: concurrent lanes")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lfr-batch: also time the lane pool with this many lanes; lfr-serve: lanes (default 4)")
     ap.add_argument("--pool", type=int, default=64, help="lfr-serve: distinct graphs in the request pool")
     ap.add_argument("--requests", type=int, default=2000, help="lfr-serve: number of requests")
     ap.add_argument("--load", type=float, default=0.8, help="lfr-serve: offered load / plain service rate")

@@ -186,6 +186,21 @@ gvl_status gvl_leiden_batch(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_d
                             int32_t lanes, void* d_workspace, size_t workspace_bytes, double* modularities,
                             gvl_status* statuses);
 
+/* Fused batch: the graphs run together as one disjoint union, every kernel
+ * launch covering all graphs still running, with per-graph gains, stop
+ * tests and pass counts (Alg. 1, Alg. 2 per graph); each result is the one
+ * gvl_leiden gives for that graph alone (bit-identical in deterministic
+ * mode).  Graphs are grouped into runs of < 1.5e9 vertices and arcs; the
+ * workspace holds the largest run.  statuses: host gvl_status[num_graphs]
+ * (per-graph input errors as gvl_leiden reports them); modularities: host
+ * double[num_graphs].  Returns GVL_E_BATCH if any graph failed, the others
+ * are still computed.  Work already queued on ctx's stream comes first; the
+ * call returns when every membership is written. */
+gvl_status gvl_fused_workspace_bytes(int32_t num_graphs, const gvl_graph_desc* graphs, const gvl_options* opt,
+                                     size_t* bytes);
+gvl_status gvl_leiden_fused(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_desc* graphs, const gvl_options* opt,
+                            void* d_workspace, size_t workspace_bytes, double* modularities, gvl_status* statuses);
+
 /* Serving with continuous admission.  The caller gives a device arena; a
  * running request holds gvl_workspace_bytes(n, m) of it (rounded up to 256),
  * returned when it completes.  Requests wait in arrival order; a free lane

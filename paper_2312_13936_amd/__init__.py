@@ -85,7 +85,8 @@ class gvl_server_info(ctypes.Structure):
 
 EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
            "gvl_modularity", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
-           "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_server_create", "gvl_server_submit",
+           "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_fused_workspace_bytes", "gvl_leiden_fused",
+           "gvl_server_create", "gvl_server_submit",
            "gvl_server_poll", "gvl_server_wait", "gvl_server_cancel", "gvl_server_release", "gvl_server_stats",
            "gvl_server_destroy", "gvl_status_string"]
 
@@ -115,6 +116,9 @@ def load_library(path: str = LIB_PATH):
     lib.gvl_batch_workspace_bytes.argtypes = [i32, GD, ctypes.POINTER(gvl_options), i32, ctypes.POINTER(sz)]
     lib.gvl_leiden_batch.argtypes = [vp, i32, GD, ctypes.POINTER(gvl_options), i32, vp, sz,
                                      ctypes.POINTER(dbl), ctypes.POINTER(i32)]
+    lib.gvl_fused_workspace_bytes.argtypes = [i32, GD, ctypes.POINTER(gvl_options), ctypes.POINTER(sz)]
+    lib.gvl_leiden_fused.argtypes = [vp, i32, GD, ctypes.POINTER(gvl_options), vp, sz, ctypes.POINTER(dbl),
+                                     ctypes.POINTER(i32)]
     lib.gvl_server_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int, i32, ctypes.POINTER(gvl_options), vp, sz]
     lib.gvl_server_submit.argtypes = [vp, GD, ctypes.POINTER(ctypes.c_uint64)]
     lib.gvl_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(gvl_request_info)]
@@ -227,6 +231,26 @@ def gvl_leiden_batch(ctx, graphs, opt: gvl_options, lanes: int, d_workspace, wor
                                            qs, sts)
     if code not in (0, -10):
         _check(code, "gvl_leiden_batch")
+    return code, list(qs)[:num], list(sts)[:num]
+
+
+def gvl_fused_workspace_bytes(graphs, opt: gvl_options) -> int:
+    arr = (gvl_graph_desc * max(len(graphs), 1))(*graphs)
+    b = ctypes.c_size_t(0)
+    _check(load_library().gvl_fused_workspace_bytes(len(graphs), arr, ctypes.byref(opt), ctypes.byref(b)),
+           "gvl_fused_workspace_bytes")
+    return int(b.value)
+
+
+def gvl_leiden_fused(ctx, graphs, opt: gvl_options, d_workspace, workspace_bytes):
+    """Returns (status, modularities[num], statuses[num]); status GVL_E_BATCH means some graphs failed."""
+    num = len(graphs)
+    arr = (gvl_graph_desc * max(num, 1))(*graphs)
+    qs = (ctypes.c_double * max(num, 1))()
+    sts = (ctypes.c_int32 * max(num, 1))()
+    code = load_library().gvl_leiden_fused(ctx, num, arr, ctypes.byref(opt), d_workspace, workspace_bytes, qs, sts)
+    if code not in (0, -10):
+        _check(code, "gvl_leiden_fused")
     return code, list(qs)[:num], list(sts)[:num]
 
 

@@ -1,0 +1,448 @@
+// Host-side internals shared by the single-graph driver and the fused batch
+// driver: the workspace layout, the context, binning, hub plans and the
+// device read-backs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <vector>
+
+#include "gvl.h"
+#include "kernels.hpp"
+
+namespace gvl {
+
+// Scalars shared between the device and one pinned host mirror.
+struct Scalars {
+  double dq[kCntSlots];                        // fast: summed move gains of an iteration
+  unsigned long long dq128[kCntSlots][2];      // det: exact summed move keys (lo, hi)
+  unsigned long long cnt[kCntSlots][8];        // kernel work counters (cumulative)
+  int32_t flags[4];                 // input checks
+  double accW;                      // total weight
+  double acc_d[2];                  // modularity: S1, S2 (floating)
+  unsigned long long acc_u[2];      // modularity: S2 exact (lo, hi)
+  int32_t total;                    // scan totals read back
+  int32_t pad;
+};
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static inline int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+// Device workspace, carved out of the caller's buffer.
+struct Workspace {
+  double *K, *Sig;
+  int32_t *size, *C, *CB, *start, *target, *newid, *brank, *lab, *rank, *cnt, *cv, *list, *scan_tmp;
+  uint8_t *flag, *targeted;
+  int32_t *off[2], *deg[2], *idx[2];
+  void* w[2];
+  int32_t* tbl_keys;
+  double* tbl_vals;
+  int64_t tbl_entries;
+  // hub path
+  int32_t *hp_chunk, *hp_tbl, *hp_slice, *hp_active, *hp_done, *hp_lcnt, *apre, *tbl_list;
+  double* hp_kid;
+  int2 *chunk_tasks, *slice_tasks;
+  double* pb_g;
+  i128_t* pb_k;
+  int32_t* pb_c;
+  int64_t max_tasks;
+  // wide rows
+  double* wd_g;
+  i128_t* wd_k;
+  int32_t *wd_c, *wd_ok, *wd_done;
+  int64_t max_wide;
+
+  Scalars* sc;
+  BinBuf* bb;
+  size_t bytes;
+};
+
+static int64_t table_entries(int64_t n) { return std::max<int64_t>(4 * next_pow2(2 * std::max<int64_t>(n, 1)), 1 << 16); }
+
+// tbl_n: the largest vertex count of one graph (hub tables never span two
+// graphs of a fused batch); < 0 means n.
+static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n = -1) {
+  Workspace w;
+  memset(&w, 0, sizeof(w));
+  size_t o = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + o : nullptr;
+    o += align_up(bytes);
+    return p;
+  };
+  const size_t N = (size_t)std::max<int64_t>(n, 1), M = (size_t)std::max<int64_t>(m, 1);
+  const size_t ws = det ? sizeof(double) : sizeof(float);
+  w.sc = (Scalars*)take(sizeof(Scalars));
+  w.bb = (BinBuf*)take(sizeof(BinBuf));
+  w.K = (double*)take(8 * N);
+  w.Sig = (double*)take(8 * N);
+  w.size = (int32_t*)take(4 * N);
+  w.C = (int32_t*)take(4 * N);
+  w.CB = (int32_t*)take(4 * N);
+  w.start = (int32_t*)take(4 * N);
+  w.target = (int32_t*)take(4 * N);
+  w.newid = (int32_t*)take(4 * (N + 1));
+  w.brank = (int32_t*)take(4 * (N + 1));
+  w.lab = (int32_t*)take(4 * N);
+  w.rank = (int32_t*)take(4 * (N + 1));
+  w.cnt = (int32_t*)take(4 * (N + 1));
+  w.cv = (int32_t*)take(4 * N);
+  w.list = (int32_t*)take(4 * N);
+  w.scan_tmp = (int32_t*)take(4 * ((size_t)scan_tiles((int64_t)N + 1) + 2));
+  w.flag = (uint8_t*)take(N);
+  w.targeted = (uint8_t*)take(N);
+  for (int b = 0; b < 2; ++b) {
+    w.off[b] = (int32_t*)take(4 * (N + 1));
+    w.deg[b] = (int32_t*)take(4 * N);
+    w.idx[b] = (int32_t*)take(4 * M);
+    w.w[b] = (void*)take(ws * M);
+  }
+  w.tbl_entries = table_entries(tbl_n < 0 ? n : std::min(tbl_n, n));
+  w.tbl_keys = (int32_t*)take(4 * (size_t)w.tbl_entries);
+  w.tbl_vals = (double*)take(8 * (size_t)w.tbl_entries);
+  w.hp_chunk = (int32_t*)take(4 * (N + 1));
+  w.hp_tbl = (int32_t*)take(4 * (N + 1));
+  w.hp_slice = (int32_t*)take(4 * (N + 1));
+  w.hp_active = (int32_t*)take(4 * N);
+  w.hp_done = (int32_t*)take(4 * N);
+  w.hp_lcnt = (int32_t*)take(4 * N);
+  w.tbl_list = (int32_t*)take(4 * (size_t)w.tbl_entries);
+  w.apre = (int32_t*)take(4 * (N + 1));
+  w.hp_kid = (double*)take(8 * N);
+  // chunk tasks <= H + M / kHubChunk; slice tasks <= H + M / (kHubSlice / 4)
+  w.max_tasks = (int64_t)N + (int64_t)M / 1024 + 2;
+  w.chunk_tasks = (int2*)take(sizeof(int2) * (size_t)w.max_tasks);
+  w.slice_tasks = (int2*)take(sizeof(int2) * (size_t)w.max_tasks);
+  w.pb_g = (double*)take(8 * (size_t)w.max_tasks);
+  w.pb_k = (i128_t*)take(16 * (size_t)w.max_tasks);
+  w.pb_c = (int32_t*)take(4 * (size_t)w.max_tasks);
+  // vertices of the wide bins: degree > kBinMax[5]
+  w.max_wide = std::min<int64_t>((int64_t)N, (int64_t)M / (kBinMax[5] + 1) + 1);
+  const size_t wq = (size_t)w.max_wide * kWideMaxParts;
+  w.wd_g = (double*)take(8 * wq);
+  w.wd_k = (i128_t*)take(16 * wq);
+  w.wd_c = (int32_t*)take(4 * wq);
+  w.wd_ok = (int32_t*)take(4 * wq);
+  w.wd_done = (int32_t*)take(4 * (size_t)w.max_wide);
+  w.bytes = o;
+  return w;
+}
+
+static unsigned long long counter(const Scalars* h, int k) {
+  unsigned long long s = 0;
+  for (int j = 0; j < kCntSlots; ++j) s += h->cnt[j][k];
+  return s;
+}
+
+// Deterministic int128 -> double: hi * 2^64 + lo (one rounding in the add).
+static double i128_to_double(unsigned long long lo, unsigned long long hi) {
+  return (double)(long long)hi * 18446744073709551616.0 + (double)lo;
+}
+
+struct PassDebug {
+  int64_t n = 0, ncom = 0, m = -1;
+  std::vector<int32_t> bound, refined, y_off, y_idx;
+  std::vector<double> y_w;
+  std::vector<int64_t> movers, refine_movers;
+};
+
+}  // namespace gvl
+
+using namespace gvl;
+
+struct gvl_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Scalars* host = nullptr;  // pinned
+  BinBuf* hbins = nullptr;  // pinned
+  std::vector<hipEvent_t> events;
+  size_t ev_used = 0;
+  std::vector<PassDebug> trace;
+};
+
+namespace {
+
+#define HIP_TRY(x)                                   \
+  do {                                               \
+    hipError_t e_ = (x);                             \
+    if (e_ != hipSuccess) {                          \
+      fprintf(stderr, "gvl: %s failed: %s\n", #x, hipGetErrorString(e_)); \
+      return GVL_E_HIP;                              \
+    }                                                \
+  } while (0)
+
+// Event pairs for per-phase timing (profile = 1).  Phase spans include the
+// host read-backs between launches; kernel spans bracket only the launches
+// of one kernel class.
+enum { kEvMove = 0, kEvRefine = 1, kEvAgg = 2, kEvOther = 3, kEvScanMoveK = 4, kEvScanRefineK = 5,
+       kEvAggK = 6, kEvClasses = 7 };
+
+struct Timer {
+  gvl_ctx* ctx;
+  bool on;
+  struct Span { int cls; hipEvent_t a, b; };
+  std::vector<Span> spans;
+  hipEvent_t get() {
+    if (ctx->ev_used == ctx->events.size()) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      ctx->events.push_back(e);
+    }
+    return ctx->events[ctx->ev_used++];
+  }
+  int begin(int cls) {
+    if (!on) return -1;
+    hipEvent_t e = get();
+    if (!e) return -1;
+    (void)hipEventRecord(e, ctx->stream);
+    spans.push_back({cls, e, nullptr});
+    return (int)spans.size() - 1;
+  }
+  void end(int h) {
+    if (h < 0) return;
+    hipEvent_t e = get();
+    if (!e) return;
+    (void)hipEventRecord(e, ctx->stream);
+    spans[h].b = e;
+  }
+  void totals(double* ms) {
+    for (int k = 0; k < kEvClasses; ++k) ms[k] = 0.0;
+    for (auto& sp : spans) {
+      float t = 0.f;
+      if (sp.b && hipEventElapsedTime(&t, sp.a, sp.b) == hipSuccess) ms[sp.cls] += t;
+    }
+  }
+};
+
+gvl_status readback(gvl_ctx* ctx, Scalars* dev) {
+  HIP_TRY(hipMemcpyAsync(ctx->host, dev, sizeof(Scalars), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return GVL_OK;
+}
+
+// Bin the items of a graph (or of a capacity array) into S groups and fill
+// `list`: bins 0..kHubBin-1 of every group (group-major), then the hub bin
+// of every group in group order.
+gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int32_t* deg, int64_t n, int S,
+                     bool wide, BinInfo& bins, const int32_t* gid = nullptr, const int32_t* vbase = nullptr) {
+  hipStream_t st = ctx->stream;
+  fill_i32(st, (int32_t*)ws.bb, 0, (int64_t)(sizeof(BinBuf) / sizeof(int32_t)));
+  bin_count(st, off, deg, n, S, wide, gid, vbase, ws.bb);
+  HIP_TRY(hipMemcpyAsync(ctx->hbins, ws.bb, sizeof(BinBuf), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  bins.S = S;
+  int32_t acc = 0;
+  for (int g = 0; g < S; ++g) {
+    bins.gstart[g] = acc;
+    for (int b = 0; b < kHubBin; ++b) {
+      bins.count[g][b] = ctx->hbins->counts[g * kNumBins + b];
+      bins.start[g][b] = acc;
+      ctx->hbins->cursors[g * kNumBins + b] = acc;
+      acc += bins.count[g][b];
+    }
+    bins.gend[g] = acc;
+  }
+  bins.gstart[S] = acc;
+  bins.H0 = acc;
+  for (int g = 0; g < S; ++g) {
+    bins.count[g][kHubBin] = ctx->hbins->counts[g * kNumBins + kHubBin];
+    bins.start[g][kHubBin] = acc;
+    ctx->hbins->cursors[g * kNumBins + kHubBin] = acc;
+    acc += bins.count[g][kHubBin];
+  }
+  bins.H = acc - bins.H0;
+  bins.binned = acc;
+  for (int b = 0; b < kNumBins; ++b) bins.maxsize[b] = ctx->hbins->maxsize[b];
+  HIP_TRY(hipMemcpyAsync(ws.bb->cursors, ctx->hbins->cursors, sizeof(int32_t) * S * kNumBins,
+                         hipMemcpyHostToDevice, st));
+  bin_scatter(st, off, deg, n, S, wide, gid, vbase, ws.bb, ws.list);
+  return GVL_OK;
+}
+
+// Hub plan of one graph (or of the giant communities of an aggregation):
+// chunk / table / slice offsets on the device, task lists, and batches of
+// consecutive hubs of one group whose tables fit the table region together.
+struct HubBatch {
+  int32_t h0, h1, c0, c1, s0, s1;
+  int64_t tbase, tend;
+};
+struct HubPlan {
+  int32_t H = 0;
+  int32_t T = 0;
+  std::vector<std::vector<HubBatch>> groups;  // per group
+};
+
+gvl_status build_hub_plan(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, bool agg, const GraphDesc& g,
+                          const int32_t* yoff, int64_t ncom, HubPlan& plan) {
+  hipStream_t st = ctx->stream;
+  plan = HubPlan();
+  plan.H = bins.H;
+  plan.groups.assign(bins.S, {});
+  if (bins.H == 0) return GVL_OK;
+  const int32_t* items = ws.list + bins.H0;
+  const int32_t H = bins.H;
+  if (agg) gagg_setup(st, yoff, items, H, ncom, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  else hub_setup(st, g.off, g.deg, items, H, g.n, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  exclusive_scan(st, ws.hp_chunk, H, ws.scan_tmp);
+  exclusive_scan(st, ws.hp_tbl, H, ws.scan_tmp);
+  exclusive_scan(st, ws.hp_slice, H, ws.scan_tmp);
+  std::vector<int32_t> hc(H + 1), ht(H + 1), hs(H + 1);
+  HIP_TRY(hipMemcpyAsync(hc.data(), ws.hp_chunk, sizeof(int32_t) * (H + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(ht.data(), ws.hp_tbl, sizeof(int32_t) * (H + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hs.data(), ws.hp_slice, sizeof(int32_t) * (H + 1), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (hc[H] > ws.max_tasks || hs[H] > ws.max_tasks) return GVL_E_WORKSPACE;
+  plan.T = hc[H];
+  hub_tasks(st, H, ws.hp_chunk, ws.hp_slice, ws.chunk_tasks, ws.slice_tasks);
+  const int64_t region = ws.tbl_entries;
+  for (int grp = 0; grp < bins.S; ++grp) {
+    int32_t a = bins.start[grp][kHubBin] - bins.H0;
+    const int32_t e = a + bins.count[grp][kHubBin];
+    while (a < e) {
+      int32_t b = a + 1;
+      while (b < e && (int64_t)(ht[b + 1] - ht[a]) * kTblUnit <= region) ++b;
+      HubBatch hb;
+      hb.h0 = a; hb.h1 = b;
+      hb.c0 = hc[a]; hb.c1 = hc[b];
+      hb.s0 = hs[a]; hb.s1 = hs[b];
+      hb.tbase = (int64_t)ht[a] * kTblUnit;
+      hb.tend = (int64_t)ht[b] * kTblUnit;
+      plan.groups[grp].push_back(hb);
+      a = b;
+    }
+  }
+  return GVL_OK;
+}
+
+HubArgs hub_args(Workspace& ws, const BinInfo& bins) {
+  HubArgs h;
+  memset(&h, 0, sizeof(h));
+  h.items = ws.list + bins.H0;
+  h.chunk_off = ws.hp_chunk; h.tbl_off = ws.hp_tbl; h.slice_off = ws.hp_slice;
+  h.chunk_tasks = ws.chunk_tasks; h.slice_tasks = ws.slice_tasks;
+  h.active = ws.hp_active; h.kid = ws.hp_kid; h.done = ws.hp_done;
+  h.pb_g = ws.pb_g; h.pb_k = ws.pb_k; h.pb_c = ws.pb_c;
+  h.tbl_keys = ws.tbl_keys; h.tbl_vals = ws.tbl_vals;
+  h.tbl_list = ws.tbl_list; h.lcnt = ws.hp_lcnt;
+  h.apre = ws.apre;
+  return h;
+}
+
+// Table slots below `clean` are known to be empty: every use leaves its
+// slots empty, so only the first use of a slot in a call needs clearing.
+struct TableState {
+  int64_t clean = 0;
+  void ensure(hipStream_t st, Workspace& ws, int64_t extent) {
+    if (extent <= clean) return;
+    fill_i32(st, ws.tbl_keys + clean, kEmpty, extent - clean);
+    fill_f64(st, ws.tbl_vals + clean, 0.0, extent - clean);
+    clean = extent;
+  }
+};
+
+// K' (row sums) of a graph: short rows by kernel, hub rows by chunks.
+void graph_weights(gvl_ctx* ctx, Workspace& ws, const GraphDesc& g, int64_t m, const BinInfo& bins,
+                   const HubPlan& plan, int validate) {
+  hipStream_t st = ctx->stream;
+  vertex_weights(st, g, m, ws.K, &ws.sc->accW, ws.sc->flags, validate);
+  if (plan.H > 0) {
+    HubArgs h = hub_args(ws, bins);
+    hub_weights(st, g, h, 0, plan.T, ws.K, &ws.sc->accW, ws.sc->flags, validate);
+  }
+}
+
+void export_graph(gvl_ctx* ctx, const GraphDesc& g, int64_t ncom, PassDebug& pd) {
+  std::vector<int32_t> off(ncom + 1), deg(ncom);
+  (void)hipMemcpyAsync(off.data(), g.off, sizeof(int32_t) * (ncom + 1), hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipMemcpyAsync(deg.data(), g.deg, sizeof(int32_t) * ncom, hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  const int64_t cap = off[ncom];
+  std::vector<int32_t> idx(std::max<int64_t>(cap, 1));
+  std::vector<double> wd(std::max<int64_t>(cap, 1));
+  std::vector<float> wf;
+  (void)hipMemcpyAsync(idx.data(), g.idx, sizeof(int32_t) * cap, hipMemcpyDeviceToHost, ctx->stream);
+  if (g.w_double) {
+    (void)hipMemcpyAsync(wd.data(), g.w, sizeof(double) * cap, hipMemcpyDeviceToHost, ctx->stream);
+  } else {
+    wf.resize(std::max<int64_t>(cap, 1));
+    (void)hipMemcpyAsync(wf.data(), g.w, sizeof(float) * cap, hipMemcpyDeviceToHost, ctx->stream);
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  pd.y_off.assign(ncom + 1, 0);
+  pd.y_idx.clear();
+  pd.y_w.clear();
+  std::vector<std::pair<int32_t, double>> row;
+  for (int64_t r = 0; r < ncom; ++r) {
+    row.clear();
+    for (int32_t k = 0; k < deg[r]; ++k) {
+      const int64_t e = (int64_t)off[r] + k;
+      row.push_back({idx[e], g.w_double ? wd[e] : (double)wf[e]});
+    }
+    std::sort(row.begin(), row.end());
+    for (auto& x : row) { pd.y_idx.push_back(x.first); pd.y_w.push_back(x.second); }
+    pd.y_off[r + 1] = (int32_t)pd.y_idx.size();
+  }
+  pd.m = (int64_t)pd.y_idx.size();
+}
+
+template <class T>
+std::vector<T> to_host(gvl_ctx* ctx, const T* d, int64_t n) {
+  std::vector<T> h(std::max<int64_t>(n, 1));
+  (void)hipMemcpyAsync(h.data(), d, sizeof(T) * n, hipMemcpyDeviceToHost, ctx->stream);
+  (void)hipStreamSynchronize(ctx->stream);
+  h.resize(n);
+  return h;
+}
+
+// Eq. 1 of `membership` on the input graph, computed on the device.
+gvl_status modularity_device(gvl_ctx* ctx, Workspace& ws, const GraphDesc& in, const int32_t* membership,
+                             double W, bool integral, double gamma, double* q) {
+  hipStream_t st = ctx->stream;
+  BinInfo bins;
+  gvl_status s = make_bins(ctx, ws, in.off, in.deg, in.n, 1, true, bins);
+  if (s != GVL_OK) return s;
+  HubPlan plan;
+  s = build_hub_plan(ctx, ws, bins, false, in, nullptr, 0, plan);
+  if (s != GVL_OK) return s;
+  fill_f64(st, ws.Sig, 0.0, in.n);
+  fill_f64(st, ws.sc->acc_d, 0.0, 2);
+  fill_u64(st, ws.sc->acc_u, 0ull, 2);
+  modularity_partial(st, in, membership, ws.Sig, ws.sc->acc_d);
+  if (plan.H > 0) hub_modularity(st, in, hub_args(ws, bins), 0, plan.T, membership, ws.Sig, ws.sc->acc_d);
+  modularity_squares(st, ws.Sig, in.n, integral, ws.sc->acc_d, ws.sc->acc_u);
+  s = readback(ctx, ws.sc);
+  if (s != GVL_OK) return s;
+  const double S1 = ctx->host->acc_d[0];
+  const double S2 = integral ? i128_to_double(ctx->host->acc_u[0], ctx->host->acc_u[1]) : ctx->host->acc_d[1];
+  *q = (W == 0.0) ? 0.0 : S1 / W - gamma * (S2 / (W * W));
+  return GVL_OK;
+}
+
+gvl_status check_args(gvl_ctx* ctx, int64_t n, int64_t m, const int32_t* off, const int32_t* idx,
+                      double resolution, const gvl_options* opt, void* wsp, size_t wsb) {
+  if (!ctx || !opt || n < 0 || m < 0 || m > 2147483647LL || n > 2147483646LL) return GVL_E_INVALID_ARG;
+  if (n > 0 && !off) return GVL_E_INVALID_ARG;
+  if (m > 0 && !idx) return GVL_E_INVALID_ARG;
+  if (!(resolution >= 0.0) || !std::isfinite(resolution)) return GVL_E_RESOLUTION;
+  if (opt->mode != GVL_MODE_FAST && opt->mode != GVL_MODE_DET) return GVL_E_INVALID_ARG;
+  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 1 ||
+      opt->subsweeps > kMaxGroups ||
+      !(opt->tolerance_drop > 0.0) || !(opt->aggregation_tolerance >= 0.0))
+    return GVL_E_INVALID_ARG;
+  size_t need = 0;
+  gvl_workspace_bytes(n, m, opt, &need);
+  if (!wsp || wsb < need) return GVL_E_WORKSPACE;
+  return GVL_OK;
+}
+
+}  // namespace

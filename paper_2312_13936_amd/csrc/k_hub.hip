@@ -196,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     const int32_t i = h.items[p];
     const int32_t d = a.C[i];
     const double ki = a.K[i];
-    const Eval<DET> ev(a, h.kid[p], ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, h.kid[p], ki, a.Sig[d]);
     int32_t* gk = tbl_keys_of(h, p);
     double* gv = tbl_vals_of(h, p);
     const int32_t* lst = tbl_list_of(h, p);
@@ -264,11 +264,15 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
             atomicSub(&a.size[d], 1);
             atomicAdd(&a.size[bc], 1);
             a.C[i] = bc;
-            dq += bg;
+            if (a.gid) atomicAdd(a.dqg + a.gid[i], bg); else dq += bg;
             ++nm;
           } else if (PH == kMove) {
             a.target[i] = bc;
-            if (DET) dqk += bk; else dq += bg;
+            if (a.gid) {
+              if (DET) atomic_add_i128(a.dqg128 + 2 * a.gid[i], bk); else atomicAdd(a.dqg + a.gid[i], bg);
+            } else {
+              if (DET) dqk += bk; else dq += bg;
+            }
           } else {
             a.target[i] = bc;
             a.targeted[bc] = 1;
@@ -376,7 +380,8 @@ void hub_weights(hipStream_t st, const GraphDesc& gd, const HubArgs& h, int32_t 
 // --------------------------------------------------- modularity of hub rows ---
 template <class WT>
 __global__ __launch_bounds__(kBlock) void k_hub_modularity(GraphView<WT> g, HubArgs h, int32_t t0, int32_t t1,
-                                                           const int32_t* C, double* tot, double* acc_d) {
+                                                           const int32_t* C, double* tot, double* acc_d,
+                                                           const int32_t* gid, double* s1g) {
   __shared__ double red[16];
   double s1 = 0.0;
   for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
@@ -385,40 +390,46 @@ __global__ __launch_bounds__(kBlock) void k_hub_modularity(GraphView<WT> g, HubA
     const int32_t beg = g.begin(i), deg = g.degree(i), ci = C[i];
     const int32_t e0 = task.y * kHubChunk;
     const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
-    double k = 0.0;
+    double k = 0.0, sc = 0.0;
     for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
       const double w = g.weight(beg + e);
       k += w;
-      if (C[g.idx[beg + e]] == ci) s1 += w;
+      if (C[g.idx[beg + e]] == ci) sc += w;
     }
     k = block_sum<double>(k, red);
     if (threadIdx.x == 0) atomicAdd(&tot[ci], k);
+    if (gid) {
+      sc = block_sum<double>(sc, red);
+      if (threadIdx.x == 0 && sc != 0.0) atomicAdd(&s1g[gid[i]], sc);
+    } else {
+      s1 += sc;
+    }
   }
   s1 = block_sum<double>(s1, red);
   if (threadIdx.x == 0 && s1 != 0.0) atomicAdd(&acc_d[0], s1);
 }
 
 void hub_modularity(hipStream_t st, const GraphDesc& gd, const HubArgs& h, int32_t c0, int32_t c1, const int32_t* C,
-                    double* tot, double* acc_d) {
+                    double* tot, double* acc_d, const int32_t* gid, double* s1g) {
   if (c1 <= c0) return;
   const int grid = grid_items(c1 - c0, 1, 2048);
   if (gd.w_double)
     hipLaunchKernelGGL(k_hub_modularity<double>, dim3(grid), dim3(kBlock), 0, st, view<double>(gd), h, c0, c1, C, tot,
-                       acc_d);
+                       acc_d, gid, s1g);
   else
     hipLaunchKernelGGL(k_hub_modularity<float>, dim3(grid), dim3(kBlock), 0, st, view<float>(gd), h, c0, c1, C, tot,
-                       acc_d);
+                       acc_d, gid, s1g);
 }
 
 // ------------------------------------------------ giant community rows ---
 template <class WT>
-__global__ void k_member_degrees(GraphView<WT> g, const int32_t* cv, int32_t* mdeg) {
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < g.n; k += (int64_t)gridDim.x * blockDim.x)
+__global__ void k_member_degrees(GraphView<WT> g, const int32_t* cv, int64_t n, int32_t* mdeg) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     mdeg[k] = g.degree(cv[k]);
 }
 void member_degrees(hipStream_t st, const GraphDesc& gd, const int32_t* cv, int64_t n, int32_t* mdeg) {
   if (n > 0) hipLaunchKernelGGL(k_member_degrees<float>, dim3(grid_items(n, kBlock, 16384)), dim3(kBlock), 0, st,
-                                view<float>(gd), cv, mdeg);
+                                view<float>(gd), cv, n, mdeg);
 }
 
 // Chunk gather over the concatenated member rows of community c: arcs

@@ -167,8 +167,13 @@ __device__ __forceinline__ int32_t size_of(const int32_t* off, const int32_t* de
 
 // Binning key of item i: group_of(i, S) * kNumBins + bin(size).  Counts
 // per key and the largest size per bin go to bb.
+__device__ __forceinline__ int group_local(int64_t i, int S, const int32_t* gid, const int32_t* vbase) {
+  return group_of(gid ? i - vbase[gid[i]] : i, S);
+}
+
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const int32_t* deg, int64_t n, int S,
-                                                      bool wide, BinBuf* bb) {
+                                                      bool wide, const int32_t* gid, const int32_t* vbase,
+                                                      BinBuf* bb) {
   __shared__ int32_t h[kMaxGroups * kNumBins], mx[kNumBins];
   const int nk = S * kNumBins;
   for (int k = threadIdx.x; k < nk; k += kBlock) h[k] = 0;
@@ -178,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
     const int32_t d = size_of(off, deg, i);
     const int b = bin_of(d, wide);
     if (b >= 0) {
-      const int grp = (S > 1) ? group_of(i, S) : 0;
+      const int grp = (S > 1) ? group_local(i, S, gid, vbase) : 0;
       atomicAdd(&h[grp * kNumBins + b], 1);
       atomicMax(&mx[b], d);
     }
@@ -188,9 +193,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
     if (h[k]) atomicAdd(&bb->counts[k], h[k]);
   if (threadIdx.x < kNumBins && mx[threadIdx.x]) atomicMax(&bb->maxsize[threadIdx.x], mx[threadIdx.x]);
 }
-void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb) {
+void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
+               const int32_t* gid, const int32_t* vbase, BinBuf* bb) {
   if (n > 0)
-    hipLaunchKernelGGL(k_bin_count, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, st, off, deg, n, S, wide, bb);
+    hipLaunchKernelGGL(k_bin_count, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, st, off, deg, n, S, wide, gid,
+                       vbase, bb);
 }
 
 // Each workgroup takes a contiguous chunk of items, reserves room per key
@@ -198,7 +205,8 @@ void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n
 // that rows of consecutive list entries sit close together in memory).
 constexpr int kBinChunk = 4096;
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, const int32_t* deg, int64_t n, int S,
-                                                        bool wide, BinBuf* bb, int32_t* list) {
+                                                        bool wide, const int32_t* gid, const int32_t* vbase,
+                                                        BinBuf* bb, int32_t* list) {
   __shared__ int32_t h[kMaxGroups * kNumBins], base[kMaxGroups * kNumBins];
   const int nk = S * kNumBins;
   for (int64_t c0 = (int64_t)blockIdx.x * kBinChunk; c0 < n; c0 += (int64_t)gridDim.x * kBinChunk) {
@@ -207,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     const int64_t c1 = (c0 + kBinChunk < n) ? c0 + kBinChunk : n;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
       const int b = bin_of(size_of(off, deg, i), wide);
-      if (b >= 0) atomicAdd(&h[((S > 1) ? group_of(i, S) : 0) * kNumBins + b], 1);
+      if (b >= 0) atomicAdd(&h[((S > 1) ? group_local(i, S, gid, vbase) : 0) * kNumBins + b], 1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nk; k += kBlock) {
@@ -218,18 +226,18 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
       const int b = bin_of(size_of(off, deg, i), wide);
       if (b >= 0) {
-        const int k = ((S > 1) ? group_of(i, S) : 0) * kNumBins + b;
+        const int k = ((S > 1) ? group_local(i, S, gid, vbase) : 0) * kNumBins + b;
         list[base[k] + atomicAdd(&h[k], 1)] = (int32_t)i;
       }
     }
     __syncthreads();
   }
 }
-void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb,
-                 int32_t* list) {
+void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
+                 const int32_t* gid, const int32_t* vbase, BinBuf* bb, int32_t* list) {
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_n(n, kBinChunk, 2048)), dim3(kBlock), 0, st, off, deg, n, S,
-                       wide, bb, list);
+                       wide, gid, vbase, bb, list);
 }
 
 // ---------------------------------------------------------- exclusive scan ---
@@ -335,11 +343,12 @@ void exclusive_scan(hipStream_t st, int32_t* data, int64_t n, int32_t* tmp) {
 }
 
 // ------------------------------------------------------------ relabelling ---
-__global__ void k_mark_used(const int32_t* C, int64_t n, int32_t* used) {
-  GRID_STRIDE(i, n) used[C[i]] = 1;
+__global__ void k_mark_used(const int32_t* C, int64_t n, int32_t* used, const int32_t* gid, const uint8_t* keep) {
+  GRID_STRIDE(i, n) if (!gid || keep[gid[i]]) used[C[i]] = 1;
 }
-void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used) {
-  if (n > 0) hipLaunchKernelGGL(k_mark_used, dim3(grid_n(n)), dim3(kBlock), 0, st, C, n, used);
+void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used, const int32_t* gid,
+               const uint8_t* keep) {
+  if (n > 0) hipLaunchKernelGGL(k_mark_used, dim3(grid_n(n)), dim3(kBlock), 0, st, C, n, used, gid, keep);
 }
 
 __global__ void k_lookup_top(int32_t* top, int64_t N, const int32_t* C, const int32_t* newid, int first) {
@@ -362,8 +371,9 @@ void lookup_raw(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, bool 
 // each vertex also keeps its slot inside its community's member list.
 template <class WT>
 __global__ void k_agg_count(GraphView<WT> g, const int32_t* C, const int32_t* newid, int32_t* lab,
-                            int32_t* rank, int32_t* cnt, int32_t* cap) {
+                            int32_t* rank, int32_t* cnt, int32_t* cap, const int32_t* gid, const uint8_t* keep) {
   GRID_STRIDE(i, g.n) {
+    if (gid && !keep[gid[i]]) { lab[i] = -1; continue; }
     const int32_t c = newid[C[i]];
     lab[i] = c;
     rank[i] = atomicAdd(&cnt[c], 1);
@@ -372,16 +382,16 @@ __global__ void k_agg_count(GraphView<WT> g, const int32_t* C, const int32_t* ne
   }
 }
 void agg_count(hipStream_t st, const GraphDesc& gd, const int32_t* C, const int32_t* newid, int32_t* lab,
-               int32_t* rank, int32_t* cnt, int32_t* cap) {
+               int32_t* rank, int32_t* cnt, int32_t* cap, const int32_t* gid, const uint8_t* keep) {
   if (gd.n <= 0) return;
   GraphView<float> g{gd.n, gd.off, gd.deg, gd.idx, nullptr};
   hipLaunchKernelGGL(k_agg_count<float>, dim3(grid_n(gd.n)), dim3(kBlock), 0, st, g, C, newid, lab, rank,
-                     cnt, cap);
+                     cnt, cap, gid, keep);
 }
 
 __global__ void k_agg_fill(const int32_t* lab, const int32_t* rank, const int32_t* coff, int64_t n,
                            int32_t* cv) {
-  GRID_STRIDE(i, n) cv[coff[lab[i]] + rank[i]] = (int32_t)i;
+  GRID_STRIDE(i, n) if (lab[i] >= 0) cv[coff[lab[i]] + rank[i]] = (int32_t)i;
 }
 void agg_fill(hipStream_t st, const int32_t* lab, const int32_t* rank, const int32_t* coff, int64_t n,
               int32_t* cv) {
@@ -390,7 +400,7 @@ void agg_fill(hipStream_t st, const int32_t* lab, const int32_t* rank, const int
 
 __global__ void k_next_labels(const int32_t* lab, const int32_t* CB, const int32_t* brank, int64_t n,
                               int32_t* start) {
-  GRID_STRIDE(i, n) start[lab[i]] = brank[CB[i]];
+  GRID_STRIDE(i, n) if (lab[i] >= 0) start[lab[i]] = brank[CB[i]];
 }
 void next_labels(hipStream_t st, const int32_t* lab, const int32_t* CB, const int32_t* brank, int64_t n,
                  int32_t* start) {
@@ -425,7 +435,7 @@ void apply_canonical(hipStream_t st, int32_t* top, const int32_t* first, const i
 // acc_d[0]) and tot[C[i]] += K_i with K_i the row sum.
 template <class WT>
 __global__ __launch_bounds__(kBlock) void k_mod_partial(GraphView<WT> g, const int32_t* C, double* tot,
-                                                        double* acc_d) {
+                                                        double* acc_d, const int32_t* gid, double* s1g) {
   __shared__ double red[16];
   double s1 = 0.0;
   const int64_t n = g.n;
@@ -458,21 +468,23 @@ __global__ __launch_bounds__(kBlock) void k_mod_partial(GraphView<WT> g, const i
       if (lane_id() == q) { k = pk; sg = ps; }
     }
     atomic_add_keyed<double>(tot, ci, k, i < n && k != 0.0);
-    if (i < n) s1 += sg;
+    if (gid) atomic_add_keyed<double>(s1g, i < n ? gid[i] : 0, sg, i < n && sg != 0.0);
+    else if (i < n) s1 += sg;
   }
   const double t = block_sum<double>(s1, red);
   if (threadIdx.x == 0) atomicAdd(&acc_d[0], t);
 }
-void modularity_partial(hipStream_t st, const GraphDesc& gd, const int32_t* C, double* tot, double* acc_d) {
+void modularity_partial(hipStream_t st, const GraphDesc& gd, const int32_t* C, double* tot, double* acc_d,
+                        const int32_t* gid, double* s1g) {
   if (gd.n <= 0) return;
   if (gd.w_double) {
     GraphView<double> g{gd.n, gd.off, gd.deg, gd.idx, (const double*)gd.w};
     hipLaunchKernelGGL(k_mod_partial<double>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st, g, C,
-                       tot, acc_d);
+                       tot, acc_d, gid, s1g);
   } else {
     GraphView<float> g{gd.n, gd.off, gd.deg, gd.idx, (const float*)gd.w};
     hipLaunchKernelGGL(k_mod_partial<float>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st, g, C,
-                       tot, acc_d);
+                       tot, acc_d, gid, s1g);
   }
 }
 

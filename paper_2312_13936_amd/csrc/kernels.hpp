@@ -60,6 +60,14 @@ struct BinBuf {
   int32_t pad;
 };
 
+// Per-graph constants of a fused batch (several graphs in one union graph).
+struct GraphParam {
+  double inv_m;             // 2 / W
+  double gk_scale;          // 2 gamma / W^2
+  long long W;              // exact total weight (deterministic mode)
+  long long p;              // resolution numerator (deterministic mode)
+};
+
 // State read and written by the local-moving / refinement decision kernels.
 struct ScanArgs {
   int32_t* C;               // community of each vertex (C')
@@ -88,6 +96,13 @@ struct ScanArgs {
   int32_t* wd_c;
   int32_t* wd_ok;           // bit 0: eligible (partition 0), bit 1: table overflow
   int32_t* wd_done;         // zero between launches
+  // fused batches: graph of each vertex, per-graph constants, per-graph
+  // summed gains and refinement moves; gid == nullptr for a single graph
+  const int32_t* gid;
+  const GraphParam* gp;
+  double* dqg;              // [G] fast mode
+  unsigned long long* dqg128;  // [G][lo, hi] deterministic mode
+  unsigned long long* mvg;  // [G] refinement moves
   int32_t sync_moves;       // local-moving records decisions (committed per group) instead of
                             // committing at once: bit 0 rows <= kBinMax[4], bit 1 longer rows
 };
@@ -190,15 +205,51 @@ void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const Hub
 // K[i] += sums of the chunks of hub rows (K[i] of hubs zeroed by the caller).
 void hub_weights(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_t c0, int32_t c1, double* K,
                  double* accW, int32_t* flags, int validate);
-// Modularity partial sums of hub rows: tot[C[i]] += K part, acc_d[0] += sigma part.
+// Modularity partial sums of hub rows: tot[C[i]] += K part, acc_d[0] (or
+// s1g[gid[i]]) += sigma part.
 void hub_modularity(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_t c0, int32_t c1,
-                    const int32_t* C, double* tot, double* acc_d);
+                    const int32_t* C, double* tot, double* acc_d, const int32_t* gid = nullptr,
+                    double* s1g = nullptr);
 // Aggregation of giant communities.
 void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom,
                 int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off);
 void member_degrees(hipStream_t st, const GraphDesc& g, const int32_t* cv, int64_t n, int32_t* mdeg);
 void gagg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
                int32_t s0, int32_t s1, int64_t* launches);
+
+// ---- fused batches (k_batch.hip)
+enum BatchState : uint8_t { kBatchCont = 0, kBatchEnd = 1, kBatchDone = 2 };
+// Device view of a batch of graphs.  vb: vertex bases of all graphs (G + 1);
+// ub, uab: vertex and arc bases of the kept graphs in the union.
+struct BatchDesc {
+  const int32_t* const* off;
+  const int32_t* const* idx;
+  const float* const* w;     // entries may be nullptr (unit weights)
+  const int64_t* n;
+  const int64_t* m;
+  const int64_t* vb;
+  const int64_t* ub;
+  const int64_t* uab;
+};
+// flags[g] |= 1 bad CSR, 2 weight not positive and finite, 4 weight not an
+// integer in [1, 2^24]; W[g] += weights.  total = vb[G].
+void batch_validate(hipStream_t st, const BatchDesc& d, int32_t G, int64_t total, int32_t* flags, double* W);
+// Union CSR of the kept graphs (src[g] = desc index of kept graph g; total =
+// ub[G] vertices): uoff[0..total) (uoff[total] set by the caller), uidx,
+// uw (float), gid.
+void batch_build(hipStream_t st, const BatchDesc& d, const int32_t* src, int32_t G, int64_t total, int32_t* uoff,
+                 int32_t* uidx, float* uw, int32_t* gid);
+void mask_flags(hipStream_t st, uint8_t* flag, const int32_t* gid, const uint8_t* active, int64_t n);
+void graph_nonzero(hipStream_t st, const GraphDesc& g, const int32_t* gid, int32_t* nz);
+void gather_at(hipStream_t st, const int32_t* data, const int32_t* pos, int32_t count, int32_t* out);
+void gid_next(hipStream_t st, const int32_t* C, const int32_t* newid, const int32_t* gid, const uint8_t* keep,
+              int64_t n, int32_t* out);
+void lookup_batch(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, const int32_t* newid,
+                  const int32_t* gid0, const uint8_t* state, const int32_t* vcur, const int32_t* goff0, bool first);
+void batch_outputs(hipStream_t st, const int32_t* canon, int64_t N, const int32_t* gid0, const int32_t* goff0,
+                   int32_t* const* out);
+void mod_squares_batch(hipStream_t st, const double* tot, int64_t n, const int32_t* cb, int32_t G, double* s2d,
+                       unsigned long long* s2u);
 
 // ---- primitives (k_prims.hip)
 int scan_tiles(int64_t n);  // number of tiles used by exclusive_scan
@@ -227,19 +278,27 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
 // Degree binning into S groups: bin_count fills bb->counts / bb->maxsize,
 // bin_scatter places item i at bb->cursors[group(i) * kNumBins + bin(i)]++.
 // wide = false leaves bins kWideBin0.. empty (aggregation capacities).
-void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb);
-void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide, BinBuf* bb,
-                 int32_t* list);
-// used[c] = 1 for every label c in C[0..n) (used zeroed by the caller).
-void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used);
+// gid / vbase (fused batches, else nullptr): the group of item i is taken
+// from its id inside its own graph, i - vbase[gid[i]].
+void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
+               const int32_t* gid, const int32_t* vbase, BinBuf* bb);
+void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
+                 const int32_t* gid, const int32_t* vbase, BinBuf* bb, int32_t* list);
+// used[c] = 1 for every label c in C[0..n) (used zeroed by the caller);
+// with gid / keep only for vertices of graphs g with keep[g].
+void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used, const int32_t* gid = nullptr,
+               const uint8_t* keep = nullptr);
 // top[v] = newid[C[top[v]]]  (first = 1: top[v] = newid[C[v]]).
 void lookup_top(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, const int32_t* newid,
                 bool first);
 // top[v] = C[top[v]] (or C[v] when first).
 void lookup_raw(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, bool first);
 // lab[i] = newid[C[i]]; rank[i] = atomic slot in cnt[lab]; cap[lab] += degree(i).
+// With gid / keep, vertices of graphs without keep get lab[i] = -1 and are
+// skipped by agg_fill and next_labels.
 void agg_count(hipStream_t st, const GraphDesc& g, const int32_t* C, const int32_t* newid,
-               int32_t* lab, int32_t* rank, int32_t* cnt, int32_t* cap);
+               int32_t* lab, int32_t* rank, int32_t* cnt, int32_t* cap, const int32_t* gid = nullptr,
+               const uint8_t* keep = nullptr);
 void agg_fill(hipStream_t st, const int32_t* lab, const int32_t* rank, const int32_t* coff, int64_t n,
               int32_t* cv);
 // start[lab[i]] = brank[CB[i]] (move-based labels of super-vertices).
@@ -252,8 +311,9 @@ void apply_canonical(hipStream_t st, int32_t* top, const int32_t* first, const i
 // Modularity (Eq. 1): S1 = sum of intra-community arc weights (acc_d[0]),
 // tot[c] += K_i; then S2 = sum tot[c]^2 (exact int128 into acc_u[0..1] when
 // integral, else double into acc_d[1]).  Hub rows are left to hub_modularity.
+// gid / s1g (fused batches): S1 per graph into s1g[gid[i]].
 void modularity_partial(hipStream_t st, const GraphDesc& g, const int32_t* C, double* tot,
-                        double* acc_d);
+                        double* acc_d, const int32_t* gid = nullptr, double* s1g = nullptr);
 void check_offsets(hipStream_t st, const int32_t* off, int64_t n, int64_t m, int32_t* flags);
 void modularity_squares(hipStream_t st, const double* tot, int64_t n, bool integral, double* acc_d,
                         unsigned long long* acc_u);

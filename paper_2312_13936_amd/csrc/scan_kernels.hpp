@@ -68,15 +68,23 @@ __device__ __forceinline__ void flush_acc(const ScanArgs& a, Acc& acc) {
 // Gain of one candidate; updates the running best.
 template <bool DET>
 struct Eval {
-  double kid, ki, sd, gk;
+  double kid, ki, sd, gk, inv_m;
   long long kidi, kii, sdi;
   i128 A, B;
-  __device__ __forceinline__ Eval(const ScanArgs& a, double kid_, double ki_, double sd_) {
+  // i: the vertex (its graph's constants in a fused batch)
+  __device__ __forceinline__ Eval(const ScanArgs& a, int32_t i, double kid_, double ki_, double sd_) {
+    double im = a.inv_m, gks = a.gk_scale;
+    long long W = a.W, p = a.p;
+    if (a.gid) {
+      const GraphParam q = a.gp[a.gid[i]];
+      im = q.inv_m; gks = q.gk_scale; W = q.W; p = q.p;
+    }
     kid = kid_; ki = ki_; sd = sd_;
-    gk = a.gk_scale * ki_;
+    inv_m = im;
+    gk = gks * ki_;
     kidi = (long long)kid_; kii = (long long)ki_; sdi = (long long)sd_;
-    A = (i128)65536 * (i128)a.W;
-    B = (i128)a.p * (i128)kii;
+    A = (i128)65536 * (i128)W;
+    B = (i128)p * (i128)kii;
   }
   __device__ __forceinline__ void operator()(const ScanArgs& a, int32_t c, double kic, double sc,
                                              double& bg, i128& bk, int32_t& bc) const {
@@ -84,11 +92,25 @@ struct Eval {
       const i128 k = A * (i128)((long long)kic - kidi) - B * (i128)(kii + (long long)sc - sdi);
       if (better_k(k, c, bk, bc)) { bk = k; bc = c; }
     } else {
-      const double x = (kic - kid) * a.inv_m - gk * (ki + sc - sd);
+      const double x = (kic - kid) * inv_m - gk * (ki + sc - sd);
       if (better_f(x, c, bg, bc)) { bg = x; bc = c; }
     }
   }
 };
+
+// Adds the gain of a move of vertex i to the iteration's sum: the
+// workgroup's accumulator for a single graph, the graph's own sum in a
+// fused batch.
+template <bool DET>
+__device__ __forceinline__ void add_gain(const ScanArgs& a, Acc& acc, int32_t i, double bg, i128 bk) {
+  if (a.gid) {
+    const int32_t g = a.gid[i];
+    if (DET) atomic_add_i128(a.dqg128 + 2 * g, bk);
+    else atomicAdd(a.dqg + g, bg);
+  } else {
+    if (DET) acc.dqk += bk; else acc.dq += bg;
+  }
+}
 
 // Workgroup argmax of (gain or key, id) over NW wavefronts; the result is
 // valid in every thread.
@@ -229,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
                                      [&](int32_t c, double w) { lds_insert(keys, vals, lg, c, w); });
     kid = sum_xor<G>(kid);
     wave_sync();
-    const Eval<DET> ev(a, kid, ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
@@ -247,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
         atomicSub(&a.size[d], 1);
         atomicAdd(&a.size[bc], 1);
         a.C[i] = bc;
-        acc.dq += bg;
+        add_gain<DET>(a, acc, i, bg, bk);
         ++acc.nm;
       }
       for (int32_t e = gl; e < deg; e += G) {
@@ -257,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
     } else if (PH == kMove) {
       if (gl == 0) {
         a.target[i] = bc;
-        if (DET) acc.dqk += bk; else acc.dq += bg;
+        add_gain<DET>(a, acc, i, bg, bk);
       }
     } else {
       if (gl == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
@@ -317,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     kid = block_sum<double>(kid, s_g);
     if (threadIdx.x == 0) s_kid = kid;
     __syncthreads();
-    const Eval<DET> ev(a, s_kid, ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, s_kid, ki, a.Sig[d]);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
@@ -348,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
         atomicSub(&a.size[d], 1);
         atomicAdd(&a.size[bc], 1);
         a.C[i] = bc;
-        acc.dq += bg;
+        add_gain<DET>(a, acc, i, bg, bk);
         ++acc.nm;
       }
       for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
@@ -358,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     } else if (PH == kMove) {
       if (threadIdx.x == 0) {
         a.target[i] = bc;
-        if (DET) acc.dqk += bk; else acc.dq += bg;
+        add_gain<DET>(a, acc, i, bg, bk);
       }
     } else {
       if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
@@ -442,7 +464,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
     if (threadIdx.x == 0) s_d[0] = kid;
     __syncthreads();
     kid = s_d[0];
-    const Eval<DET> ev(a, kid, ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
     eval_table<TS / kWideThreads, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
     block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
   }
@@ -502,11 +524,11 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
           atomicSub(&a.size[d], 1);
           atomicAdd(&a.size[bc], 1);
           a.C[i] = bc;
-          acc.dq += bg;
+          add_gain<DET>(a, acc, i, bg, bk);
           ++acc.nm;
         } else if (PH == kMove) {
           a.target[i] = bc;
-          if (DET) acc.dqk += bk; else acc.dq += bg;
+          add_gain<DET>(a, acc, i, bg, bk);
         } else {
           a.target[i] = bc;
           a.targeted[bc] = 1;
@@ -554,6 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
         atomicAdd(&a.size[t], 1);
         a.C[i] = t;
         ++nm;
+        if (PH == kRefine && a.gid) atomicAdd(&a.mvg[a.gid[i]], 1ull);
       }
     }
     if (PH == kMove) {

@@ -144,6 +144,96 @@ def test_batch_workspace_checks(eng):
     assert code == 0 and qs == []
 
 
+# ------------------------------------------------------------- fused batch ---
+
+def run_fused(eng, gs, mode, resolutions=None, corrupt=None, **kw):
+    tensors = [dev(g) for g in gs]
+    mems = [torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda") for g in gs]
+    if corrupt is not None:
+        tensors[corrupt][0][1] = tensors[corrupt][0][-1] + 1
+    res = resolutions or [1.0] * len(gs)
+    descs = [gvl.graph_desc(o, i, w, mm, r) for (o, i, w), mm, r in zip(tensors, mems, res)]
+    opt = eng.options(mode, **kw)
+    wsb = gvl.gvl_fused_workspace_bytes(descs, opt)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    code, qs, sts = gvl.gvl_leiden_fused(eng.ctx, descs, opt, ws.data_ptr(), wsb)
+    torch.cuda.synchronize()
+    return code, [m[:g.n].cpu().numpy() for m, g in zip(mems, gs)], qs, sts
+
+
+def solo_opts(eng, g, mode, resolution=1.0, **kw):
+    off, idx, w = dev(g)
+    r = eng.run(off, idx, w, resolution, eng.options(mode, **kw))
+    torch.cuda.synchronize()
+    return r.membership.cpu().numpy(), r.modularity
+
+
+def fused_graphs():
+    from test_gpu_parity import GRAPHS
+    gs = batch_graphs()
+    gs += [GRAPHS[k]() for k in ("hubs-wide", "hub+cliques", "grid64-w100", "er-selfloops", "planted-small")]
+    return gs
+
+
+def test_fused_det_matches_solo(eng):
+    gs = fused_graphs()
+    print("fused det: %d graphs" % len(gs), flush=True)
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_DET)
+    assert code == 0 and all(x == 0 for x in sts), sts
+    for g, mem, q in zip(gs, mems, qs):
+        m1, q1 = solo(eng, g, gvl.GVL_MODE_DET)
+        assert np.array_equal(mem, m1), g.name
+        assert q == q1, g.name
+
+
+def test_fused_det_resolutions_and_subsweeps(eng):
+    gs = lfr_mix(8, 1000, 20000, seed=17) + [gen.ring_of_cliques(30, 3), gen.rmat(12, 16, seed=2)]
+    res = [0.5, 1.0, 1.5, 0.25, 2.0, 1.0, 0.75, 1.25, 1.0, 0.5]
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_DET, resolutions=res, subsweeps=7)
+    assert code == 0
+    for g, r, mem, q in zip(gs, res, mems, qs):
+        m1, q1 = solo_opts(eng, g, gvl.GVL_MODE_DET, r, subsweeps=7)
+        assert np.array_equal(mem, m1), (g.name, r)
+        assert q == q1, (g.name, r)
+        o = oracle.leiden(g, mode=oracle.DET_SYNC, resolution=r, subsweeps=7)
+        assert np.array_equal(mem, o.membership) and q == o.q, (g.name, r)
+
+
+def test_fused_fast_quality(eng):
+    gs = fused_graphs()
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_FAST)
+    assert code == 0
+    check_fast_mix(gs, mems, qs)
+
+
+def test_fused_fast_sync_matches_solo(eng):
+    gs = batch_graphs()
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_FAST, sync_moves=3)
+    assert code == 0
+    for g, mem, q in zip(gs, mems, qs):
+        m1, q1 = solo_opts(eng, g, gvl.GVL_MODE_FAST, sync_moves=3)
+        assert np.array_equal(mem, m1), g.name
+        assert q == q1, g.name
+
+
+def test_fused_bad_graph_in_mix(eng):
+    gs = batch_graphs()[:8]
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_DET, corrupt=3)
+    assert code == -10
+    assert sts[3] == -2 and all(x == 0 for k, x in enumerate(sts) if k != 3)
+    for k, g in enumerate(gs):
+        if k != 3:
+            assert np.array_equal(mems[k], solo(eng, g, gvl.GVL_MODE_DET)[0]), g.name
+
+
+def test_fused_noninteger_weights_det(eng):
+    g = gen.ring_of_cliques(10, 5)
+    h = gen.Graph(g.n, g.m, g.offsets, g.indices, g.weights * 0.5, None, "half-weights")
+    code, mems, qs, sts = run_fused(eng, [g, h, g], gvl.GVL_MODE_DET)
+    assert code == -10 and sts == [0, -4, 0]
+    assert np.array_equal(mems[0], mems[2]) and qs[0] == qs[2]
+
+
 # ------------------------------------------------------------------ serving ---
 
 WAIT_MS = 60000  # a request that is not done by then fails the test (GVL_E_BUSY)
