@@ -330,6 +330,11 @@ def main():
     ap.add_argument("--subsweeps", type=int, default=0, help="0 = library default")
     ap.add_argument("--cpu-sample-scale", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch-serve", action="store_true",
+                    help="default workload: skip the batched and served parts of the metric")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--serve-requests", type=int, default=400)
+    ap.add_argument("--serve-pool", type=int, default=32)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed region "
                          "(a kernel of known traffic for scaling profiler byte counters)")
@@ -449,6 +454,34 @@ def main():
     }
     eng.close()
     del off, idx, wt
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    if args.workload == "rmat-s24" and not args.no_batch_serve:
+        # the metric's other two parts: batched graphs/s vs plain, p99 latency
+        import argparse as _ap
+        sub = _ap.Namespace(**vars(args))
+        sub.graphs, sub.plain_graphs, sub.steps, sub.warmup, sub.lanes = args.batch_graphs, 128, 2, 1, 0
+        try:
+            b = bench_batch(sub, mode)
+            out["batched"] = {k: b[k] for k in ("batched_graphs_per_s", "batched_edges_per_s", "plain_graphs_per_s",
+                                                "plain_edges_per_s", "speedup_vs_plain", "modularity_mean",
+                                                "modularity_mean_plain_sample", "modularity_mean_fused_sample",
+                                                "plain_sample", "ms_per_step")}
+            out["batched"]["workload"] = b["config"]["workload"]
+        except Exception as e:  # reported, the main measurement stands
+            out["batched"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
+        sub = _ap.Namespace(**vars(args))
+        sub.pool, sub.requests, sub.lanes, sub.load = args.serve_pool, args.serve_requests, 4, 0.8
+        try:
+            r = bench_serve(sub, mode)
+            out["serving"] = {k: r[k] for k in ("p50_ms", "p99_ms", "mean_ms", "edges_per_s", "requests_per_s",
+                                                "plain_mean_service_ms", "max_running", "failed",
+                                                "modularity_max_abs_diff_vs_alone")}
+            out["serving"]["workload"] = r["config"]["workload"]
+        except Exception as e:
+            out["serving"] = {"error": repr(e)}
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle on R-MAT scale %d" % args.cpu_sample_scale)
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_scale)
