@@ -262,6 +262,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   fill_i32(st, ws.hp_done, 0, ch.n);
   fill_i32(st, ws.hp_lcnt, 0, ch.n);
   fill_i32(st, ws.wd_done, 0, ws.max_wide);
+  fill_i32(st, ws.wd_ctr, 0, 2);
   ScanArgs a;
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
@@ -269,6 +270,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.tbl_keys = ws.tbl_keys; a.tbl_vals = ws.tbl_vals;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
+  a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
   a.gp = B.gp; a.dqg = B.dqg; a.dqg128 = B.dqg128; a.mvg = B.mvg;
   const bool sync_mv = det || opt->sync_moves != 0;
   a.sync_moves = det ? 3 : (opt->sync_moves & 3);

@@ -144,6 +144,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   fill_i32(st, ws.hp_done, 0, n);
   fill_i32(st, ws.hp_lcnt, 0, n);
   fill_i32(st, ws.wd_done, 0, ws.max_wide);
+  fill_i32(st, ws.wd_ctr, 0, 2);
   if (opt->validate) {
     check_offsets(st, d_off, n, m, ws.sc->flags);
     s = readback(ctx, ws.sc);
@@ -158,6 +159,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.tbl_keys = ws.tbl_keys; a.tbl_vals = ws.tbl_vals;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
+  a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
   const bool sync_mv = det || opt->sync_moves != 0;
   a.sync_moves = det ? 3 : (opt->sync_moves & 3);
 

@@ -59,7 +59,7 @@ struct Workspace {
   // wide rows
   double* wd_g;
   i128_t* wd_k;
-  int32_t *wd_c, *wd_ok, *wd_done;
+  int32_t *wd_c, *wd_ok, *wd_done, *wd_ctr;
   int64_t max_wide;
 
   Scalars* sc;
@@ -134,6 +134,7 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.wd_c = (int32_t*)take(4 * wq);
   w.wd_ok = (int32_t*)take(4 * wq);
   w.wd_done = (int32_t*)take(4 * (size_t)w.max_wide);
+  w.wd_ctr = (int32_t*)take(4 * 2);
   w.bytes = o;
   return w;
 }

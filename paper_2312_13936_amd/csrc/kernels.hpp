@@ -96,6 +96,8 @@ struct ScanArgs {
   int32_t* wd_c;
   int32_t* wd_ok;           // bit 0: eligible (partition 0), bit 1: table overflow
   int32_t* wd_done;         // zero between launches
+  int32_t* wd_next;         // task counter of the persistent wide kernel (zero between launches)
+  int32_t* wd_exit;         // workgroups finished (zero between launches)
   // fused batches: graph of each vertex, per-graph constants, per-graph
   // summed gains and refinement moves; gid == nullptr for a single graph
   const int32_t* gid;

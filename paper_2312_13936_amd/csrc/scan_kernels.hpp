@@ -403,10 +403,12 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
 // for rows of at most 2^12 P arcs) cancels the move of its vertex.
 constexpr int kWideThreads = 1024;
 constexpr int kWideLg = 13;
+constexpr int64_t kWideGrid = 256;  // persistent workgroups: one per CU (the LDS table fits once)
 
 struct WideLaunch {
   int32_t count[kWideClasses];  // vertices of class k in this launch
   int32_t start[kWideClasses];  // their offset in the list
+  int32_t tasks;                // sum of count[k] << k
 };
 
 template <class WT, int PH, bool DET>
@@ -420,71 +422,82 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
   __shared__ i128 s_k[NW];
   __shared__ int32_t s_c[NW];
   __shared__ double s_d[NW];
-  __shared__ int s_ok, s_ovf, s_last, s_take;
-  // task -> (class k, vertex r of the launch, partition)
-  int32_t b = blockIdx.x, r = 0;
-  int k = 0;
-  for (; k < kWideClasses - 1; ++k) {
-    const int32_t tk = wl.count[k] << k;
-    if (b < tk) break;
-    b -= tk;
-    r += wl.count[k];
-  }
-  const int P = 1 << k;
-  const int32_t vloc = b >> k;
-  const int part = b & (P - 1);
-  r += vloc;
-  const int32_t i = list[wl.start[k] + vloc];
-  const int32_t beg = g.begin(i), deg = g.degree(i);
-  const int lg = (P == 1) ? min(kWideLg, ceil_log2(2 * (int64_t)deg)) : kWideLg;
-  const int ts = 1 << lg;
-  for (int s = threadIdx.x; s < ts; s += kWideThreads) { keys[s] = kEmpty; vals[s] = 0.0; }
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    if (part == 0 || PH == kRefine) ok = (int)Decide<PH, DET>::eligible(a, i);
-    if (PH == kMove && part == 0 && ok) a.flag[i] = 0;  // processed (Alg. 2 prune)
-    s_ok = ok;
-    s_ovf = 0;
-  }
-  __syncthreads();
-  const int ok = s_ok;
+  __shared__ int s_ok, s_ovf, s_last, s_take, s_task;
+  // the table starts empty; every task leaves it empty (eval_table clears
+  // what it reads, and nothing is inserted for a skipped vertex)
+  for (int s = threadIdx.x; s < TS; s += kWideThreads) { keys[s] = kEmpty; vals[s] = 0.0; }
   Acc acc;
-  int32_t bc = -1;
-  double bg = 0.0;
-  i128 bk = 0;
-  const int32_t d = a.C[i];
-  const double ki = a.K[i];
-  if (ok) {  // uniform
-    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
-    double kid = scan_row<4, kWideThreads, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
-      if ((int)(wide_part(c) & (uint32_t)(P - 1)) != part) return;
-      if (!lds_insert_bounded(keys, vals, lg, c, w)) s_ovf = 1;
-    });
-    kid = block_sum<double>(kid, s_d);
-    if (threadIdx.x == 0) s_d[0] = kid;
+  // persistent workgroups take tasks from a counter, so a vertex that is
+  // skipped (not flagged, not isolated) costs a few loads, not a dispatch
+  for (;;) {
     __syncthreads();
-    kid = s_d[0];
-    const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
-    eval_table<TS / kWideThreads, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
-    block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
-  }
-  const int ovf = s_ovf;
-  int last = 1;
-  if (P > 1) {
+    if (threadIdx.x == 0) s_task = atomicAdd(a.wd_next, 1);
+    __syncthreads();
+    int32_t b = s_task;
+    if (b >= wl.tasks) break;  // uniform
+    // task -> (class k, vertex r of the launch, partition)
+    int32_t r = 0;
+    int k = 0;
+    for (; k < kWideClasses - 1; ++k) {
+      const int32_t tk = wl.count[k] << k;
+      if (b < tk) break;
+      b -= tk;
+      r += wl.count[k];
+    }
+    const int P = 1 << k;
+    const int32_t vloc = b >> k;
+    const int part = b & (P - 1);
+    r += vloc;
+    const int32_t i = list[wl.start[k] + vloc];
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int lg = (P == 1) ? min(kWideLg, ceil_log2(2 * (int64_t)deg)) : kWideLg;
+    const int ts = 1 << lg;
     if (threadIdx.x == 0) {
-      const int64_t q = (int64_t)r * kWideMaxParts + part;
-      a.wd_g[q] = bg;
-      a.wd_k[q] = bk;
-      a.wd_c[q] = bc;
-      a.wd_ok[q] = ok | (ovf << 1);
-      __threadfence();
-      const int prev = atomicAdd(&a.wd_done[r], 1);
-      s_last = (prev == P - 1) ? 1 : 0;
+      int ok = 1;
+      if (part == 0 || PH == kRefine) ok = (int)Decide<PH, DET>::eligible(a, i);
+      if (PH == kMove && part == 0 && ok) a.flag[i] = 0;  // processed (Alg. 2 prune)
+      s_ok = ok;
+      s_ovf = 0;
     }
     __syncthreads();
-    last = s_last;
-  }
-  if (last) {  // uniform
+    const int ok = s_ok;
+    if (!ok && P == 1) continue;  // uniform: nothing to decide, nothing to combine
+    int32_t bc = -1;
+    double bg = 0.0;
+    i128 bk = 0;
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
+    if (ok) {  // uniform
+      const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+      double kid = scan_row<4, kWideThreads, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
+        if ((int)(wide_part(c) & (uint32_t)(P - 1)) != part) return;
+        if (!lds_insert_bounded(keys, vals, lg, c, w)) s_ovf = 1;
+      });
+      kid = block_sum<double>(kid, s_d);
+      if (threadIdx.x == 0) s_d[0] = kid;
+      __syncthreads();
+      kid = s_d[0];
+      const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
+      eval_table<TS / kWideThreads, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
+      block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
+    }
+    const int ovf = s_ovf;
+    int last = 1;
+    if (P > 1) {
+      if (threadIdx.x == 0) {
+        const int64_t q = (int64_t)r * kWideMaxParts + part;
+        a.wd_g[q] = bg;
+        a.wd_k[q] = bk;
+        a.wd_c[q] = bc;
+        a.wd_ok[q] = ok | (ovf << 1);
+        __threadfence();
+        const int prev = atomicAdd(&a.wd_done[r], 1);
+        s_last = (prev == P - 1) ? 1 : 0;
+      }
+      __syncthreads();
+      last = s_last;
+    }
+    if (!last) continue;  // uniform
     int ok0 = ok, ovf_any = ovf;
     if (P > 1) {
       __threadfence();
@@ -542,6 +555,14 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
         const int32_t j = g.idx[beg + e];
         if (j != i) a.flag[j] = 1;
       }
+    }
+  }
+  // the last workgroup out resets the task counter for the next launch
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(a.wd_exit, 1) == (int)gridDim.x - 1) {
+      *a.wd_next = 0;
+      *a.wd_exit = 0;
     }
   }
   flush_acc<PH, DET>(a, acc);
@@ -695,8 +716,9 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
     tasks += (int64_t)wl.count[k] << k;
   }
   if (tasks > 0) {
-    hipLaunchKernelGGL((k_decide_wide<WT, PH, DET>), dim3((unsigned)tasks), dim3(kWideThreads), 0, st, g, a,
-                       list, wl);
+    wl.tasks = (int32_t)tasks;
+    const unsigned grid = (unsigned)(tasks < kWideGrid ? tasks : kWideGrid);
+    hipLaunchKernelGGL((k_decide_wide<WT, PH, DET>), dim3(grid), dim3(kWideThreads), 0, st, g, a, list, wl);
     ++*launches;
   }
   (void)hub_grid;  // the hub bin goes through the chunked hub path
