@@ -292,8 +292,10 @@ gvl_status build_hub_plan(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, bool
   if (bins.H == 0) return GVL_OK;
   const int32_t* items = ws.list + bins.H0;
   const int32_t H = bins.H;
-  if (agg) gagg_setup(st, yoff, items, H, ncom, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
-  else hub_setup(st, g.off, g.deg, items, H, g.n, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  // Distinct keys of one table are at most the items with arcs (bins.binned):
+  // communities / vertices without arcs are never anyone's neighbour.
+  if (agg) gagg_setup(st, yoff, items, H, bins.binned, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  else hub_setup(st, g.off, g.deg, items, H, bins.binned, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
   exclusive_scan(st, ws.hp_chunk, H, ws.scan_tmp);
   exclusive_scan(st, ws.hp_tbl, H, ws.scan_tmp);
   exclusive_scan(st, ws.hp_slice, H, ws.scan_tmp);
