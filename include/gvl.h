@@ -239,6 +239,12 @@ gvl_status gvl_server_wait(gvl_server_t srv, uint64_t ticket, int64_t timeout_ms
 gvl_status gvl_server_cancel(gvl_server_t srv, uint64_t ticket);
 /* Forgets a finished or cancelled request (GVL_E_BUSY while it waits or runs). */
 gvl_status gvl_server_release(gvl_server_t srv, uint64_t ticket);
+/* Micro-batching: a lane that admits a request of at most max_vertices
+ * vertices also takes up to max_batch - 1 further waiting requests of at
+ * most that size whose fused workspace fits, and runs them together through
+ * gvl_leiden_fused (each result as alone).  max_batch 1 turns it off.
+ * Default: 32 requests of at most 262144 vertices. */
+gvl_status gvl_server_set_batching(gvl_server_t srv, int32_t max_batch, int64_t max_vertices);
 gvl_status gvl_server_stats(gvl_server_t srv, gvl_server_info* info);
 /* Finishes running requests, cancels waiting ones, joins the workers. */
 gvl_status gvl_server_destroy(gvl_server_t srv);

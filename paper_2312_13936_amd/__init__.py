@@ -87,7 +87,8 @@ EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_by
            "gvl_modularity", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
            "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_fused_workspace_bytes", "gvl_leiden_fused",
            "gvl_server_create", "gvl_server_submit",
-           "gvl_server_poll", "gvl_server_wait", "gvl_server_cancel", "gvl_server_release", "gvl_server_stats",
+           "gvl_server_poll", "gvl_server_wait", "gvl_server_cancel", "gvl_server_release",
+           "gvl_server_set_batching", "gvl_server_stats",
            "gvl_server_destroy", "gvl_status_string"]
 
 _lib = None
@@ -125,6 +126,7 @@ def load_library(path: str = LIB_PATH):
     lib.gvl_server_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(gvl_request_info)]
     lib.gvl_server_cancel.argtypes = [vp, ctypes.c_uint64]
     lib.gvl_server_release.argtypes = [vp, ctypes.c_uint64]
+    lib.gvl_server_set_batching.argtypes = [vp, i32, i64]
     lib.gvl_server_stats.argtypes = [vp, ctypes.POINTER(gvl_server_info)]
     lib.gvl_server_destroy.argtypes = [vp]
     for f in EXPORTS[:-1]:
@@ -287,6 +289,10 @@ def gvl_server_release(srv, ticket: int) -> None:
     _check(load_library().gvl_server_release(srv, ticket), "gvl_server_release")
 
 
+def gvl_server_set_batching(srv, max_batch: int, max_vertices: int) -> None:
+    _check(load_library().gvl_server_set_batching(srv, max_batch, max_vertices), "gvl_server_set_batching")
+
+
 def gvl_server_stats(srv) -> gvl_server_info:
     info = gvl_server_info()
     _check(load_library().gvl_server_stats(srv, ctypes.byref(info)), "gvl_server_stats")
@@ -424,6 +430,9 @@ class Server:
 
     def release(self, ticket: int) -> None:
         gvl_server_release(self.srv, ticket)
+
+    def set_batching(self, max_batch: int, max_vertices: int) -> None:
+        gvl_server_set_batching(self.srv, max_batch, max_vertices)
 
     def stats(self) -> gvl_server_info:
         return gvl_server_stats(self.srv)

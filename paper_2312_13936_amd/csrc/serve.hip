@@ -113,6 +113,11 @@ class Arena {
     }
   }
   size_t total() const { return total_; }
+  size_t largest() const {
+    size_t mx = 0;
+    for (const auto& kv : free_) mx = std::max(mx, kv.second);
+    return mx;
+  }
   size_t used() const { return used_; }
   size_t peak() const { return peak_; }
 
@@ -212,6 +217,51 @@ struct gvl_server {
   uint64_t next_id = 1;
   bool stop = false;
   int64_t completed = 0, running = 0, max_running = 0;
+  // micro-batching: a lane that admits a request of at most batch_vertices
+  // vertices fuses up to batch_max waiting requests of that size into one
+  // gvl_leiden_fused run (results identical to solo runs)
+  int32_t batch_max = 32;
+  int64_t batch_vertices = 262144;
+
+  // With the lock held: the waiting requests fused with the admitted `head`
+  // (its own workspace at head.off), their workspace allocated in the arena.
+  // Returns the group (head first); group size 1 keeps the solo workspace.
+  std::vector<uint64_t> fuse_group(uint64_t head, size_t* off, size_t* bytes) {
+    std::vector<uint64_t> group{head};
+    Request& h = reqs[head];
+    *off = h.off;
+    *bytes = h.ws_bytes;
+    if (batch_max < 2 || h.g.n > batch_vertices) return group;
+    std::vector<gvl_graph_desc> descs{h.g};
+    alloc.release(h.off, h.ws_bytes);
+    const size_t room = alloc.largest();
+    size_t fb = 0;
+    for (auto it = pending.begin(); it != pending.end() && (int32_t)group.size() < batch_max; ++it) {
+      const Request& q = reqs[*it];
+      if (q.g.n > batch_vertices) continue;
+      descs.push_back(q.g);
+      size_t b = 0;
+      if (gvl_fused_workspace_bytes((int32_t)descs.size(), descs.data(), &opt, &b) != GVL_OK || b > room) {
+        descs.pop_back();
+        break;
+      }
+      group.push_back(*it);
+      fb = b;
+    }
+    size_t o = 0;
+    if (group.size() > 1 && alloc.alloc(fb, &o)) {
+      for (size_t j = 1; j < group.size(); ++j) {
+        pending.erase(std::find(pending.begin(), pending.end(), group[j]));
+        if (!pending.empty() && pending.front() != group[j]) ++reqs[pending.front()].bypassed;
+      }
+      *off = o;
+      *bytes = fb;
+      return group;
+    }
+    (void)alloc.alloc(h.ws_bytes, &h.off);  // the block just freed: always fits again
+    *off = h.off;
+    return std::vector<uint64_t>{head};
+  }
 
   void worker(int k) {
     (void)hipSetDevice(device);
@@ -237,26 +287,44 @@ struct gvl_server {
         cv.wait(lk);
       }
       if (!r) return;  // stopping
-      r->state = GVL_REQ_RUNNING;
-      r->t_start = std::chrono::steady_clock::now();
-      ++running;
+      size_t goff = 0, gbytes = 0;
+      const std::vector<uint64_t> group = fuse_group(id, &goff, &gbytes);
+      const auto t_start = std::chrono::steady_clock::now();
+      std::vector<gvl_graph_desc> descs;
+      for (uint64_t gid : group) {
+        Request& q = reqs[gid];
+        q.state = GVL_REQ_RUNNING;
+        q.t_start = t_start;
+        descs.push_back(q.g);
+      }
+      running += (int64_t)group.size();
       max_running = std::max(max_running, running);
-      const gvl_graph_desc g = r->g;
-      char* ws = arena + r->off;
-      const size_t wsb = r->ws_bytes;
+      char* ws = arena + goff;
       lk.unlock();
-      double q = 0.0;
-      gvl_status st = gvl_leiden(lanes[k].ctx, g.n, g.m, g.d_offsets, g.d_indices, g.d_weights, g.resolution, &opt,
-                                 ws, wsb, g.d_membership, &q, nullptr);
+      std::vector<double> qs(group.size(), 0.0);
+      std::vector<gvl_status> sts(group.size(), GVL_OK);
+      if (group.size() == 1) {
+        const gvl_graph_desc& g = descs[0];
+        sts[0] = gvl_leiden(lanes[k].ctx, g.n, g.m, g.d_offsets, g.d_indices, g.d_weights, g.resolution, &opt, ws,
+                            gbytes, g.d_membership, &qs[0], nullptr);
+      } else {
+        const gvl_status all = gvl_leiden_fused(lanes[k].ctx, (int32_t)group.size(), descs.data(), &opt, ws, gbytes,
+                                                qs.data(), sts.data());
+        if (all != GVL_OK && all != GVL_E_BATCH)
+          for (auto& x : sts) x = all;
+      }
       lk.lock();
-      Request& rr = reqs[id];
-      rr.q = q;
-      rr.result = st;
-      rr.t_done = std::chrono::steady_clock::now();
-      rr.state = GVL_REQ_DONE;
-      alloc.release(rr.off, rr.ws_bytes);
-      --running;
-      ++completed;
+      const auto t_done = std::chrono::steady_clock::now();
+      for (size_t j = 0; j < group.size(); ++j) {
+        Request& rr = reqs[group[j]];
+        rr.q = qs[j];
+        rr.result = sts[j];
+        rr.t_done = t_done;
+        rr.state = GVL_REQ_DONE;
+      }
+      alloc.release(goff, gbytes);
+      running -= (int64_t)group.size();
+      completed += (int64_t)group.size();
       cv.notify_all();
     }
   }
@@ -359,6 +427,14 @@ gvl_status gvl_server_release(gvl_server_t s, uint64_t ticket) {
   if (r.state == GVL_REQ_PENDING || r.state == GVL_REQ_RUNNING) return GVL_E_BUSY;
   s->reqs.erase(it);
   s->cv.notify_all();
+  return GVL_OK;
+}
+
+gvl_status gvl_server_set_batching(gvl_server_t s, int32_t max_batch, int64_t max_vertices) {
+  if (!s || max_batch < 1 || max_vertices < 0) return GVL_E_INVALID_ARG;
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->batch_max = max_batch;
+  s->batch_vertices = max_vertices;
   return GVL_OK;
 }
 
