@@ -26,6 +26,9 @@ METRIC = "Leiden edges/s at matched modularity; batched graphs/s vs plain; p99 l
 # rocprofv3 FETCH_SIZE / WRITE_SIZE of one step of the default workload (fast
 # mode), valid while the kernel sources are unchanged
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "leiden_rmat_s24_fast_counters.md")
+# the sequential oracle's modularity on the same R-MAT graph (written by
+# tests/golden/make_rmat_s24_reference.py)
+ORACLE_Q_FILE = os.path.join(ROOT, "tests", "golden", "rmat_s24_oracle.json")
 HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
@@ -70,6 +73,16 @@ def agg_bytes(st) -> float:
     (neighbour id, weight, its super-vertex label), per arc written 8 B, per
     member vertex 12 B (member id, row offset, row length)."""
     return 12.0 * st.agg_arcs + 8.0 * st.agg_out_arcs + 12.0 * st.agg_vertices
+
+
+def oracle_q(workload):
+    """Recorded sequential-oracle modularity of the workload's graph, if any."""
+    if workload != "rmat-s24" or not os.path.exists(ORACLE_Q_FILE):
+        return None
+    with open(ORACLE_Q_FILE) as f:
+        rec = json.load(f)
+    return {"value": rec["modularity"], "mode": rec["mode"], "passes": rec["passes"],
+            "source": os.path.relpath(ORACLE_Q_FILE, ROOT)}
 
 
 def cpu_baseline(scale: int):
@@ -328,6 +341,7 @@ def main():
     ap.add_argument("--load", type=float, default=0.8, help="lfr-serve: offered load / plain service rate")
     ap.add_argument("--mode", default="fast", choices=["fast", "det"])
     ap.add_argument("--subsweeps", type=int, default=0, help="0 = library default")
+    ap.add_argument("--sync-moves", type=int, default=-1, help="fast mode local-moving schedule (-1 = default)")
     ap.add_argument("--cpu-sample-scale", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-serve", action="store_true",
@@ -378,6 +392,8 @@ def main():
     kw = dict(profile=1)
     if args.subsweeps:
         kw["subsweeps"] = args.subsweeps
+    if args.sync_moves >= 0:
+        kw["sync_moves"] = args.sync_moves
     opt = eng.options(mode, **kw)
     for k in range(args.warmup):
         r = eng.run(off, idx, wt, 1.0, opt)
@@ -432,10 +448,12 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": w["desc"], "vertices": g.n, "arcs": g.m, "mode": args.mode,
-                   "subsweeps": opt.subsweeps, "resolution": 1.0, "tolerance": opt.tolerance,
+                   "subsweeps": opt.subsweeps, "sync_moves": opt.sync_moves, "resolution": 1.0,
+                   "tolerance": opt.tolerance,
                    "max_passes": opt.max_passes, "parallelism": "single GPU"},
         "modularity": float(np.median(qs)),
         "modularity_min": float(min(qs)),
+        "modularity_oracle": oracle_q(args.workload),
         "communities": int(last.num_communities),
         "passes": int(last.passes),
         "phases": phase,

@@ -67,10 +67,11 @@ typedef struct {
   int32_t validate;              /* 0: none; 1: CSR bounds and weight checks on the device */
   int32_t profile;               /* 1: time every kernel class with HIP events (fills gvl_stats ms_*) */
   int32_t debug_trace;           /* 1: keep per-pass labels and super-vertex CSRs for gvl_debug_* */
-  int32_t sync_moves;            /* fast mode local-moving: 0 commits every move at once
-                                    (asynchronous); bit 0 (rows of <= 128 arcs) and bit 1 (longer
-                                    rows) instead decide the group on one snapshot and commit it
-                                    afterwards (the deterministic schedule, FP64 gains) */
+  int32_t sync_moves;            /* fast mode local-moving: 0 commits every move at once (the
+                                    paper's asynchronous updates, Sec. 4.1); bit 0 (rows of <= 128
+                                    arcs) and bit 1 (longer rows) instead decide a group on one
+                                    snapshot and commit it afterwards (the deterministic schedule with
+                                    FP64 gains).  Default 3. */
   int32_t reserved[6];
 } gvl_options;
 

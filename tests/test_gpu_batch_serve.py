@@ -62,13 +62,13 @@ def batch_graphs():
     return gs
 
 
-def run_batch(eng, gs, mode, lanes, corrupt=None):
+def run_batch(eng, gs, mode, lanes, corrupt=None, **kw):
     tensors = [dev(g) for g in gs]
     mems = [torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda") for g in gs]
     if corrupt is not None:  # a decreasing offset makes that graph's CSR invalid
         tensors[corrupt][0][1] = tensors[corrupt][0][-1] + 1
     descs = [gvl.graph_desc(o, i, w, mm) for (o, i, w), mm in zip(tensors, mems)]
-    opt = eng.options(mode)
+    opt = eng.options(mode, **kw)
     wsb = gvl.gvl_batch_workspace_bytes(descs, opt, lanes)
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     code, qs, sts = gvl.gvl_leiden_batch(eng.ctx, descs, opt, lanes, ws.data_ptr(), wsb)
@@ -113,7 +113,7 @@ def check_fast_mix(gs, mems, qs):
 def test_batch_fast_quality(eng):
     gs = batch_graphs()
     print("batch fast: %d graphs" % len(gs), flush=True)
-    code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_FAST, 6)
+    code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_FAST, 6, sync_moves=0)
     assert code == 0
     check_fast_mix(gs, mems, qs)
 
@@ -199,9 +199,10 @@ def test_fused_det_resolutions_and_subsweeps(eng):
         assert np.array_equal(mem, o.membership) and q == o.q, (g.name, r)
 
 
-def test_fused_fast_quality(eng):
+@pytest.mark.parametrize("sync_moves", [3, 0])
+def test_fused_fast_quality(eng, sync_moves):
     gs = fused_graphs()
-    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_FAST)
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
     assert code == 0
     check_fast_mix(gs, mems, qs)
 
@@ -297,9 +298,9 @@ def test_serve_mix_fast_quality(eng):
     opt = gvl.Leiden.options(gvl.GVL_MODE_FAST)
     arena = 6 * max(footprint(g, opt) for g in gs)
     print("serve fast: %d requests" % len(gs), flush=True)
-    mix, st = serve(gs, tensors, gvl.GVL_MODE_FAST, 4, arena, alone=False)
-    # asynchronous commits make every fast run differ a little, alone or in
-    # a mix, so the mix is held to the fast-mode quality bar
+    mix, st = serve(gs, tensors, gvl.GVL_MODE_FAST, 4, arena, alone=False, sync_moves=0)
+    # asynchronous commits make every run differ a little, alone or in a
+    # mix, so the mix is held to the fast-mode quality bar
     check_fast_mix(gs, [m for m, _ in mix], [q for _, q in mix])
 
 

@@ -158,11 +158,12 @@ def oracle_reference_q(g, orders=4):
     return q0, min(qs)
 
 
+@pytest.mark.parametrize("sync_moves", [3, 0])
 @pytest.mark.parametrize("name", list(GRAPHS))
-def test_fast_mode_quality(eng, name):
+def test_fast_mode_quality(eng, name, sync_moves):
     g = graph(name)
-    print("fast quality:", name, g.n, g.m, flush=True)
-    mem, q, st = run(eng, g, gvl.GVL_MODE_FAST)
+    print("fast quality:", name, g.n, g.m, "sync_moves", sync_moves, flush=True)
+    mem, q, st = run(eng, g, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
     q0, qmin = oracle_reference_q(g)
     assert q == oracle.modularity(g, mem)  # reported Q is Eq. 1 of the returned membership
     assert q >= qmin - FAST_TOL, "fast Q %.6f vs oracle %.6f (lowest over numberings %.6f)" % (q, q0, qmin)
@@ -171,11 +172,11 @@ def test_fast_mode_quality(eng, name):
     assert np.all(np.diff(first) > 0) and mem[0] == 0  # first-occurrence labels
 
 
-@pytest.mark.parametrize("sync_moves", [1, 2, 3])
+@pytest.mark.parametrize("sync_moves", [0, 1, 2])
 @pytest.mark.parametrize("name", ["rmat-s14", "planted-C1", "hubs-wide", "grid200-w100"])
 def test_fast_mode_sync_moves(eng, name, sync_moves):
-    # local-moving that decides a group on one snapshot and commits it
-    # afterwards, for short rows (bit 0), long rows (bit 1) or both
+    # asynchronous local-moving (0), or group-synchronous for short rows
+    # (bit 0) or long rows (bit 1) only; the default is both bits
     g = graph(name)
     mem, q, st = run(eng, g, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
     q0, qmin = oracle_reference_q(g, orders=2)
