@@ -211,18 +211,23 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
-      const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
-      const int32_t c = glb_load_key(gk, slot);
-      if (c == kEmpty) continue;
-      if (c != d) {
-        ++nc;
-        ev(a, c, glb_load_val(gv, slot), a.Sig[c], bg, bk, bc);
+    // a slice past the end of a sparse table's list has nothing to read: it
+    // only reports an empty partial result (no workgroup-wide reduction)
+    const bool empty = q0 >= lim;
+    if (!empty) {  // uniform
+      for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
+        const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
+        const int32_t c = glb_load_key(gk, slot);
+        if (c == kEmpty) continue;
+        if (c != d) {
+          ++nc;
+          ev(a, c, glb_load_val(gv, slot), a.Sig[c], bg, bk, bc);
+        }
+        gk[slot] = kEmpty;
+        gv[slot] = 0.0;
       }
-      gk[slot] = kEmpty;
-      gv[slot] = 0.0;
+      block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     }
-    block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     if (threadIdx.x == 0) {
       h.pb_g[t] = bg;
       h.pb_k[t] = bk;
@@ -514,6 +519,17 @@ __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int3
     const int64_t lim = dense ? ts : len;
     const int64_t q0 = (int64_t)task.y * kHubSlice;
     const int64_t q1 = (lim - q0 < kHubSlice) ? lim : q0 + kHubSlice;
+    if (q0 >= lim) {  // uniform: a slice past the end of the list only counts itself done
+      if (threadIdx.x == 0) {
+        __threadfence();
+        const int nsl = h.slice_off[p + 1] - h.slice_off[p];
+        if (atomicAdd(&h.done[p], 1) == nsl - 1) {
+          h.done[p] = 0;
+          h.lcnt[p] = 0;
+        }
+      }
+      continue;
+    }
     // kHubSlice / kBlock consecutive positions per thread
     constexpr int PER = kHubSlice / kBlock;
     const int64_t my0 = q0 + (int64_t)threadIdx.x * PER;
