@@ -157,6 +157,23 @@ __device__ __forceinline__ bool lds_insert_bounded(int32_t* keys, double* vals, 
   return false;
 }
 
+// As lds_insert_bounded for a table of any size ts: the home slot is the
+// high word of (multiplicative hash of c) * ts, which for ts = 2^lg is
+// hslot(c, lg); probing wraps at ts.
+__device__ __forceinline__ bool lds_insert_sized(int32_t* keys, double* vals, uint32_t ts, int32_t c, double w) {
+  uint32_t h = (uint32_t)(((u64)((uint32_t)c * 0x9E3779B1u) * (u64)ts) >> 32);
+  for (uint32_t probe = 0; probe < ts; ++probe) {
+    int32_t k = keys[h];
+    if (k == c) { atomicAdd(&vals[h], w); return true; }
+    if (k == kEmpty) {
+      int32_t old = atomicCAS(&keys[h], kEmpty, c);
+      if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return true; }
+    }
+    h = (h + 1u == ts) ? 0u : h + 1u;
+  }
+  return false;
+}
+
 // Partition hash of a community id for wide rows (Wellons' "lowbias32"
 // integer mixer); independent of hslot, which takes the high bits of a
 // multiplicative hash.
@@ -240,6 +257,69 @@ __device__ __forceinline__ void atomic_add_keyed(T* p, int32_t key, T v, bool ac
     rem &= ~m;
   }
   if ((rem >> lane_id()) & 1) atomicAdd(&p[key], v);
+}
+
+// Workgroup-combined keyed adds pv[key] += dv, pu[key] += du.  Threads put
+// their entries (any number, at most 2 NT distinct keys per flush) into an
+// LDS table of 4 NT slots, where equal keys are summed; the flush adds each
+// distinct key once to global memory.  A community shared by many threads
+// of the workgroup (the totals of a giant community) so costs one atomic per
+// workgroup instead of one per member.  put is per thread; clear and flush
+// must be reached by every thread of the workgroup; flush leaves the table
+// empty.
+template <int NT>
+struct KeyedLds {
+  static constexpr int kSlots = 4 * NT;
+  int32_t key[kSlots];
+  double v[kSlots];
+  int32_t u[kSlots];
+};
+
+template <int NT>
+__device__ __forceinline__ void keyed_clear(KeyedLds<NT>& t) {
+  for (int s = threadIdx.x; s < KeyedLds<NT>::kSlots; s += NT) {
+    t.key[s] = kEmpty;
+    t.v[s] = 0.0;
+    t.u[s] = 0;
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ void keyed_put(KeyedLds<NT>& t, int32_t key, double dv, int32_t du) {
+  constexpr int kLg = __builtin_ctz(KeyedLds<NT>::kSlots);
+  constexpr uint32_t mask = KeyedLds<NT>::kSlots - 1;
+  static_assert((KeyedLds<NT>::kSlots & mask) == 0, "power-of-two table");
+  uint32_t h = hslot(key, kLg);
+  while (true) {
+    const int32_t k = t.key[h];
+    if (k == key) break;
+    if (k == kEmpty) {
+      const int32_t old = atomicCAS(&t.key[h], kEmpty, key);
+      if (old == kEmpty || old == key) break;
+    }
+    h = (h + 1u) & mask;
+  }
+  if (dv != 0.0) atomicAdd(&t.v[h], dv);
+  if (du != 0) atomicAdd(&t.u[h], du);
+}
+
+template <int NT>
+__device__ __forceinline__ void keyed_flush(KeyedLds<NT>& t, double* pv, int32_t* pu) {
+  __syncthreads();
+  for (int s = threadIdx.x; s < KeyedLds<NT>::kSlots; s += NT) {
+    const int32_t k = t.key[s];
+    if (k != kEmpty) {
+      const double v = t.v[s];
+      const int32_t u = t.u[s];
+      if (v != 0.0) atomicAdd(&pv[k], v);
+      if (pu && u != 0) atomicAdd(&pu[k], u);
+      t.key[s] = kEmpty;
+      t.v[s] = 0.0;
+      t.u[s] = 0;
+    }
+  }
+  __syncthreads();
 }
 
 // Sub-sweep group of vertex i: MurmurHash3's 32-bit finalizer of i, mod S.

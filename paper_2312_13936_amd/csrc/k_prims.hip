@@ -135,14 +135,14 @@ __global__ void k_check_offsets(const int32_t* off, int64_t n, int64_t m, int32_
 }
 
 // ------------------------------------------------------- community totals ---
-__global__ void k_community_totals(const int32_t* C, const double* K, double* Sig, int32_t* size,
-                                   int64_t n) {
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+__global__ __launch_bounds__(kBlock) void k_community_totals(const int32_t* C, const double* K, double* Sig,
+                                                             int32_t* size, int64_t n) {
+  __shared__ KeyedLds<kBlock> kt;
+  keyed_clear(kt);
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
     const int64_t i = base + threadIdx.x;
-    const bool ok = i < n;
-    const int32_t c = ok ? C[i] : 0;
-    atomic_add_keyed<double>(Sig, c, ok ? K[i] : 0.0, ok);
-    atomic_add_keyed<int32_t>(size, c, 1, ok);
+    if (i < n) keyed_put(kt, C[i], K[i], 1);
+    keyed_flush(kt, Sig, size);
   }
 }
 void community_totals(hipStream_t st, const int32_t* C, const double* K, double* Sig, int32_t* size,
@@ -474,9 +474,115 @@ __global__ __launch_bounds__(kBlock) void k_mod_partial(GraphView<WT> g, const i
   const double t = block_sum<double>(s1, red);
   if (threadIdx.x == 0) atomicAdd(&acc_d[0], t);
 }
+// The same partials for one graph, arc-parallel: a workgroup takes kBlock
+// consecutive rows (hub rows excluded), lays their arcs end to end, and
+// every lane takes one arc per step, so the label gathers of short and long
+// rows alike are issued by full wavefronts.  The row of an arc comes from a
+// binary search over the workgroup's row offsets in LDS; the row sums K_i
+// are reduced per row by a segmented wavefront scan (rows of consecutive
+// arcs are non-decreasing across the lanes) and one LDS add per segment,
+// and added to the community totals through the workgroup-combined table.
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_mod_rows(GraphView<WT> g, const int32_t* C, double* tot,
+                                                     double* acc_d) {
+  constexpr int U = 4;  // arcs per lane per step
+  __shared__ int32_t s_off[kBlock + 1];
+  __shared__ int32_t s_beg[kBlock];
+  __shared__ int32_t s_c[kBlock];
+  __shared__ double s_k[kBlock];
+  __shared__ int32_t s_wsum[kBlock / kWave];
+  __shared__ double red[16];
+  __shared__ KeyedLds<kBlock> kt;
+  keyed_clear(kt);
+  double s1 = 0.0;
+  const int64_t n = g.n;
+  const int t = threadIdx.x;
+  const int wv = t / kWave;
+  for (int64_t r0 = (int64_t)blockIdx.x * kBlock; r0 < n; r0 += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = r0 + t;
+    int32_t deg = 0, beg = 0, ci = -1;
+    if (i < n) { beg = g.begin(i); deg = g.degree(i); ci = C[i]; }
+    if (deg > kBinMax[kHubBin - 1]) deg = 0;  // hub rows: hub_modularity
+    int incl = deg;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    if (lane_id() == kWave - 1) s_wsum[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < kBlock / kWave; ++k) {
+      if (k < wv) before += s_wsum[k];
+      total += s_wsum[k];
+    }
+    s_off[t] = before + incl - deg;
+    if (t == 0) s_off[kBlock] = total;
+    s_beg[t] = beg;
+    s_c[t] = ci;
+    s_k[t] = 0.0;
+    __syncthreads();
+    for (int32_t qb = 0; qb < total; qb += U * kBlock) {  // uniform over the workgroup
+      int32_t row[U], j[U];
+      double w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t q = qb + u * kBlock + t;
+        row[u] = -1;
+        j[u] = 0;
+        w[u] = 0.0;
+        if (q < total) {
+          int lo = 0, hi = kBlock;  // s_off[lo] <= q < s_off[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_off[mid] <= q) lo = mid; else hi = mid;
+          }
+          const int64_t e = (int64_t)s_beg[lo] + (q - s_off[lo]);
+          row[u] = lo;
+          j[u] = g.idx[e];
+          w[u] = g.weight(e);
+        }
+      }
+      int32_t cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) cj[u] = (row[u] >= 0) ? C[j[u]] : -1;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (row[u] >= 0 && cj[u] == s_c[row[u]]) s1 += w[u];
+        double v = w[u];
+        const int32_t r = row[u];
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const double v2 = __shfl_down(v, o);
+          const int32_t r2 = __shfl_down(r, o);
+          if (lane_id() + o < kWave && r2 == r) v += v2;
+        }
+        const int32_t rp = __shfl_up(r, 1);
+        if (r >= 0 && (lane_id() == 0 || rp != r)) atomicAdd(&s_k[r], v);
+      }
+    }
+    __syncthreads();
+    const double k = s_k[t];
+    if (i < n && k != 0.0) keyed_put(kt, ci, k, 0);
+    keyed_flush(kt, tot, (int32_t*)nullptr);  // also: s_* are rewritten by the next rows
+  }
+  const double s = block_sum<double>(s1, red);
+  if (threadIdx.x == 0) atomicAdd(&acc_d[0], s);
+}
+
 void modularity_partial(hipStream_t st, const GraphDesc& gd, const int32_t* C, double* tot, double* acc_d,
                         const int32_t* gid, double* s1g) {
   if (gd.n <= 0) return;
+  if (!gid) {
+    const int grid = grid_n(gd.n, kBlock, 8192);
+    if (gd.w_double)
+      hipLaunchKernelGGL(k_mod_rows<double>, dim3(grid), dim3(kBlock), 0, st,
+                         GraphView<double>{gd.n, gd.off, gd.deg, gd.idx, (const double*)gd.w}, C, tot, acc_d);
+    else
+      hipLaunchKernelGGL(k_mod_rows<float>, dim3(grid), dim3(kBlock), 0, st,
+                         GraphView<float>{gd.n, gd.off, gd.deg, gd.idx, (const float*)gd.w}, C, tot, acc_d);
+    return;
+  }
   if (gd.w_double) {
     GraphView<double> g{gd.n, gd.off, gd.deg, gd.idx, (const double*)gd.w};
     hipLaunchKernelGGL(k_mod_partial<double>, dim3(grid_n(gd.n, kBlock, 2048)), dim3(kBlock), 0, st, g, C,

@@ -20,18 +20,21 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 // bin with d <= kBinMax[b]; d == 0 is never binned.  Bins 0-4 map a group of
 // kBinLanes[b] lanes of one wavefront to each item with an LDS hash table of
 // 2^kBinLg[b] slots; bin 5 maps a 256-thread workgroup with an LDS table.
-// Bins 6-8 ("wide" rows, vertex scan only) map 1, 2 or 4 workgroups of 1024
-// threads to a vertex, each with a 2^13-slot LDS table for one partition of
-// the neighbour communities; aggregation bins skip them (wide = false), so a
-// capacity above kBinMax[5] goes straight to the last bin.  The last bin
-// (hubs / giant communities) uses global-memory tables.
+// Bins 6-8 ("wide" rows, vertex scan only) map 1, 1 or 2 workgroups of 1024
+// threads to a vertex, each with an LDS table of up to kWideSlots slots for
+// one partition of the neighbour communities; aggregation bins skip them
+// (wide = false), so a capacity above kBinMax[5] goes straight to the last
+// bin.  The last bin (hubs / giant communities) uses global-memory tables.
 constexpr int kNumBins = 10;
 constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 4096, 8192, 16384, 0x7fffffff};
-constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 1024, 2048, 4096, 256};
-constexpr int kBinLg[kNumBins] = {3, 4, 5, 6, 8, 11, 13, 13, 13, 0};
-constexpr int kWideBin0 = 6;       // first wide bin; bin kWideBin0 + k uses 2^k partitions
+constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 1024, 1024, 2048, 256};
+constexpr int kBinLg[kNumBins] = {3, 4, 5, 6, 8, 11, 13, 14, 14, 0};
+constexpr int kWideBin0 = 6;       // first wide bin
 constexpr int kWideClasses = 3;
-constexpr int kWideMaxParts = 1 << (kWideClasses - 1);
+// bin kWideBin0 + k uses 2^kWideShift[k] partitions of the key space
+constexpr int kWideShift[kWideClasses] = {0, 0, 1};
+constexpr int kWideMaxParts = 2;
+constexpr int kWideSlots = 12288;  // 144 KiB of LDS (keys + FP64 values)
 constexpr int kHubBin = kNumBins - 1;
 
 // Local-moving and refinement visit the vertices in S pseudo-random groups

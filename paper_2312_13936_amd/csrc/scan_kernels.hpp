@@ -391,19 +391,21 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
 
 // ------------------------------------ wide rows: P workgroups per vertex ---
 // Vertices of the wide bins (kBinMax[5] < deg <= kBinMax[kHubBin - 1]).  The
-// P = 2^k workgroups of a vertex of wide class k each stream the whole row,
-// but accumulate only the neighbour communities c with wide_part(c) mod P
-// equal to their partition, in an LDS table of up to 2^13 slots, so no
-// global table or global atomics are needed.  K_{i->d} is a plain sum over
-// the row.  Every partition evaluates its own candidates; the last one to
-// finish reduces the partial bests and applies the decision.  Only partition
-// 0 tests (and, for local-moving, clears) the pruning flag: the others scan
-// regardless, and the decision follows partition 0.  A partition whose keys
-// overflow the table (more than 2^13 distinct; statistically out of reach
-// for rows of at most 2^12 P arcs) cancels the move of its vertex.
+// P = 2^kWideShift[k] workgroups of a vertex of wide class k each stream the
+// whole row, but accumulate only the neighbour communities c with
+// wide_part(c) mod P equal to their partition, in an LDS table of up to
+// kWideSlots slots, so no global table or global atomics are needed.  Rows
+// of up to 8192 arcs fit one table (P = 1, load factor <= 2/3) and are read
+// once.  K_{i->d} is a plain sum over the row.  Every partition evaluates
+// its own candidates; the last one to finish reduces the partial bests and
+// applies the decision.  Only partition 0 tests (and, for local-moving,
+// clears) the pruning flag: the others scan regardless, and the decision
+// follows partition 0.  A partition whose keys overflow the table (more than
+// kWideSlots distinct; statistically out of reach for rows of at most 8192 P
+// arcs) cancels the move of its vertex.
 constexpr int kWideThreads = 1024;
-constexpr int kWideLg = 13;
 constexpr int64_t kWideGrid = 256;  // persistent workgroups: one per CU (the LDS table fits once)
+static_assert(kWideSlots % kWideThreads == 0, "wide table: whole slots per thread");
 
 struct WideLaunch {
   int32_t count[kWideClasses];  // vertices of class k in this launch
@@ -414,7 +416,7 @@ struct WideLaunch {
 template <class WT, int PH, bool DET>
 __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, ScanArgs a,
                                                               const int32_t* __restrict__ list, WideLaunch wl) {
-  constexpr int TS = 1 << kWideLg;
+  constexpr int TS = kWideSlots;
   constexpr int NW = kWideThreads / kWave;
   __shared__ int32_t keys[TS];
   __shared__ double vals[TS];
@@ -439,19 +441,24 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
     int32_t r = 0;
     int k = 0;
     for (; k < kWideClasses - 1; ++k) {
-      const int32_t tk = wl.count[k] << k;
+      const int32_t tk = wl.count[k] << kWideShift[k];
       if (b < tk) break;
       b -= tk;
       r += wl.count[k];
     }
-    const int P = 1 << k;
-    const int32_t vloc = b >> k;
+    const int sh = kWideShift[k];
+    const int P = 1 << sh;
+    const int32_t vloc = b >> sh;
     const int part = b & (P - 1);
     r += vloc;
     const int32_t i = list[wl.start[k] + vloc];
     const int32_t beg = g.begin(i), deg = g.degree(i);
-    const int lg = (P == 1) ? min(kWideLg, ceil_log2(2 * (int64_t)deg)) : kWideLg;
-    const int ts = 1 << lg;
+    // P == 1: 2 deg slots (whole multiples of the workgroup), at most TS
+    int ts = TS;
+    if (P == 1) {
+      const int64_t want = ((2 * (int64_t)deg + kWideThreads - 1) / kWideThreads) * kWideThreads;
+      if (want < ts) ts = (int)want;
+    }
     if (threadIdx.x == 0) {
       int ok = 1;
       if (part == 0 || PH == kRefine) ok = (int)Decide<PH, DET>::eligible(a, i);
@@ -471,7 +478,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
       double kid = scan_row<4, kWideThreads, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
         if ((int)(wide_part(c) & (uint32_t)(P - 1)) != part) return;
-        if (!lds_insert_bounded(keys, vals, lg, c, w)) s_ovf = 1;
+        if (!lds_insert_sized(keys, vals, (uint32_t)ts, c, w)) s_ovf = 1;
       });
       kid = block_sum<double>(kid, s_d);
       if (threadIdx.x == 0) s_d[0] = kid;
@@ -570,14 +577,18 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
 
 // ------------------------------------------------------------- commit ---
 // Applies the recorded synchronous decisions of the vertices list[0..count)
-// (one group).  Refinement: vertex i moves only if its own community was not
-// chosen as a target in this group.  Local-moving: every recorded move
-// applies and the neighbours of movers are marked unprocessed (one
-// wavefront walks each mover's row).
-template <class WT, int PH>
+// (one group); the community totals go through the workgroup-combined
+// table.  Refinement: vertex i moves only if its own community was not
+// chosen as a target in this group.  Local-moving with MARK: every recorded
+// move applies, the target is forgotten and the neighbours of movers are
+// marked unprocessed (one wavefront walks each mover's row).  Without MARK
+// (long rows) the targets stay for k_mark_rows.
+template <class WT, int PH, bool MARK = true>
 __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
                                                    const int32_t* __restrict__ list, int32_t count) {
   __shared__ unsigned long long red_u[16];
+  __shared__ KeyedLds<kBlock> kt;
+  keyed_clear(kt);
   unsigned long long nm = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
     const int64_t k = base + threadIdx.x;
@@ -586,21 +597,20 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
     if (k < count) t = a.target[i];
     bool mv = t >= 0;
     if (mv) {
-      if (PH == kMove) a.target[i] = -1;
+      if (PH == kMove && MARK) a.target[i] = -1;
       const int32_t d = a.C[i];
       if (PH == kRefine && a.targeted[d]) mv = false;
       if (mv) {
         const double ki = a.K[i];
-        atomicAdd(&a.Sig[d], -ki);
-        atomicAdd(&a.Sig[t], ki);
-        atomicSub(&a.size[d], 1);
-        atomicAdd(&a.size[t], 1);
+        keyed_put(kt, d, -ki, -1);
+        keyed_put(kt, t, ki, 1);
         a.C[i] = t;
         ++nm;
         if (PH == kRefine && a.gid) atomicAdd(&a.mvg[a.gid[i]], 1ull);
       }
     }
-    if (PH == kMove) {
+    keyed_flush(kt, a.Sig, a.size);
+    if (PH == kMove && MARK) {
       u64 mask = __ballot(mv);
       while (mask) {
         const int l = __ffsll((unsigned long long)mask) - 1;
@@ -618,30 +628,18 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
   if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
 }
 
-// Local-moving commit of vertices with long rows: one workgroup per vertex,
-// so that the neighbours of a mover are marked by the whole workgroup.
+// Local-moving, long rows, after k_commit<WT, kMove, false>: one workgroup
+// per vertex forgets its target and, if it moved, marks its neighbours.
 template <class WT>
-__global__ __launch_bounds__(kBlock) void k_commit_rows(GraphView<WT> g, ScanArgs a,
-                                                        const int32_t* __restrict__ list, int32_t count) {
+__global__ __launch_bounds__(kBlock) void k_mark_rows(GraphView<WT> g, ScanArgs a,
+                                                      const int32_t* __restrict__ list, int32_t count) {
   __shared__ int s_mv;
-  unsigned long long nm = 0;
   for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
     const int32_t i = list[k];
     if (threadIdx.x == 0) {
       const int32_t t = a.target[i];
-      s_mv = 0;
-      if (t >= 0) {
-        a.target[i] = -1;
-        const int32_t d = a.C[i];
-        const double ki = a.K[i];
-        atomicAdd(&a.Sig[d], -ki);
-        atomicAdd(&a.Sig[t], ki);
-        atomicSub(&a.size[d], 1);
-        atomicAdd(&a.size[t], 1);
-        a.C[i] = t;
-        ++nm;
-        s_mv = 1;
-      }
+      s_mv = t >= 0;
+      if (t >= 0) a.target[i] = -1;
     }
     __syncthreads();
     if (s_mv) {
@@ -653,7 +651,6 @@ __global__ __launch_bounds__(kBlock) void k_commit_rows(GraphView<WT> g, ScanArg
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
 }
 
 // Refinement: forget the group's targets once every commit has read them.
@@ -713,7 +710,7 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   for (int k = 0; k < kWideClasses; ++k) {
     wl.count[k] = count[kWideBin0 + k];
     wl.start[k] = start[kWideBin0 + k];
-    tasks += (int64_t)wl.count[k] << k;
+    tasks += (int64_t)wl.count[k] << kWideShift[k];
   }
   if (tasks > 0) {
     wl.tasks = (int32_t)tasks;
@@ -730,8 +727,9 @@ void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   if (count <= 0) return;
   const GraphView<WT> g = view<WT>(gd);
   if (PH == kMove && long_rows) {
-    hipLaunchKernelGGL((k_commit_rows<WT>), dim3(grid_for(count, 1, 2048)), dim3(kBlock), 0, st, g, a, list,
-                       count);
+    hipLaunchKernelGGL((k_commit<WT, kMove, false>), dim3(grid_for(count, kBlock, 2048)), dim3(kBlock), 0, st, g,
+                       a, list, count);
+    hipLaunchKernelGGL((k_mark_rows<WT>), dim3(grid_for(count, 1, 2048)), dim3(kBlock), 0, st, g, a, list, count);
     return;
   }
   const int grid = grid_for(count, kBlock, 2048);
