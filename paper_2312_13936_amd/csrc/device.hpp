@@ -183,59 +183,28 @@ __device__ __forceinline__ uint32_t wide_part(int32_t c) {
   return h;
 }
 
-__device__ __forceinline__ double lds_lookup(const int32_t* keys, const double* vals, int lg, int32_t c) {
+// Global-memory table (hubs and giant communities), 16-byte slots.  Inserts
+// are atomics performed at L2; a table is read back only by later kernels
+// (plain loads after the launch boundary).
+// Inserts H[c] += w; returns the slot if this call created the key, else -1.
+__device__ __forceinline__ int64_t slot_insert_new(TblSlot* t, int lg, int32_t c, double w) {
   const uint32_t mask = (1u << lg) - 1u;
   uint32_t h = hslot(c, lg);
   while (true) {
-    int32_t k = keys[h];
-    if (k == c) return vals[h];
-    if (k == kEmpty) return 0.0;
-    h = (h + 1u) & mask;
-  }
-}
-
-// Global-memory table (hubs and giant communities).  Every probe is an
-// atomic performed at L2, so no stale L1 line is ever consulted.
-__device__ __forceinline__ void glb_insert(int32_t* keys, double* vals, int lg, int32_t c, double w) {
-  const uint32_t mask = (1u << lg) - 1u;
-  uint32_t h = hslot(c, lg);
-  while (true) {
-    int32_t old = atomicCAS(&keys[h], kEmpty, c);
-    if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return; }
-    h = (h + 1u) & mask;
-  }
-}
-
-// As glb_insert; returns the slot if this call created the key, else -1.
-__device__ __forceinline__ int64_t glb_insert_new(int32_t* keys, double* vals, int lg, int32_t c, double w) {
-  const uint32_t mask = (1u << lg) - 1u;
-  uint32_t h = hslot(c, lg);
-  while (true) {
-    int32_t old = atomicCAS(&keys[h], kEmpty, c);
+    const int32_t old = atomicCAS(&t[h].key, kEmpty, c);
     if (old == kEmpty || old == c) {
-      atomicAdd(&vals[h], w);
+      atomicAdd(&t[h].val, w);
       return old == kEmpty ? (int64_t)h : -1;
     }
     h = (h + 1u) & mask;
   }
 }
 
-__device__ __forceinline__ int32_t glb_load_key(const int32_t* keys, uint32_t h) {
-  return __hip_atomic_load(keys + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double glb_load_val(const double* vals, uint32_t h) {
-  return __hip_atomic_load(vals + h, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ __forceinline__ double glb_lookup(const int32_t* keys, const double* vals, int lg, int32_t c) {
-  const uint32_t mask = (1u << lg) - 1u;
-  uint32_t h = hslot(c, lg);
-  while (true) {
-    int32_t k = glb_load_key(keys, h);
-    if (k == c) return glb_load_val(vals, h);
-    if (k == kEmpty) return 0.0;
-    h = (h + 1u) & mask;
-  }
+// Reads a slot written by an earlier launch and frees it.
+__device__ __forceinline__ TblSlot slot_take(TblSlot* t, uint32_t h) {
+  const TblSlot s = t[h];
+  if (s.key != kEmpty) t[h] = TblSlot{kEmpty, 0, 0.0};
+  return s;
 }
 
 // p[key] += v for every active lane.  Lanes of the wavefront that share the

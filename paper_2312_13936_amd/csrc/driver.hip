@@ -160,7 +160,6 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
-  a.tbl_keys = ws.tbl_keys; a.tbl_vals = ws.tbl_vals;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
   a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
   const bool sync_mv = det || opt->sync_moves != 0;
@@ -399,7 +398,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       memset(&g, 0, sizeof(g));
       g.lab = ws.lab; g.coff = ws.cnt; g.cv = ws.cv; g.yoff = yoff; g.ydeg = ydeg;
       g.yidx = ws.idx[nb]; g.yw = ws.w[nb]; g.yw_double = det; g.cnt = &ws.sc->cnt[0][0];
-      g.tbl_keys = ws.tbl_keys; g.tbl_vals = ws.tbl_vals; g.ncom = ncom;
+      g.ncom = ncom;
       const int hk = tm.begin(kEvAggK);
       launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], grid_cap, 0, &S->agg_launches);
       if (gp.H > 0) {

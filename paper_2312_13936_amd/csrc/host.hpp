@@ -45,8 +45,7 @@ struct Workspace {
   uint8_t *flag, *targeted;
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
-  int32_t* tbl_keys;
-  double* tbl_vals;
+  TblSlot* tbl;
   int64_t tbl_entries;
   // hub path
   int32_t *hp_chunk, *hp_tbl, *hp_slice, *hp_active, *hp_done, *hp_lcnt, *apre, *tbl_list;
@@ -108,8 +107,7 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
     w.w[b] = (void*)take(ws * M);
   }
   w.tbl_entries = table_entries(tbl_n < 0 ? n : std::min(tbl_n, n));
-  w.tbl_keys = (int32_t*)take(4 * (size_t)w.tbl_entries);
-  w.tbl_vals = (double*)take(8 * (size_t)w.tbl_entries);
+  w.tbl = (TblSlot*)take(sizeof(TblSlot) * (size_t)w.tbl_entries);
   w.hp_chunk = (int32_t*)take(4 * (N + 1));
   w.hp_tbl = (int32_t*)take(4 * (N + 1));
   w.hp_slice = (int32_t*)take(4 * (N + 1));
@@ -335,7 +333,7 @@ HubArgs hub_args(Workspace& ws, const BinInfo& bins) {
   h.chunk_tasks = ws.chunk_tasks; h.slice_tasks = ws.slice_tasks;
   h.active = ws.hp_active; h.kid = ws.hp_kid; h.done = ws.hp_done;
   h.pb_g = ws.pb_g; h.pb_k = ws.pb_k; h.pb_c = ws.pb_c;
-  h.tbl_keys = ws.tbl_keys; h.tbl_vals = ws.tbl_vals;
+  h.tbl = ws.tbl;
   h.tbl_list = ws.tbl_list; h.lcnt = ws.hp_lcnt;
   h.apre = ws.apre;
   return h;
@@ -347,8 +345,7 @@ struct TableState {
   int64_t clean = 0;
   void ensure(hipStream_t st, Workspace& ws, int64_t extent) {
     if (extent <= clean) return;
-    fill_i32(st, ws.tbl_keys + clean, kEmpty, extent - clean);
-    fill_f64(st, ws.tbl_vals + clean, 0.0, extent - clean);
+    fill_slots(st, ws.tbl + clean, extent - clean);
     clean = extent;
   }
 };

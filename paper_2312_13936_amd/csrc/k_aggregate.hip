@@ -108,39 +108,26 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
   }
 }
 
-// One workgroup per community.  LG > 0: LDS table; LG == 0: global table of
-// next_pow2(2 min(capacity, |Gamma|)) slots in this workgroup's slice.
+// One workgroup per community, LDS table of 2^LG slots.
 template <class WTin, class WTout, int LG>
 __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs a,
                                                       const int32_t* __restrict__ list,
                                                       int32_t count) {
-  constexpr bool GLB = (LG == 0);
-  constexpr int TS = GLB ? 1 : (1 << LG);
-  __shared__ int32_t skeys[TS];
-  __shared__ double svals[TS];
+  constexpr int TS = 1 << LG;
+  __shared__ int32_t keys[TS];
+  __shared__ double vals[TS];
   __shared__ int s_wsum[kBlock / kWave];
   __shared__ unsigned long long red_u[16];
   __shared__ double s_red[kBlock / kWave];
-  int32_t* keys = GLB ? a.tbl_keys + (int64_t)blockIdx.x * a.tbl_slot : skeys;
-  double* vals = GLB ? a.tbl_vals + (int64_t)blockIdx.x * a.tbl_slot : svals;
   WTout* yw = (WTout*)a.yw;
-  if (!GLB) {
-    for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-    __syncthreads();
-  }
+  for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+  __syncthreads();
   unsigned long long nv = 0, na = 0, no = 0;
   for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
     const int32_t c = list[v];
     const int32_t mb = a.coff[c], me = a.coff[c + 1];
-    int lg = LG;
-    if (GLB) {
-      int64_t cap = (int64_t)a.yoff[c + 1] - a.yoff[c];
-      if (cap > a.ncom) cap = a.ncom;
-      lg = ceil_log2(2 * cap);
-      for (int s = threadIdx.x; s < (1 << lg); s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-      __syncthreads();
-    }
-    const int ts = 1 << lg;
+    constexpr int lg = LG;
+    constexpr int ts = TS;
     double self = 0.0;  // arcs inside c: the super-vertex's self-loop
     for (int32_t kb = mb; kb < me; kb += kBlock) {
       const int32_t k = kb + threadIdx.x;
@@ -153,7 +140,6 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
         for (int32_t e = 0; e < deg; ++e) {
           const int32_t d = a.lab[g.idx[beg + e]];
           if (d == c) self += g.weight(beg + e);
-          else if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
           else lds_insert(keys, vals, lg, d, g.weight(beg + e));
         }
       }
@@ -167,21 +153,17 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
         for (int32_t e = lane_id(); e < dg; e += kWave) {
           const int32_t d = a.lab[g.idx[beg + e]];
           if (d == c) self += g.weight(beg + e);
-          else if (GLB) glb_insert(keys, vals, lg, d, g.weight(beg + e));
           else lds_insert(keys, vals, lg, d, g.weight(beg + e));
         }
       }
     }
     self = block_sum<double>(self, s_red);
-    if (threadIdx.x == 0 && self != 0.0) {
-      if (GLB) glb_insert(keys, vals, lg, c, self);
-      else lds_insert(keys, vals, lg, c, self);
-    }
+    if (threadIdx.x == 0 && self != 0.0) lds_insert(keys, vals, lg, c, self);
     __syncthreads();
     // emit: block exclusive scan of per-thread occupied counts
     int cnt = 0;
     for (int s = threadIdx.x; s < ts; s += kBlock) {
-      const int32_t d = GLB ? glb_load_key(keys, s) : keys[s];
+      const int32_t d = keys[s];
       cnt += (d != kEmpty);
     }
     int incl = cnt;
@@ -200,18 +182,16 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
     }
     int32_t pos = a.yoff[c] + before + (incl - cnt);
     for (int s = threadIdx.x; s < ts; s += kBlock) {
-      const int32_t d = GLB ? glb_load_key(keys, s) : keys[s];
+      const int32_t d = keys[s];
       if (d == kEmpty) continue;
       a.yidx[pos] = d;
-      yw[pos] = (WTout)(GLB ? glb_load_val(vals, s) : vals[s]);
+      yw[pos] = (WTout)vals[s];
       ++pos;
     }
     if (threadIdx.x == 0) { a.ydeg[c] = total; no += (unsigned long long)total; }
     __syncthreads();
-    if (!GLB) {
-      for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-      __syncthreads();
-    }
+    for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+    __syncthreads();
   }
   nv = block_sum<unsigned long long>(nv, red_u);
   na = block_sum<unsigned long long>(na, red_u);

@@ -28,11 +28,8 @@ __device__ __forceinline__ int64_t table_slots(int64_t arcs, int64_t n) {
   return t;
 }
 
-__device__ __forceinline__ int32_t* tbl_keys_of(const HubArgs& h, int32_t p) {
-  return h.tbl_keys + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
-}
-__device__ __forceinline__ double* tbl_vals_of(const HubArgs& h, int32_t p) {
-  return h.tbl_vals + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
+__device__ __forceinline__ TblSlot* tbl_of(const HubArgs& h, int32_t p) {
+  return h.tbl + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
 }
 __device__ __forceinline__ int32_t* tbl_list_of(const HubArgs& h, int32_t p) {
   return h.tbl_list + ((int64_t)h.tbl_off[p] * kTblUnit - h.tbase);
@@ -111,15 +108,14 @@ __global__ void k_hub_prep(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
 __device__ __forceinline__ void flush_chunk(const HubArgs& h, int32_t p, int32_t* skeys, double* svals,
                                             int32_t* snew, int* s_nnew, int* s_base) {
   constexpr int TS = 1 << kHubGatherLg;
-  int32_t* gk = tbl_keys_of(h, p);
-  double* gv = tbl_vals_of(h, p);
+  TblSlot* gt = tbl_of(h, p);
   const int lg = tbl_lg(h, p);
   if (threadIdx.x == 0) *s_nnew = 0;
   __syncthreads();
   for (int s = threadIdx.x; s < TS; s += kBlock) {
     const int32_t c = skeys[s];
     if (c != kEmpty) {
-      const int64_t slot = glb_insert_new(gk, gv, lg, c, svals[s]);
+      const int64_t slot = slot_insert_new(gt, lg, c, svals[s]);
       if (slot >= 0) snew[atomicAdd(s_nnew, 1)] = (int32_t)slot;
       skeys[s] = kEmpty;
       svals[s] = 0.0;
@@ -197,8 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     const int32_t d = a.C[i];
     const double ki = a.K[i];
     const Eval<DET> ev(a, i, h.kid[p], ki, a.Sig[d]);
-    int32_t* gk = tbl_keys_of(h, p);
-    double* gv = tbl_vals_of(h, p);
+    TblSlot* gt = tbl_of(h, p);
     const int32_t* lst = tbl_list_of(h, p);
     const int32_t len = h.lcnt[p];
     const int64_t ts = (int64_t)1 << tbl_lg(h, p);
@@ -217,14 +212,10 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     if (!empty) {  // uniform
       for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
         const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
-        const int32_t c = glb_load_key(gk, slot);
-        if (c == kEmpty) continue;
-        if (c != d) {
-          ++nc;
-          ev(a, c, glb_load_val(gv, slot), a.Sig[c], bg, bk, bc);
-        }
-        gk[slot] = kEmpty;
-        gv[slot] = 0.0;
+        const TblSlot e = slot_take(gt, slot);
+        if (e.key == kEmpty || e.key == d) continue;
+        ++nc;
+        ev(a, e.key, e.val, a.Sig[e.key], bg, bk, bc);
       }
       block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     }
@@ -497,79 +488,81 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
   if (threadIdx.x == 0 && na) atomicAdd(&cnt_of(a.cnt)[5], na);
 }
 
-// Slice emit: append the slice's entries of the community's occupied-slot
-// list, (d, H[d]), to row c (ydeg[c] is the row cursor, zeroed by the
-// caller) and clear the slots; the last slice resets the list.
+// Slice emit: append the slice's entries of the community's table, (d,
+// H[d]), to row c (ydeg[c] is the row cursor, zeroed by the caller) and free
+// their slots; the last slice resets the occupied-slot list.  Dense tables
+// are read slot by slot, sparse ones through their occupied-slot list; in
+// both, round r of a workgroup covers kBlock consecutive positions (one per
+// thread), and the occupied entries of each (round, wavefront) are written
+// contiguously at offsets from one workgroup-wide scan.
 template <class WTout>
 __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int32_t s0, int32_t s1) {
-  __shared__ int s_wsum[kBlock / kWave];
+  constexpr int R = kHubSlice / kBlock;  // rounds per slice
+  constexpr int NW = kBlock / kWave;
+  static_assert(R * NW == 2 * kWave, "one scan of two entries per lane");
+  __shared__ int32_t s_off[R * NW];      // [round][wavefront]: entries, then their offsets
   __shared__ int s_base;
   WTout* yw = (WTout*)a.yw;
+  const int w = threadIdx.x / kWave;
   unsigned long long no = 0;
   for (int64_t t = s0 + (int64_t)blockIdx.x; t < s1; t += gridDim.x) {
     const int2 task = h.slice_tasks[t];
     const int32_t p = task.x;
     const int32_t c = h.items[p];
-    int32_t* gk = tbl_keys_of(h, p);
-    double* gv = tbl_vals_of(h, p);
+    TblSlot* gt = tbl_of(h, p);
     const int32_t* lst = tbl_list_of(h, p);
     const int32_t len = h.lcnt[p];
     const int64_t ts = (int64_t)1 << tbl_lg(h, p);
     const bool dense = (int64_t)len * 8 > ts;
     const int64_t lim = dense ? ts : len;
     const int64_t q0 = (int64_t)task.y * kHubSlice;
-    const int64_t q1 = (lim - q0 < kHubSlice) ? lim : q0 + kHubSlice;
-    if (q0 >= lim) {  // uniform: a slice past the end of the list only counts itself done
-      if (threadIdx.x == 0) {
-        __threadfence();
-        const int nsl = h.slice_off[p + 1] - h.slice_off[p];
-        if (atomicAdd(&h.done[p], 1) == nsl - 1) {
-          h.done[p] = 0;
-          h.lcnt[p] = 0;
+    if (q0 < lim) {  // uniform: a slice past the end of the list only counts itself done
+      uint32_t slot[R];
+      int32_t key[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t q = q0 + r * kBlock + threadIdx.x;
+        key[r] = kEmpty;
+        slot[r] = 0;
+        if (q < lim) {
+          slot[r] = dense ? (uint32_t)q : (uint32_t)lst[q];
+          key[r] = gt[slot[r]].key;
+        }
+        const u64 b = __ballot(key[r] != kEmpty);
+        if (lane_id() == 0) s_off[r * NW + w] = __popcll(b);
+      }
+      __syncthreads();
+      if (w == 0) {  // exclusive scan of the 2 kWave counts, in (round, wavefront) order
+        const int v0 = s_off[2 * lane_id()], v1 = s_off[2 * lane_id() + 1];
+        int incl = v0 + v1;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int x = __shfl_up(incl, o);
+          if (lane_id() >= o) incl += x;
+        }
+        const int excl = incl - v0 - v1;
+        s_off[2 * lane_id()] = excl;
+        s_off[2 * lane_id() + 1] = excl + v0;
+        if (lane_id() == kWave - 1) {
+          s_base = incl ? atomicAdd(&a.ydeg[c], incl) : 0;
+          no += (unsigned long long)incl;
         }
       }
-      continue;
-    }
-    // kHubSlice / kBlock consecutive positions per thread
-    constexpr int PER = kHubSlice / kBlock;
-    const int64_t my0 = q0 + (int64_t)threadIdx.x * PER;
-    const int64_t my1 = (my0 + PER < q1) ? my0 + PER : q1;
-    int cnt = 0;
-    if (dense) {
-      for (int64_t q = my0; q < my1; ++q) cnt += (glb_load_key(gk, (uint32_t)q) != kEmpty);
-    } else {
-      cnt = my1 > my0 ? (int)(my1 - my0) : 0;
-    }
-    int incl = cnt;
+      __syncthreads();
+      const int64_t base = (int64_t)a.yoff[c] + s_base;
 #pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int x = __shfl_up(incl, o);
-      if (lane_id() >= o) incl += x;
+      for (int r = 0; r < R; ++r) {
+        const u64 b = __ballot(key[r] != kEmpty);
+        if (key[r] != kEmpty) {
+          const int64_t pos = base + s_off[r * NW + w] + __popcll(b & lanemask_lt());
+          a.yidx[pos] = key[r];
+          yw[pos] = (WTout)gt[slot[r]].val;
+          gt[slot[r]] = TblSlot{kEmpty, 0, 0.0};
+        }
+      }
+      __syncthreads();  // every thread's reads and frees of this slice are done; s_off reusable
     }
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) s_wsum[w] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int k = 0; k < kBlock / kWave; ++k) {
-      if (k < w) before += s_wsum[k];
-      total += s_wsum[k];
-    }
-    if (threadIdx.x == 0) s_base = total ? atomicAdd(&a.ydeg[c], total) : 0;
-    __syncthreads();
-    int64_t pos = (int64_t)a.yoff[c] + s_base + before + (incl - cnt);
-    for (int64_t q = my0; q < my1; ++q) {
-      const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
-      const int32_t key = glb_load_key(gk, slot);
-      if (key == kEmpty) continue;
-      a.yidx[pos] = key;
-      yw[pos] = (WTout)glb_load_val(gv, slot);
-      ++pos;
-      gk[slot] = kEmpty;
-      gv[slot] = 0.0;
-    }
-    __syncthreads();  // every thread's reads and clears of this slice are done
     if (threadIdx.x == 0) {
-      no += (unsigned long long)total;
       __threadfence();
       const int nsl = h.slice_off[p + 1] - h.slice_off[p];
       if (atomicAdd(&h.done[p], 1) == nsl - 1) {
@@ -577,9 +570,8 @@ __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int3
         h.lcnt[p] = 0;
       }
     }
-    __syncthreads();
   }
-  if (threadIdx.x == 0 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
+  if (threadIdx.x == kWave - 1 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
 }
 
 void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,

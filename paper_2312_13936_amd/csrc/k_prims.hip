@@ -33,6 +33,12 @@ void fill_u8(hipStream_t st, uint8_t* p, uint8_t v, int64_t n) {
 void fill_f64(hipStream_t st, double* p, double v, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fill<double>, dim3(grid_n(n)), dim3(kBlock), 0, st, p, v, n);
 }
+__global__ void k_fill_slots(TblSlot* p, int64_t n) {
+  GRID_STRIDE(k, n) p[k] = TblSlot{kEmpty, 0, 0.0};
+}
+void fill_slots(hipStream_t st, TblSlot* p, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL(k_fill_slots, dim3(grid_n(n)), dim3(kBlock), 0, st, p, n);
+}
 void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(grid_n(n)), dim3(kBlock), 0, st, p, v, n);
 }

@@ -89,9 +89,6 @@ struct ScanArgs {
   unsigned long long* dq128;  // deterministic mode: exact int128 sums of move keys [kCntSlots][lo, hi]
   unsigned long long* cnt;  // [kCntSlots][8]: [0] vertices scanned, [1] arcs, [2] candidates,
                             // [3] moves, [4..6] aggregation, [7] arcs scanned by refinement
-  int32_t* tbl_keys;        // global hash tables for the hub bin
-  double* tbl_vals;
-  int64_t tbl_slot;         // slots per workgroup table
   // wide rows: partial bests of the partitions of each vertex of a launch
   // ([vertex][kWideMaxParts]) and the partitions finished per vertex
   double* wd_g;
@@ -124,6 +121,14 @@ constexpr int kHubGatherLg = 12;      // LDS pre-aggregation table: 4096 slots
 constexpr int kHubSlice = 8192;
 constexpr int kTblUnit = 1024;
 
+// Slot of a global hash table: key and value share one 16-byte slot, so an
+// insert (CAS on the key, add on the value) and a read touch one cache line.
+struct alignas(16) TblSlot {
+  int32_t key;   // kEmpty when free
+  int32_t pad;
+  double val;
+};
+
 struct HubArgs {
   const int32_t* items;       // hub vertex (or giant community) of each hub index p
   const int32_t* chunk_off;   // [H+1] first chunk task of p
@@ -137,8 +142,7 @@ struct HubArgs {
   double* pb_g;               // per slice task: best gain
   i128_t* pb_k;               // per slice task: best exact key
   int32_t* pb_c;              // per slice task: best community
-  int32_t* tbl_keys;          // table region
-  double* tbl_vals;
+  TblSlot* tbl;               // table region
   int32_t* tbl_list;          // occupied slots of each item's table, at the item's table offset
   int32_t* lcnt;              // [H] length of each item's occupied-slot list
   int64_t tbase;              // region offset of the current batch (slots)
@@ -166,9 +170,6 @@ struct AggArgs {
   void* yw;              // float or double
   bool yw_double;
   unsigned long long* cnt;  // [kCntSlots][8]: [4] vertices, [5] arcs read, [6] arcs written
-  int32_t* tbl_keys;
-  double* tbl_vals;
-  int64_t tbl_slot;
   int64_t ncom;
 };
 
@@ -264,6 +265,7 @@ void exclusive_scan(hipStream_t st, int32_t* data, int64_t n, int32_t* tmp);
 void fill_i32(hipStream_t st, int32_t* p, int32_t v, int64_t n);
 void fill_u8(hipStream_t st, uint8_t* p, uint8_t v, int64_t n);
 void fill_f64(hipStream_t st, double* p, double v, int64_t n);
+void fill_slots(hipStream_t st, TblSlot* p, int64_t n);  // empty slots
 void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64_t n);
 void iota_i32(hipStream_t st, int32_t* p, int64_t n);
 void copy_i32(hipStream_t st, int32_t* dst, const int32_t* src, int64_t n);

@@ -288,28 +288,22 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
   flush_acc<PH, DET>(a, acc);
 }
 
-// ------------------------------------------- one workgroup per (hub) vertex ---
-// LG > 0: LDS table of 2^LG slots.  LG == 0: global-memory table of
-// next_pow2(2 deg) slots inside this workgroup's slice of the table region.
+// ------------------------------------------------ one workgroup per vertex ---
+// LDS table of 2^LG slots.
 template <int LG, class WT, int PH, bool DET>
 __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanArgs a,
                                                          const int32_t* __restrict__ list,
                                                          int32_t count) {
-  constexpr bool GLB = (LG == 0);
-  constexpr int TS = GLB ? 1 : (1 << LG);
-  __shared__ int32_t skeys[TS];
-  __shared__ double svals[TS];
+  constexpr int TS = 1 << LG;
+  __shared__ int32_t keys[TS];
+  __shared__ double vals[TS];
   __shared__ double s_g[kBlock / kWave];
   __shared__ i128 s_k[kBlock / kWave];
   __shared__ int32_t s_c[kBlock / kWave];
   __shared__ int s_flag, s_take;
   __shared__ double s_kid;
-  int32_t* keys = GLB ? a.tbl_keys + (int64_t)blockIdx.x * a.tbl_slot : skeys;
-  double* vals = GLB ? a.tbl_vals + (int64_t)blockIdx.x * a.tbl_slot : svals;
-  if (!GLB) {
-    for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-    __syncthreads();
-  }
+  for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
+  __syncthreads();
   Acc acc;
   for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
     const int32_t i = list[v];
@@ -321,20 +315,12 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     if (PH == kMove && threadIdx.x == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
     const int32_t beg = g.begin(i), deg = g.degree(i);
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
-    // distinct neighbour communities <= min(deg, n): the table slice holds
-    // next_pow2(2 min(max hub degree, n)) slots
-    const int lg = GLB ? ceil_log2(2 * ((int64_t)deg < g.n ? (int64_t)deg : g.n))
-                       : min(LG, ceil_log2(2 * (int64_t)deg));
+    const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
-    if (GLB) {
-      for (int s = threadIdx.x; s < ts; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-      __syncthreads();
-    }
     const int32_t d = a.C[i];
     const double ki = a.K[i];
     double kid = scan_row<4, kBlock, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
-      if (GLB) glb_insert(keys, vals, lg, c, w);
-      else lds_insert(keys, vals, lg, c, w);
+      lds_insert(keys, vals, lg, c, w);
     });
     kid = block_sum<double>(kid, s_g);
     if (threadIdx.x == 0) s_kid = kid;
@@ -343,17 +329,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    if (GLB) {
-      for (int s = threadIdx.x; s < ts; s += kBlock) {
-        const int32_t c = glb_load_key(keys, s);
-        if (c == kEmpty) continue;
-        ++acc.nc;
-        ev(a, c, glb_load_val(vals, s), a.Sig[c], bg, bk, bc);
-      }
-    } else {
-      eval_table<(TS / kBlock > 0 ? TS / kBlock : 1), kBlock, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk,
-                                                                   bc);
-    }
+    eval_table<(TS / kBlock > 0 ? TS / kBlock : 1), kBlock, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk,
+                                                                 bc);
     block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     if (threadIdx.x == 0) {
       ++acc.nv;
