@@ -203,6 +203,140 @@ __global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs
   }
 }
 
+// Communities of capacity kBinMax[5] < cap <= kBinMax[kAggLastBin]: one
+// workgroup of kWideThreads threads per community, LDS table of up to
+// kWideSlots slots (2 cap slots, at most 3/2 cap: load factor <= 2/3, and
+// at most cap distinct keys, so the table never fills).  The members' rows
+// are laid end to end, kWideThreads members at a time, and every lane takes
+// one arc per step (row of an arc by binary search over the members'
+// offsets in LDS), so short and long member rows alike stream coalesced.
+constexpr int kAggWideThreads = 1024;
+template <class WTin, class WTout>
+__global__ __launch_bounds__(kAggWideThreads) void k_agg_wide(GraphView<WTin> g, AggArgs a,
+                                                              const int32_t* __restrict__ list, int32_t count) {
+  constexpr int NT = kAggWideThreads;
+  constexpr int NW = NT / kWave;
+  constexpr int TS = kWideSlots;
+  constexpr int R = TS / NT;  // emit rounds
+  static_assert(R * NW <= 3 * kWave, "emit scan: at most three entries per lane");
+  __shared__ int32_t keys[TS];
+  __shared__ double vals[TS];
+  __shared__ int32_t s_off[NT + 1];
+  __shared__ int32_t s_beg[NT];
+  __shared__ int32_t s_w[NW];
+  __shared__ int32_t s_cnt[3 * kWave];
+  __shared__ double s_red[NW];
+  __shared__ unsigned long long red_u[16];
+  WTout* yw = (WTout*)a.yw;
+  const int t = threadIdx.x;
+  const int w = t / kWave;
+  for (int s = t; s < TS; s += NT) { keys[s] = kEmpty; vals[s] = 0.0; }
+  unsigned long long nv = 0, na = 0, no = 0;
+  for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
+    const int32_t c = list[v];
+    const int32_t mb = a.coff[c], me = a.coff[c + 1];
+    const int64_t cap = (int64_t)a.yoff[c + 1] - a.yoff[c];
+    int ts = TS;
+    if (2 * cap < ts) ts = (int)(((2 * cap + NT - 1) / NT) * NT);
+    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
+    for (int32_t kb = mb; kb < me; kb += NT) {  // uniform
+      const int32_t k = kb + t;
+      int32_t deg = 0, beg = 0;
+      if (k < me) {
+        const int32_t i = a.cv[k];
+        beg = g.begin(i);
+        deg = g.degree(i);
+        ++nv;
+      }
+      int incl = deg;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int x = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += x;
+      }
+      __syncthreads();  // the previous members' s_off / s_beg are no longer read
+      if (lane_id() == kWave - 1) s_w[w] = incl;
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int q = 0; q < NW; ++q) {
+        if (q < w) before += s_w[q];
+        total += s_w[q];
+      }
+      s_off[t] = before + incl - deg;
+      if (t == 0) s_off[NT] = total;
+      s_beg[t] = beg;
+      __syncthreads();
+      na += (unsigned long long)deg;
+      for (int32_t q = t; q < total; q += NT) {
+        int lo = 0, hi = NT;  // s_off[lo] <= q < s_off[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[mid] <= q) lo = mid; else hi = mid;
+        }
+        const int64_t e = (int64_t)s_beg[lo] + (q - s_off[lo]);
+        const int32_t d = a.lab[g.idx[e]];
+        const double wt = g.weight(e);
+        if (d == c) self += wt;
+        else lds_insert_sized(keys, vals, (uint32_t)ts, d, wt);
+      }
+    }
+    self = block_sum<double>(self, s_red);
+    if (t == 0 && self != 0.0) lds_insert_sized(keys, vals, (uint32_t)ts, c, self);
+    __syncthreads();
+    // emit: round r covers slots [r NT, (r + 1) NT); entries of (round,
+    // wavefront) are written contiguously
+    int32_t key[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int s = r * NT + t;
+      key[r] = (s < ts) ? keys[s] : kEmpty;
+      const u64 b = __ballot(key[r] != kEmpty);
+      if (lane_id() == 0) s_cnt[r * NW + w] = __popcll(b);
+    }
+    for (int q = R * NW + t; q < 3 * kWave; q += NT) s_cnt[q] = 0;
+    __syncthreads();
+    if (w == 0) {
+      const int v0 = s_cnt[3 * lane_id()], v1 = s_cnt[3 * lane_id() + 1], v2 = s_cnt[3 * lane_id() + 2];
+      int incl = v0 + v1 + v2;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int x = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += x;
+      }
+      const int excl = incl - v0 - v1 - v2;
+      s_cnt[3 * lane_id()] = excl;
+      s_cnt[3 * lane_id() + 1] = excl + v0;
+      s_cnt[3 * lane_id() + 2] = excl + v0 + v1;
+      if (lane_id() == kWave - 1) {
+        a.ydeg[c] = incl;
+        no += (unsigned long long)incl;
+      }
+    }
+    __syncthreads();
+    const int64_t base = a.yoff[c];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const u64 b = __ballot(key[r] != kEmpty);
+      if (key[r] != kEmpty) {
+        const int s = r * NT + t;
+        const int64_t pos = base + s_cnt[r * NW + w] + __popcll(b & lanemask_lt());
+        a.yidx[pos] = key[r];
+        yw[pos] = (WTout)vals[s];
+        keys[s] = kEmpty;
+        vals[s] = 0.0;
+      }
+    }
+    __syncthreads();  // table empty again; s_cnt reusable
+  }
+  nv = block_sum<unsigned long long>(nv, red_u);
+  na = block_sum<unsigned long long>(na, red_u);
+  if (t == 0) {
+    if (nv) atomicAdd(&cnt_of(a.cnt)[4], nv);
+    if (na) atomicAdd(&cnt_of(a.cnt)[5], na);
+  }
+  if (t == kWave - 1 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
+}
+
 template <class WTin, class WTout>
 static void agg_bins(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const int32_t* list,
                      const int32_t* count, const int32_t* start, int grid_cap, int hub_grid, int64_t* launches) {
@@ -230,6 +364,14 @@ static void agg_bins(hipStream_t st, const GraphDesc& gd, const AggArgs& a, cons
   if (count[5] > 0) {
     hipLaunchKernelGGL((k_agg_block<WTin, WTout, 11>), dim3(grid_for(count[5], 1, grid_cap)),
                        dim3(kBlock), 0, st, g, a, list + start[5], count[5]);
+    ++*launches;
+  }
+  // bins kWideBin0 .. kAggLastBin are contiguous in the list (one group)
+  int32_t nwide = 0;
+  for (int b = kWideBin0; b <= kAggLastBin; ++b) nwide += count[b];
+  if (nwide > 0) {
+    hipLaunchKernelGGL((k_agg_wide<WTin, WTout>), dim3(grid_for(nwide, 1, grid_cap)), dim3(kAggWideThreads), 0,
+                       st, g, a, list + start[kWideBin0], nwide);
     ++*launches;
   }
   (void)hub_grid;  // giant communities go through the chunked hub path

@@ -75,17 +75,20 @@ void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32
                        chunk_off, tbl_off, slice_off);
 }
 
+// One workgroup per item writes its (item, chunk) and (item, slice) tasks.
 __global__ void k_hub_tasks(int32_t H, const int32_t* chunk_off, const int32_t* slice_off, int2* chunk_tasks,
                             int2* slice_tasks) {
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
-    for (int32_t c = 0; c < chunk_off[p + 1] - chunk_off[p]; ++c) chunk_tasks[chunk_off[p] + c] = make_int2((int)p, c);
-    for (int32_t c = 0; c < slice_off[p + 1] - slice_off[p]; ++c) slice_tasks[slice_off[p] + c] = make_int2((int)p, c);
+  for (int64_t p = blockIdx.x; p < H; p += gridDim.x) {
+    const int32_t c0 = chunk_off[p], nc = chunk_off[p + 1] - c0;
+    const int32_t s0 = slice_off[p], ns = slice_off[p + 1] - s0;
+    for (int32_t c = threadIdx.x; c < nc; c += blockDim.x) chunk_tasks[c0 + c] = make_int2((int)p, c);
+    for (int32_t c = threadIdx.x; c < ns; c += blockDim.x) slice_tasks[s0 + c] = make_int2((int)p, c);
   }
 }
 void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_t* slice_off, int2* chunk_tasks,
                int2* slice_tasks) {
   if (H > 0)
-    hipLaunchKernelGGL(k_hub_tasks, dim3(grid_items(H, kBlock, 4096)), dim3(kBlock), 0, st, H, chunk_off, slice_off,
+    hipLaunchKernelGGL(k_hub_tasks, dim3(grid_items(H, 1, 4096)), dim3(kBlock), 0, st, H, chunk_off, slice_off,
                        chunk_tasks, slice_tasks);
 }
 

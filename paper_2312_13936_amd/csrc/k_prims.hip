@@ -161,7 +161,7 @@ __device__ __forceinline__ int bin_of(int32_t d, bool wide) {
   if (d <= 0) return -1;
 #pragma unroll
   for (int b = 0; b < kNumBins; ++b) {
-    if (!wide && b == kWideBin0) return kHubBin;
+    if (!wide && b > kAggLastBin) return kHubBin;
     if (d <= kBinMax[b]) return b;
   }
   return kHubBin;

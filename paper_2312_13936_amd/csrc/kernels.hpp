@@ -35,6 +35,10 @@ constexpr int kWideClasses = 3;
 constexpr int kWideShift[kWideClasses] = {0, 0, 1};
 constexpr int kWideMaxParts = 2;
 constexpr int kWideSlots = 12288;  // 144 KiB of LDS (keys + FP64 values)
+// Aggregation uses bins kWideBin0 .. kAggLastBin (capacities up to 8192 arcs,
+// one 1024-thread workgroup and LDS table per community); larger
+// capacities take the global-table path.
+constexpr int kAggLastBin = 7;
 constexpr int kHubBin = kNumBins - 1;
 
 // Local-moving and refinement visit the vertices in S pseudo-random groups
@@ -284,7 +288,8 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
                       int32_t* size, int64_t n);
 // Degree binning into S groups: bin_count fills bb->counts / bb->maxsize,
 // bin_scatter places item i at bb->cursors[group(i) * kNumBins + bin(i)]++.
-// wide = false leaves bins kWideBin0.. empty (aggregation capacities).
+// wide = false (aggregation capacities) stops at bin kAggLastBin: larger
+// capacities go to the hub bin.
 // gid / vbase (fused batches, else nullptr): the group of item i is taken
 // from its id inside its own graph, i - vbase[gid[i]].
 void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
