@@ -200,13 +200,6 @@ __device__ __forceinline__ int64_t slot_insert_new(TblSlot* t, int lg, int32_t c
   }
 }
 
-// Reads a slot written by an earlier launch and frees it.
-__device__ __forceinline__ TblSlot slot_take(TblSlot* t, uint32_t h) {
-  const TblSlot s = t[h];
-  if (s.key != kEmpty) t[h] = TblSlot{kEmpty, 0, 0.0};
-  return s;
-}
-
 // p[key] += v for every active lane.  Lanes of the wavefront that share the
 // key of the first remaining active lane are summed into one atomic (two
 // rounds), which takes the load off the address of a giant community; the

@@ -213,12 +213,36 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     // only reports an empty partial result (no workgroup-wide reduction)
     const bool empty = q0 >= lim;
     if (!empty) {  // uniform
-      for (int64_t q = q0 + threadIdx.x; q < q1; q += kBlock) {
-        const uint32_t slot = dense ? (uint32_t)q : (uint32_t)lst[q];
-        const TblSlot e = slot_take(gt, slot);
-        if (e.key == kEmpty || e.key == d) continue;
-        ++nc;
-        ev(a, e.key, e.val, a.Sig[e.key], bg, bk, bc);
+      // U positions per thread per step: all slot reads, then all Sigma
+      // gathers, are in flight together
+      constexpr int U = 8;
+      for (int64_t qb = q0; qb < q1; qb += U * kBlock) {
+        uint32_t sl[U];
+        int32_t ck[U];
+        double cw[U], sg[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int64_t q = qb + u * kBlock + threadIdx.x;
+          sl[u] = 0;
+          ck[u] = kEmpty;
+          cw[u] = 0.0;
+          if (q < q1) {
+            sl[u] = dense ? (uint32_t)q : (uint32_t)lst[q];
+            const TblSlot e = gt[sl[u]];
+            ck[u] = e.key;
+            cw[u] = e.val;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) sg[u] = (ck[u] != kEmpty && ck[u] != d) ? a.Sig[ck[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (ck[u] == kEmpty) continue;
+          gt[sl[u]] = TblSlot{kEmpty, 0, 0.0};
+          if (ck[u] == d) continue;
+          ++nc;
+          ev(a, ck[u], cw[u], sg[u], bg, bk, bc);
+        }
       }
       block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     }

@@ -19,7 +19,7 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 // of degree d (or a community whose member arcs total d) goes to the first
 // bin with d <= kBinMax[b]; d == 0 is never binned.  Bins 0-4 map a group of
 // kBinLanes[b] lanes of one wavefront to each item with an LDS hash table of
-// 2^kBinLg[b] slots; bin 5 maps a 256-thread workgroup with an LDS table.
+// up to 2^8 slots; bin 5 maps a 256-thread workgroup with an LDS table.
 // Bins 6-8 ("wide" rows, vertex scan only) map 1, 1 or 2 workgroups of 1024
 // threads to a vertex, each with an LDS table of up to kWideSlots slots for
 // one partition of the neighbour communities; aggregation bins skip them
@@ -28,7 +28,6 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 constexpr int kNumBins = 10;
 constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 4096, 8192, 16384, 0x7fffffff};
 constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 1024, 1024, 2048, 256};
-constexpr int kBinLg[kNumBins] = {3, 4, 5, 6, 8, 11, 13, 14, 14, 0};
 constexpr int kWideBin0 = 6;       // first wide bin
 constexpr int kWideClasses = 3;
 // bin kWideBin0 + k uses 2^kWideShift[k] partitions of the key space
