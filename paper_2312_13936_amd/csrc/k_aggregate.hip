@@ -108,116 +108,22 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
   }
 }
 
-// One workgroup per community, LDS table of 2^LG slots.
-template <class WTin, class WTout, int LG>
-__global__ __launch_bounds__(kBlock) void k_agg_block(GraphView<WTin> g, AggArgs a,
-                                                      const int32_t* __restrict__ list,
-                                                      int32_t count) {
-  constexpr int TS = 1 << LG;
-  __shared__ int32_t keys[TS];
-  __shared__ double vals[TS];
-  __shared__ int s_wsum[kBlock / kWave];
-  __shared__ unsigned long long red_u[16];
-  __shared__ double s_red[kBlock / kWave];
-  WTout* yw = (WTout*)a.yw;
-  for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-  __syncthreads();
-  unsigned long long nv = 0, na = 0, no = 0;
-  for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
-    const int32_t c = list[v];
-    const int32_t mb = a.coff[c], me = a.coff[c + 1];
-    constexpr int lg = LG;
-    constexpr int ts = TS;
-    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
-    for (int32_t kb = mb; kb < me; kb += kBlock) {
-      const int32_t k = kb + threadIdx.x;
-      const int32_t i = (k < me) ? a.cv[k] : 0;
-      const int32_t deg = (k < me) ? g.degree(i) : 0;
-      if (k < me) ++nv;
-      if (k < me && deg < kWave) {
-        const int32_t beg = g.begin(i);
-        na += (unsigned long long)deg;
-        for (int32_t e = 0; e < deg; ++e) {
-          const int32_t d = a.lab[g.idx[beg + e]];
-          if (d == c) self += g.weight(beg + e);
-          else lds_insert(keys, vals, lg, d, g.weight(beg + e));
-        }
-      }
-      u64 mask = __ballot(k < me && deg >= kWave);
-      while (mask) {
-        const int q = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
-        const int32_t ii = __shfl(i, q);
-        const int32_t beg = g.begin(ii), dg = g.degree(ii);
-        if (lane_id() == 0) na += (unsigned long long)dg;
-        for (int32_t e = lane_id(); e < dg; e += kWave) {
-          const int32_t d = a.lab[g.idx[beg + e]];
-          if (d == c) self += g.weight(beg + e);
-          else lds_insert(keys, vals, lg, d, g.weight(beg + e));
-        }
-      }
-    }
-    self = block_sum<double>(self, s_red);
-    if (threadIdx.x == 0 && self != 0.0) lds_insert(keys, vals, lg, c, self);
-    __syncthreads();
-    // emit: block exclusive scan of per-thread occupied counts
-    int cnt = 0;
-    for (int s = threadIdx.x; s < ts; s += kBlock) {
-      const int32_t d = keys[s];
-      cnt += (d != kEmpty);
-    }
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int t = __shfl_up(incl, o);
-      if (lane_id() >= o) incl += t;
-    }
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) s_wsum[w] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int k = 0; k < kBlock / kWave; ++k) {
-      if (k < w) before += s_wsum[k];
-      total += s_wsum[k];
-    }
-    int32_t pos = a.yoff[c] + before + (incl - cnt);
-    for (int s = threadIdx.x; s < ts; s += kBlock) {
-      const int32_t d = keys[s];
-      if (d == kEmpty) continue;
-      a.yidx[pos] = d;
-      yw[pos] = (WTout)vals[s];
-      ++pos;
-    }
-    if (threadIdx.x == 0) { a.ydeg[c] = total; no += (unsigned long long)total; }
-    __syncthreads();
-    for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
-    __syncthreads();
-  }
-  nv = block_sum<unsigned long long>(nv, red_u);
-  na = block_sum<unsigned long long>(na, red_u);
-  no = block_sum<unsigned long long>(no, red_u);
-  if (threadIdx.x == 0) {
-    if (nv) atomicAdd(&cnt_of(a.cnt)[4], nv);
-    if (na) atomicAdd(&cnt_of(a.cnt)[5], na);
-    if (no) atomicAdd(&cnt_of(a.cnt)[6], no);
-  }
-}
-
-// Communities of capacity kBinMax[5] < cap <= kBinMax[kAggLastBin]: one
-// workgroup of kWideThreads threads per community, LDS table of up to
-// kWideSlots slots (2 cap slots, at most 3/2 cap: load factor <= 2/3, and
-// at most cap distinct keys, so the table never fills).  The members' rows
-// are laid end to end, kWideThreads members at a time, and every lane takes
-// one arc per step (row of an arc by binary search over the members'
-// offsets in LDS), so short and long member rows alike stream coalesced.
+// One workgroup of NT threads per community, LDS table of up to TS slots
+// (2 cap slots rounded up to whole multiples of NT, at most TS; the bins
+// keep cap <= 2 TS / 3, so the load factor stays <= 2/3 and the table never
+// fills: a row has at most cap distinct keys).  The members' rows are laid
+// end to end, NT members at a time, and every lane takes one arc per step
+// (row of an arc by binary search over the members' offsets in LDS), so
+// short and long member rows alike stream coalesced.  Used for capacities
+// kBinMax[4] < cap <= kBinMax[5] (NT = 256) and kBinMax[5] < cap <=
+// kBinMax[kAggLastBin] (NT = 1024, kWideSlots slots).
 constexpr int kAggWideThreads = 1024;
-template <class WTin, class WTout>
-__global__ __launch_bounds__(kAggWideThreads) void k_agg_wide(GraphView<WTin> g, AggArgs a,
-                                                              const int32_t* __restrict__ list, int32_t count) {
-  constexpr int NT = kAggWideThreads;
+template <class WTin, class WTout, int NT, int TS>
+__global__ __launch_bounds__(NT) void k_agg_rows(GraphView<WTin> g, AggArgs a, const int32_t* __restrict__ list,
+                                                 int32_t count) {
   constexpr int NW = NT / kWave;
-  constexpr int TS = kWideSlots;
   constexpr int R = TS / NT;  // emit rounds
+  static_assert(TS % NT == 0, "whole rounds");
   static_assert(R * NW <= 3 * kWave, "emit scan: at most three entries per lane");
   __shared__ int32_t keys[TS];
   __shared__ double vals[TS];
@@ -362,7 +268,7 @@ static void agg_bins(hipStream_t st, const GraphDesc& gd, const AggArgs& a, cons
   GVL_AGG_BIN(4, 64, 8)
 #undef GVL_AGG_BIN
   if (count[5] > 0) {
-    hipLaunchKernelGGL((k_agg_block<WTin, WTout, 11>), dim3(grid_for(count[5], 1, grid_cap)),
+    hipLaunchKernelGGL((k_agg_rows<WTin, WTout, kBlock, 2048>), dim3(grid_for(count[5], 1, grid_cap)),
                        dim3(kBlock), 0, st, g, a, list + start[5], count[5]);
     ++*launches;
   }
@@ -370,8 +276,8 @@ static void agg_bins(hipStream_t st, const GraphDesc& gd, const AggArgs& a, cons
   int32_t nwide = 0;
   for (int b = kWideBin0; b <= kAggLastBin; ++b) nwide += count[b];
   if (nwide > 0) {
-    hipLaunchKernelGGL((k_agg_wide<WTin, WTout>), dim3(grid_for(nwide, 1, grid_cap)), dim3(kAggWideThreads), 0,
-                       st, g, a, list + start[kWideBin0], nwide);
+    hipLaunchKernelGGL((k_agg_rows<WTin, WTout, kAggWideThreads, kWideSlots>), dim3(grid_for(nwide, 1, grid_cap)),
+                       dim3(kAggWideThreads), 0, st, g, a, list + start[kWideBin0], nwide);
     ++*launches;
   }
   (void)hub_grid;  // giant communities go through the chunked hub path
