@@ -328,7 +328,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       for (const HubBatch& hb : plan.groups[grp]) {
         tstate.ensure(st, ws, hb.tend - hb.tbase);
         hargs.tbase = hb.tbase;
-        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, phase, det, &dummy_launches);
+        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
+                   &dummy_launches);
       }
     };
     auto commit_group = [&](int grp, int phase) {
@@ -338,9 +339,10 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       const int32_t n1 = bins.count[grp][kHubBin];
       if (phase == kMove) {
         const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];
-        launch_commit_move(st, cur, a, l0, n0s, false);
-        launch_commit_move(st, cur, a, l0 + n0s, n0 - n0s, true);
-        launch_commit_move(st, cur, a, l1, n1, true);
+        launch_commit_move(st, cur, a, l0, n0s, 0);
+        launch_commit_move(st, cur, a, l0 + n0s, n0 - n0s, 1);
+        launch_commit_move(st, cur, a, l1, n1, 2);
+        for (const HubBatch& hb : plan.groups[grp]) hub_mark(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1);
       } else {
         launch_commit_refine(st, cur, a, l0, n0);
         launch_commit_refine(st, cur, a, l1, n1);

@@ -252,7 +252,8 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       for (const HubBatch& hb : plan.groups[grp]) {
         tstate.ensure(st, ws, hb.tend - hb.tbase);
         hargs.tbase = hb.tbase;
-        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, phase, det, &S->scan_launches);
+        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
+                   &S->scan_launches);
       }
     };
     auto commit_group = [&](int grp, int phase) {
@@ -263,9 +264,10 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       if (phase == kMove) {
         // rows of at most kBinMax[4] arcs, longer rows, hubs
         const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];
-        launch_commit_move(st, cur, a, l0, n0s, false);
-        launch_commit_move(st, cur, a, l0 + n0s, n0 - n0s, true);
-        launch_commit_move(st, cur, a, l1, n1, true);
+        launch_commit_move(st, cur, a, l0, n0s, 0);
+        launch_commit_move(st, cur, a, l0 + n0s, n0 - n0s, 1);
+        launch_commit_move(st, cur, a, l1, n1, 2);
+        for (const HubBatch& hb : plan.groups[grp]) hub_mark(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1);
       } else {
         launch_commit_refine(st, cur, a, l0, n0);
         launch_commit_refine(st, cur, a, l1, n1);

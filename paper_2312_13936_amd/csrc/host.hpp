@@ -46,6 +46,9 @@ struct Workspace {
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
   TblSlot* tbl;
+  int32_t* lbuf;  // partitioned hubs: sorted candidates, their weights, chunk offsets
+  void* wbuf;
+  uint16_t* poff;
   int64_t tbl_entries;
   // hub path
   int32_t *hp_chunk, *hp_tbl, *hp_slice, *hp_active, *hp_done, *hp_lcnt, *apre, *tbl_list;
@@ -108,6 +111,10 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   }
   w.tbl_entries = table_entries(tbl_n < 0 ? n : std::min(tbl_n, n));
   w.tbl = (TblSlot*)take(sizeof(TblSlot) * (size_t)w.tbl_entries);
+  w.lbuf = (int32_t*)take(4 * M);
+  w.wbuf = take(ws * M);
+  w.poff = (uint16_t*)take(2 * (kPartMaxP + 1) *
+                           ((size_t)M / kHubChunk + (size_t)M / ((size_t)kBinMax[kHubBin - 1] + 1) + 2));
   w.hp_chunk = (int32_t*)take(4 * (N + 1));
   w.hp_tbl = (int32_t*)take(4 * (N + 1));
   w.hp_slice = (int32_t*)take(4 * (N + 1));
@@ -334,6 +341,9 @@ HubArgs hub_args(Workspace& ws, const BinInfo& bins) {
   h.active = ws.hp_active; h.kid = ws.hp_kid; h.done = ws.hp_done;
   h.pb_g = ws.pb_g; h.pb_k = ws.pb_k; h.pb_c = ws.pb_c;
   h.tbl = ws.tbl;
+  h.lbuf = ws.lbuf;
+  h.wbuf = ws.wbuf;
+  h.poff = ws.poff;
   h.tbl_list = ws.tbl_list; h.lcnt = ws.hp_lcnt;
   h.apre = ws.apre;
   return h;

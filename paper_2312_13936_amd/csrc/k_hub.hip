@@ -44,10 +44,15 @@ __global__ void k_hub_setup(const int32_t* off, const int32_t* deg, const int32_
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
     const int32_t i = items[p];
     const int64_t d = deg ? deg[i] : off[i + 1] - off[i];
-    const int64_t ts = table_slots(d, n);
     chunk_off[p] = (int32_t)((d + kHubChunk - 1) / kHubChunk);
-    tbl_off[p] = (int32_t)(ts / kTblUnit);
-    slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
+    if (hub_partitioned(d)) {  // no table; one task per key partition
+      tbl_off[p] = 0;
+      slice_off[p] = hub_parts(d);
+    } else {
+      const int64_t ts = table_slots(d, n);
+      tbl_off[p] = (int32_t)(ts / kTblUnit);
+      slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
+    }
   }
 }
 void hub_setup(hipStream_t st, const int32_t* off, const int32_t* deg, const int32_t* items, int32_t H, int64_t n,
@@ -143,6 +148,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
   __shared__ int32_t snew[kHubChunk];
   __shared__ int s_nnew, s_base;
   __shared__ double s_red[kBlock / kWave];
+  __shared__ int s_wsum[kBlock / kWave];
+  static_assert(kPartMaxP <= kBlock && kPartMaxP < kHubChunk, "partition counts: one per thread");
+  static_assert(kHubChunk % kBlock == 0 && kHubChunk <= (1 << kHubGatherLg), "chunk staging in the LDS table");
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -156,6 +164,86 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
     const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
     const int32_t d = a.C[i];
+    if (hub_partitioned(deg)) {  // uniform: sort the chunk's candidates by partition
+      constexpr int U = kHubChunk / kBlock;
+      const int P = h.slice_off[p + 1] - h.slice_off[p];
+      int32_t* s_cnt = snew;  // [P + 1] counts, then offsets
+      for (int k = threadIdx.x; k <= P; k += kBlock) s_cnt[k] = 0;
+      __syncthreads();
+      int32_t c[U], rk[U];
+      double w[U];
+      double kid = 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t e = e0 + u * kBlock + threadIdx.x;
+        const int32_t j = (e < e1) ? g.idx[beg + e] : i;
+        w[u] = (e < e1) ? g.weight(beg + e) : 0.0;
+        c[u] = j;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t j = c[u];
+        const bool ok = j != i;
+        c[u] = ok ? a.C[j] : kEmpty;
+        if (PH == kRefine) {
+          const int32_t b = ok ? a.CB[j] : bi;
+          if (b != bi) c[u] = kEmpty;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (c[u] == d) {
+          kid += w[u];
+          c[u] = kEmpty;
+        }
+        rk[u] = (c[u] != kEmpty) ? atomicAdd(&s_cnt[wide_part(c[u]) & (uint32_t)(P - 1)], 1) : 0;
+      }
+      __syncthreads();
+      {  // exclusive scan of the P <= kBlock counts; s_cnt[P] = total
+        const int v = (threadIdx.x < P) ? s_cnt[threadIdx.x] : 0;
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+          const int x = __shfl_up(incl, o);
+          if (lane_id() >= o) incl += x;
+        }
+        const int wv = threadIdx.x / kWave;
+        if (lane_id() == kWave - 1) s_wsum[wv] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int k = 0; k < kBlock / kWave; ++k) {
+          if (k < wv) before += s_wsum[k];
+          total += s_wsum[k];
+        }
+        if (threadIdx.x < P) s_cnt[threadIdx.x] = before + incl - v;
+        if (threadIdx.x == 0) s_cnt[P] = total;
+        __syncthreads();
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (c[u] == kEmpty) continue;
+        const int pos = s_cnt[wide_part(c[u]) & (uint32_t)(P - 1)] + rk[u];
+        skeys[pos] = c[u];
+        svals[pos] = w[u];
+      }
+      __syncthreads();
+      const int n = s_cnt[P];
+      WT* wb = (WT*)h.wbuf;
+      for (int k = threadIdx.x; k < n; k += kBlock) {
+        h.lbuf[(int64_t)beg + e0 + k] = skeys[k];
+        wb[(int64_t)beg + e0 + k] = (WT)svals[k];
+        skeys[k] = kEmpty;
+        svals[k] = 0.0;
+      }
+      uint16_t* po = h.poff + t * (kPartMaxP + 1);
+      for (int k = threadIdx.x; k <= P; k += kBlock) po[k] = (uint16_t)s_cnt[k];
+      kid = block_sum<double>(kid, s_red);  // (its barriers also end this chunk's LDS use)
+      if (threadIdx.x == 0) {
+        na += (unsigned long long)(e1 - e0);
+        if (kid != 0.0) atomicAdd(&h.kid[p], kid);
+      }
+      continue;
+    }
     // arcs to the hub's own community are summed apart into kid[p]
     double kid = scan_row<4, kBlock, PH>(g, a, i, beg, e1, e0 + threadIdx.x, d, bi, [&](int32_t c, double w) {
       lds_insert(skeys, svals, kHubGatherLg, c, w);
@@ -193,6 +281,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
     const int32_t p = task.x;
     if (!h.active[p]) continue;  // uniform
     const int32_t i = h.items[p];
+    if (hub_partitioned(g.degree(i))) continue;  // uniform: k_hub_part_eval
     const int32_t d = a.C[i];
     const double ki = a.K[i];
     const Eval<DET> ev(a, i, h.kid[p], ki, a.Sig[d]);
@@ -325,25 +414,192 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
   if (threadIdx.x == 0 && nc) atomicAdd(&cnt_of(a.cnt)[2], nc);
 }
 
+// Partition evaluation of the partitioned hubs: task (p, q) accumulates the
+// candidates c of hub p with wide_part(c) mod P == q from lbuf into an LDS
+// table, evaluates them (Eq. 2) and leaves its partial best at the task's
+// index; the last partition of p to finish reduces them, applies the
+// min-label rule and the sign test, and commits (fast local-moving) or
+// records the decision.  A partition whose keys overflow the table
+// (statistically out of reach: at most kPartKeys expected per kPartSlots
+// slots) reports kOverflow and cancels the hub's move.
+constexpr int32_t kOverflow = -2;
+template <class WT, int PH, bool DET>
+__global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t s0,
+                                                                int32_t s1) {
+  constexpr int NT = kPartThreads;
+  constexpr int NW = NT / kWave;
+  constexpr int TS = kPartSlots;
+  static_assert(TS % NT == 0, "whole slots per thread");
+  __shared__ int32_t keys[TS];
+  __shared__ double vals[TS];
+  __shared__ double s_g[NW];
+  __shared__ i128 s_k[NW];
+  __shared__ int32_t s_c[NW];
+  __shared__ int s_ovf, s_last, s_take;
+  __shared__ int32_t s_pre[NT + 1];
+  __shared__ int32_t s_r0[NT];
+  __shared__ int32_t s_w[NW];
+  static_assert(kPartMaxDeg / kHubChunk <= NT, "one chunk per thread");
+  for (int s = threadIdx.x; s < TS; s += NT) { keys[s] = kEmpty; vals[s] = 0.0; }
+  Acc acc;
+  for (int64_t t = s0 + (int64_t)blockIdx.x; t < s1; t += gridDim.x) {
+    const int2 task = h.slice_tasks[t];
+    const int32_t p = task.x;
+    if (!h.active[p]) continue;  // uniform
+    const int32_t i = h.items[p];
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    if (!hub_partitioned(deg)) continue;  // uniform: k_hub_eval
+    const int32_t sb = h.slice_off[p], se = h.slice_off[p + 1];
+    const uint32_t pm = (uint32_t)(se - sb) - 1u;  // P - 1
+    const uint32_t q = (uint32_t)task.y;
+    // this partition's run in every chunk of p: start inside the chunk and
+    // prefix of the run lengths
+    const int32_t nch = h.chunk_off[p + 1] - h.chunk_off[p];
+    int32_t r0 = 0, len = 0;
+    if ((int)threadIdx.x < nch) {
+      const uint16_t* po = h.poff + ((int64_t)h.chunk_off[p] + threadIdx.x) * (kPartMaxP + 1);
+      r0 = po[q];
+      len = (int32_t)po[q + 1] - r0;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    __syncthreads();  // the previous task's reads of s_pre / s_r0 and of the table are done
+    if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = incl;
+    if (threadIdx.x == 0) s_ovf = 0;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NW; ++k) {
+      if (k < (int)(threadIdx.x / kWave)) before += s_w[k];
+      total += s_w[k];
+    }
+    s_pre[threadIdx.x] = before + incl - len;
+    s_r0[threadIdx.x] = r0;
+    if (threadIdx.x == 0) s_pre[NT] = total;
+    __syncthreads();
+    const WT* wb = (const WT*)h.wbuf;
+    constexpr int U = 4;  // entries per thread per step, their loads in flight together
+    for (int32_t kb = threadIdx.x; kb < total; kb += U * NT) {
+      int32_t ck[U];
+      double cw[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int32_t k = kb + u * NT;
+        ck[u] = kEmpty;
+        cw[u] = 0.0;
+        if (k < total) {
+          int lo = 0, hi = NT;  // s_pre[lo] <= k < s_pre[hi]
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= k) lo = mid; else hi = mid;
+          }
+          const int64_t pos = (int64_t)beg + (int64_t)lo * kHubChunk + s_r0[lo] + (k - s_pre[lo]);
+          ck[u] = h.lbuf[pos];
+          cw[u] = (double)wb[pos];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (ck[u] != kEmpty && !lds_insert_sized(keys, vals, (uint32_t)TS, ck[u], cw[u])) s_ovf = 1;
+    }
+    __syncthreads();
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
+    const Eval<DET> ev(a, i, h.kid[p], ki, a.Sig[d]);
+    int32_t bc = -1;
+    double bg = 0.0;
+    i128 bk = 0;
+    eval_table<TS / NT, NT, DET>(keys, vals, TS, threadIdx.x, a, ev, acc, bg, bk, bc);
+    block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
+    if (threadIdx.x == 0) {
+      h.pb_g[t] = bg;
+      h.pb_k[t] = bk;
+      h.pb_c[t] = s_ovf ? kOverflow : bc;
+      __threadfence();
+      const int prev = atomicAdd(&h.done[p], 1);
+      s_last = (prev == (int)pm) ? 1 : 0;
+    }
+    __syncthreads();
+    if (!s_last) continue;  // uniform
+    __threadfence();
+    bc = -1; bg = 0.0; bk = 0;
+    int ovf = 0;
+    for (int32_t k = sb + (int32_t)threadIdx.x; k < se; k += NT) {
+      const int32_t c2 = __hip_atomic_load(h.pb_c + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c2 == kOverflow) { ovf = 1; continue; }
+      if (DET) {
+        const unsigned long long* kw = (const unsigned long long*)(h.pb_k + k);
+        const unsigned long long lo = __hip_atomic_load(kw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long hi = __hip_atomic_load(kw + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const i128 k2 = make_i128((long long)hi, lo);
+        if (better_k(k2, c2, bk, bc)) { bk = k2; bc = c2; }
+      } else {
+        const double g2 = __hip_atomic_load(h.pb_g + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (better_f(g2, c2, bg, bc)) { bg = g2; bc = c2; }
+      }
+    }
+    ovf = __syncthreads_or(ovf);
+    block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
+    if (threadIdx.x == 0) {
+      h.done[p] = 0;
+      ++acc.nv;
+      const bool take = !ovf && accept<PH, DET>(a, d, bc, bg, bk);
+      s_take = take ? 1 : 0;
+      if (take) {
+        if (PH == kMove && !DET && !(a.sync_moves & 2)) {
+          atomicAdd(&a.Sig[d], -ki);
+          atomicAdd(&a.Sig[bc], ki);
+          atomicSub(&a.size[d], 1);
+          atomicAdd(&a.size[bc], 1);
+          a.C[i] = bc;
+          add_gain<DET>(a, acc, i, bg, bk);
+          ++acc.nm;
+        } else if (PH == kMove) {
+          a.target[i] = bc;
+          add_gain<DET>(a, acc, i, bg, bk);
+        } else {
+          a.target[i] = bc;
+          a.targeted[bc] = 1;
+        }
+      }
+    }
+    __syncthreads();
+    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) {
+      for (int32_t e = threadIdx.x; e < deg; e += NT) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i) a.flag[j] = 1;
+      }
+    }
+  }
+  flush_acc<PH, DET>(a, acc);  // (the arcs were counted by the chunk pass)
+}
+
 template <class WT, int PH, bool DET>
 static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const HubArgs& h, int32_t h0,
-                         int32_t h1, int32_t c0, int32_t c1, int32_t s0, int32_t s1, int64_t* launches) {
+                         int32_t h1, int32_t c0, int32_t c1, int32_t s0, int32_t s1, bool tables, int64_t* launches) {
   const GraphView<WT> g = view<WT>(gd);
   const int hb = grid_items(h1 - h0, kBlock, 1024);
   hipLaunchKernelGGL((k_hub_prep<PH, DET>), dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
   if (c1 > c0)
     hipLaunchKernelGGL((k_hub_gather<WT, PH>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g, a, h, c0,
                        c1);
-  if (s1 > s0)
-    hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a, h,
-                       s0, s1);
-  *launches += 3;
+  if (s1 > s0) {
+    if (tables)
+      hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a,
+                         h, s0, s1);
+    hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kPartThreads), 0,
+                       st, g, a, h, s0, s1);
+  }
+  *launches += tables ? 4 : 3;
 }
 
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
-                int32_t c0, int32_t c1, int32_t s0, int32_t s1, int phase, bool det, int64_t* launches) {
+                int32_t c0, int32_t c1, int32_t s0, int32_t s1, bool tables, int phase, bool det, int64_t* launches) {
   if (h1 <= h0) return;
-#define GVL_HUB(WT, PH, DET) hub_decide_t<WT, PH, DET>(st, g, a, h, h0, h1, c0, c1, s0, s1, launches)
+#define GVL_HUB(WT, PH, DET) hub_decide_t<WT, PH, DET>(st, g, a, h, h0, h1, c0, c1, s0, s1, tables, launches)
   if (g.w_double) {
     if (phase == kMove) { if (det) GVL_HUB(double, kMove, true); else GVL_HUB(double, kMove, false); }
     else { if (det) GVL_HUB(double, kRefine, true); else GVL_HUB(double, kRefine, false); }
@@ -352,6 +608,40 @@ void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const Hub
     else { if (det) GVL_HUB(float, kRefine, true); else GVL_HUB(float, kRefine, false); }
   }
 #undef GVL_HUB
+}
+
+// ------------------------------------------------- marks after hub moves ---
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_hub_mark(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t t0, int32_t t1) {
+  for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
+    const int2 task = h.chunk_tasks[t];
+    const int32_t i = h.items[task.x];
+    if (a.target[i] < 0) continue;  // uniform: no move
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t e0 = task.y * kHubChunk;
+    const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
+    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+      const int32_t j = g.idx[beg + e];
+      if (j != i) a.flag[j] = 1;
+    }
+  }
+}
+__global__ void k_hub_forget(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
+  for (int64_t p = h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += (int64_t)gridDim.x * blockDim.x)
+    a.target[h.items[p]] = -1;
+}
+void hub_mark(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
+              int32_t c0, int32_t c1) {
+  if (h1 <= h0) return;
+  if (c1 > c0) {
+    if (gd.w_double)
+      hipLaunchKernelGGL(k_hub_mark<double>, dim3(grid_items(c1 - c0, 1, 4096)), dim3(kBlock), 0, st, view<double>(gd),
+                         a, h, c0, c1);
+    else
+      hipLaunchKernelGGL(k_hub_mark<float>, dim3(grid_items(c1 - c0, 1, 4096)), dim3(kBlock), 0, st, view<float>(gd),
+                         a, h, c0, c1);
+  }
+  hipLaunchKernelGGL(k_hub_forget, dim3(grid_items(h1 - h0, kBlock, 64)), dim3(kBlock), 0, st, a, h, h0, h1);
 }
 
 // ------------------------------------------------------ row sums of hubs ---

@@ -17,9 +17,9 @@ void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, c
 }
 
 void launch_commit_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        int32_t count, bool long_rows) {
-  if (g.w_double) commit_list<double, kMove>(st, g, a, list, count, long_rows);
-  else commit_list<float, kMove>(st, g, a, list, count, long_rows);
+                        int32_t count, int kind) {
+  if (g.w_double) commit_list<double, kMove>(st, g, a, list, count, kind);
+  else commit_list<float, kMove>(st, g, a, list, count, kind);
 }
 
 }  // namespace gvl

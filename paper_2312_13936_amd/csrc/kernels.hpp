@@ -123,6 +123,26 @@ constexpr int kHubChunk = 2048;
 constexpr int kHubGatherLg = 12;      // LDS pre-aggregation table: 4096 slots
 constexpr int kHubSlice = 8192;
 constexpr int kTblUnit = 1024;
+// Vertex hubs of up to kPartMaxDeg arcs are scanned partitioned instead,
+// with P = next_pow2(ceil(deg / kPartKeys)) partitions of the neighbour
+// communities (wide_part mod P).  The chunk pass sorts each chunk's
+// candidates (community, weight) by partition in LDS and stores them at the
+// chunk's own arc positions in lbuf / wbuf, with the chunk's partition
+// offsets in poff; then one workgroup of kPartThreads threads per partition
+// reads its runs of every chunk and accumulates them in an LDS table of
+// kPartSlots slots (two workgroups per CU).  No global table and no global
+// atomic per key are needed, and every arc is read once.
+constexpr int32_t kPartKeys = 4096;
+constexpr int kPartThreads = 512;
+constexpr int kPartSlots = 6144;
+constexpr int kPartMaxP = 256;
+constexpr int32_t kPartMaxDeg = kPartMaxP * kPartKeys;
+__host__ __device__ __forceinline__ bool hub_partitioned(int64_t deg) { return deg <= kPartMaxDeg; }
+__host__ __device__ __forceinline__ int32_t hub_parts(int64_t deg) {
+  int32_t p = 1;
+  while ((int64_t)p * kPartKeys < deg) p <<= 1;
+  return p;
+}
 
 // Slot of a global hash table: key and value share one 16-byte slot, so an
 // insert (CAS on the key, add on the value) and a read touch one cache line.
@@ -146,6 +166,9 @@ struct HubArgs {
   i128_t* pb_k;               // per slice task: best exact key
   int32_t* pb_c;              // per slice task: best community
   TblSlot* tbl;               // table region
+  int32_t* lbuf;              // partitioned hubs: candidates of each chunk sorted by partition (arc positions)
+  void* wbuf;                 // their weights (the graph's weight type)
+  uint16_t* poff;             // [chunk task][kPartMaxP + 1] partition offsets inside the chunk
   int32_t* tbl_list;          // occupied slots of each item's table, at the item's table offset
   int32_t* lcnt;              // [H] length of each item's occupied-slot list
   int64_t tbase;              // region offset of the current batch (slots)
@@ -182,9 +205,10 @@ void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, c
                         const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
                         int64_t* launches);
 // Apply the recorded moves of the vertices list[0..count) and mark the
-// neighbours of movers (long_rows: one workgroup per vertex).
+// neighbours of movers.  kind: 0 short rows, 1 long rows (one workgroup per
+// vertex marks), 2 hubs (moves applied only; hub_mark marks and forgets).
 void launch_commit_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        int32_t count, bool long_rows);
+                        int32_t count, int kind);
 void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
                           const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
                           int64_t* launches);
@@ -210,7 +234,12 @@ void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_
 // One batch [h0, h1) of one group: eligibility snapshot, gather, own-community
 // weight, evaluation (+ commit in fast local-moving).
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
-                int32_t c0, int32_t c1, int32_t s0, int32_t s1, int phase, bool det, int64_t* launches);
+                int32_t c0, int32_t c1, int32_t s0, int32_t s1, bool tables, int phase, bool det, int64_t* launches);
+// Local-moving, after launch_commit_move(kind 2) of the hubs items[h0, h1):
+// marks the neighbours of the movers chunk by chunk (chunk tasks [c0, c1)),
+// then forgets the hubs' targets.
+void hub_mark(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
+              int32_t c0, int32_t c1);
 // K[i] += sums of the chunks of hub rows (K[i] of hubs zeroed by the caller).
 void hub_weights(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_t c0, int32_t c1, double* K,
                  double* accW, int32_t* flags, int validate);

@@ -558,13 +558,16 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
 // table.  Refinement: vertex i moves only if its own community was not
 // chosen as a target in this group.  Local-moving with MARK: every recorded
 // move applies, the target is forgotten and the neighbours of movers are
-// marked unprocessed (one wavefront walks each mover's row).  Without MARK
-// (long rows) the targets stay for k_mark_rows.
+// marked unprocessed; the workgroup lays its movers' rows end to end and
+// every lane marks one arc per step.  Without MARK (long rows, hubs) the
+// targets stay for the marking kernels.
 template <class WT, int PH, bool MARK = true>
 __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
                                                    const int32_t* __restrict__ list, int32_t count) {
   __shared__ unsigned long long red_u[16];
   __shared__ KeyedLds<kBlock> kt;
+  __shared__ int32_t s_off[kBlock + 1], s_beg[kBlock], s_vi[kBlock];
+  __shared__ int32_t s_w[kBlock / kWave];
   keyed_clear(kt);
   unsigned long long nm = 0;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
@@ -587,18 +590,37 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
       }
     }
     keyed_flush(kt, a.Sig, a.size);
-    if (PH == kMove && MARK) {
-      u64 mask = __ballot(mv);
-      while (mask) {
-        const int l = __ffsll((unsigned long long)mask) - 1;
-        mask &= mask - 1;
-        const int32_t ii = __shfl(i, l);
-        const int32_t beg = g.begin(ii), deg = g.degree(ii);
-        for (int32_t e = lane_id(); e < deg; e += kWave) {
-          const int32_t j = g.idx[beg + e];
-          if (j != ii) a.flag[j] = 1;
-        }
+    if (PH == kMove && MARK) {  // uniform
+      const int32_t deg = mv ? g.degree(i) : 0;
+      int incl = deg;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int x = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += x;
       }
+      const int w = threadIdx.x / kWave;
+      if (lane_id() == kWave - 1) s_w[w] = incl;
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int k = 0; k < kBlock / kWave; ++k) {
+        if (k < w) before += s_w[k];
+        total += s_w[k];
+      }
+      s_off[threadIdx.x] = before + incl - deg;
+      if (threadIdx.x == 0) s_off[kBlock] = total;
+      s_beg[threadIdx.x] = mv ? g.begin(i) : 0;
+      s_vi[threadIdx.x] = i;
+      __syncthreads();
+      for (int32_t q = threadIdx.x; q < total; q += kBlock) {
+        int lo = 0, hi = kBlock;  // s_off[lo] <= q < s_off[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_off[mid] <= q) lo = mid; else hi = mid;
+        }
+        const int32_t j = g.idx[(int64_t)s_beg[lo] + (q - s_off[lo])];
+        if (j != s_vi[lo]) a.flag[j] = 1;
+      }
+      __syncthreads();  // s_* are rewritten by the next entries
     }
   }
   nm = block_sum<unsigned long long>(nm, red_u);
@@ -698,12 +720,19 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   (void)hub_grid;  // the hub bin goes through the chunked hub path
 }
 
+// kind (local-moving): 0 short rows, 1 long rows (marked per vertex), 2 hubs
+// (applied only: marked and forgotten by hub_mark).
 template <class WT, int PH>
 void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count,
-                 bool long_rows = false) {
+                 int kind = 0) {
   if (count <= 0) return;
   const GraphView<WT> g = view<WT>(gd);
-  if (PH == kMove && long_rows) {
+  if (PH == kMove && kind == 2) {
+    hipLaunchKernelGGL((k_commit<WT, kMove, false>), dim3(grid_for(count, kBlock, 2048)), dim3(kBlock), 0, st, g,
+                       a, list, count);
+    return;
+  }
+  if (PH == kMove && kind == 1) {
     hipLaunchKernelGGL((k_commit<WT, kMove, false>), dim3(grid_for(count, kBlock, 2048)), dim3(kBlock), 0, st, g,
                        a, list, count);
     hipLaunchKernelGGL((k_mark_rows<WT>), dim3(grid_for(count, 1, 2048)), dim3(kBlock), 0, st, g, a, list, count);
