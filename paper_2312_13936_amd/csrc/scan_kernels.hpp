@@ -462,7 +462,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       __syncthreads();
       kid = s_d[0];
       const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
-      eval_table<TS / kWideThreads, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
+      eval_table<TS / kWideThreads / 2, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
       block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
     }
     const int ovf = s_ovf;
