@@ -72,7 +72,11 @@ typedef struct {
                                     arcs) and bit 1 (longer rows) instead decide a group on one
                                     snapshot and commit it afterwards (the deterministic schedule with
                                     FP64 gains).  Default 3. */
-  int32_t reserved[6];
+  int32_t louvain;               /* 1: no refinement -- the super-vertices of each pass are the
+                                    local-moving communities, i.e. the Louvain method that Leiden
+                                    refines (Sec. 3.2, 3.3); the run stops when local-moving converges
+                                    in its first iteration.  Default 0. */
+  int32_t reserved[5];
 } gvl_options;
 
 #define GVL_MAX_PASS_STATS 64
@@ -143,6 +147,19 @@ gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_
                           const int32_t* d_indices, const float* d_weights,
                           const int32_t* d_membership, double resolution, void* d_workspace,
                           size_t workspace_bytes, double* modularity);
+
+/* Alg. 5 on the device: the number of communities of d_membership (labels
+ * in [0, n)) whose members are not all connected by arcs inside the
+ * community (the quality check of Sec. 5: Leiden guarantees 0, Louvain does
+ * not).  d_flags: optional device int32[n] output, 1 at the label of every
+ * disconnected community, else 0.  Workspace: gvl_workspace_bytes(n, m) of
+ * the fast mode.  *count receives the number on the host; the call blocks
+ * until it is known.  Errors: GVL_E_INVALID_ARG (null count or membership),
+ * GVL_E_BAD_CSR (offsets not monotone or not ending at m), GVL_E_WORKSPACE. */
+gvl_status gvl_disconnected_communities(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,
+                                        const int32_t* d_indices, const int32_t* d_membership,
+                                        void* d_workspace, size_t workspace_bytes, int32_t* d_flags,
+                                        int64_t* count);
 
 /* Debug export of the last gvl_leiden run made with debug_trace = 1.
  * For pass p: n_out = |V'|, m_out = arcs of the super-vertex graph built in

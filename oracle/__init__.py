@@ -38,7 +38,7 @@ class Opts(ctypes.Structure):
                 ("tolerance_drop", ctypes.c_double), ("aggregation_tolerance", ctypes.c_double),
                 ("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
-                ("resolution", ctypes.c_double), ("trace", ctypes.c_int32)]
+                ("resolution", ctypes.c_double), ("trace", ctypes.c_int32), ("louvain", ctypes.c_int32)]
 
 
 def _load():

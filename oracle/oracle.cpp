@@ -14,6 +14,9 @@
 //   * Alg. 3 refinement by constrained merges        -> refine_seq / refine_det
 //   * Alg. 4 aggregation into the super-vertex graph -> aggregate
 //   * Alg. 5 disconnected-community check            -> disconnected
+//   * the Louvain method (louvain = 1): the same pass loop without the
+//     refinement, so each pass aggregates the local-moving communities
+//     (Sec. 3.2; the paper's comparison of Leiden with Louvain, Sec. 5)
 //
 // Two modes:
 //   mode 0 "seq-async": the paper's algorithm run by a single thread that
@@ -95,6 +98,7 @@ struct Opts {
   int32_t max_iterations, max_passes, refine_sweeps, subsweeps;
   double resolution;
   int32_t trace;
+  int32_t louvain = 0;
 };
 
 // Sub-sweep group of vertex i: the MurmurHash3 32-bit finalizer of i, mod S
@@ -494,12 +498,15 @@ int run_leiden(const Graph& g0, const Opts& o, Result& res) {
                         : move_seq(cur, st, tau, o, Wd, &tr.movers, &first);
     tr.converged_first = first;
     std::vector<int32_t> bound = st.C;
-    // refinement starts from singletons inside the bounds (Alg. 1)
-    std::vector<int32_t> ident(n);
-    for (i64 i = 0; i < n; ++i) ident[i] = (int32_t)i;
-    init_state(cur, st, ident);
-    tr.refine_sweeps = det ? refine_det(cur, st, bound, o, Wi, p, &tr.refine_movers)
-                           : refine_seq(cur, st, bound, o, Wd, &tr.refine_movers);
+    if (!o.louvain) {
+      // refinement starts from singletons inside the bounds (Alg. 1)
+      std::vector<int32_t> ident(n);
+      for (i64 i = 0; i < n; ++i) ident[i] = (int32_t)i;
+      init_state(cur, st, ident);
+      tr.refine_sweeps = det ? refine_det(cur, st, bound, o, Wi, p, &tr.refine_movers)
+                             : refine_seq(cur, st, bound, o, Wd, &tr.refine_movers);
+    }
+    // (the Louvain method aggregates the local-moving communities themselves)
     i64 ncom = 0;
     std::vector<int32_t> rank = dense_rank(st.C, n, &ncom);
     tr.communities = ncom;
@@ -585,6 +592,7 @@ typedef struct {
   int32_t subsweeps;             // det-sync: pseudo-random vertex groups visited in turn
   double resolution;             // gamma
   int32_t trace;                 // keep per-pass labels and super-vertex CSRs
+  int32_t louvain;               // 1: no refinement (the Louvain method)
 } oracle_opts;
 
 void oracle_default_opts(oracle_opts* o, int32_t mode) {
@@ -598,6 +606,7 @@ void oracle_default_opts(oracle_opts* o, int32_t mode) {
   o->subsweeps = mode == 1 ? 32 : 1;
   o->resolution = 1.0;
   o->trace = 0;
+  o->louvain = 0;
 }
 
 // Runs Leiden; returns an opaque result handle, or NULL with *status set.
@@ -608,7 +617,7 @@ void* oracle_leiden(int64_t n, const int32_t* off, const int32_t* idx, const flo
   op.mode = o->mode; op.tolerance = o->tolerance; op.tolerance_drop = o->tolerance_drop;
   op.aggregation_tolerance = o->aggregation_tolerance; op.max_iterations = o->max_iterations;
   op.max_passes = o->max_passes; op.refine_sweeps = o->refine_sweeps; op.subsweeps = o->subsweeps;
-  op.resolution = o->resolution; op.trace = o->trace;
+  op.resolution = o->resolution; op.trace = o->trace; op.louvain = o->louvain;
   Result* r = new Result();
   int rc = run_leiden(g, op, *r);
   *status = rc;

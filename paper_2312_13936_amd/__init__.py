@@ -43,7 +43,7 @@ class gvl_options(ctypes.Structure):
                 ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("debug_trace", ctypes.c_int32), ("sync_moves", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("louvain", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 _P = GVL_MAX_PASS_STATS
@@ -84,7 +84,7 @@ class gvl_server_info(ctypes.Structure):
 
 
 EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
-           "gvl_modularity", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
+           "gvl_modularity", "gvl_disconnected_communities", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
            "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_fused_workspace_bytes", "gvl_leiden_fused",
            "gvl_server_create", "gvl_server_submit",
            "gvl_server_poll", "gvl_server_wait", "gvl_server_cancel", "gvl_server_release",
@@ -110,6 +110,7 @@ def load_library(path: str = LIB_PATH):
     lib.gvl_leiden.argtypes = [vp, i64, i64, vp, vp, vp, dbl, ctypes.POINTER(gvl_options), vp, sz, vp,
                                ctypes.POINTER(dbl), ctypes.POINTER(gvl_stats)]
     lib.gvl_modularity.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(dbl)]
+    lib.gvl_disconnected_communities.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp, ctypes.POINTER(i64)]
     lib.gvl_debug_pass_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.gvl_debug_export_pass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
     lib.gvl_debug_pass_movers.argtypes = [vp, i32, vp, i32, vp, i32]
@@ -183,6 +184,15 @@ def gvl_modularity(ctx, n, m, d_offsets, d_indices, d_weights, d_membership, res
                                          d_workspace, workspace_bytes, ctypes.byref(q))
     _check(code, "gvl_modularity")
     return q.value
+
+
+def gvl_disconnected_communities(ctx, n, m, d_offsets, d_indices, d_membership, d_workspace, workspace_bytes,
+                                 d_flags=None) -> int:
+    count = ctypes.c_int64(0)
+    code = load_library().gvl_disconnected_communities(ctx, n, m, d_offsets, d_indices, d_membership, d_workspace,
+                                                       workspace_bytes, d_flags, ctypes.byref(count))
+    _check(code, "gvl_disconnected_communities")
+    return count.value
 
 
 def gvl_debug_pass_info(ctx, p: int):
@@ -382,6 +392,15 @@ class Leiden:
         return gvl_modularity(self.ctx, n, m, offsets.data_ptr(), indices.data_ptr(),
                               None if weights is None else weights.data_ptr(), membership.data_ptr(),
                               float(resolution), ws.data_ptr(), ws.numel())
+
+    def disconnected(self, offsets, indices, membership, flags=None) -> int:
+        """Alg. 5 on the device: communities of `membership` that are not connected."""
+        n = offsets.numel() - 1
+        m = indices.numel()
+        ws = self.workspace(gvl_workspace_bytes(n, m, self.options()))
+        return gvl_disconnected_communities(self.ctx, n, m, offsets.data_ptr(),
+                                            indices.data_ptr() if m else None, membership.data_ptr(),
+                                            ws.data_ptr(), ws.numel(), None if flags is None else flags.data_ptr())
 
 
 def leiden(offsets, indices, weights=None, resolution: float = 1.0, mode: int = GVL_MODE_FAST, **kw):

@@ -387,17 +387,20 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       }
     }
 
-    // ---- refinement (Alg. 3)
+    // ---- refinement (Alg. 3); the Louvain method keeps the local-moving
+    // communities as they are (C' = C'_B)
     copy_i32(st, ws.CB, ws.C, nn);
-    iota_i32(st, ws.C, nn);
-    copy_f64(st, ws.Sig, ws.K, nn);
-    set_size_one(st, ws.size, nn);
-    fill_u8(st, ws.targeted, 0, nn);
+    if (!opt->louvain) {
+      iota_i32(st, ws.C, nn);
+      copy_f64(st, ws.Sig, ws.K, nn);
+      set_size_one(st, ws.size, nn);
+      fill_u8(st, ws.targeted, 0, nn);
+    }
     fill_u64(st, B.mvg, 0ull, K);
     s = readback(ctx, ws.sc);
     if (s != GVL_OK) return s;
     moves_before = counter(ctx->host, 3);
-    for (int32_t sw = 0; sw < opt->refine_sweeps; ++sw) {
+    for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         decide_group(grp, kRefine);
         commit_group(grp, kRefine);

@@ -118,6 +118,32 @@ gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_
   return modularity_device(ctx, ws, in, d_membership, W, integral, resolution, modularity);
 }
 
+gvl_status gvl_disconnected_communities(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
+                                        const int32_t* d_idx, const int32_t* d_membership, void* d_ws,
+                                        size_t ws_bytes, int32_t* d_flags, int64_t* count) {
+  gvl_options opt;
+  gvl_default_options(&opt, GVL_MODE_FAST);
+  gvl_status s = check_args(ctx, n, m, d_off, d_idx, 1.0, &opt, d_ws, ws_bytes);
+  if (s != GVL_OK) return s;
+  if (!count || (n > 0 && !d_membership)) return GVL_E_INVALID_ARG;
+  *count = 0;
+  if (n == 0) return GVL_OK;
+  if (hipSetDevice(ctx->device) != hipSuccess) return GVL_E_HIP;
+  Workspace ws = carve(n, m, false, (char*)d_ws);
+  hipStream_t st = ctx->stream;
+  fill_u64(st, (unsigned long long*)ws.sc, 0ull, sizeof(Scalars) / 8);
+  check_offsets(st, d_off, n, m, ws.sc->flags);
+  s = readback(ctx, ws.sc);
+  if (s != GVL_OK) return s;
+  if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
+  disconnected_communities(st, d_off, d_idx, d_membership, n, ws.C, ws.CB, d_flags ? d_flags : ws.target,
+                           &ws.sc->acc_u[0]);
+  s = readback(ctx, ws.sc);
+  if (s != GVL_OK) return s;
+  *count = (int64_t)ctx->host->acc_u[0];
+  return GVL_OK;
+}
+
 gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off, const int32_t* d_idx,
                       const float* d_w, double resolution, const gvl_options* opt, void* d_ws,
                       size_t ws_bytes, int32_t* d_membership, double* modularity, gvl_stats* stats) {
@@ -315,16 +341,19 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       }
     }
     tm.end(h);
-    // ---- 3. refinement (Alg. 3)
+    // ---- 3. refinement (Alg. 3); the Louvain method keeps the local-moving
+    // communities as they are (C' = C'_B)
     h = tm.begin(kEvRefine);
     copy_i32(st, ws.CB, ws.C, nn);
-    iota_i32(st, ws.C, nn);
-    copy_f64(st, ws.Sig, ws.K, nn);
-    set_size_one(st, ws.size, nn);
-    fill_u8(st, ws.targeted, 0, nn);
     int32_t sweeps = 0;
     int64_t refine_moved = 0;
-    for (int32_t sw = 0; sw < opt->refine_sweeps; ++sw) {
+    if (!opt->louvain) {
+      iota_i32(st, ws.C, nn);
+      copy_f64(st, ws.Sig, ws.K, nn);
+      set_size_one(st, ws.size, nn);
+      fill_u8(st, ws.targeted, 0, nn);
+    }
+    for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         const int hk = tm.begin(kEvScanRefineK);
         decide_group(grp, kRefine);

@@ -309,3 +309,66 @@ def test_det_mode_is_reproducible_and_traced():
     assert np.array_equal(a.membership, b.membership) and a.q == b.q
     for x, y in zip(a.passes, b.passes):
         assert np.array_equal(x.bound, y.bound) and np.array_equal(x.refined, y.refined)
+
+
+# ------------------------------------------------ Louvain mode, Alg. 5 ---
+
+def _components_per_community(g, membership):
+    """Connected pieces of each community, by scipy's graph search on the
+    subgraph of intra-community arcs (independent of the oracle's BFS)."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import connected_components
+    rows = np.repeat(np.arange(g.n), np.diff(g.offsets))
+    cols = g.indices.astype(np.int64)
+    keep = membership[rows] == membership[cols]
+    a = csr_matrix((np.ones(int(keep.sum())), (rows[keep], cols[keep])), shape=(g.n, g.n))
+    _, comp = connected_components(a, directed=False)
+    pieces = {}
+    for v in range(g.n):
+        pieces.setdefault(int(membership[v]), set()).add(int(comp[v]))
+    return {c: len(s) for c, s in pieces.items()}
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_disconnected_count_matches_graph_search(seed):
+    rng = np.random.default_rng(seed)
+    g = gen.random_graph(200, 0.02, 900 + seed, wmax=3)
+    for k in (2, 7, 40, 200):
+        mem = rng.integers(0, k, g.n).astype(np.int32)
+        want = sum(1 for v in _components_per_community(g, mem).values() if v > 1)
+        assert oracle.disconnected(g, mem) == want
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_louvain_ring_of_cliques(mode):
+    k, s = 10, 5
+    g = gen.ring_of_cliques(k, s)
+    r = oracle.leiden(g, mode=mode, louvain=1)
+    assert np.array_equal(r.membership, np.repeat(np.arange(k), s))
+    assert r.q == pytest.approx(89 / 110, abs=1e-15)
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_louvain_aggregates_local_moving_communities(mode):
+    g = gen.rmat(11, 8, seed=5)
+    r = oracle.leiden(g, mode=mode, louvain=1, trace=True)
+    lei = oracle.leiden(g, mode=mode, trace=True)
+    # the first local-moving phase is the same algorithm on the same input
+    assert np.array_equal(r.passes[0].bound, lei.passes[0].bound)
+    for t in r.passes:
+        assert t.refine_sweeps == 0
+        assert np.array_equal(t.refined, t.bound)
+    assert r.q == oracle.modularity(g, r.membership)
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_louvain_can_leave_disconnected_communities(mode):
+    # the failure that the refinement phase removes (Sec. 3.3): on this
+    # R-MAT graph the Louvain result has disconnected communities, the
+    # Leiden result none
+    g = gen.rmat(14, 16, seed=7)
+    lou = oracle.leiden(g, mode=mode, louvain=1)
+    lei = oracle.leiden(g, mode=mode)
+    parts = _components_per_community(g, lou.membership)
+    assert sum(1 for v in parts.values() if v > 1) == oracle.disconnected(g, lou.membership) > 0
+    assert oracle.disconnected(g, lei.membership) == 0
