@@ -326,6 +326,42 @@ def bench_serve(args, mode):
     }
 
 
+def compare_louvain(eng, off, idx, wt, r, leiden_ms, mode, kw, args):
+    """The paper's Leiden-versus-Louvain comparison (Sec. 5) on the same
+    graph: the same pipeline without refinement, its time and modularity,
+    and the communities that each leaves disconnected (Alg. 5 on the
+    device).  Untimed by the metric."""
+    import torch
+    t0 = time.perf_counter()
+    dis = eng.disconnected(off, idx, r.membership)
+    torch.cuda.synchronize()
+    check_ms = 1e3 * (time.perf_counter() - t0)
+    lopt = eng.options(mode, louvain=1, **kw)
+    rl = eng.run(off, idx, wt, 1.0, lopt)
+    torch.cuda.synchronize()
+    lt = []
+    for _ in range(max(1, min(args.steps, 3))):
+        t1 = time.perf_counter()
+        rl = eng.run(off, idx, wt, 1.0, lopt)
+        torch.cuda.synchronize()
+        lt.append(time.perf_counter() - t1)
+    ldis = eng.disconnected(off, idx, rl.membership)
+
+    def nontrivial(m):
+        return int((torch.bincount(m.long()) > 1).sum().item())
+
+    lms = 1e3 * sum(lt) / len(lt)
+    nl = nontrivial(rl.membership)
+    log("louvain: %.1f ms Q=%.6f disconnected %d of %d communities with >1 member (leiden: %d)" % (
+        lms, rl.modularity, ldis, nl, dis))
+    return {"leiden_ms": leiden_ms, "louvain_ms": lms, "leiden_time_over_louvain": leiden_ms / lms,
+            "leiden_modularity": r.modularity, "louvain_modularity": rl.modularity,
+            "leiden_communities": int(r.stats.num_communities), "louvain_communities": int(rl.stats.num_communities),
+            "leiden_disconnected": dis, "louvain_disconnected": ldis,
+            "louvain_disconnected_of_nonsingleton": ldis / max(nl, 1),
+            "check_ms": check_ms}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -346,6 +382,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-serve", action="store_true",
                     help="default workload: skip the batched and served parts of the metric")
+    ap.add_argument("--no-louvain", action="store_true",
+                    help="single-graph workloads: skip the Leiden / Louvain comparison")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--serve-pool", type=int, default=32)
@@ -470,6 +508,8 @@ def main():
                                  "kernel_ms_per_step": ams / len(stats)},
         "cpu_baseline": None,
     }
+    if not args.no_louvain:
+        out["louvain_comparison"] = compare_louvain(eng, off, idx, wt, r, ms_per_step, mode, kw, args)
     eng.close()
     del off, idx, wt
     torch.cuda.synchronize()
