@@ -76,7 +76,14 @@ typedef struct {
                                     local-moving communities, i.e. the Louvain method that Leiden
                                     refines (Sec. 3.2, 3.3); the run stops when local-moving converges
                                     in its first iteration.  Default 0. */
-  int32_t reserved[5];
+  int32_t refine_random;         /* 1: randomized refinement (Sec. 4.1's alternative to the greedy
+                                    one, Traag's original rule): among the in-bound targets with a
+                                    positive gain a vertex picks c with probability proportional to
+                                    the gain, from counter-based draws of (seed, pass, sweep, vertex,
+                                    candidate); deterministic mode stays bit-reproducible for a seed.
+                                    Default 0 (greedy). */
+  uint32_t seed;                 /* seed of the randomized refinement */
+  int32_t reserved[3];
 } gvl_options;
 
 #define GVL_MAX_PASS_STATS 64

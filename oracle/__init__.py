@@ -38,7 +38,8 @@ class Opts(ctypes.Structure):
                 ("tolerance_drop", ctypes.c_double), ("aggregation_tolerance", ctypes.c_double),
                 ("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
-                ("resolution", ctypes.c_double), ("trace", ctypes.c_int32), ("louvain", ctypes.c_int32)]
+                ("resolution", ctypes.c_double), ("trace", ctypes.c_int32), ("louvain", ctypes.c_int32),
+                ("refine_random", ctypes.c_int32), ("seed", ctypes.c_uint32)]
 
 
 def _load():
@@ -68,6 +69,10 @@ def _load():
         lib.oracle_delta_modularity.restype = dbl
         lib.oracle_aggregate.argtypes = [i64, vp, vp, vp, vp, i64, vp, vp, vp]
         lib.oracle_aggregate.restype = i64
+        lib.oracle_random_score.argtypes = [dbl, ctypes.c_uint32, i32, i32, i64, i32]
+        lib.oracle_random_score.restype = dbl
+        lib.oracle_neg_ln_unit.argtypes = [ctypes.c_uint32]
+        lib.oracle_neg_ln_unit.restype = dbl
         lib.oracle_disconnected.argtypes = [i64, vp, vp, vp, vp]
         lib.oracle_disconnected.restype = i64
         _lib = lib
@@ -193,3 +198,13 @@ def disconnected(g, membership) -> int:
     mem = np.ascontiguousarray(membership, dtype=np.int32)
     flags = np.zeros(g.n, np.int32)
     return int(_load().oracle_disconnected(g.n, _p(off), _p(idx), _p(mem), _p(flags)))
+
+
+def random_score(gain: float, seed: int, pass_: int, sweep: int, i: int, c: int) -> float:
+    """Randomized refinement: selection score gain / (-ln u) of candidate c."""
+    return float(_load().oracle_random_score(gain, seed, pass_, sweep, i, c))
+
+
+def neg_ln_unit(x: int) -> float:
+    """-ln((x + 1/2) / 2^32) as the randomized refinement computes it."""
+    return float(_load().oracle_neg_ln_unit(x))

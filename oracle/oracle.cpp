@@ -99,6 +99,8 @@ struct Opts {
   double resolution;
   int32_t trace;
   int32_t louvain = 0;
+  int32_t refine_random = 0;  // refinement picks c with probability proportional to its gain
+  uint32_t seed = 0;
 };
 
 // Sub-sweep group of vertex i: the MurmurHash3 32-bit finalizer of i, mod S
@@ -108,6 +110,49 @@ uint32_t fmix32(uint32_t h) {
   return h;
 }
 int32_t group_of(i64 i, int32_t S) { return (int32_t)(fmix32((uint32_t)i) % (uint32_t)S); }
+
+// ---------------------------------------------- randomized refinement ---
+// The alternative refinement of Sec. 4.1 (Traag's original rule): among the
+// targets with a positive gain, vertex i picks c with probability
+// proportional to the gain.  Draws are counter-based, one per (seed, pass,
+// sweep, vertex, candidate) of the pass graph: MurmurHash3's finalizer
+// mixes the counters into a nonzero xorshift32 state (Marsaglia, "Xorshift
+// RNGs", 2003) that takes one step, and u = (x + 1/2) / 2^32.  The candidate
+// with the largest gain / (-ln u) wins: -ln u / gain is an exponential clock
+// of rate gain, and the first of independent clocks to ring is c with
+// probability gain_c / sum of gains.
+uint32_t draw32(uint32_t seed, int32_t pass, int32_t sweep, i64 i, int32_t c) {
+  uint32_t x = fmix32((uint32_t)pass * 0x9E3779B9u + (uint32_t)sweep);
+  x = fmix32((uint32_t)c ^ x);
+  x = fmix32((uint32_t)i ^ x);
+  x = fmix32(seed ^ x);
+  if (x == 0) x = 0x6D2B79F5u;
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+
+// -ln(u) for u = (x + 1/2) / 2^32, with ln written out: u = m 2^e with m in
+// [1, 2), ln m = 2 atanh(z) = 2 (z + z^3/3 + ...), z = (m - 1) / (m + 1) < 1/3,
+// 24 terms (the tail is below 1e-23).
+double neg_ln_unit(uint32_t x) {
+  double m = ((double)x + 0.5) * (1.0 / 4294967296.0);
+  int32_t e = 0;
+  while (m < 1.0) { m *= 2.0; --e; }
+  const double z = (m - 1.0) / (m + 1.0), z2 = z * z;
+  double s = 0.0, t = z;
+  for (int32_t k = 0; k < 24; ++k) {
+    s += t * (1.0 / (double)(2 * k + 1));
+    t *= z2;
+  }
+  return -((double)e * 0.6931471805599453 + 2.0 * s);
+}
+
+// Selection score of a candidate with a positive gain (key or FP64 gain).
+double random_score(double gain, const Opts& o, int32_t pass, int32_t sweep, i64 i, int32_t c) {
+  return gain / neg_ln_unit(draw32(o.seed, pass, sweep, i, c));
+}
 
 struct Result {
   std::vector<int32_t> membership;
@@ -313,7 +358,7 @@ int32_t move_det(const Graph& g, State& st, double tau, const Opts& o, i64 W, i6
 // One sweep in ascending order (the paper's single parallel loop with one
 // thread); the isolation test is the paper's Sigma'[c] == K'[i].
 int32_t refine_seq(const Graph& g, State& st, const std::vector<int32_t>& bound, const Opts& o,
-                   double W, std::vector<i64>* movers) {
+                   double W, int32_t pass, std::vector<i64>* movers) {
   const i64 n = g.n;
   const double m = W / 2.0, gamma = o.resolution;
   Table H(n);
@@ -330,6 +375,10 @@ int32_t refine_seq(const Graph& g, State& st, const std::vector<int32_t>& bound,
       for (int32_t c : H.keys) {
         if (c == d) continue;
         double x = gain_fp(H.val[c], kid, ki, st.S[c], st.S[d], m, gamma);
+        if (o.refine_random) {
+          if (!(x > 0.0)) continue;
+          x = random_score(x, o, pass, sw, i, c);
+        }
         if (best < 0 || x > bg || (x == bg && c < best)) { best = c; bg = x; }
       }
       H.clear();
@@ -354,7 +403,7 @@ int32_t refine_seq(const Graph& g, State& st, const std::vector<int32_t>& bound,
 // the start of the group, and moves only if no vertex of the group picked
 // its own community as a target.
 int32_t refine_det(const Graph& g, State& st, const std::vector<int32_t>& bound, const Opts& o,
-                   i64 W, i64 p, std::vector<i64>* movers) {
+                   i64 W, i64 p, int32_t pass, std::vector<i64>* movers) {
   const i64 n = g.n;
   const int32_t S = std::max<int32_t>(1, o.subsweeps);
   std::vector<int32_t> target(n, -1);
@@ -374,9 +423,16 @@ int32_t refine_det(const Graph& g, State& st, const std::vector<int32_t>& bound,
         const i64 kid = (i64)H.get(d), ki = (i64)st.K[i];
         int32_t best = -1;
         i128 bk = 0;
+        double bs = 0.0;
         for (int32_t c : H.keys) {
           if (c == d) continue;
           i128 x = gain_key((i64)H.val[c], kid, ki, (i64)st.S[c], (i64)st.S[d], W, p);
+          if (o.refine_random) {  // largest score among positive keys, lowest id on ties
+            if (!(x > 0)) continue;
+            const double s = random_score(i128_to_double(x), o, pass, sw, i, c);
+            if (best < 0 || s > bs || (s == bs && c < best)) { best = c; bs = s; bk = x; }
+            continue;
+          }
           if (best < 0 || x > bk || (x == bk && c < best)) { best = c; bk = x; }
         }
         H.clear();
@@ -503,8 +559,8 @@ int run_leiden(const Graph& g0, const Opts& o, Result& res) {
       std::vector<int32_t> ident(n);
       for (i64 i = 0; i < n; ++i) ident[i] = (int32_t)i;
       init_state(cur, st, ident);
-      tr.refine_sweeps = det ? refine_det(cur, st, bound, o, Wi, p, &tr.refine_movers)
-                             : refine_seq(cur, st, bound, o, Wd, &tr.refine_movers);
+      tr.refine_sweeps = det ? refine_det(cur, st, bound, o, Wi, p, pass, &tr.refine_movers)
+                             : refine_seq(cur, st, bound, o, Wd, pass, &tr.refine_movers);
     }
     // (the Louvain method aggregates the local-moving communities themselves)
     i64 ncom = 0;
@@ -593,6 +649,8 @@ typedef struct {
   double resolution;             // gamma
   int32_t trace;                 // keep per-pass labels and super-vertex CSRs
   int32_t louvain;               // 1: no refinement (the Louvain method)
+  int32_t refine_random;         // 1: randomized refinement (gain-proportional choice)
+  uint32_t seed;                 // its seed
 } oracle_opts;
 
 void oracle_default_opts(oracle_opts* o, int32_t mode) {
@@ -607,6 +665,8 @@ void oracle_default_opts(oracle_opts* o, int32_t mode) {
   o->resolution = 1.0;
   o->trace = 0;
   o->louvain = 0;
+  o->refine_random = 0;
+  o->seed = 0;
 }
 
 // Runs Leiden; returns an opaque result handle, or NULL with *status set.
@@ -618,6 +678,7 @@ void* oracle_leiden(int64_t n, const int32_t* off, const int32_t* idx, const flo
   op.aggregation_tolerance = o->aggregation_tolerance; op.max_iterations = o->max_iterations;
   op.max_passes = o->max_passes; op.refine_sweeps = o->refine_sweeps; op.subsweeps = o->subsweeps;
   op.resolution = o->resolution; op.trace = o->trace; op.louvain = o->louvain;
+  op.refine_random = o->refine_random; op.seed = o->seed;
   Result* r = new Result();
   int rc = run_leiden(g, op, *r);
   *status = rc;
@@ -708,6 +769,15 @@ int64_t oracle_aggregate(int64_t n, const int32_t* off, const int32_t* idx, cons
   if (y_w) memcpy(y_w, y.w.data(), sizeof(double) * y.w.size());
   return (int64_t)y.idx.size();
 }
+
+// Selection score of the randomized refinement for one candidate (exposed
+// for the distribution tests).
+double oracle_random_score(double gain, uint32_t seed, int32_t pass, int32_t sweep, int64_t i, int32_t c) {
+  Opts o{};
+  o.seed = seed;
+  return random_score(gain, o, pass, sweep, i, c);
+}
+double oracle_neg_ln_unit(uint32_t x) { return neg_ln_unit(x); }
 
 // Alg. 5: flag[c] = 1 if the vertices of community c are not all reachable
 // from one member through vertices of c.  Returns the number flagged.

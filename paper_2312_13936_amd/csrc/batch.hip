@@ -291,9 +291,13 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   if ((s = upload(st, B.vcur, vcur)) != GVL_OK) return s;
   int32_t alive = K;
 
+  a.seed = opt->seed;
+  a.vbase = B.vcur;
   for (int32_t pass = 0; pass < opt->max_passes && alive > 0; ++pass) {
     const int64_t nn = cur.n;
     a.gid = gid;
+    a.pass = pass;
+    a.rnd = 0;
     // ---- bins, hub plan, K', initial labels
     BinInfo bins;
     s = make_bins(ctx, ws, cur.off, cur.deg, nn, opt->subsweeps, true, bins, gid, B.vcur);
@@ -401,6 +405,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     if (s != GVL_OK) return s;
     moves_before = counter(ctx->host, 3);
     for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
+      a.rnd = opt->refine_random;
+      a.sweep = sw;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         decide_group(grp, kRefine);
         commit_group(grp, kRefine);

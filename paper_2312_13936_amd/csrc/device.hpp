@@ -174,6 +174,48 @@ __device__ __forceinline__ bool lds_insert_sized(int32_t* keys, double* vals, ui
   return false;
 }
 
+// ------------------------------------------------ randomized refinement ---
+// Counter-based draw for (seed, pass, sweep, vertex, candidate):
+// MurmurHash3's 32-bit finalizer mixes the counters into a nonzero
+// xorshift32 state (Marsaglia, "Xorshift RNGs", 2003) that takes one step.
+__device__ __forceinline__ uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16; h *= 0x85ebca6bu; h ^= h >> 13; h *= 0xc2b2ae35u; h ^= h >> 16;
+  return h;
+}
+__device__ __forceinline__ uint32_t draw32(uint32_t seed, int32_t pass, int32_t sweep, int32_t i, int32_t c) {
+  uint32_t x = fmix32((uint32_t)pass * 0x9E3779B9u + (uint32_t)sweep);
+  x = fmix32((uint32_t)c ^ x);
+  x = fmix32((uint32_t)i ^ x);
+  x = fmix32(seed ^ x);
+  if (x == 0) x = 0x6D2B79F5u;
+  x ^= x << 13;
+  x ^= x >> 17;
+  x ^= x << 5;
+  return x;
+}
+// -ln(u), u = (x + 1/2) / 2^32: u = m 2^e with m in [1, 2), ln m = 2 atanh(z)
+// summed as the series z + z^3/3 + ... (24 terms, z = (m - 1)/(m + 1) < 1/3);
+// plain IEEE operations only, so the value is the same on every device.
+__device__ __forceinline__ double neg_ln_unit(uint32_t x) {
+  double m = ((double)x + 0.5) * (1.0 / 4294967296.0);
+  int32_t e = 0;
+  while (m < 1.0) { m *= 2.0; --e; }
+  const double z = (m - 1.0) / (m + 1.0), z2 = z * z;
+  double s = 0.0, t = z;
+#pragma unroll
+  for (int32_t k = 0; k < 24; ++k) {
+    s += t * (1.0 / (double)(2 * k + 1));
+    t *= z2;
+  }
+  return -((double)e * 0.6931471805599453 + 2.0 * s);
+}
+// int128 -> double as hi 2^64 + lo (each part converted exactly rounded).
+__device__ __forceinline__ double key_to_double(i128 k) {
+  const long long hi = (long long)(k >> 64);
+  const unsigned long long lo = (unsigned long long)k;
+  return (double)hi * 18446744073709551616.0 + (double)lo;
+}
+
 // Partition hash of a community id for wide rows (Wellons' "lowbias32"
 // integer mixer); independent of hslot, which takes the high bits of a
 // multiplicative hash.

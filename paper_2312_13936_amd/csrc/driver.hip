@@ -206,7 +206,10 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   long long Wi = 0, p = 0;
   tm.end(h);
 
+  a.seed = opt->seed;
   for (pass = 0; pass < opt->max_passes; ++pass) {
+    a.pass = pass;
+    a.rnd = 0;
     const int64_t nn = cur.n;
     PassDebug pd;
     pd.n = nn;
@@ -354,6 +357,8 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       fill_u8(st, ws.targeted, 0, nn);
     }
     for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
+      a.rnd = opt->refine_random;
+      a.sweep = sw;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         const int hk = tm.begin(kEvScanRefineK);
         decide_group(grp, kRefine);

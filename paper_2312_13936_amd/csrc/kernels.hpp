@@ -110,6 +110,13 @@ struct ScanArgs {
   unsigned long long* mvg;  // [G] refinement moves
   int32_t sync_moves;       // local-moving records decisions (committed per group) instead of
                             // committing at once: bit 0 rows <= kBinMax[4], bit 1 longer rows
+  // randomized refinement (rnd = 1 during refinement sweeps only): draws of
+  // (seed, pass, sweep, vertex, candidate) in graph-local ids (vbase: first
+  // union id of each graph of a fused batch, else nullptr)
+  int32_t rnd;
+  uint32_t seed;
+  int32_t pass, sweep;
+  const int32_t* vbase;
 };
 
 // Hub path (vertices with more than kBinMax[kHubBin - 1] arcs, communities

@@ -65,20 +65,30 @@ __device__ __forceinline__ void flush_acc(const ScanArgs& a, Acc& acc) {
   }
 }
 
-// Gain of one candidate; updates the running best.
+// Gain of one candidate; updates the running best.  With the randomized
+// refinement (a.rnd) only positive gains compete, each by the score
+// gain / (-ln u) of its own draw (the largest wins: c is chosen with
+// probability proportional to its gain); in deterministic mode the score of
+// the exact key is carried in the key slot as its IEEE bit pattern, which
+// orders positive doubles like their values.
 template <bool DET>
 struct Eval {
   double kid, ki, sd, gk, inv_m;
   long long kidi, kii, sdi;
   i128 A, B;
+  int32_t rnd, il, base;
   // i: the vertex (its graph's constants in a fused batch)
   __device__ __forceinline__ Eval(const ScanArgs& a, int32_t i, double kid_, double ki_, double sd_) {
     double im = a.inv_m, gks = a.gk_scale;
     long long W = a.W, p = a.p;
+    base = 0;
     if (a.gid) {
       const GraphParam q = a.gp[a.gid[i]];
       im = q.inv_m; gks = q.gk_scale; W = q.W; p = q.p;
+      if (a.rnd) base = a.vbase[a.gid[i]];
     }
+    rnd = a.rnd;
+    il = i - base;
     kid = kid_; ki = ki_; sd = sd_;
     inv_m = im;
     gk = gks * ki_;
@@ -86,13 +96,24 @@ struct Eval {
     A = (i128)65536 * (i128)W;
     B = (i128)p * (i128)kii;
   }
+  __device__ __forceinline__ double score(const ScanArgs& a, double gain, int32_t c) const {
+    return gain / neg_ln_unit(draw32(a.seed, a.pass, a.sweep, il, c - base));
+  }
   __device__ __forceinline__ void operator()(const ScanArgs& a, int32_t c, double kic, double sc,
                                              double& bg, i128& bk, int32_t& bc) const {
     if (DET) {
-      const i128 k = A * (i128)((long long)kic - kidi) - B * (i128)(kii + (long long)sc - sdi);
+      i128 k = A * (i128)((long long)kic - kidi) - B * (i128)(kii + (long long)sc - sdi);
+      if (rnd) {
+        if (!(k > 0)) return;
+        k = (i128)__double_as_longlong(score(a, key_to_double(k), c));
+      }
       if (better_k(k, c, bk, bc)) { bk = k; bc = c; }
     } else {
-      const double x = (kic - kid) * inv_m - gk * (ki + sc - sd);
+      double x = (kic - kid) * inv_m - gk * (ki + sc - sd);
+      if (rnd) {
+        if (!(x > 0.0)) return;
+        x = score(a, x, c);
+      }
       if (better_f(x, c, bg, bc)) { bg = x; bc = c; }
     }
   }

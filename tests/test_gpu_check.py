@@ -133,3 +133,58 @@ def test_louvain_fused_matches_solo(eng):
     for g, mem, q in zip(gs, mems, qs):
         o = oracle.leiden(g, mode=oracle.DET_SYNC, louvain=1)
         assert np.array_equal(mem, o.membership) and q == o.q, g.name
+
+
+# ------------------------------------------------ randomized refinement ---
+
+RANDOM_GRAPHS = ["ring30xK3", "planted-small", "grid64-w100", "rmat-s12", "rmat-s14", "er-selfloops",
+                 "hub+cliques", "hubs-wide"]
+
+
+@pytest.mark.parametrize("seed", [1, 12345])
+@pytest.mark.parametrize("name", RANDOM_GRAPHS)
+def test_random_refinement_det_bit_exact(eng, name, seed):
+    g = graph(name)
+    print("random refinement det parity:", name, seed, flush=True)
+    mem, q, st = run(eng, g, gvl.GVL_MODE_DET, refine_random=1, seed=seed, debug_trace=1)
+    o = oracle.leiden(g, mode=oracle.DET_SYNC, refine_random=1, seed=seed, trace=True)
+    assert st.passes == len(o.passes)
+    for p, t in enumerate(o.passes):
+        bound, refined, _, _, _ = gvl.gvl_debug_export_pass(eng.ctx, p)
+        movers, rmovers = gvl.gvl_debug_pass_movers(eng.ctx, p)
+        assert rmovers == t.refine_movers, "pass %d refinement movers" % p
+        assert np.array_equal(bound, t.bound), "pass %d bound labels" % p
+        assert np.array_equal(refined, t.refined), "pass %d refined labels" % p
+    assert np.array_equal(mem, o.membership)
+    assert q == o.q
+    c, _ = check(eng, g, mem)
+    assert c == 0
+
+
+def test_random_refinement_fused_matches_oracle(eng):
+    # draws use graph-local vertex and community ids, so a graph's result
+    # does not depend on its place in the union
+    from test_gpu_batch_serve import run_fused
+    gs = [graph(k) for k in ("rmat-s12", "planted-small", "hub+cliques", "grid64-w100", "er-selfloops")]
+    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_DET, refine_random=1, seed=99)
+    assert code == 0 and all(x == 0 for x in sts)
+    for g, mem, q in zip(gs, mems, qs):
+        o = oracle.leiden(g, mode=oracle.DET_SYNC, refine_random=1, seed=99)
+        assert np.array_equal(mem, o.membership) and q == o.q, g.name
+
+
+@pytest.mark.parametrize("name", ["rmat-s14", "planted-C1", "grid200-w100"])
+def test_random_refinement_fast_quality(eng, name):
+    g = graph(name)
+    mem, q, _ = run(eng, g, gvl.GVL_MODE_FAST, refine_random=1, seed=7)
+    assert q == pytest.approx(oracle.modularity(g, mem), abs=1e-9)
+    assert check(eng, g, mem)[0] == 0
+    ref = min(oracle.leiden(g, mode=m, refine_random=1, seed=7).q for m in (oracle.SEQ_ASYNC, oracle.DET_SYNC))
+    assert q >= ref - 1e-3, (q, ref)
+
+
+def test_option_values_checked(eng):
+    g = graph("ring10xK5")
+    for kw in ({"louvain": 2}, {"refine_random": -1}):
+        with pytest.raises(gvl.GvlError):
+            run(eng, g, gvl.GVL_MODE_FAST, **kw)

@@ -372,3 +372,55 @@ def test_louvain_can_leave_disconnected_communities(mode):
     parts = _components_per_community(g, lou.membership)
     assert sum(1 for v in parts.values() if v > 1) == oracle.disconnected(g, lou.membership) > 0
     assert oracle.disconnected(g, lei.membership) == 0
+
+
+# ------------------------------------------------ randomized refinement ---
+
+def test_neg_ln_unit_matches_log():
+    import math
+    xs = [0, 1, 2, 3, 1000, 2 ** 31 - 1, 2 ** 31, 2 ** 32 - 1]
+    xs += np.random.default_rng(3).integers(0, 2 ** 32, 2000).tolist()
+    for x in xs:
+        want = -math.log((x + 0.5) / 2.0 ** 32)
+        assert oracle.neg_ln_unit(int(x)) == pytest.approx(want, rel=1e-14, abs=1e-15), x
+
+
+def test_random_refinement_choice_is_gain_proportional():
+    # the candidate with the largest gain / (-ln u) over independent draws:
+    # P(c) = gain_c / sum of gains
+    gains = {10: 1.0, 11: 2.0, 12: 3.0, 13: 4.0}
+    n = 40000
+    hits = dict.fromkeys(gains, 0)
+    for i in range(n):
+        best = max(gains, key=lambda c: (oracle.random_score(gains[c], 77, 0, 0, i, c), -c))
+        hits[best] += 1
+    tot = sum(gains.values())
+    for c, g in gains.items():
+        p = g / tot
+        assert abs(hits[c] / n - p) < 5 * np.sqrt(p * (1 - p) / n), (c, hits[c] / n, p)
+    # the draw depends on every counter
+    base = oracle.random_score(1.0, 77, 0, 0, 5, 10)
+    for args in ((78, 0, 0, 5, 10), (77, 1, 0, 5, 10), (77, 0, 1, 5, 10), (77, 0, 0, 6, 10), (77, 0, 0, 5, 11)):
+        assert oracle.random_score(1.0, *args) != base
+
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+def test_random_refinement_keeps_leiden_invariants(mode):
+    g = gen.rmat(11, 8, seed=5)
+    qs = set()
+    for seed in (1, 2, 3):
+        r = oracle.leiden(g, mode=mode, trace=True, refine_random=1, seed=seed)
+        assert oracle.disconnected(g, r.membership) == 0
+        cur = g
+        for t in r.passes:
+            pairs = np.unique(np.stack([t.refined, t.bound]), axis=1)
+            assert len(np.unique(pairs[0])) == pairs.shape[1]  # nested in the bounds
+            assert oracle.disconnected(cur, t.refined) == 0
+            if t.y_off is not None:
+                u = np.unique(t.refined)
+                cur = gen.Graph(len(u), len(t.y_idx), t.y_off, t.y_idx, t.y_w.astype(np.float32))
+        assert r.q == oracle.modularity(g, r.membership)
+        again = oracle.leiden(g, mode=mode, refine_random=1, seed=seed)
+        assert np.array_equal(again.membership, r.membership)  # reproducible for a seed
+        qs.add(r.q)
+    assert len(qs) > 1  # and the seed matters
