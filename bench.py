@@ -330,7 +330,8 @@ def compare_louvain(eng, off, idx, wt, r, leiden_ms, mode, kw, args):
     """The paper's Leiden-versus-Louvain comparison (Sec. 5) on the same
     graph: the same pipeline without refinement, its time and modularity,
     and the communities that each leaves disconnected (Alg. 5 on the
-    device).  Untimed by the metric."""
+    device); also the randomized refinement against the greedy one (Sec.
+    4.1).  Untimed by the metric."""
     import torch
     t0 = time.perf_counter()
     dis = eng.disconnected(off, idx, r.membership)
@@ -352,6 +353,19 @@ def compare_louvain(eng, off, idx, wt, r, leiden_ms, mode, kw, args):
 
     lms = 1e3 * sum(lt) / len(lt)
     nl = nontrivial(rl.membership)
+    # greedy versus randomized refinement (the paper's Figs. 1-2 on this graph)
+    ropt = eng.options(mode, refine_random=1, seed=1, **kw)
+    rr = eng.run(off, idx, wt, 1.0, ropt)
+    torch.cuda.synchronize()
+    rt = []
+    for _ in range(max(1, min(args.steps, 3))):
+        t1 = time.perf_counter()
+        rr = eng.run(off, idx, wt, 1.0, ropt)
+        torch.cuda.synchronize()
+        rt.append(time.perf_counter() - t1)
+    rdis = eng.disconnected(off, idx, rr.membership)
+    rms = 1e3 * sum(rt) / len(rt)
+    log("random refinement: %.1f ms Q=%.6f disconnected %d" % (rms, rr.modularity, rdis))
     log("louvain: %.1f ms Q=%.6f disconnected %d of %d communities with >1 member (leiden: %d)" % (
         lms, rl.modularity, ldis, nl, dis))
     return {"leiden_ms": leiden_ms, "louvain_ms": lms, "leiden_time_over_louvain": leiden_ms / lms,
@@ -359,6 +373,8 @@ def compare_louvain(eng, off, idx, wt, r, leiden_ms, mode, kw, args):
             "leiden_communities": int(r.stats.num_communities), "louvain_communities": int(rl.stats.num_communities),
             "leiden_disconnected": dis, "louvain_disconnected": ldis,
             "louvain_disconnected_of_nonsingleton": ldis / max(nl, 1),
+            "random_refinement_ms": rms, "random_refinement_modularity": rr.modularity,
+            "random_refinement_disconnected": rdis,
             "check_ms": check_ms}
 
 
