@@ -136,8 +136,8 @@ gvl_status gvl_disconnected_communities(gvl_ctx_t ctx, int64_t n, int64_t m, con
   s = readback(ctx, ws.sc);
   if (s != GVL_OK) return s;
   if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
-  disconnected_communities(st, d_off, d_idx, d_membership, n, ws.C, ws.CB, d_flags ? d_flags : ws.target,
-                           &ws.sc->acc_u[0]);
+  disconnected_communities(st, d_off, d_idx, d_membership, n, ws.C, ws.start, ws.CB,
+                           d_flags ? d_flags : ws.target, &ws.sc->acc_u[0]);
   s = readback(ctx, ws.sc);
   if (s != GVL_OK) return s;
   *count = (int64_t)ctx->host->acc_u[0];

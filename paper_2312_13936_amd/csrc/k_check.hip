@@ -105,23 +105,26 @@ __global__ __launch_bounds__(kBlock) void k_cc_union(const int32_t* off, const i
   }
 }
 
-// comp[i] = root of i; rep[C[i]] = the root of some member of C[i].
-__global__ void k_cc_flatten(int32_t* comp, const int32_t* C, int64_t n, int32_t* rep) {
+// root[i] = root of i; rep[C[i]] = the root of some member of C[i].  The
+// roots go to their own array: finds of other threads keep halving paths in
+// comp during this kernel and may store an intermediate ancestor over a
+// root written there.
+__global__ void k_cc_flatten(int32_t* comp, const int32_t* C, int64_t n, int32_t* root, int32_t* rep) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t r = cc_find(comp, (int32_t)i);
-    comp[i] = r;
+    root[i] = r;
     rep[C[i]] = r;
   }
 }
 
 // dis[c] = 1 for communities with a member outside rep[c]'s component;
 // cnt[0] counts them.
-__global__ void k_cc_mark(const int32_t* comp, const int32_t* C, const int32_t* rep, int64_t n, int32_t* dis,
+__global__ void k_cc_mark(const int32_t* root, const int32_t* C, const int32_t* rep, int64_t n, int32_t* dis,
                           unsigned long long* cnt) {
   unsigned long long mine = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int32_t c = C[i];
-    if (comp[i] == rep[c] || dis[c]) continue;  // (a stale 0 is settled by the exchange)
+    if (root[i] == rep[c] || dis[c]) continue;  // (a stale 0 is settled by the exchange)
     if (atomicExch(&dis[c], 1) == 0) ++mine;
   }
   if (mine) atomicAdd(cnt, mine);
@@ -133,12 +136,12 @@ static inline int grid_of(int64_t n, int cap) {
 }
 
 void disconnected_communities(hipStream_t st, const int32_t* off, const int32_t* idx, const int32_t* C, int64_t n,
-                              int32_t* comp, int32_t* rep, int32_t* dis, unsigned long long* cnt) {
+                              int32_t* comp, int32_t* root, int32_t* rep, int32_t* dis, unsigned long long* cnt) {
   if (n <= 0) return;
   hipLaunchKernelGGL(k_cc_init, dim3(grid_of(n, 16384)), dim3(kBlock), 0, st, comp, rep, dis, n);
   hipLaunchKernelGGL(k_cc_union, dim3(grid_of(n, 8192)), dim3(kBlock), 0, st, off, idx, C, n, comp);
-  hipLaunchKernelGGL(k_cc_flatten, dim3(grid_of(n, 16384)), dim3(kBlock), 0, st, comp, C, n, rep);
-  hipLaunchKernelGGL(k_cc_mark, dim3(grid_of(n, 16384)), dim3(kBlock), 0, st, comp, C, rep, n, dis, cnt);
+  hipLaunchKernelGGL(k_cc_flatten, dim3(grid_of(n, 16384)), dim3(kBlock), 0, st, comp, C, n, root, rep);
+  hipLaunchKernelGGL(k_cc_mark, dim3(grid_of(n, 16384)), dim3(kBlock), 0, st, root, C, rep, n, dis, cnt);
 }
 
 }  // namespace gvl

@@ -363,10 +363,10 @@ void modularity_partial(hipStream_t st, const GraphDesc& g, const int32_t* C, do
                         double* acc_d, const int32_t* gid = nullptr, double* s1g = nullptr);
 void check_offsets(hipStream_t st, const int32_t* off, int64_t n, int64_t m, int32_t* flags);
 // Alg. 5: components of the intra-community arcs (union-find); dis[c] = 1
-// and ++cnt[0] for every community c with more than one (comp, rep, dis:
-// int32[n] scratch / output).
+// and ++cnt[0] for every community c with more than one (comp, root, rep,
+// dis: int32[n] scratch / output).
 void disconnected_communities(hipStream_t st, const int32_t* off, const int32_t* idx, const int32_t* C, int64_t n,
-                              int32_t* comp, int32_t* rep, int32_t* dis, unsigned long long* cnt);
+                              int32_t* comp, int32_t* root, int32_t* rep, int32_t* dis, unsigned long long* cnt);
 void modularity_squares(hipStream_t st, const double* tot, int64_t n, bool integral, double* acc_d,
                         unsigned long long* acc_u);
 
