@@ -164,39 +164,31 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
     const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
     const int32_t d = a.C[i];
-    if (hub_partitioned(deg)) {  // uniform: sort the chunk's candidates by partition
-      constexpr int U = kHubChunk / kBlock;
+    if (hub_partitioned(deg)) {  // uniform: sum the chunk's candidates, sort them by partition
       const int P = h.slice_off[p + 1] - h.slice_off[p];
       int32_t* s_cnt = snew;  // [P + 1] counts, then offsets
       for (int k = threadIdx.x; k <= P; k += kBlock) s_cnt[k] = 0;
+      // 1. candidates into the LDS table (equal communities summed)
+      double kid = scan_row<4, kBlock, PH>(g, a, i, beg, e1, e0 + threadIdx.x, d, bi, [&](int32_t c, double w) {
+        lds_insert(skeys, svals, kHubGatherLg, c, w);
+      });
       __syncthreads();
-      int32_t c[U], rk[U];
-      double w[U];
-      double kid = 0.0;
+      // 2. the table's entries into registers (the table is left empty),
+      // with their rank inside their partition
+      constexpr int R = TS / kBlock;
+      int32_t ck[R], rk[R];
+      double cw[R];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t e = e0 + u * kBlock + threadIdx.x;
-        const int32_t j = (e < e1) ? g.idx[beg + e] : i;
-        w[u] = (e < e1) ? g.weight(beg + e) : 0.0;
-        c[u] = j;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int32_t j = c[u];
-        const bool ok = j != i;
-        c[u] = ok ? a.C[j] : kEmpty;
-        if (PH == kRefine) {
-          const int32_t b = ok ? a.CB[j] : bi;
-          if (b != bi) c[u] = kEmpty;
+      for (int r = 0; r < R; ++r) {
+        const int sl = r * kBlock + threadIdx.x;
+        ck[r] = skeys[sl];
+        cw[r] = svals[sl];
+        rk[r] = 0;
+        if (ck[r] != kEmpty) {
+          skeys[sl] = kEmpty;
+          svals[sl] = 0.0;
+          rk[r] = atomicAdd(&s_cnt[wide_part(ck[r]) & (uint32_t)(P - 1)], 1);
         }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (c[u] == d) {
-          kid += w[u];
-          c[u] = kEmpty;
-        }
-        rk[u] = (c[u] != kEmpty) ? atomicAdd(&s_cnt[wide_part(c[u]) & (uint32_t)(P - 1)], 1) : 0;
       }
       __syncthreads();
       {  // exclusive scan of the P <= kBlock counts; s_cnt[P] = total
@@ -219,14 +211,16 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
         if (threadIdx.x == 0) s_cnt[P] = total;
         __syncthreads();
       }
+      // 3. staged in partition order at the front of the (empty) table
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if (c[u] == kEmpty) continue;
-        const int pos = s_cnt[wide_part(c[u]) & (uint32_t)(P - 1)] + rk[u];
-        skeys[pos] = c[u];
-        svals[pos] = w[u];
+      for (int r = 0; r < R; ++r) {
+        if (ck[r] == kEmpty) continue;
+        const int pos = s_cnt[wide_part(ck[r]) & (uint32_t)(P - 1)] + rk[r];
+        skeys[pos] = ck[r];
+        svals[pos] = cw[r];
       }
       __syncthreads();
+      // 4. out to the chunk's own arc positions; the table is emptied again
       const int n = s_cnt[P];
       WT* wb = (WT*)h.wbuf;
       for (int k = threadIdx.x; k < n; k += kBlock) {

@@ -132,9 +132,10 @@ constexpr int kHubSlice = 8192;
 constexpr int kTblUnit = 1024;
 // Vertex hubs of up to kPartMaxDeg arcs are scanned partitioned instead,
 // with P = next_pow2(ceil(deg / kPartKeys)) partitions of the neighbour
-// communities (wide_part mod P).  The chunk pass sorts each chunk's
-// candidates (community, weight) by partition in LDS and stores them at the
-// chunk's own arc positions in lbuf / wbuf, with the chunk's partition
+// communities (wide_part mod P).  The chunk pass sums each chunk's
+// candidates (community, weight) in an LDS table, sorts the distinct ones by
+// partition and stores them at the chunk's own arc positions in lbuf / wbuf,
+// with the chunk's partition
 // offsets in poff; then one workgroup of kPartThreads threads per partition
 // reads its runs of every chunk and accumulates them in an LDS table of
 // kPartSlots slots (two workgroups per CU).  No global table and no global
