@@ -350,8 +350,6 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       } else {
         launch_commit_refine(st, cur, a, l0, n0);
         launch_commit_refine(st, cur, a, l1, n1);
-        launch_refine_cleanup(st, a, l0, n0);
-        launch_refine_cleanup(st, a, l1, n1);
       }
     };
 
@@ -398,7 +396,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       iota_i32(st, ws.C, nn);
       copy_f64(st, ws.Sig, ws.K, nn);
       set_size_one(st, ws.size, nn);
-      fill_u8(st, ws.targeted, 0, nn);
+      fill_i32(st, ws.targeted, 0, nn);
     }
     fill_u64(st, B.mvg, 0ull, K);
     s = readback(ctx, ws.sc);
@@ -408,6 +406,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       a.rnd = opt->refine_random;
       a.sweep = sw;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
+        a.stamp = sw * bins.S + grp + 1;
         decide_group(grp, kRefine);
         commit_group(grp, kRefine);
       }

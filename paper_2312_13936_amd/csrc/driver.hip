@@ -300,8 +300,6 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       } else {
         launch_commit_refine(st, cur, a, l0, n0);
         launch_commit_refine(st, cur, a, l1, n1);
-        launch_refine_cleanup(st, a, l0, n0);
-        launch_refine_cleanup(st, a, l1, n1);
       }
     };
 
@@ -354,12 +352,13 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       iota_i32(st, ws.C, nn);
       copy_f64(st, ws.Sig, ws.K, nn);
       set_size_one(st, ws.size, nn);
-      fill_u8(st, ws.targeted, 0, nn);
+      fill_i32(st, ws.targeted, 0, nn);
     }
     for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
       a.rnd = opt->refine_random;
       a.sweep = sw;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
+        a.stamp = sw * bins.S + grp + 1;
         const int hk = tm.begin(kEvScanRefineK);
         decide_group(grp, kRefine);
         tm.end(hk);

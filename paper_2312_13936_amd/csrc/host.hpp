@@ -42,7 +42,8 @@ static inline int64_t next_pow2(int64_t x) {
 struct Workspace {
   double *K, *Sig;
   int32_t *size, *C, *CB, *start, *target, *newid, *brank, *lab, *rank, *cnt, *cv, *list, *scan_tmp;
-  uint8_t *flag, *targeted;
+  uint8_t* flag;
+  int32_t* targeted;
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
   TblSlot* tbl;
@@ -102,7 +103,7 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.list = (int32_t*)take(4 * N);
   w.scan_tmp = (int32_t*)take(4 * ((size_t)scan_tiles((int64_t)N + 1) + 2));
   w.flag = (uint8_t*)take(N);
-  w.targeted = (uint8_t*)take(N);
+  w.targeted = (int32_t*)take(4 * N);
   for (int b = 0; b < 2; ++b) {
     w.off[b] = (int32_t*)take(4 * (N + 1));
     w.deg[b] = (int32_t*)take(4 * N);

@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
             }
           } else {
             a.target[i] = bc;
-            a.targeted[bc] = 1;
+            a.targeted[bc] = a.stamp;
           }
         }
       }
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
           add_gain<DET>(a, acc, i, bg, bk);
         } else {
           a.target[i] = bc;
-          a.targeted[bc] = 1;
+          a.targeted[bc] = a.stamp;
         }
       }
     }

@@ -22,8 +22,4 @@ void launch_commit_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a,
   else commit_list<float, kRefine>(st, g, a, list, count);
 }
 
-void launch_refine_cleanup(hipStream_t st, const ScanArgs& a, const int32_t* list, int32_t count) {
-  cleanup_list(st, a, list, count);
-}
-
 }  // namespace gvl

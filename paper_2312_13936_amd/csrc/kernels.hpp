@@ -83,7 +83,8 @@ struct ScanArgs {
   const double* K;          // weighted degree of each vertex (K')
   uint8_t* flag;            // local-moving: 1 = unprocessed
   int32_t* target;          // synchronous decisions: chosen community or -1
-  uint8_t* targeted;        // refinement: community chosen as a target this sweep
+  int32_t* targeted;        // refinement: stamp of the last group that chose the community as a target
+  int32_t stamp;            // refinement: stamp of the current group (unique within a pass, > 0)
   double inv_m;             // 1/m = 2/W
   double gk_scale;          // 2 gamma / W^2
   long long W;              // exact total weight (deterministic mode)
@@ -223,9 +224,6 @@ void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a,
 // Apply the recorded merges of list[0..count).
 void launch_commit_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
                           int32_t count);
-// Clear target / targeted of list[0..count): only after every commit of the
-// group has read the targeted flags.
-void launch_refine_cleanup(hipStream_t st, const ScanArgs& a, const int32_t* list, int32_t count);
 
 // ---- aggregation (k_aggregate.hip)
 void launch_agg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const int32_t* list,

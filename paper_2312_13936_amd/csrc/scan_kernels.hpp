@@ -238,14 +238,24 @@ __device__ __forceinline__ void eval_table(int32_t* keys, double* vals, int ts, 
 }
 
 // ------------------------------------------------ group of G lanes per vertex ---
+// Bins 0-4 in one launch: blocks [blk[b], blk[b+1]) serve bin b, each with
+// groups of kBinLanes[b] lanes per vertex.
+struct GroupLaunch {
+  int32_t count[5];
+  int32_t start[5];
+  int32_t blk[6];
+};
+constexpr int kGroupSlots = 1024;  // LDS slots of one workgroup: the largest GPB * 2^LG of bins 0-4
+
+// Body of one workgroup of bin (G, LG): workgroup `bid` of `nb` strides over
+// the bin's vertices; skeys / svals: the workgroup's kGroupSlots LDS slots.
 template <int G, int LG, class WT, int PH, bool DET>
-__global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanArgs a,
-                                                         const int32_t* __restrict__ list,
-                                                         int32_t count) {
+__device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const ScanArgs& a,
+                                                  const int32_t* __restrict__ list, int32_t count, int32_t bid,
+                                                  int32_t nb, int32_t* skeys, double* svals) {
   constexpr int TS = 1 << LG;
   constexpr int GPB = kBlock / G;
-  __shared__ int32_t skeys[GPB * TS];
-  __shared__ double svals[GPB * TS];
+  static_assert(GPB * TS <= kGroupSlots, "group tables fit the workgroup's LDS");
   const int gl = threadIdx.x % G;
   const int gb = threadIdx.x / G;
   int32_t* keys = skeys + gb * TS;
@@ -253,7 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
   for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
   wave_sync();
   Acc acc;
-  for (int64_t v = (int64_t)blockIdx.x * GPB + gb; v < count; v += (int64_t)gridDim.x * GPB) {
+  for (int64_t v = (int64_t)bid * GPB + gb; v < count; v += (int64_t)nb * GPB) {
     const int32_t i = list[v];
     // One lane reads the (possibly concurrently updated) eligibility state.
     int ok = (gl == 0) ? (int)Decide<PH, DET>::eligible(a, i) : 0;
@@ -303,10 +313,28 @@ __global__ __launch_bounds__(kBlock) void k_decide_group(GraphView<WT> g, ScanAr
         add_gain<DET>(a, acc, i, bg, bk);
       }
     } else {
-      if (gl == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
+      if (gl == 0) { a.target[i] = bc; a.targeted[bc] = a.stamp; }
     }
   }
   flush_acc<PH, DET>(a, acc);
+}
+
+template <class WT, int PH, bool DET>
+__global__ __launch_bounds__(kBlock) void k_decide_groups(GraphView<WT> g, ScanArgs a,
+                                                          const int32_t* __restrict__ list, GroupLaunch gl) {
+  __shared__ int32_t skeys[kGroupSlots];
+  __shared__ double svals[kGroupSlots];
+  int b = 0;
+  while (b < 4 && (int32_t)blockIdx.x >= gl.blk[b + 1]) ++b;  // uniform over the workgroup
+  const int32_t bid = (int32_t)blockIdx.x - gl.blk[b], nb = gl.blk[b + 1] - gl.blk[b];
+  const int32_t* l = list + gl.start[b];
+  switch (b) {
+    case 0: decide_group_body<4, 3, WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
+    case 1: decide_group_body<8, 4, WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
+    case 2: decide_group_body<16, 5, WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
+    case 3: decide_group_body<32, 6, WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
+    default: decide_group_body<64, 8, WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
+  }
 }
 
 // ------------------------------------------------ one workgroup per vertex ---
@@ -381,7 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
         add_gain<DET>(a, acc, i, bg, bk);
       }
     } else {
-      if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = 1; }
+      if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = a.stamp; }
     }
   }
   flush_acc<PH, DET>(a, acc);
@@ -549,7 +577,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
           add_gain<DET>(a, acc, i, bg, bk);
         } else {
           a.target[i] = bc;
-          a.targeted[bc] = 1;
+          a.targeted[bc] = a.stamp;
         }
       }
       s_take = take;
@@ -600,7 +628,10 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
     if (mv) {
       if (PH == kMove && MARK) a.target[i] = -1;
       const int32_t d = a.C[i];
-      if (PH == kRefine && a.targeted[d]) mv = false;
+      if (PH == kRefine) {
+        a.target[i] = -1;
+        if (a.targeted[d] == a.stamp) mv = false;  // own community chosen by this group
+      }
       if (mv) {
         const double ki = a.K[i];
         keyed_put(kt, d, -ki, -1);
@@ -673,20 +704,6 @@ __global__ __launch_bounds__(kBlock) void k_mark_rows(GraphView<WT> g, ScanArgs 
   }
 }
 
-// Refinement: forget the group's targets once every commit has read them.
-template <int PH>
-__global__ __launch_bounds__(kBlock) void k_refine_cleanup(ScanArgs a, const int32_t* __restrict__ list,
-                                                           int32_t count) {
-  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < count; k += (int64_t)gridDim.x * kBlock) {
-    const int32_t i = list[k];
-    const int32_t t = a.target[i];
-    if (t >= 0) {
-      a.targeted[t] = 0;
-      a.target[i] = -1;
-    }
-  }
-}
-
 // ------------------------------------------------------------- launchers ---
 template <class WT>
 inline GraphView<WT> view(const GraphDesc& g) {
@@ -706,19 +723,20 @@ template <class WT, int PH, bool DET>
 void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list,
                  const int32_t* count, const int32_t* start, int grid_cap, int hub_grid, int64_t* launches) {
   const GraphView<WT> g = view<WT>(gd);
-#define GVL_GROUP_BIN(B, G, LG)                                                                 \
-  if (count[B] > 0) {                                                                           \
-    const int grid = grid_for(count[B], kBlock / (G), grid_cap);                                \
-    hipLaunchKernelGGL((k_decide_group<G, LG, WT, PH, DET>), dim3(grid), dim3(kBlock), 0, st, g, \
-                       a, list + start[B], count[B]);                                           \
-    ++*launches;                                                                                \
+  {  // bins 0-4: one launch
+    GroupLaunch gl;
+    constexpr int kLanes[5] = {4, 8, 16, 32, 64};
+    gl.blk[0] = 0;
+    for (int b = 0; b < 5; ++b) {
+      gl.count[b] = count[b];
+      gl.start[b] = start[b];
+      gl.blk[b + 1] = gl.blk[b] + (count[b] > 0 ? grid_for(count[b], kBlock / kLanes[b], grid_cap) : 0);
+    }
+    if (gl.blk[5] > 0) {
+      hipLaunchKernelGGL((k_decide_groups<WT, PH, DET>), dim3(gl.blk[5]), dim3(kBlock), 0, st, g, a, list, gl);
+      ++*launches;
+    }
   }
-  GVL_GROUP_BIN(0, 4, 3)
-  GVL_GROUP_BIN(1, 8, 4)
-  GVL_GROUP_BIN(2, 16, 5)
-  GVL_GROUP_BIN(3, 32, 6)
-  GVL_GROUP_BIN(4, 64, 8)
-#undef GVL_GROUP_BIN
   if (count[5] > 0) {
     const int grid = grid_for(count[5], 1, grid_cap);
     hipLaunchKernelGGL((k_decide_block<11, WT, PH, DET>), dim3(grid), dim3(kBlock), 0, st, g, a,
@@ -761,12 +779,6 @@ void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   }
   const int grid = grid_for(count, kBlock, 2048);
   hipLaunchKernelGGL((k_commit<WT, PH>), dim3(grid), dim3(kBlock), 0, st, g, a, list, count);
-}
-
-inline void cleanup_list(hipStream_t st, const ScanArgs& a, const int32_t* list, int32_t count) {
-  if (count <= 0) return;
-  const int grid = grid_for(count, kBlock, 2048);
-  hipLaunchKernelGGL((k_refine_cleanup<kRefine>), dim3(grid), dim3(kBlock), 0, st, a, list, count);
 }
 
 }  // namespace gvl
