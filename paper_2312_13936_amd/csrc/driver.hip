@@ -286,21 +286,25 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       }
     };
     auto commit_group = [&](int grp, int phase) {
-      const int32_t* l0 = ws.list + bins.gstart[grp];
-      const int32_t n0 = bins.gend[grp] - bins.gstart[grp];
-      const int32_t* l1 = ws.list + bins.start[grp][kHubBin];
-      const int32_t n1 = bins.count[grp][kHubBin];
+      CommitLaunch cl;
+      memset(&cl, 0, sizeof(cl));
+      const int32_t n0 = bins.gend[grp] - bins.gstart[grp];  // bins 0 .. kHubBin-1 of the group
+      const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];  // rows of at most kBinMax[4] arcs
+      cl.l0 = ws.list + bins.gstart[grp];
+      cl.l2 = ws.list + bins.start[grp][kHubBin];
+      cl.n2 = bins.count[grp][kHubBin];
       if (phase == kMove) {
-        // rows of at most kBinMax[4] arcs, longer rows, hubs
-        const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];
-        launch_commit_move(st, cur, a, l0, n0s, 0);
-        launch_commit_move(st, cur, a, l0 + n0s, n0 - n0s, 1);
-        launch_commit_move(st, cur, a, l1, n1, 2);
-        for (const HubBatch& hb : plan.groups[grp]) hub_mark(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1);
+        cl.n0 = n0s;
+        cl.l1 = cl.l0 + n0s;
+        cl.n1 = n0 - n0s;
+        if (!plan.groups[grp].empty()) {
+          cl.c0 = plan.groups[grp].front().c0;
+          cl.c1 = plan.groups[grp].back().c1;
+        }
       } else {
-        launch_commit_refine(st, cur, a, l0, n0);
-        launch_commit_refine(st, cur, a, l1, n1);
+        cl.n0 = n0;
       }
+      launch_commit(st, cur, a, hargs, cl, phase);
     };
 
     // ---- 2. local-moving (Alg. 2)

@@ -105,6 +105,7 @@ __global__ void k_hub_prep(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
     const bool act = Decide<PH, DET>::eligible(a, i);
     h.active[p] = act ? 1 : 0;
     h.kid[p] = 0.0;
+    a.target[i] = -1;  // (a synchronous local-moving commit applies a hub's target without forgetting it)
     if (PH == kMove && act) a.flag[i] = 0;  // processed (Alg. 2 prune)
   }
 }
@@ -602,40 +603,6 @@ void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const Hub
     else { if (det) GVL_HUB(float, kRefine, true); else GVL_HUB(float, kRefine, false); }
   }
 #undef GVL_HUB
-}
-
-// ------------------------------------------------- marks after hub moves ---
-template <class WT>
-__global__ __launch_bounds__(kBlock) void k_hub_mark(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t t0, int32_t t1) {
-  for (int64_t t = t0 + (int64_t)blockIdx.x; t < t1; t += gridDim.x) {
-    const int2 task = h.chunk_tasks[t];
-    const int32_t i = h.items[task.x];
-    if (a.target[i] < 0) continue;  // uniform: no move
-    const int32_t beg = g.begin(i), deg = g.degree(i);
-    const int32_t e0 = task.y * kHubChunk;
-    const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
-    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      const int32_t j = g.idx[beg + e];
-      if (j != i) a.flag[j] = 1;
-    }
-  }
-}
-__global__ void k_hub_forget(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
-  for (int64_t p = h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += (int64_t)gridDim.x * blockDim.x)
-    a.target[h.items[p]] = -1;
-}
-void hub_mark(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
-              int32_t c0, int32_t c1) {
-  if (h1 <= h0) return;
-  if (c1 > c0) {
-    if (gd.w_double)
-      hipLaunchKernelGGL(k_hub_mark<double>, dim3(grid_items(c1 - c0, 1, 4096)), dim3(kBlock), 0, st, view<double>(gd),
-                         a, h, c0, c1);
-    else
-      hipLaunchKernelGGL(k_hub_mark<float>, dim3(grid_items(c1 - c0, 1, 4096)), dim3(kBlock), 0, st, view<float>(gd),
-                         a, h, c0, c1);
-  }
-  hipLaunchKernelGGL(k_hub_forget, dim3(grid_items(h1 - h0, kBlock, 64)), dim3(kBlock), 0, st, a, h, h0, h1);
 }
 
 // ------------------------------------------------------ row sums of hubs ---

@@ -16,10 +16,15 @@ void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, c
   }
 }
 
-void launch_commit_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        int32_t count, int kind) {
-  if (g.w_double) commit_list<double, kMove>(st, g, a, list, count, kind);
-  else commit_list<float, kMove>(st, g, a, list, count, kind);
+void launch_commit(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, const CommitLaunch& cl,
+                   int phase) {
+  if (phase == kMove) {
+    if (g.w_double) commit_group_launch<double, kMove>(st, g, a, h, cl);
+    else commit_group_launch<float, kMove>(st, g, a, h, cl);
+  } else {
+    if (g.w_double) commit_group_launch<double, kRefine>(st, g, a, h, cl);
+    else commit_group_launch<float, kRefine>(st, g, a, h, cl);
+  }
 }
 
 }  // namespace gvl

@@ -16,10 +16,4 @@ void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a,
   }
 }
 
-void launch_commit_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        int32_t count) {
-  if (g.w_double) commit_list<double, kRefine>(st, g, a, list, count);
-  else commit_list<float, kRefine>(st, g, a, list, count);
-}
-
 }  // namespace gvl

@@ -213,17 +213,27 @@ struct AggArgs {
 void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
                         const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
                         int64_t* launches);
-// Apply the recorded moves of the vertices list[0..count) and mark the
-// neighbours of movers.  kind: 0 short rows, 1 long rows (one workgroup per
-// vertex marks), 2 hubs (moves applied only; hub_mark marks and forgets).
-void launch_commit_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        int32_t count, int kind);
 void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
                           const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
                           int64_t* launches);
-// Apply the recorded merges of list[0..count).
-void launch_commit_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                          int32_t count);
+// Applies the recorded synchronous decisions of one group in one launch.
+// Local-moving: rows of up to kBinMax[4] arcs in tiles (community totals
+// through the workgroup-combined table; the movers' rows marked end to end),
+// longer rows one workgroup each, hub moves applied in tiles (their targets
+// are forgotten by the next k_hub_prep) and hub rows marked chunk by chunk.
+// Refinement: both lists in tiles; vertex i moves only if its own community
+// was not chosen as a target by this group (stamp).
+struct CommitLaunch {
+  const int32_t* l0;   // short rows (local-moving) or every non-hub row (refinement)
+  const int32_t* l1;   // long rows (local-moving)
+  const int32_t* l2;   // hubs
+  int32_t n0, n1, n2;
+  int32_t c0, c1;      // chunk tasks of the hubs (local-moving marks)
+  int32_t b[5];        // block ranges of the roles: [b[r], b[r+1])
+};
+
+void launch_commit(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, const CommitLaunch& cl,
+                   int phase);
 
 // ---- aggregation (k_aggregate.hip)
 void launch_agg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const int32_t* list,
@@ -241,11 +251,6 @@ void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_
 // weight, evaluation (+ commit in fast local-moving).
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
                 int32_t c0, int32_t c1, int32_t s0, int32_t s1, bool tables, int phase, bool det, int64_t* launches);
-// Local-moving, after launch_commit_move(kind 2) of the hubs items[h0, h1):
-// marks the neighbours of the movers chunk by chunk (chunk tasks [c0, c1)),
-// then forgets the hubs' targets.
-void hub_mark(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
-              int32_t c0, int32_t c1);
 // K[i] += sums of the chunks of hub rows (K[i] of hubs zeroed by the caller).
 void hub_weights(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_t c0, int32_t c1, double* K,
                  double* accW, int32_t* flags, int validate);

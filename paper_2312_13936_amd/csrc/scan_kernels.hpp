@@ -610,16 +610,21 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
 // marked unprocessed; the workgroup lays its movers' rows end to end and
 // every lane marks one arc per step.  Without MARK (long rows, hubs) the
 // targets stay for the marking kernels.
-template <class WT, int PH, bool MARK = true>
-__global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
-                                                   const int32_t* __restrict__ list, int32_t count) {
-  __shared__ unsigned long long red_u[16];
-  __shared__ KeyedLds<kBlock> kt;
-  __shared__ int32_t s_off[kBlock + 1], s_beg[kBlock], s_vi[kBlock];
-  __shared__ int32_t s_w[kBlock / kWave];
-  keyed_clear(kt);
+// Shared memory of the commit roles.
+struct CommitLds {
+  KeyedLds<kBlock> kt;
+  int32_t off[kBlock + 1], beg[kBlock], vi[kBlock];
+  int32_t w[kBlock / kWave];
+  int mv;
+};
+
+// Tiles of kBlock entries of list[0..count): workgroup `bid` of `nb`.
+template <class WT, int PH, bool MARK>
+__device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& g, const ScanArgs& a,
+                                                           const int32_t* __restrict__ list, int32_t count,
+                                                           int32_t bid, int32_t nb, CommitLds& L) {
   unsigned long long nm = 0;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
+  for (int64_t base = (int64_t)bid * kBlock; base < count; base += (int64_t)nb * kBlock) {
     const int64_t k = base + threadIdx.x;
     const int32_t i = (k < count) ? list[k] : 0;
     int32_t t = -1;
@@ -634,15 +639,15 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
       }
       if (mv) {
         const double ki = a.K[i];
-        keyed_put(kt, d, -ki, -1);
-        keyed_put(kt, t, ki, 1);
+        keyed_put(L.kt, d, -ki, -1);
+        keyed_put(L.kt, t, ki, 1);
         a.C[i] = t;
         ++nm;
         if (PH == kRefine && a.gid) atomicAdd(&a.mvg[a.gid[i]], 1ull);
       }
     }
-    keyed_flush(kt, a.Sig, a.size);
-    if (PH == kMove && MARK) {  // uniform
+    keyed_flush(L.kt, a.Sig, a.size);
+    if (PH == kMove && MARK) {  // uniform: the tile's movers' rows end to end
       const int32_t deg = mv ? g.degree(i) : 0;
       int incl = deg;
 #pragma unroll
@@ -651,49 +656,59 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a,
         if (lane_id() >= o) incl += x;
       }
       const int w = threadIdx.x / kWave;
-      if (lane_id() == kWave - 1) s_w[w] = incl;
+      if (lane_id() == kWave - 1) L.w[w] = incl;
       __syncthreads();
       int before = 0, total = 0;
-      for (int k = 0; k < kBlock / kWave; ++k) {
-        if (k < w) before += s_w[k];
-        total += s_w[k];
+      for (int q = 0; q < kBlock / kWave; ++q) {
+        if (q < w) before += L.w[q];
+        total += L.w[q];
       }
-      s_off[threadIdx.x] = before + incl - deg;
-      if (threadIdx.x == 0) s_off[kBlock] = total;
-      s_beg[threadIdx.x] = mv ? g.begin(i) : 0;
-      s_vi[threadIdx.x] = i;
+      L.off[threadIdx.x] = before + incl - deg;
+      if (threadIdx.x == 0) L.off[kBlock] = total;
+      L.beg[threadIdx.x] = mv ? g.begin(i) : 0;
+      L.vi[threadIdx.x] = i;
       __syncthreads();
       for (int32_t q = threadIdx.x; q < total; q += kBlock) {
-        int lo = 0, hi = kBlock;  // s_off[lo] <= q < s_off[hi]
+        int lo = 0, hi = kBlock;  // off[lo] <= q < off[hi]
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
-          if (s_off[mid] <= q) lo = mid; else hi = mid;
+          if (L.off[mid] <= q) lo = mid; else hi = mid;
         }
-        const int32_t j = g.idx[(int64_t)s_beg[lo] + (q - s_off[lo])];
-        if (j != s_vi[lo]) a.flag[j] = 1;
+        const int32_t j = g.idx[(int64_t)L.beg[lo] + (q - L.off[lo])];
+        if (j != L.vi[lo]) a.flag[j] = 1;
       }
-      __syncthreads();  // s_* are rewritten by the next entries
+      __syncthreads();  // L.* are rewritten by the next entries
     }
   }
-  nm = block_sum<unsigned long long>(nm, red_u);
-  if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
+  return nm;
 }
 
-// Local-moving, long rows, after k_commit<WT, kMove, false>: one workgroup
-// per vertex forgets its target and, if it moved, marks its neighbours.
+// Long rows: one workgroup per entry applies the move, forgets the target
+// and marks the mover's neighbours with all its threads.
 template <class WT>
-__global__ __launch_bounds__(kBlock) void k_mark_rows(GraphView<WT> g, ScanArgs a,
-                                                      const int32_t* __restrict__ list, int32_t count) {
-  __shared__ int s_mv;
-  for (int64_t k = blockIdx.x; k < count; k += gridDim.x) {
+__device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g, const ScanArgs& a,
+                                                          const int32_t* __restrict__ list, int32_t count,
+                                                          int32_t bid, int32_t nb, CommitLds& L) {
+  unsigned long long nm = 0;
+  for (int64_t k = bid; k < count; k += nb) {
     const int32_t i = list[k];
     if (threadIdx.x == 0) {
       const int32_t t = a.target[i];
-      s_mv = t >= 0;
-      if (t >= 0) a.target[i] = -1;
+      L.mv = t >= 0;
+      if (t >= 0) {
+        a.target[i] = -1;
+        const int32_t d = a.C[i];
+        const double ki = a.K[i];
+        atomicAdd(&a.Sig[d], -ki);
+        atomicAdd(&a.Sig[t], ki);
+        atomicSub(&a.size[d], 1);
+        atomicAdd(&a.size[t], 1);
+        a.C[i] = t;
+        ++nm;
+      }
     }
     __syncthreads();
-    if (s_mv) {
+    if (L.mv) {
       const int32_t beg = g.begin(i), deg = g.degree(i);
       for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
         const int32_t j = g.idx[beg + e];
@@ -702,6 +717,45 @@ __global__ __launch_bounds__(kBlock) void k_mark_rows(GraphView<WT> g, ScanArgs 
     }
     __syncthreads();
   }
+  return nm;
+}
+
+// Applies the recorded synchronous decisions of one group (CommitLaunch).
+template <class WT, int PH>
+__global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, HubArgs h, CommitLaunch cl) {
+  __shared__ CommitLds L;
+  __shared__ unsigned long long red_u[16];
+  keyed_clear(L.kt);
+  const int32_t x = (int32_t)blockIdx.x;
+  int r = 0;
+  while (r < 3 && x >= cl.b[r + 1]) ++r;  // uniform over the workgroup
+  const int32_t bid = x - cl.b[r], nb = cl.b[r + 1] - cl.b[r];
+  unsigned long long nm = 0;
+  if (PH == kRefine) {
+    if (r == 0) nm = commit_tiles<WT, kRefine, false>(g, a, cl.l0, cl.n0, bid, nb, L);
+    else nm = commit_tiles<WT, kRefine, false>(g, a, cl.l2, cl.n2, bid, nb, L);
+  } else if (r == 0) {
+    nm = commit_tiles<WT, kMove, true>(g, a, cl.l0, cl.n0, bid, nb, L);
+  } else if (r == 1) {
+    nm = commit_long<WT>(g, a, cl.l1, cl.n1, bid, nb, L);
+  } else if (r == 2) {
+    nm = commit_tiles<WT, kMove, false>(g, a, cl.l2, cl.n2, bid, nb, L);
+  } else {
+    for (int64_t t = cl.c0 + (int64_t)bid; t < cl.c1; t += nb) {
+      const int2 task = h.chunk_tasks[t];
+      const int32_t i = h.items[task.x];
+      if (a.target[i] < 0) continue;  // uniform: no move
+      const int32_t beg = g.begin(i), deg = g.degree(i);
+      const int32_t e0 = task.y * kHubChunk;
+      const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
+      for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i) a.flag[j] = 1;
+      }
+    }
+  }
+  nm = block_sum<unsigned long long>(nm, red_u);
+  if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -759,26 +813,26 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   (void)hub_grid;  // the hub bin goes through the chunked hub path
 }
 
-// kind (local-moving): 0 short rows, 1 long rows (marked per vertex), 2 hubs
-// (applied only: marked and forgotten by hub_mark).
+// One launch for the commits of a group (see k_commit).
 template <class WT, int PH>
-void commit_list(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count,
-                 int kind = 0) {
-  if (count <= 0) return;
+void commit_group_launch(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const HubArgs& h,
+                         CommitLaunch cl) {
   const GraphView<WT> g = view<WT>(gd);
-  if (PH == kMove && kind == 2) {
-    hipLaunchKernelGGL((k_commit<WT, kMove, false>), dim3(grid_for(count, kBlock, 2048)), dim3(kBlock), 0, st, g,
-                       a, list, count);
-    return;
+  int32_t nblk[4];
+  if (PH == kRefine) {
+    nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, 2048) : 0;
+    nblk[1] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, 2048) : 0;
+    nblk[2] = nblk[3] = 0;
+  } else {
+    nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, 2048) : 0;
+    nblk[1] = cl.n1 > 0 ? grid_for(cl.n1, 1, 2048) : 0;
+    nblk[2] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, 64) : 0;
+    nblk[3] = cl.c1 > cl.c0 ? grid_for(cl.c1 - cl.c0, 1, 4096) : 0;
   }
-  if (PH == kMove && kind == 1) {
-    hipLaunchKernelGGL((k_commit<WT, kMove, false>), dim3(grid_for(count, kBlock, 2048)), dim3(kBlock), 0, st, g,
-                       a, list, count);
-    hipLaunchKernelGGL((k_mark_rows<WT>), dim3(grid_for(count, 1, 2048)), dim3(kBlock), 0, st, g, a, list, count);
-    return;
-  }
-  const int grid = grid_for(count, kBlock, 2048);
-  hipLaunchKernelGGL((k_commit<WT, PH>), dim3(grid), dim3(kBlock), 0, st, g, a, list, count);
+  cl.b[0] = 0;
+  for (int r = 0; r < 4; ++r) cl.b[r + 1] = cl.b[r] + nblk[r];
+  if (cl.b[4] > 0)
+    hipLaunchKernelGGL((k_commit<WT, PH>), dim3(cl.b[4]), dim3(kBlock), 0, st, g, a, h, cl);
 }
 
 }  // namespace gvl
