@@ -48,7 +48,7 @@ struct Workspace {
   void* w[2];
   TblSlot* tbl;
   int32_t* lbuf;  // partitioned hubs: sorted candidates, their weights, chunk offsets
-  void* wbuf;
+  double* wbuf;
   uint16_t* poff;
   int64_t tbl_entries;
   // hub path
@@ -113,9 +113,11 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.tbl_entries = table_entries(tbl_n < 0 ? n : std::min(tbl_n, n));
   w.tbl = (TblSlot*)take(sizeof(TblSlot) * (size_t)w.tbl_entries);
   w.lbuf = (int32_t*)take(4 * M);
-  w.wbuf = take(ws * M);
+  w.wbuf = (double*)take(8 * M);
+  // chunk tasks of one plan: sum of ceil(arcs / kHubChunk) over items of
+  // more than kBinMax[kAggLastBin] arcs (aggregation; vertex hubs are longer)
   w.poff = (uint16_t*)take(2 * (kPartMaxP + 1) *
-                           ((size_t)M / kHubChunk + (size_t)M / ((size_t)kBinMax[kHubBin - 1] + 1) + 2));
+                           ((size_t)M / kHubChunk + (size_t)M / ((size_t)kBinMax[kAggLastBin] + 1) + 2));
   w.hp_chunk = (int32_t*)take(4 * (N + 1));
   w.hp_tbl = (int32_t*)take(4 * (N + 1));
   w.hp_slice = (int32_t*)take(4 * (N + 1));

@@ -67,10 +67,15 @@ __global__ void k_gagg_setup(const int32_t* yoff, const int32_t* items, int32_t 
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
     const int32_t c = items[p];
     const int64_t cap = (int64_t)yoff[c + 1] - yoff[c];
-    const int64_t ts = table_slots(cap, ncom);
     chunk_off[p] = (int32_t)((cap + kHubChunk - 1) / kHubChunk);
-    tbl_off[p] = (int32_t)(ts / kTblUnit);
-    slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
+    if (hub_partitioned(cap)) {  // no table; one task per key partition
+      tbl_off[p] = 0;
+      slice_off[p] = hub_parts(cap);
+    } else {
+      const int64_t ts = table_slots(cap, ncom);
+      tbl_off[p] = (int32_t)(ts / kTblUnit);
+      slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
+    }
   }
 }
 void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom, int32_t* chunk_off,
@@ -138,6 +143,73 @@ __device__ __forceinline__ void flush_chunk(const HubArgs& h, int32_t p, int32_t
   __syncthreads();
 }
 
+// The distinct entries of a chunk's LDS table (2^kHubGatherLg slots), sorted
+// by key partition (wide_part mod P), are written to lb / wb[0..n) with the
+// partition offsets to po[0..P]; the table is left empty.  s_cnt: P + 1
+// ints of LDS, zeroed by the caller before the table was filled and made
+// visible by a barrier since; s_wsum: kBlock / kWave ints of LDS.
+__device__ __forceinline__ void stage_chunk_partitions(int32_t* skeys, double* svals, int32_t* s_cnt, int* s_wsum,
+                                                       int P, int32_t* lb, double* wb, uint16_t* po) {
+  constexpr int TS = 1 << kHubGatherLg;
+  // the table's entries into registers (the table is left empty), with
+  // their rank inside their partition
+  constexpr int R = TS / kBlock;
+  int32_t ck[R], rk[R];
+  double cw[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int sl = r * kBlock + threadIdx.x;
+    ck[r] = skeys[sl];
+    cw[r] = svals[sl];
+    rk[r] = 0;
+    if (ck[r] != kEmpty) {
+      skeys[sl] = kEmpty;
+      svals[sl] = 0.0;
+      rk[r] = atomicAdd(&s_cnt[wide_part(ck[r]) & (uint32_t)(P - 1)], 1);
+    }
+  }
+  __syncthreads();
+  {  // exclusive scan of the P <= kBlock counts; s_cnt[P] = total
+    const int v = ((int)threadIdx.x < P) ? s_cnt[threadIdx.x] : 0;
+    int incl = v;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    const int wv = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) s_wsum[wv] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < kBlock / kWave; ++k) {
+      if (k < wv) before += s_wsum[k];
+      total += s_wsum[k];
+    }
+    if ((int)threadIdx.x < P) s_cnt[threadIdx.x] = before + incl - v;
+    if (threadIdx.x == 0) s_cnt[P] = total;
+    __syncthreads();
+  }
+  // staged in partition order at the front of the (empty) table
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (ck[r] == kEmpty) continue;
+    const int pos = s_cnt[wide_part(ck[r]) & (uint32_t)(P - 1)] + rk[r];
+    skeys[pos] = ck[r];
+    svals[pos] = cw[r];
+  }
+  __syncthreads();
+  // out; the table is emptied again
+  const int n = s_cnt[P];
+  for (int k = threadIdx.x; k < n; k += kBlock) {
+    lb[k] = skeys[k];
+    wb[k] = svals[k];
+    skeys[k] = kEmpty;
+    svals[k] = 0.0;
+  }
+  for (int k = threadIdx.x; k <= P; k += kBlock) po[k] = (uint16_t)s_cnt[k];
+  __syncthreads();  // s_cnt is read above before the caller reuses it
+}
+
 // Chunk gather: H_chunk[C[j]] += w over the chunk's arcs (j != i; in
 // refinement only j inside i's bound), merged into the hub's global table.
 template <class WT, int PH>
@@ -174,64 +246,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
         lds_insert(skeys, svals, kHubGatherLg, c, w);
       });
       __syncthreads();
-      // 2. the table's entries into registers (the table is left empty),
-      // with their rank inside their partition
-      constexpr int R = TS / kBlock;
-      int32_t ck[R], rk[R];
-      double cw[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int sl = r * kBlock + threadIdx.x;
-        ck[r] = skeys[sl];
-        cw[r] = svals[sl];
-        rk[r] = 0;
-        if (ck[r] != kEmpty) {
-          skeys[sl] = kEmpty;
-          svals[sl] = 0.0;
-          rk[r] = atomicAdd(&s_cnt[wide_part(ck[r]) & (uint32_t)(P - 1)], 1);
-        }
-      }
-      __syncthreads();
-      {  // exclusive scan of the P <= kBlock counts; s_cnt[P] = total
-        const int v = (threadIdx.x < P) ? s_cnt[threadIdx.x] : 0;
-        int incl = v;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-          const int x = __shfl_up(incl, o);
-          if (lane_id() >= o) incl += x;
-        }
-        const int wv = threadIdx.x / kWave;
-        if (lane_id() == kWave - 1) s_wsum[wv] = incl;
-        __syncthreads();
-        int before = 0, total = 0;
-        for (int k = 0; k < kBlock / kWave; ++k) {
-          if (k < wv) before += s_wsum[k];
-          total += s_wsum[k];
-        }
-        if (threadIdx.x < P) s_cnt[threadIdx.x] = before + incl - v;
-        if (threadIdx.x == 0) s_cnt[P] = total;
-        __syncthreads();
-      }
-      // 3. staged in partition order at the front of the (empty) table
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (ck[r] == kEmpty) continue;
-        const int pos = s_cnt[wide_part(ck[r]) & (uint32_t)(P - 1)] + rk[r];
-        skeys[pos] = ck[r];
-        svals[pos] = cw[r];
-      }
-      __syncthreads();
-      // 4. out to the chunk's own arc positions; the table is emptied again
-      const int n = s_cnt[P];
-      WT* wb = (WT*)h.wbuf;
-      for (int k = threadIdx.x; k < n; k += kBlock) {
-        h.lbuf[(int64_t)beg + e0 + k] = skeys[k];
-        wb[(int64_t)beg + e0 + k] = (WT)svals[k];
-        skeys[k] = kEmpty;
-        svals[k] = 0.0;
-      }
-      uint16_t* po = h.poff + t * (kPartMaxP + 1);
-      for (int k = threadIdx.x; k <= P; k += kBlock) po[k] = (uint16_t)s_cnt[k];
+      stage_chunk_partitions(skeys, svals, s_cnt, s_wsum, P, h.lbuf + (int64_t)beg + e0, h.wbuf + (int64_t)beg + e0,
+                             h.poff + t * (kPartMaxP + 1));
       kid = block_sum<double>(kid, s_red);  // (its barriers also end this chunk's LDS use)
       if (threadIdx.x == 0) {
         na += (unsigned long long)(e1 - e0);
@@ -475,7 +491,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
     s_r0[threadIdx.x] = r0;
     if (threadIdx.x == 0) s_pre[NT] = total;
     __syncthreads();
-    const WT* wb = (const WT*)h.wbuf;
+    const double* wb = h.wbuf;
     constexpr int U = 4;  // entries per thread per step, their loads in flight together
     for (int32_t kb = threadIdx.x; kb < total; kb += U * NT) {
       int32_t ck[U];
@@ -493,7 +509,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
           }
           const int64_t pos = (int64_t)beg + (int64_t)lo * kHubChunk + s_r0[lo] + (k - s_pre[lo]);
           ck[u] = h.lbuf[pos];
-          cw[u] = (double)wb[pos];
+          cw[u] = wb[pos];
         }
       }
 #pragma unroll
@@ -718,6 +734,7 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
   __shared__ int32_t snew[kHubChunk];
   __shared__ int s_nnew, s_base;
   __shared__ double s_red[kBlock / kWave];
+  __shared__ int s_wsum[kBlock / kWave];
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -726,6 +743,10 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     const int32_t p = task.x;
     const int32_t c = h.items[p];
     const int32_t mb = a.coff[c], me = a.coff[c + 1];
+    const bool part = hub_partitioned((int64_t)a.yoff[c + 1] - a.yoff[c]);  // uniform
+    const int P = part ? h.slice_off[p + 1] - h.slice_off[p] : 0;
+    if (part)
+      for (int k = threadIdx.x; k <= P; k += kBlock) snew[k] = 0;
     const int64_t cend = h.apre[me];
     const int64_t A0 = (int64_t)h.apre[mb] + (int64_t)task.y * kHubChunk;
     double self = 0.0;  // arcs inside c: the super-vertex's self-loop
@@ -759,7 +780,12 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     }
     self = block_sum<double>(self, s_red);
     if (threadIdx.x == 0 && self != 0.0) lds_insert(skeys, svals, kHubGatherLg, c, self);
-    flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
+    if (part) {  // the distinct entries, by partition, at the chunk's arc positions
+      __syncthreads();
+      stage_chunk_partitions(skeys, svals, snew, s_wsum, P, h.lbuf + A0, h.wbuf + A0, h.poff + t * (kPartMaxP + 1));
+    } else {
+      flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
+    }
   }
   __shared__ unsigned long long red_u[16];
   na = block_sum<unsigned long long>(na, red_u);
@@ -787,6 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int3
     const int2 task = h.slice_tasks[t];
     const int32_t p = task.x;
     const int32_t c = h.items[p];
+    if (hub_partitioned((int64_t)a.yoff[c + 1] - a.yoff[c])) continue;  // uniform: k_gagg_part_emit
     TblSlot* gt = tbl_of(h, p);
     const int32_t* lst = tbl_list_of(h, p);
     const int32_t len = h.lcnt[p];
@@ -852,8 +879,140 @@ __global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int3
   if (threadIdx.x == kWave - 1 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
 }
 
+// Partition emit of the partitioned giant communities: task (p, q) sums the
+// entries of partition q of every chunk of community c = items[p] in an LDS
+// table and appends its distinct (d, H[d]) to row c.  Entries are inserted
+// kPartBatch at a time; a batch that could overfill the table first flushes
+// it to the row (then a key can occur twice in the row, with partial sums,
+// which every later step adds up; statistically out of reach, as the table
+// holds 1.5 times the expected keys of a partition).
+constexpr int kPartBatch = 1024;
+__device__ __forceinline__ int lds_insert_new_sized(int32_t* keys, double* vals, uint32_t ts, int32_t c, double w) {
+  uint32_t h = (uint32_t)(((u64)((uint32_t)c * 0x9E3779B1u) * (u64)ts) >> 32);
+  for (uint32_t probe = 0; probe < ts; ++probe) {
+    int32_t k = keys[h];
+    if (k == c) { atomicAdd(&vals[h], w); return 0; }
+    if (k == kEmpty) {
+      const int32_t old = atomicCAS(&keys[h], kEmpty, c);
+      if (old == kEmpty || old == c) { atomicAdd(&vals[h], w); return old == kEmpty ? 1 : 0; }
+    }
+    h = (h + 1u == ts) ? 0u : h + 1u;
+  }
+  return -1;
+}
+
+template <class WTout>
+__global__ __launch_bounds__(kPartThreads) void k_gagg_part_emit(AggArgs a, HubArgs h, int32_t s0, int32_t s1) {
+  constexpr int NT = kPartThreads;
+  constexpr int NW = NT / kWave;
+  constexpr int TS = kPartSlots;
+  constexpr int R = TS / NT;
+  static_assert(TS % NT == 0 && kPartBatch < TS, "table rounds, batch below the table size");
+  __shared__ int32_t keys[TS];
+  __shared__ double vals[TS];
+  __shared__ int32_t s_pre[NT + 1];
+  __shared__ int32_t s_r0[NT];
+  __shared__ int32_t s_w[NW];
+  __shared__ int s_occ, s_base;
+  WTout* yw = (WTout*)a.yw;
+  unsigned long long no = 0;
+  for (int s = threadIdx.x; s < TS; s += NT) { keys[s] = kEmpty; vals[s] = 0.0; }
+  // appends the table's entries to row c and empties the table (every
+  // thread; starts and ends with a barrier)
+  auto flush = [&](int32_t c) {
+    __syncthreads();
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) cnt += (keys[r * NT + threadIdx.x] != kEmpty);
+    int incl = cnt;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) s_w[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NW; ++k) {
+      if (k < w) before += s_w[k];
+      total += s_w[k];
+    }
+    if (threadIdx.x == 0) {
+      s_base = total ? atomicAdd(&a.ydeg[c], total) : 0;
+      s_occ = 0;
+      no += (unsigned long long)total;
+    }
+    __syncthreads();
+    int64_t pos = (int64_t)a.yoff[c] + s_base + before + (incl - cnt);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int sl = r * NT + threadIdx.x;
+      const int32_t k = keys[sl];
+      if (k == kEmpty) continue;
+      a.yidx[pos] = k;
+      yw[pos] = (WTout)vals[sl];
+      ++pos;
+      keys[sl] = kEmpty;
+      vals[sl] = 0.0;
+    }
+    __syncthreads();
+  };
+  for (int64_t t = s0 + (int64_t)blockIdx.x; t < s1; t += gridDim.x) {
+    const int2 task = h.slice_tasks[t];
+    const int32_t p = task.x;
+    const int32_t c = h.items[p];
+    if (!hub_partitioned((int64_t)a.yoff[c + 1] - a.yoff[c])) continue;  // uniform: k_gagg_emit
+    const int32_t q = task.y;
+    const int64_t A0 = h.apre[a.coff[c]];
+    // this partition's run in every chunk of c
+    const int32_t nch = h.chunk_off[p + 1] - h.chunk_off[p];
+    int32_t r0 = 0, len = 0;
+    if ((int)threadIdx.x < nch) {
+      const uint16_t* po = h.poff + ((int64_t)h.chunk_off[p] + threadIdx.x) * (kPartMaxP + 1);
+      r0 = po[q];
+      len = (int32_t)po[q + 1] - r0;
+    }
+    int incl = len;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    __syncthreads();  // the previous task's reads of s_pre / s_r0 are done
+    if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = incl;
+    if (threadIdx.x == 0) s_occ = 0;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int k = 0; k < NW; ++k) {
+      if (k < (int)(threadIdx.x / kWave)) before += s_w[k];
+      total += s_w[k];
+    }
+    s_pre[threadIdx.x] = before + incl - len;
+    s_r0[threadIdx.x] = r0;
+    if (threadIdx.x == 0) s_pre[NT] = total;
+    __syncthreads();
+    for (int32_t kb = 0; kb < total; kb += kPartBatch) {  // uniform
+      if (s_occ + kPartBatch > TS) flush(c);  // (s_occ is read after a barrier)
+      const int32_t ke = (kb + kPartBatch < total) ? kb + kPartBatch : total;
+      for (int32_t k = kb + threadIdx.x; k < ke; k += NT) {
+        int lo = 0, hi = NT;  // s_pre[lo] <= k < s_pre[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] <= k) lo = mid; else hi = mid;
+        }
+        const int64_t pos = A0 + (int64_t)lo * kHubChunk + s_r0[lo] + (k - s_pre[lo]);
+        if (lds_insert_new_sized(keys, vals, (uint32_t)TS, h.lbuf[pos], h.wbuf[pos]) > 0) atomicAdd(&s_occ, 1);
+      }
+      __syncthreads();
+    }
+    flush(c);
+  }
+  if (threadIdx.x == 0 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
+}
+
 void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
-               int32_t s0, int32_t s1, int64_t* launches) {
+               int32_t s0, int32_t s1, bool tables, int64_t* launches) {
   if (c1 > c0) {
     const int grid = grid_items(c1 - c0, 1, 2048);
     if (gd.w_double)
@@ -864,8 +1023,15 @@ void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubA
   }
   if (s1 > s0) {
     const int grid = grid_items(s1 - s0, 1, 2048);
-    if (a.yw_double) hipLaunchKernelGGL(k_gagg_emit<double>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
-    else hipLaunchKernelGGL(k_gagg_emit<float>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
+    if (tables) {
+      if (a.yw_double) hipLaunchKernelGGL(k_gagg_emit<double>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
+      else hipLaunchKernelGGL(k_gagg_emit<float>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
+      ++*launches;
+    }
+    if (a.yw_double)
+      hipLaunchKernelGGL(k_gagg_part_emit<double>, dim3(grid), dim3(kPartThreads), 0, st, a, h, s0, s1);
+    else
+      hipLaunchKernelGGL(k_gagg_part_emit<float>, dim3(grid), dim3(kPartThreads), 0, st, a, h, s0, s1);
     ++*launches;
   }
 }

@@ -176,7 +176,7 @@ struct HubArgs {
   int32_t* pb_c;              // per slice task: best community
   TblSlot* tbl;               // table region
   int32_t* lbuf;              // partitioned hubs: candidates of each chunk sorted by partition (arc positions)
-  void* wbuf;                 // their weights (the graph's weight type)
+  double* wbuf;               // their weights (sums: FP64 keeps them exact in det mode)
   uint16_t* poff;             // [chunk task][kPartMaxP + 1] partition offsets inside the chunk
   int32_t* tbl_list;          // occupied slots of each item's table, at the item's table offset
   int32_t* lcnt;              // [H] length of each item's occupied-slot list
@@ -264,7 +264,7 @@ void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32
                 int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off);
 void member_degrees(hipStream_t st, const GraphDesc& g, const int32_t* cv, int64_t n, int32_t* mdeg);
 void gagg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
-               int32_t s0, int32_t s1, int64_t* launches);
+               int32_t s0, int32_t s1, bool tables, int64_t* launches);
 
 // ---- fused batches (k_batch.hip)
 enum BatchState : uint8_t { kBatchCont = 0, kBatchEnd = 1, kBatchDone = 2 };
