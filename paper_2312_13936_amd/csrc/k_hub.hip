@@ -333,13 +333,16 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
             cw[u] = e.val;
           }
         }
+        bool e[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) sg[u] = (ck[u] != kEmpty && ck[u] != d) ? a.Sig[ck[u]] : 0.0;
+        for (int u = 0; u < U; ++u) e[u] = ck[u] != kEmpty && ck[u] != d && ev.may_gain(cw[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) sg[u] = e[u] ? a.Sig[ck[u]] : 0.0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           if (ck[u] == kEmpty) continue;
           gt[sl[u]] = TblSlot{kEmpty, 0, 0.0};
-          if (ck[u] == d) continue;
+          if (!e[u]) continue;
           ++nc;
           ev(a, ck[u], cw[u], sg[u], bg, bk, bc);
         }

@@ -96,6 +96,18 @@ struct Eval {
     A = (i128)65536 * (i128)W;
     B = (i128)p * (i128)kii;
   }
+  // Every arc from i into a candidate community c also counts in the weight
+  // of its member, so Sigma_c >= K_{i->c}; Eq. 2 with Sigma_c = K_{i->c}
+  // then bounds the gain from above (the gain falls as Sigma_c grows).  A
+  // candidate whose bound is not positive is never chosen (a move needs a
+  // positive gain, also in randomized refinement), so its total is not read.
+  __device__ __forceinline__ bool may_gain(double kic) const {
+    if (DET) {
+      const long long k = (long long)kic;
+      return A * (i128)(k - kidi) - B * (i128)(kii + k - sdi) > 0;
+    }
+    return (kic - kid) * inv_m - gk * (ki + kic - sd) > 0.0;
+  }
   __device__ __forceinline__ double score(const ScanArgs& a, double gain, int32_t c) const {
     return gain / neg_ln_unit(draw32(a.seed, a.pass, a.sweep, il, c - base));
   }
@@ -222,14 +234,19 @@ __device__ __forceinline__ void eval_table(int32_t* keys, double* vals, int ts, 
       c[u] = (s < ts) ? keys[s] : kEmpty;
       v[u] = (c[u] != kEmpty) ? vals[s] : 0.0;
     }
+    bool e[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) sg[u] = (c[u] != kEmpty) ? a.Sig[c[u]] : 0.0;
+    for (int u = 0; u < U; ++u) e[u] = c[u] != kEmpty && ev.may_gain(v[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) sg[u] = e[u] ? a.Sig[c[u]] : 0.0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int s = base + u * NT;
-      if (c[u] != kEmpty) {
+      if (e[u]) {
         ++acc.nc;
         ev(a, c[u], v[u], sg[u], bg, bk, bc);
+      }
+      if (c[u] != kEmpty) {
         keys[s] = kEmpty;
         vals[s] = 0.0;
       }
