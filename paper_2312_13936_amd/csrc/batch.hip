@@ -512,7 +512,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       for (const HubBatch& hb : gp.groups[0]) {
         tstate.ensure(st, ws, hb.tend - hb.tbase);
         gh.tbase = hb.tbase;
-        gagg_rows(st, cur, g, gh, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, &dummy_launches);
+        gagg_rows(st, cur, g, gh, hb.c0, hb.c1, hb.s0, hb.s1, &dummy_launches);
       }
     }
     // move-based labels of the super-vertices, their graphs and bases

@@ -447,7 +447,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         for (const HubBatch& hb : gp.groups[0]) {
           tstate.ensure(st, ws, hb.tend - hb.tbase);
           gh.tbase = hb.tbase;
-          gagg_rows(st, cur, g, gh, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, &S->agg_launches);
+          gagg_rows(st, cur, g, gh, hb.c0, hb.c1, hb.s0, hb.s1, &S->agg_launches);
         }
       }
       tm.end(hk);

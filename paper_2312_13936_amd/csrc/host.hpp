@@ -302,7 +302,7 @@ gvl_status build_hub_plan(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, bool
   const int32_t H = bins.H;
   // Distinct keys of one table are at most the items with arcs (bins.binned):
   // communities / vertices without arcs are never anyone's neighbour.
-  if (agg) gagg_setup(st, yoff, items, H, bins.binned, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
+  if (agg) gagg_setup(st, yoff, items, H, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
   else hub_setup(st, g.off, g.deg, items, H, bins.binned, ws.hp_chunk, ws.hp_tbl, ws.hp_slice);
   exclusive_scan(st, ws.hp_chunk, H, ws.scan_tmp);
   exclusive_scan(st, ws.hp_tbl, H, ws.scan_tmp);

@@ -62,26 +62,20 @@ void hub_setup(hipStream_t st, const int32_t* off, const int32_t* deg, const int
                        chunk_off, tbl_off, slice_off);
 }
 
-__global__ void k_gagg_setup(const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom, int32_t* chunk_off,
+__global__ void k_gagg_setup(const int32_t* yoff, const int32_t* items, int32_t H, int32_t* chunk_off,
                              int32_t* tbl_off, int32_t* slice_off) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < H; p += (int64_t)gridDim.x * blockDim.x) {
     const int32_t c = items[p];
     const int64_t cap = (int64_t)yoff[c + 1] - yoff[c];
     chunk_off[p] = (int32_t)((cap + kHubChunk - 1) / kHubChunk);
-    if (hub_partitioned(cap)) {  // no table; one task per key partition
-      tbl_off[p] = 0;
-      slice_off[p] = hub_parts(cap);
-    } else {
-      const int64_t ts = table_slots(cap, ncom);
-      tbl_off[p] = (int32_t)(ts / kTblUnit);
-      slice_off[p] = (int32_t)((ts + kHubSlice - 1) / kHubSlice);
-    }
+    tbl_off[p] = 0;  // no table; one task per key partition
+    slice_off[p] = agg_parts(cap);
   }
 }
-void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom, int32_t* chunk_off,
+void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int32_t* chunk_off,
                 int32_t* tbl_off, int32_t* slice_off) {
   if (H > 0)
-    hipLaunchKernelGGL(k_gagg_setup, dim3(grid_items(H, kBlock, 4096)), dim3(kBlock), 0, st, yoff, items, H, ncom,
+    hipLaunchKernelGGL(k_gagg_setup, dim3(grid_items(H, kBlock, 4096)), dim3(kBlock), 0, st, yoff, items, H,
                        chunk_off, tbl_off, slice_off);
 }
 
@@ -505,7 +499,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
         ck[u] = kEmpty;
         cw[u] = 0.0;
         if (k < total) {
-          int lo = 0, hi = NT;  // s_pre[lo] <= k < s_pre[hi]
+          int lo = 0, hi = nch;  // s_pre[lo] <= k < s_pre[hi] (s_pre[nch] = total)
           while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (s_pre[mid] <= k) lo = mid; else hi = mid;
@@ -734,8 +728,7 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
   constexpr int PER = kHubChunk / kBlock;  // arcs per thread
   __shared__ int32_t skeys[TS];
   __shared__ double svals[TS];
-  __shared__ int32_t snew[kHubChunk];
-  __shared__ int s_nnew, s_base;
+  __shared__ int32_t s_cnt[kPartMaxP + 1];
   __shared__ double s_red[kBlock / kWave];
   __shared__ int s_wsum[kBlock / kWave];
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
@@ -746,10 +739,8 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     const int32_t p = task.x;
     const int32_t c = h.items[p];
     const int32_t mb = a.coff[c], me = a.coff[c + 1];
-    const bool part = hub_partitioned((int64_t)a.yoff[c + 1] - a.yoff[c]);  // uniform
-    const int P = part ? h.slice_off[p + 1] - h.slice_off[p] : 0;
-    if (part)
-      for (int k = threadIdx.x; k <= P; k += kBlock) snew[k] = 0;
+    const int P = h.slice_off[p + 1] - h.slice_off[p];
+    for (int k = threadIdx.x; k <= P; k += kBlock) s_cnt[k] = 0;
     const int64_t cend = h.apre[me];
     const int64_t A0 = (int64_t)h.apre[mb] + (int64_t)task.y * kHubChunk;
     double self = 0.0;  // arcs inside c: the super-vertex's self-loop
@@ -783,112 +774,25 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     }
     self = block_sum<double>(self, s_red);
     if (threadIdx.x == 0 && self != 0.0) lds_insert(skeys, svals, kHubGatherLg, c, self);
-    if (part) {  // the distinct entries, by partition, at the chunk's arc positions
-      __syncthreads();
-      stage_chunk_partitions(skeys, svals, snew, s_wsum, P, h.lbuf + A0, h.wbuf + A0, h.poff + t * (kPartMaxP + 1));
-    } else {
-      flush_chunk(h, p, skeys, svals, snew, &s_nnew, &s_base);
-    }
+    // the distinct entries, by partition, at the chunk's arc positions
+    __syncthreads();
+    stage_chunk_partitions(skeys, svals, s_cnt, s_wsum, P, h.lbuf + A0, h.wbuf + A0, h.poff + t * (kPartMaxP + 1));
   }
   __shared__ unsigned long long red_u[16];
   na = block_sum<unsigned long long>(na, red_u);
   if (threadIdx.x == 0 && na) atomicAdd(&cnt_of(a.cnt)[5], na);
 }
 
-// Slice emit: append the slice's entries of the community's table, (d,
-// H[d]), to row c (ydeg[c] is the row cursor, zeroed by the caller) and free
-// their slots; the last slice resets the occupied-slot list.  Dense tables
-// are read slot by slot, sparse ones through their occupied-slot list; in
-// both, round r of a workgroup covers kBlock consecutive positions (one per
-// thread), and the occupied entries of each (round, wavefront) are written
-// contiguously at offsets from one workgroup-wide scan.
-template <class WTout>
-__global__ __launch_bounds__(kBlock) void k_gagg_emit(AggArgs a, HubArgs h, int32_t s0, int32_t s1) {
-  constexpr int R = kHubSlice / kBlock;  // rounds per slice
-  constexpr int NW = kBlock / kWave;
-  static_assert(R * NW == 2 * kWave, "one scan of two entries per lane");
-  __shared__ int32_t s_off[R * NW];      // [round][wavefront]: entries, then their offsets
-  __shared__ int s_base;
-  WTout* yw = (WTout*)a.yw;
-  const int w = threadIdx.x / kWave;
-  unsigned long long no = 0;
-  for (int64_t t = s0 + (int64_t)blockIdx.x; t < s1; t += gridDim.x) {
-    const int2 task = h.slice_tasks[t];
-    const int32_t p = task.x;
-    const int32_t c = h.items[p];
-    if (hub_partitioned((int64_t)a.yoff[c + 1] - a.yoff[c])) continue;  // uniform: k_gagg_part_emit
-    TblSlot* gt = tbl_of(h, p);
-    const int32_t* lst = tbl_list_of(h, p);
-    const int32_t len = h.lcnt[p];
-    const int64_t ts = (int64_t)1 << tbl_lg(h, p);
-    const bool dense = (int64_t)len * 8 > ts;
-    const int64_t lim = dense ? ts : len;
-    const int64_t q0 = (int64_t)task.y * kHubSlice;
-    if (q0 < lim) {  // uniform: a slice past the end of the list only counts itself done
-      uint32_t slot[R];
-      int32_t key[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int64_t q = q0 + r * kBlock + threadIdx.x;
-        key[r] = kEmpty;
-        slot[r] = 0;
-        if (q < lim) {
-          slot[r] = dense ? (uint32_t)q : (uint32_t)lst[q];
-          key[r] = gt[slot[r]].key;
-        }
-        const u64 b = __ballot(key[r] != kEmpty);
-        if (lane_id() == 0) s_off[r * NW + w] = __popcll(b);
-      }
-      __syncthreads();
-      if (w == 0) {  // exclusive scan of the 2 kWave counts, in (round, wavefront) order
-        const int v0 = s_off[2 * lane_id()], v1 = s_off[2 * lane_id() + 1];
-        int incl = v0 + v1;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-          const int x = __shfl_up(incl, o);
-          if (lane_id() >= o) incl += x;
-        }
-        const int excl = incl - v0 - v1;
-        s_off[2 * lane_id()] = excl;
-        s_off[2 * lane_id() + 1] = excl + v0;
-        if (lane_id() == kWave - 1) {
-          s_base = incl ? atomicAdd(&a.ydeg[c], incl) : 0;
-          no += (unsigned long long)incl;
-        }
-      }
-      __syncthreads();
-      const int64_t base = (int64_t)a.yoff[c] + s_base;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const u64 b = __ballot(key[r] != kEmpty);
-        if (key[r] != kEmpty) {
-          const int64_t pos = base + s_off[r * NW + w] + __popcll(b & lanemask_lt());
-          a.yidx[pos] = key[r];
-          yw[pos] = (WTout)gt[slot[r]].val;
-          gt[slot[r]] = TblSlot{kEmpty, 0, 0.0};
-        }
-      }
-      __syncthreads();  // every thread's reads and frees of this slice are done; s_off reusable
-    }
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const int nsl = h.slice_off[p + 1] - h.slice_off[p];
-      if (atomicAdd(&h.done[p], 1) == nsl - 1) {
-        h.done[p] = 0;
-        h.lcnt[p] = 0;
-      }
-    }
-  }
-  if (threadIdx.x == kWave - 1 && no) atomicAdd(&cnt_of(a.cnt)[6], no);
-}
-
-// Partition emit of the partitioned giant communities: task (p, q) sums the
-// entries of partition q of every chunk of community c = items[p] in an LDS
-// table and appends its distinct (d, H[d]) to row c.  Entries are inserted
-// kPartBatch at a time; a batch that could overfill the table first flushes
-// it to the row (then a key can occur twice in the row, with partial sums,
-// which every later step adds up; statistically out of reach, as the table
-// holds 1.5 times the expected keys of a partition).
+// Partition emit of the giant communities: task (p, q) sums the entries of
+// partition q of every chunk of community c = items[p] in an LDS table and
+// appends its distinct (d, H[d]) to row c.  The chunks are taken kPartThreads
+// at a time (their run offsets in LDS).  Entries are inserted kPartBatch at a
+// time; a batch that could overfill the table first flushes it to the row
+// (then a key can occur twice in the row, with partial sums, which every
+// later step adds up).  Up to kPartMaxDeg member arcs this is statistically
+// out of reach (the table holds 1.5 times the expected keys of a
+// partition); beyond, it happens when a partition has more distinct keys
+// than its table.
 constexpr int kPartBatch = 1024;
 __device__ __forceinline__ int lds_insert_new_sized(int32_t* keys, double* vals, uint32_t ts, int32_t c, double w) {
   uint32_t h = (uint32_t)(((u64)((uint32_t)c * 0x9E3779B1u) * (u64)ts) >> 32);
@@ -965,49 +869,52 @@ __global__ __launch_bounds__(kPartThreads) void k_gagg_part_emit(AggArgs a, HubA
     const int2 task = h.slice_tasks[t];
     const int32_t p = task.x;
     const int32_t c = h.items[p];
-    if (!hub_partitioned((int64_t)a.yoff[c + 1] - a.yoff[c])) continue;  // uniform: k_gagg_emit
     const int32_t q = task.y;
     const int64_t A0 = h.apre[a.coff[c]];
-    // this partition's run in every chunk of c
     const int32_t nch = h.chunk_off[p + 1] - h.chunk_off[p];
-    int32_t r0 = 0, len = 0;
-    if ((int)threadIdx.x < nch) {
-      const uint16_t* po = h.poff + ((int64_t)h.chunk_off[p] + threadIdx.x) * (kPartMaxP + 1);
-      r0 = po[q];
-      len = (int32_t)po[q + 1] - r0;
-    }
-    int incl = len;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int x = __shfl_up(incl, o);
-      if (lane_id() >= o) incl += x;
-    }
-    __syncthreads();  // the previous task's reads of s_pre / s_r0 are done
-    if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = incl;
     if (threadIdx.x == 0) s_occ = 0;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int k = 0; k < NW; ++k) {
-      if (k < (int)(threadIdx.x / kWave)) before += s_w[k];
-      total += s_w[k];
-    }
-    s_pre[threadIdx.x] = before + incl - len;
-    s_r0[threadIdx.x] = r0;
-    if (threadIdx.x == 0) s_pre[NT] = total;
-    __syncthreads();
-    for (int32_t kb = 0; kb < total; kb += kPartBatch) {  // uniform
-      if (s_occ + kPartBatch > TS) flush(c);  // (s_occ is read after a barrier)
-      const int32_t ke = (kb + kPartBatch < total) ? kb + kPartBatch : total;
-      for (int32_t k = kb + threadIdx.x; k < ke; k += NT) {
-        int lo = 0, hi = NT;  // s_pre[lo] <= k < s_pre[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_pre[mid] <= k) lo = mid; else hi = mid;
-        }
-        const int64_t pos = A0 + (int64_t)lo * kHubChunk + s_r0[lo] + (k - s_pre[lo]);
-        if (lds_insert_new_sized(keys, vals, (uint32_t)TS, h.lbuf[pos], h.wbuf[pos]) > 0) atomicAdd(&s_occ, 1);
+    for (int32_t cb = 0; cb < nch; cb += NT) {  // uniform
+      // this partition's run in chunks cb .. cb + nb - 1 of c
+      const int32_t nb = (nch - cb < NT) ? nch - cb : NT;
+      int32_t r0 = 0, len = 0;
+      if ((int)threadIdx.x < nb) {
+        const uint16_t* po = h.poff + ((int64_t)h.chunk_off[p] + cb + threadIdx.x) * (kPartMaxP + 1);
+        r0 = po[q];
+        len = (int32_t)po[q + 1] - r0;
       }
+      int incl = len;
+#pragma unroll
+      for (int o = 1; o < kWave; o <<= 1) {
+        const int x = __shfl_up(incl, o);
+        if (lane_id() >= o) incl += x;
+      }
+      __syncthreads();  // the previous block's reads of s_pre / s_r0 are done
+      if (lane_id() == kWave - 1) s_w[threadIdx.x / kWave] = incl;
       __syncthreads();
+      int before = 0, total = 0;
+      for (int k = 0; k < NW; ++k) {
+        if (k < (int)(threadIdx.x / kWave)) before += s_w[k];
+        total += s_w[k];
+      }
+      s_pre[threadIdx.x] = before + incl - len;
+      s_r0[threadIdx.x] = r0;
+      if (threadIdx.x == 0) s_pre[NT] = total;
+      __syncthreads();
+      const int64_t base = A0 + (int64_t)cb * kHubChunk;
+      for (int32_t kb = 0; kb < total; kb += kPartBatch) {  // uniform
+        if (s_occ + kPartBatch > TS) flush(c);  // (s_occ is read after a barrier)
+        const int32_t ke = (kb + kPartBatch < total) ? kb + kPartBatch : total;
+        for (int32_t k = kb + threadIdx.x; k < ke; k += NT) {
+          int lo = 0, hi = nb;  // s_pre[lo] <= k < s_pre[hi] (s_pre[nb] = total)
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (s_pre[mid] <= k) lo = mid; else hi = mid;
+          }
+          const int64_t pos = base + (int64_t)lo * kHubChunk + s_r0[lo] + (k - s_pre[lo]);
+          if (lds_insert_new_sized(keys, vals, (uint32_t)TS, h.lbuf[pos], h.wbuf[pos]) > 0) atomicAdd(&s_occ, 1);
+        }
+        __syncthreads();
+      }
     }
     flush(c);
   }
@@ -1015,7 +922,7 @@ __global__ __launch_bounds__(kPartThreads) void k_gagg_part_emit(AggArgs a, HubA
 }
 
 void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
-               int32_t s0, int32_t s1, bool tables, int64_t* launches) {
+               int32_t s0, int32_t s1, int64_t* launches) {
   if (c1 > c0) {
     const int grid = grid_items(c1 - c0, 1, 2048);
     if (gd.w_double)
@@ -1026,11 +933,6 @@ void gagg_rows(hipStream_t st, const GraphDesc& gd, const AggArgs& a, const HubA
   }
   if (s1 > s0) {
     const int grid = grid_items(s1 - s0, 1, 2048);
-    if (tables) {
-      if (a.yw_double) hipLaunchKernelGGL(k_gagg_emit<double>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
-      else hipLaunchKernelGGL(k_gagg_emit<float>, dim3(grid), dim3(kBlock), 0, st, a, h, s0, s1);
-      ++*launches;
-    }
     if (a.yw_double)
       hipLaunchKernelGGL(k_gagg_part_emit<double>, dim3(grid), dim3(kPartThreads), 0, st, a, h, s0, s1);
     else

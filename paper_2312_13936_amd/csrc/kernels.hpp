@@ -149,8 +149,15 @@ constexpr int32_t kPartMaxDeg = kPartMaxP * kPartKeys;
 __host__ __device__ __forceinline__ bool hub_partitioned(int64_t deg) { return deg <= kPartMaxDeg; }
 __host__ __device__ __forceinline__ int32_t hub_parts(int64_t deg) {
   int32_t p = 1;
-  while ((int64_t)p * kPartKeys < deg) p <<= 1;
+  while ((int64_t)p * kPartKeys < deg && p < (1 << 24)) p <<= 1;
   return p;
+}
+// Giant communities of the aggregation are always partitioned, into at most
+// kPartMaxP partitions: beyond kPartMaxDeg member arcs a partition's table
+// can fill up, and it then emits its share of the row in parts.
+__host__ __device__ __forceinline__ int32_t agg_parts(int64_t cap) {
+  const int32_t p = hub_parts(cap);
+  return p < kPartMaxP ? p : kPartMaxP;
 }
 
 // Slot of a global hash table: key and value share one 16-byte slot, so an
@@ -260,11 +267,11 @@ void hub_modularity(hipStream_t st, const GraphDesc& g, const HubArgs& h, int32_
                     const int32_t* C, double* tot, double* acc_d, const int32_t* gid = nullptr,
                     double* s1g = nullptr);
 // Aggregation of giant communities.
-void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int64_t ncom,
-                int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off);
+void gagg_setup(hipStream_t st, const int32_t* yoff, const int32_t* items, int32_t H, int32_t* chunk_off,
+                int32_t* tbl_off, int32_t* slice_off);
 void member_degrees(hipStream_t st, const GraphDesc& g, const int32_t* cv, int64_t n, int32_t* mdeg);
 void gagg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const HubArgs& h, int32_t c0, int32_t c1,
-               int32_t s0, int32_t s1, bool tables, int64_t* launches);
+               int32_t s0, int32_t s1, int64_t* launches);
 
 // ---- fused batches (k_batch.hip)
 enum BatchState : uint8_t { kBatchCont = 0, kBatchEnd = 1, kBatchDone = 2 };

@@ -303,7 +303,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    eval_table<TS / G, G, DET>(keys, vals, ts, gl, a, ev, acc, bg, bk, bc);
+    eval_table<(TS / G > 2 ? 2 : TS / G), G, DET>(keys, vals, ts, gl, a, ev, acc, bg, bk, bc);
     if (DET) argmax_k<G>(bk, bc); else argmax_f<G>(bg, bc);
     wave_sync();
     if (gl == 0) { ++acc.nv; acc.na += (unsigned long long)deg; }
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    eval_table<(TS / kBlock > 0 ? TS / kBlock : 1), kBlock, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk,
+    eval_table<(TS / kBlock > 4 ? 4 : TS / kBlock), kBlock, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk,
                                                                  bc);
     block_argmax<DET>(bg, bk, bc, s_g, s_k, s_c);
     if (threadIdx.x == 0) {
