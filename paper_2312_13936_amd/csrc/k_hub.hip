@@ -721,6 +721,11 @@ void member_degrees(hipStream_t st, const GraphDesc& gd, const int32_t* cv, int6
 
 // Chunk gather over the concatenated member rows of community c: arcs
 // [apre[coff[c]] + chunk * kHubChunk, ...) of the community-vertex order.
+// One wavefront finds the member holding the chunk's first arc (a 65-way
+// search over the member offsets, one load per step), the workgroup copies
+// the offsets and row starts of the chunk's members to LDS, and thread t
+// takes the chunk's arcs t, t + kBlock, ... (coalesced), each finding its
+// member by a binary search in LDS.
 template <class WT>
 __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs a, HubArgs h, int32_t t0,
                                                         int32_t t1) {
@@ -731,6 +736,9 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
   __shared__ int32_t s_cnt[kPartMaxP + 1];
   __shared__ double s_red[kBlock / kWave];
   __shared__ int s_wsum[kBlock / kWave];
+  __shared__ int32_t s_mo[kHubChunk + 1];  // member offsets (apre) from the chunk's first member on
+  __shared__ int32_t s_mb[kHubChunk];      // their row starts
+  __shared__ int32_t s_k0;
   for (int s = threadIdx.x; s < TS; s += kBlock) { skeys[s] = kEmpty; svals[s] = 0.0; }
   __syncthreads();
   unsigned long long na = 0;
@@ -743,35 +751,83 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     for (int k = threadIdx.x; k <= P; k += kBlock) s_cnt[k] = 0;
     const int64_t cend = h.apre[me];
     const int64_t A0 = (int64_t)h.apre[mb] + (int64_t)task.y * kHubChunk;
-    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
-    int64_t pos = A0 + (int64_t)threadIdx.x * PER;
-    int64_t end = pos + PER;
-    if (end > cend) end = cend;
-    if (pos < end) {
-      // member k with apre[k] <= pos < apre[k+1]
-      int32_t lo = mb, hi = me;  // invariant: apre[lo] <= pos < apre[hi]
-      while (hi - lo > 1) {
-        const int32_t mid = lo + (hi - lo) / 2;
-        if (h.apre[mid] <= pos) lo = mid; else hi = mid;
-      }
-      int32_t k = lo;
-      while (pos < end) {
-        const int32_t i = a.cv[k];
-        const int32_t beg = g.begin(i);
-        const int64_t r0 = pos - h.apre[k];
-        int64_t take = (int64_t)h.apre[k + 1] - pos;
-        if (take > end - pos) take = end - pos;
-        for (int64_t x = 0; x < take; ++x) {
-          const int64_t e = beg + r0 + x;
-          const int32_t dl = a.lab[g.idx[e]];
-          if (dl == c) self += g.weight(e);
-          else lds_insert(skeys, svals, kHubGatherLg, dl, g.weight(e));
+    const int64_t A1 = (A0 + kHubChunk < cend) ? A0 + kHubChunk : cend;
+    if (threadIdx.x < kWave) {  // member k0 of [mb, me) with apre[k0] <= A0 < apre[k0 + 1]
+      int32_t lo = mb, hi = me;
+      const int l = lane_id();
+      while (hi - lo > 1) {  // uniform over the wavefront
+        const int64_t span = hi - lo;
+        int32_t x;
+        bool ok;
+        if (span <= kWave) {
+          x = lo + 1 + l;
+          ok = x < hi && h.apre[x] <= A0;
+        } else {
+          x = lo + (int32_t)((span * (l + 1)) / (kWave + 1));  // strictly increasing in (lo, hi)
+          ok = h.apre[x] <= A0;
         }
-        na += (unsigned long long)take;
-        pos += take;
-        ++k;
+        const int L = __popcll(__ballot(ok));  // the probes are ordered and apre is monotone
+        const int32_t xlo = __shfl(x, L > 0 ? L - 1 : 0);
+        const int32_t xhi = __shfl(x, L < kWave ? L : kWave - 1);
+        if (span <= kWave) {
+          lo = L > 0 ? xlo : lo;
+          hi = lo + 1;
+        } else {
+          if (L > 0) lo = xlo;
+          if (L < kWave) hi = xhi;
+        }
+      }
+      if (l == 0) s_k0 = lo;
+    }
+    __syncthreads();
+    const int32_t k0 = s_k0;
+    // offsets and row starts of the members k0, k0 + 1, ... that start
+    // before A1 (at most kHubChunk: each holds an arc of the chunk)
+    int32_t nm = 0;
+    for (int32_t r = 0; r < kHubChunk; r += kBlock) {  // uniform
+      const int32_t k = k0 + r + (int32_t)threadIdx.x;
+      int in = 0;
+      if (k < me) {
+        const int32_t o = h.apre[k];
+        if (o < A1) {
+          s_mo[r + threadIdx.x] = o;
+          s_mb[r + threadIdx.x] = g.begin(a.cv[k]);
+          in = 1;
+        }
+      }
+      const int cnt = __syncthreads_count(in);  // members start in order, so these are a prefix
+      nm += cnt;
+      if (cnt < kBlock) break;
+    }
+    double self = 0.0;  // arcs inside c: the super-vertex's self-loop
+    int32_t j[PER];
+    double w[PER];
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int64_t q = A0 + (int64_t)x * kBlock + threadIdx.x;
+      j[x] = -1;
+      w[x] = 0.0;
+      if (q < A1) {
+        int lo = 0, hi = nm;  // s_mo[lo] <= q < s_mo[hi] (s_mo[nm] taken as A1)
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (s_mo[mid] <= q) lo = mid; else hi = mid;
+        }
+        const int64_t e = (int64_t)s_mb[lo] + (q - s_mo[lo]);
+        j[x] = g.idx[e];
+        w[x] = g.weight(e);
       }
     }
+    int32_t dl[PER];
+#pragma unroll
+    for (int x = 0; x < PER; ++x) dl[x] = (j[x] >= 0) ? a.lab[j[x]] : kEmpty;
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      if (dl[x] == kEmpty) continue;
+      if (dl[x] == c) self += w[x];
+      else lds_insert(skeys, svals, kHubGatherLg, dl[x], w[x]);
+    }
+    na += (unsigned long long)((A1 - A0 + kBlock - 1 - threadIdx.x) / kBlock);
     self = block_sum<double>(self, s_red);
     if (threadIdx.x == 0 && self != 0.0) lds_insert(skeys, svals, kHubGatherLg, c, self);
     // the distinct entries, by partition, at the chunk's arc positions
