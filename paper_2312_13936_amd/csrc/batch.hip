@@ -266,6 +266,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   ScanArgs a;
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
+  a.CP = ws.CP;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
@@ -402,6 +403,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       copy_f64(st, ws.Sig, ws.K, nn);
       set_size_one(st, ws.size, nn);
       fill_i32(st, ws.targeted, 0, nn);
+      pack_labels(st, ws.C, ws.CB, ws.CP, nn);
     }
     fill_u64(st, B.mvg, 0ull, K);
     s = readback(ctx, ws.sc);

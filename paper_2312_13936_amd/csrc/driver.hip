@@ -184,6 +184,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   ScanArgs a;
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
+  a.CP = ws.CP;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
@@ -357,6 +358,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       copy_f64(st, ws.Sig, ws.K, nn);
       set_size_one(st, ws.size, nn);
       fill_i32(st, ws.targeted, 0, nn);
+      pack_labels(st, ws.C, ws.CB, ws.CP, nn);
     }
     for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
       a.rnd = opt->refine_random;

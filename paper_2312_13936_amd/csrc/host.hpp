@@ -44,6 +44,7 @@ struct Workspace {
   int32_t *size, *C, *CB, *start, *target, *newid, *brank, *lab, *rank, *cnt, *cv, *list, *scan_tmp;
   uint8_t* flag;
   int32_t* targeted;
+  int2* CP;
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
   TblSlot* tbl;
@@ -104,6 +105,7 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.scan_tmp = (int32_t*)take(4 * ((size_t)scan_tiles((int64_t)N + 1) + 2));
   w.flag = (uint8_t*)take(N);
   w.targeted = (int32_t*)take(4 * N);
+  w.CP = (int2*)take(8 * N);
   for (int b = 0; b < 2; ++b) {
     w.off[b] = (int32_t*)take(4 * (N + 1));
     w.deg[b] = (int32_t*)take(4 * N);

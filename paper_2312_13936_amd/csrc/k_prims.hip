@@ -48,6 +48,12 @@ void iota_i32(hipStream_t st, int32_t* p, int64_t n) {
 void copy_i32(hipStream_t st, int32_t* d, const int32_t* s, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_n(n)), dim3(kBlock), 0, st, d, s, n);
 }
+__global__ void k_pack_labels(const int32_t* C, const int32_t* CB, int2* CP, int64_t n) {
+  GRID_STRIDE(i, n) CP[i] = make_int2(C[i], CB[i]);
+}
+void pack_labels(hipStream_t st, const int32_t* C, const int32_t* CB, int2* CP, int64_t n) {
+  if (n > 0) hipLaunchKernelGGL(k_pack_labels, dim3(grid_n(n)), dim3(kBlock), 0, st, C, CB, CP, n);
+}
 void copy_f64(hipStream_t st, double* d, const double* s, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_copy<double>, dim3(grid_n(n)), dim3(kBlock), 0, st, d, s, n);
 }

@@ -78,6 +78,8 @@ struct GraphParam {
 struct ScanArgs {
   int32_t* C;               // community of each vertex (C')
   const int32_t* CB;        // community bound (C'_B), refinement only
+  int2* CP;                 // refinement: (C'[j], C'_B[j]) side by side, so one load per arc serves the
+                            // bound test (the commit keeps .x equal to C')
   double* Sig;              // total weight of each community (Sigma')
   int32_t* size;            // vertices in each community
   const double* K;          // weighted degree of each vertex (K')
@@ -319,6 +321,7 @@ void fill_slots(hipStream_t st, TblSlot* p, int64_t n);  // empty slots
 void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64_t n);
 void iota_i32(hipStream_t st, int32_t* p, int64_t n);
 void copy_i32(hipStream_t st, int32_t* dst, const int32_t* src, int64_t n);
+void pack_labels(hipStream_t st, const int32_t* C, const int32_t* CB, int2* CP, int64_t n);
 void copy_f64(hipStream_t st, double* dst, const double* src, int64_t n);
 void set_size_one(hipStream_t st, int32_t* size, int64_t n);
 

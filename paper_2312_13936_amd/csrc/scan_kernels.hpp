@@ -204,10 +204,15 @@ __device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArg
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const bool ok = j[u] != i;
-      c[u] = ok ? a.C[j[u]] : kEmpty;
-      if (PH == kRefine) {
-        const int32_t b = ok ? a.CB[j[u]] : bi;
-        if (b != bi) c[u] = kEmpty;
+      if (PH == kRefine && a.CP) {
+        const int2 cb = ok ? a.CP[j[u]] : make_int2(kEmpty, bi);
+        c[u] = (cb.y == bi) ? cb.x : kEmpty;
+      } else {
+        c[u] = ok ? a.C[j[u]] : kEmpty;
+        if (PH == kRefine) {
+          const int32_t b = ok ? a.CB[j[u]] : bi;
+          if (b != bi) c[u] = kEmpty;
+        }
       }
     }
 #pragma unroll
@@ -659,6 +664,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
         keyed_put(L.kt, d, -ki, -1);
         keyed_put(L.kt, t, ki, 1);
         a.C[i] = t;
+        if (PH == kRefine && a.CP) a.CP[i].x = t;
         ++nm;
         if (PH == kRefine && a.gid) atomicAdd(&a.mvg[a.gid[i]], 1ull);
       }
