@@ -192,8 +192,10 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   const bool sync_mv = det || opt->sync_moves != 0;
   a.sync_moves = det ? 3 : (opt->sync_moves & 3);
 
-  // grids are capped near the number of resident workgroups (256 CUs x 8)
-  const int grid_cap = 2048;
+  // workgroups of one decision launch per bin (measured best on R-MAT scale
+  // 24: 1024, four per CU; 2048 and 512 are slower) and of one aggregation
+  // launch
+  const int grid_cap = 1024, agg_grid_cap = 4096;
   GraphDesc cur = input;
   int buf = 0;
   double tau = opt->tolerance;
@@ -441,7 +443,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       g.yidx = ws.idx[nb]; g.yw = ws.w[nb]; g.yw_double = det; g.cnt = &ws.sc->cnt[0][0];
       g.ncom = ncom;
       const int hk = tm.begin(kEvAggK);
-      launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], grid_cap, 0, &S->agg_launches);
+      launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], agg_grid_cap, 0, &S->agg_launches);
       if (gp.H > 0) {
         member_degrees(st, cur, ws.cv, nn, ws.apre);
         exclusive_scan(st, ws.apre, nn, ws.scan_tmp);

@@ -598,7 +598,9 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
     if (tables)
       hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a,
                          h, s0, s1);
-    hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kPartThreads), 0,
+    // one workgroup per CU takes the partitions in turn (measured faster on
+    // R-MAT scale 24 than two or more per CU)
+    hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 256)), dim3(kPartThreads), 0,
                        st, g, a, h, s0, s1);
   }
   *launches += tables ? 4 : 3;
