@@ -274,7 +274,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.gp = B.gp; a.dqg = B.dqg; a.dqg128 = B.dqg128; a.mvg = B.mvg;
   const bool sync_mv = det || opt->sync_moves != 0;
   a.sync_moves = det ? 3 : (opt->sync_moves & 3);
-  const int grid_cap = 2048;
+  const int grid_cap = 1024, agg_grid_cap = 4096;  // as for one graph
   int64_t dummy_launches = 0;
   TableState tstate;
 
@@ -502,7 +502,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     g.lab = ws.lab; g.coff = ws.cnt; g.cv = ws.cv; g.yoff = yoff; g.ydeg = ydeg;
     g.yidx = ws.idx[nb]; g.yw = ws.w[nb]; g.yw_double = det; g.cnt = &ws.sc->cnt[0][0];
     g.ncom = ncom_all;
-    launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], grid_cap, 0, &dummy_launches);
+    launch_agg_rows(st, cur, g, ws.list, cb.count[0], cb.start[0], agg_grid_cap, 0, &dummy_launches);
     if (gp.H > 0) {
       // members: the vertices of the continuing graphs
       int64_t nkept = 0;
