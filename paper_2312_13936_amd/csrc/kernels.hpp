@@ -18,13 +18,16 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 // Degree bins (vertex scan) and capacity bins (aggregation rows).  A vertex
 // of degree d (or a community whose member arcs total d) goes to the first
 // bin with d <= kBinMax[b]; d == 0 is never binned.  Bins 0-4 map a group of
-// kBinLanes[b] lanes of one wavefront to each item with an LDS hash table of
-// up to 2^8 slots; bin 5 maps a 256-thread workgroup with an LDS table.
-// Bins 6-8 ("wide" rows, vertex scan only) map 1, 1 or 2 workgroups of 1024
-// threads to a vertex, each with an LDS table of up to kWideSlots slots for
-// one partition of the neighbour communities; aggregation bins skip them
-// (wide = false), so a capacity above kBinMax[5] goes straight to the last
-// bin.  The last bin (hubs / giant communities) uses global-memory tables.
+// lanes of one wavefront to each item with an LDS hash table of up to 2^8
+// slots (kBinLanes[b] lanes in the aggregation; the vertex scan uses 4, 8, 8,
+// 16 and 32, which keeps more short rows in flight); bin 5 maps a 256-thread
+// workgroup with an LDS table.  Bins 6-8 ("wide" rows) map 1, 1 or 2
+// workgroups of 1024 threads to a vertex, each with an LDS table of up to
+// kWideSlots slots for one partition of the neighbour communities; the
+// aggregation uses bins 6-7 (one workgroup per community) and sends
+// capacities above kBinMax[kAggLastBin] to the last bin.  The last bin (hubs
+// and giant communities) is split by key partitions; only vertex hubs of
+// more than kPartMaxDeg arcs use global-memory tables.
 constexpr int kNumBins = 10;
 constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 4096, 8192, 16384, 0x7fffffff};
 constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 1024, 1024, 2048, 256};

@@ -175,13 +175,6 @@ __device__ __forceinline__ bool accept(const ScanArgs& a, int32_t d, int32_t bc,
   return true;
 }
 
-// Largest degree of the bin served by groups of G lanes.
-constexpr int bin_max_for_lanes(int G) {
-  for (int b = 0; b < 5; ++b)
-    if (kBinLanes[b] == G) return kBinMax[b];
-  return G;
-}
-
 // Accumulates the arcs e0, e0 + NT, ... of row i: arcs to the vertex's own
 // community d are summed into the returned K_{i->d} (kept out of the table,
 // whose slot would otherwise take an atomic per intra-community arc), every
@@ -261,17 +254,17 @@ __device__ __forceinline__ void eval_table(int32_t* keys, double* vals, int ts, 
 
 // ------------------------------------------------ group of G lanes per vertex ---
 // Bins 0-4 in one launch: blocks [blk[b], blk[b+1]) serve bin b, each with
-// groups of kBinLanes[b] lanes per vertex.
+// groups of G lanes per vertex (the bin's rows have at most BMAX arcs).
 struct GroupLaunch {
   int32_t count[5];
   int32_t start[5];
   int32_t blk[6];
 };
-constexpr int kGroupSlots = 1024;  // LDS slots of one workgroup: the largest GPB * 2^LG of bins 0-4
+constexpr int kGroupSlots = 2048;  // LDS slots of one workgroup: the largest GPB * 2^LG of bins 0-4
 
 // Body of one workgroup of bin (G, LG): workgroup `bid` of `nb` strides over
 // the bin's vertices; skeys / svals: the workgroup's kGroupSlots LDS slots.
-template <int G, int LG, class WT, int PH, bool DET>
+template <int G, int LG, int BMAX, class WT, int PH, bool DET>
 __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const ScanArgs& a,
                                                   const int32_t* __restrict__ list, int32_t count, int32_t bid,
                                                   int32_t nb, int32_t* skeys, double* svals) {
@@ -299,7 +292,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     // table of next_pow2(2 deg) <= TS slots: at most deg distinct keys
     const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
-    constexpr int UA = (bin_max_for_lanes(G) + G - 1) / G;
+    constexpr int UA = (BMAX + G - 1) / G;
     double kid = scan_row<UA, G, PH>(g, a, i, beg, deg, gl, d, bi,
                                      [&](int32_t c, double w) { lds_insert(keys, vals, lg, c, w); });
     kid = sum_xor<G>(kid);
@@ -351,11 +344,11 @@ __global__ __launch_bounds__(kBlock) void k_decide_groups(GraphView<WT> g, ScanA
   const int32_t bid = (int32_t)blockIdx.x - gl.blk[b], nb = gl.blk[b + 1] - gl.blk[b];
   const int32_t* l = list + gl.start[b];
   switch (b) {
-    case 0: decide_group_body<4, 3, WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
-    case 1: decide_group_body<8, 4, WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
-    case 2: decide_group_body<16, 5, WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
-    case 3: decide_group_body<32, 6, WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
-    default: decide_group_body<64, 8, WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
+    case 0: decide_group_body<4, 3, 4, WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
+    case 1: decide_group_body<8, 4, 8, WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
+    case 2: decide_group_body<8, 5, 16, WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
+    case 3: decide_group_body<16, 6, 32, WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
+    default: decide_group_body<32, 8, 128, WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
   }
 }
 
@@ -802,7 +795,7 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   const GraphView<WT> g = view<WT>(gd);
   {  // bins 0-4: one launch
     GroupLaunch gl;
-    constexpr int kLanes[5] = {4, 8, 16, 32, 64};
+    constexpr int kLanes[5] = {4, 8, 8, 16, 32};  // lanes per vertex of bins 0-4
     gl.blk[0] = 0;
     for (int b = 0; b < 5; ++b) {
       gl.count[b] = count[b];
