@@ -7,8 +7,8 @@
 // degree of c's members (an over-estimate), and ydeg[c] receives the count.
 //
 // Communities are binned by that capacity; small ones map a group of G lanes
-// with an LDS table, large ones a workgroup with an LDS table, giant ones a
-// workgroup with a global-memory table.  Members with fewer than G arcs are
+// with an LDS table, large ones a workgroup with an LDS table; giant ones are
+// split by key partitions (k_hub.hip).  Members with fewer than G arcs are
 // walked one per lane; larger members are walked by all lanes of the group
 // so that their rows stream coalesced.
 #include "device.hpp"
@@ -261,11 +261,11 @@ static void agg_bins(hipStream_t st, const GraphDesc& gd, const AggArgs& a, cons
                        g, a, list + start[B], count[B]);                              \
     ++*launches;                                                                                \
   }
-  GVL_AGG_BIN(0, 4, 3)
-  GVL_AGG_BIN(1, 8, 4)
-  GVL_AGG_BIN(2, 16, 5)
-  GVL_AGG_BIN(3, 32, 6)
-  GVL_AGG_BIN(4, 64, 8)
+  GVL_AGG_BIN(0, kBinLanes[0], 3)
+  GVL_AGG_BIN(1, kBinLanes[1], 4)
+  GVL_AGG_BIN(2, kBinLanes[2], 5)
+  GVL_AGG_BIN(3, kBinLanes[3], 6)
+  GVL_AGG_BIN(4, kBinLanes[4], 8)
 #undef GVL_AGG_BIN
   if (count[5] > 0) {
     hipLaunchKernelGGL((k_agg_rows<WTin, WTout, kBlock, 2048>), dim3(grid_for(count[5], 1, grid_cap)),

@@ -18,10 +18,9 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 // Degree bins (vertex scan) and capacity bins (aggregation rows).  A vertex
 // of degree d (or a community whose member arcs total d) goes to the first
 // bin with d <= kBinMax[b]; d == 0 is never binned.  Bins 0-4 map a group of
-// lanes of one wavefront to each item with an LDS hash table of up to 2^8
-// slots (kBinLanes[b] lanes in the aggregation; the vertex scan uses 4, 8, 8,
-// 16 and 32, which keeps more short rows in flight); bin 5 maps a 256-thread
-// workgroup with an LDS table.  Bins 6-8 ("wide" rows) map 1, 1 or 2
+// kBinLanes[b] lanes of one wavefront to each item with an LDS hash table of
+// up to 2^8 slots (one to four arcs per lane: more rows in flight than one
+// arc per lane); bin 5 maps a 256-thread workgroup with an LDS table.  Bins 6-8 ("wide" rows) map 1, 1 or 2
 // workgroups of 1024 threads to a vertex, each with an LDS table of up to
 // kWideSlots slots for one partition of the neighbour communities; the
 // aggregation uses bins 6-7 (one workgroup per community) and sends
@@ -30,7 +29,7 @@ enum Phase { kMove = 0, kRefine = 1 };  // local-moving (Alg. 2) / refinement (A
 // more than kPartMaxDeg arcs use global-memory tables.
 constexpr int kNumBins = 10;
 constexpr int32_t kBinMax[kNumBins] = {4, 8, 16, 32, 128, 1024, 4096, 8192, 16384, 0x7fffffff};
-constexpr int kBinLanes[kNumBins] = {4, 8, 16, 32, 64, 256, 1024, 1024, 2048, 256};
+constexpr int kBinLanes[kNumBins] = {4, 8, 8, 16, 32, 256, 1024, 1024, 2048, 256};
 constexpr int kWideBin0 = 6;       // first wide bin
 constexpr int kWideClasses = 3;
 // bin kWideBin0 + k uses 2^kWideShift[k] partitions of the key space

@@ -344,11 +344,11 @@ __global__ __launch_bounds__(kBlock) void k_decide_groups(GraphView<WT> g, ScanA
   const int32_t bid = (int32_t)blockIdx.x - gl.blk[b], nb = gl.blk[b + 1] - gl.blk[b];
   const int32_t* l = list + gl.start[b];
   switch (b) {
-    case 0: decide_group_body<4, 3, 4, WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
-    case 1: decide_group_body<8, 4, 8, WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
-    case 2: decide_group_body<8, 5, 16, WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
-    case 3: decide_group_body<16, 6, 32, WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
-    default: decide_group_body<32, 8, 128, WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
+    case 0: decide_group_body<kBinLanes[0], 3, kBinMax[0], WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
+    case 1: decide_group_body<kBinLanes[1], 4, kBinMax[1], WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
+    case 2: decide_group_body<kBinLanes[2], 5, kBinMax[2], WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
+    case 3: decide_group_body<kBinLanes[3], 6, kBinMax[3], WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
+    default: decide_group_body<kBinLanes[4], 8, kBinMax[4], WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
   }
 }
 
@@ -795,12 +795,11 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
   const GraphView<WT> g = view<WT>(gd);
   {  // bins 0-4: one launch
     GroupLaunch gl;
-    constexpr int kLanes[5] = {4, 8, 8, 16, 32};  // lanes per vertex of bins 0-4
     gl.blk[0] = 0;
     for (int b = 0; b < 5; ++b) {
       gl.count[b] = count[b];
       gl.start[b] = start[b];
-      gl.blk[b + 1] = gl.blk[b] + (count[b] > 0 ? grid_for(count[b], kBlock / kLanes[b], grid_cap) : 0);
+      gl.blk[b + 1] = gl.blk[b] + (count[b] > 0 ? grid_for(count[b], kBlock / kBinLanes[b], grid_cap) : 0);
     }
     if (gl.blk[5] > 0) {
       hipLaunchKernelGGL((k_decide_groups<WT, PH, DET>), dim3(gl.blk[5]), dim3(kBlock), 0, st, g, a, list, gl);
