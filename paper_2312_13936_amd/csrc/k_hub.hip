@@ -520,7 +520,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    eval_table<TS / NT, NT, DET>(keys, vals, TS, threadIdx.x, a, ev, acc, bg, bk, bc);
+    eval_table<4, NT, DET>(keys, vals, TS, threadIdx.x, a, ev, acc, bg, bk, bc);  // (fewer registers: two workgroups per CU)
     block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
     if (threadIdx.x == 0) {
       h.pb_g[t] = bg;
@@ -598,9 +598,8 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
     if (tables)
       hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a,
                          h, s0, s1);
-    // one workgroup per CU takes the partitions in turn (measured faster on
-    // R-MAT scale 24 than two or more per CU)
-    hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 256)), dim3(kPartThreads), 0,
+    // two workgroups per CU (their LDS tables fill it) take the partitions in turn
+    hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 512)), dim3(kPartThreads), 0,
                        st, g, a, h, s0, s1);
   }
   *launches += tables ? 4 : 3;
