@@ -205,14 +205,17 @@ __device__ __forceinline__ void stage_chunk_partitions(int32_t* skeys, double* s
 }
 
 // Chunk gather: H_chunk[C[j]] += w over the chunk's arcs (j != i; in
-// refinement only j inside i's bound), merged into the hub's global table.
-template <class WT, int PH>
+// refinement only j inside i's bound), staged by key partition (PART: hubs
+// of up to kPartMaxDeg arcs) or merged into the hub's global table (longer
+// hubs).  Two instances, so the partitioned one keeps the LDS of the
+// table's new-slot list free (three workgroups per CU instead of two).
+template <class WT, int PH, bool PART>
 __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t t0,
                                                        int32_t t1) {
   constexpr int TS = 1 << kHubGatherLg;
   __shared__ int32_t skeys[TS];
   __shared__ double svals[TS];
-  __shared__ int32_t snew[kHubChunk];
+  __shared__ int32_t snew[PART ? kPartMaxP + 1 : kHubChunk];
   __shared__ int s_nnew, s_base;
   __shared__ double s_red[kBlock / kWave];
   __shared__ int s_wsum[kBlock / kWave];
@@ -227,11 +230,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_gather(GraphView<WT> g, ScanArgs
     if (!h.active[p]) continue;  // uniform over the workgroup
     const int32_t i = h.items[p];
     const int32_t beg = g.begin(i), deg = g.degree(i);
+    if (hub_partitioned(deg) != PART) continue;  // uniform: the other instance
     const int32_t e0 = task.y * kHubChunk;
     const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
     const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
     const int32_t d = a.C[i];
-    if (hub_partitioned(deg)) {  // uniform: sum the chunk's candidates, sort them by partition
+    if (PART) {  // sum the chunk's candidates, sort them by partition
       const int P = h.slice_off[p + 1] - h.slice_off[p];
       int32_t* s_cnt = snew;  // [P + 1] counts, then offsets
       for (int k = threadIdx.x; k <= P; k += kBlock) s_cnt[k] = 0;
@@ -591,9 +595,13 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
   const GraphView<WT> g = view<WT>(gd);
   const int hb = grid_items(h1 - h0, kBlock, 1024);
   hipLaunchKernelGGL((k_hub_prep<PH, DET>), dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
-  if (c1 > c0)
-    hipLaunchKernelGGL((k_hub_gather<WT, PH>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g, a, h, c0,
-                       c1);
+  if (c1 > c0) {
+    hipLaunchKernelGGL((k_hub_gather<WT, PH, true>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g, a,
+                       h, c0, c1);
+    if (tables)
+      hipLaunchKernelGGL((k_hub_gather<WT, PH, false>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g,
+                         a, h, c0, c1);
+  }
   if (s1 > s0) {
     if (tables)
       hipLaunchKernelGGL((k_hub_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 2048)), dim3(kBlock), 0, st, g, a,
@@ -602,7 +610,7 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
     hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 512)), dim3(kPartThreads), 0,
                        st, g, a, h, s0, s1);
   }
-  *launches += tables ? 4 : 3;
+  *launches += tables ? 5 : 3;
 }
 
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
