@@ -185,6 +185,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
   a.CP = ws.CP;
+  a.mark_after = INT32_MAX;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
@@ -322,7 +323,10 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         decide_group(grp, kMove);
         if (sync_mv) {
           tm.end(hk);
+          a.groups = bins.S;
+          a.mark_after = (it == 0) ? grp : INT32_MAX;
           commit_group(grp, kMove);
+          a.mark_after = INT32_MAX;
         }
       }
       if (!sync_mv) tm.end(hk);

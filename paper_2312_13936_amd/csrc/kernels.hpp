@@ -80,6 +80,11 @@ struct GraphParam {
 struct ScanArgs {
   int32_t* C;               // community of each vertex (C')
   const int32_t* CB;        // community bound (C'_B), refinement only
+  // synchronous local-moving commits: in the first sweep of a pass every
+  // vertex of a later sub-sweep group (of `groups`) is still unprocessed
+  // (flag 1), so the commit of group mark_after skips marking those;
+  // mark_after = INT32_MAX marks every neighbour
+  int32_t mark_after, groups;
   int2* CP;                 // refinement: (C'[j], C'_B[j]) side by side, so one load per arc serves the
                             // bound test (the commit keeps .x equal to C')
   double* Sig;              // total weight of each community (Sigma')

@@ -162,6 +162,11 @@ __device__ __forceinline__ void block_argmax(double& bg, i128& bk, int32_t& bc, 
   }
 }
 
+// Whether a synchronous commit must mark neighbour j (see mark_after).
+__device__ __forceinline__ bool mark_needed(const ScanArgs& a, int32_t j) {
+  return a.mark_after == INT32_MAX || group_of(j, a.groups) <= a.mark_after;
+}
+
 // After the argmax: apply the min-label rule and the sign test.
 template <int PH, bool DET>
 __device__ __forceinline__ bool accept(const ScanArgs& a, int32_t d, int32_t bc, double bg, i128 bk) {
@@ -691,7 +696,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
           if (L.off[mid] <= q) lo = mid; else hi = mid;
         }
         const int32_t j = g.idx[(int64_t)L.beg[lo] + (q - L.off[lo])];
-        if (j != L.vi[lo]) a.flag[j] = 1;
+        if (j != L.vi[lo] && mark_needed(a, j)) a.flag[j] = 1;
       }
       __syncthreads();  // L.* are rewritten by the next entries
     }
@@ -728,7 +733,7 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
       const int32_t beg = g.begin(i), deg = g.degree(i);
       for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
         const int32_t j = g.idx[beg + e];
-        if (j != i) a.flag[j] = 1;
+        if (j != i && mark_needed(a, j)) a.flag[j] = 1;
       }
     }
     __syncthreads();
@@ -766,7 +771,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
       const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
       for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
         const int32_t j = g.idx[beg + e];
-        if (j != i) a.flag[j] = 1;
+        if (j != i && mark_needed(a, j)) a.flag[j] = 1;
       }
     }
   }
