@@ -268,6 +268,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
   a.CP = ws.CP;
   a.mark_after = INT32_MAX;
+  a.ident_after = -1;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;

@@ -186,6 +186,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
   a.CP = ws.CP;
   a.mark_after = INT32_MAX;
+  a.ident_after = -1;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
@@ -318,12 +319,14 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     for (int32_t it = 0; it < opt->max_iterations; ++it) {
       fill_u64(st, (unsigned long long*)ws.sc->dq, 0ull, 3 * kCntSlots);
       int hk = sync_mv ? -1 : tm.begin(kEvScanMoveK);
+      a.groups = bins.S;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         if (sync_mv) hk = tm.begin(kEvScanMoveK);
+        a.ident_after = (pass == 0 && it == 0) ? grp : -1;
         decide_group(grp, kMove);
+        a.ident_after = -1;
         if (sync_mv) {
           tm.end(hk);
-          a.groups = bins.S;
           a.mark_after = (it == 0) ? grp : INT32_MAX;
           commit_group(grp, kMove);
           a.mark_after = INT32_MAX;

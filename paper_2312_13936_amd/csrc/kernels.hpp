@@ -85,6 +85,10 @@ struct ScanArgs {
   // (flag 1), so the commit of group mark_after skips marking those;
   // mark_after = INT32_MAX marks every neighbour
   int32_t mark_after, groups;
+  // pass 0, first local-moving sweep, decisions of group ident_after: a
+  // vertex of a later sub-sweep group has not moved yet, so C'[j] = j needs
+  // no load; -1 = off
+  int32_t ident_after;
   int2* CP;                 // refinement: (C'[j], C'_B[j]) side by side, so one load per arc serves the
                             // bound test (the commit keeps .x equal to C')
   double* Sig;              // total weight of each community (Sigma')

@@ -205,6 +205,8 @@ __device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArg
       if (PH == kRefine && a.CP) {
         const int2 cb = ok ? a.CP[j[u]] : make_int2(kEmpty, bi);
         c[u] = (cb.y == bi) ? cb.x : kEmpty;
+      } else if (PH == kMove && a.ident_after >= 0 && ok && group_of(j[u], a.groups) > a.ident_after) {
+        c[u] = j[u];
       } else {
         c[u] = ok ? a.C[j[u]] : kEmpty;
         if (PH == kRefine) {
