@@ -382,23 +382,67 @@ void lookup_raw(hipStream_t st, int32_t* top, int64_t N, const int32_t* C, bool 
 // countCommunityVertices and communityTotalDegree of Alg. 4 in one pass;
 // each vertex also keeps its slot inside its community's member list.
 template <class WT>
-__global__ void k_agg_count(GraphView<WT> g, const int32_t* C, const int32_t* newid, int32_t* lab,
-                            int32_t* rank, int32_t* cnt, int32_t* cap, const int32_t* gid, const uint8_t* keep) {
-  GRID_STRIDE(i, g.n) {
-    if (gid && !keep[gid[i]]) { lab[i] = -1; continue; }
-    const int32_t c = newid[C[i]];
-    lab[i] = c;
-    rank[i] = atomicAdd(&cnt[c], 1);
-    const int32_t d = g.degree(i);
-    if (d) atomicAdd(&cap[c], d);
+__global__ __launch_bounds__(kBlock) void k_agg_count(GraphView<WT> g, const int32_t* C, const int32_t* newid,
+                                                      int32_t* lab, int32_t* rank, int32_t* cnt, int32_t* cap,
+                                                      const int32_t* gid, const uint8_t* keep) {
+  // The workgroup's vertices are first counted per community in LDS (local
+  // rank, members, arcs), then each community present reserves its block of
+  // member slots with one global atomic: a community of a million members
+  // costs one atomic per workgroup, not one per member on one address.
+  constexpr int TS = 2 * kBlock;
+  constexpr uint32_t mask = TS - 1;
+  __shared__ int32_t skey[TS];
+  __shared__ int32_t scnt[TS];
+  __shared__ int32_t scap[TS];
+  for (int s = threadIdx.x; s < TS; s += kBlock) { skey[s] = kEmpty; scnt[s] = 0; scap[s] = 0; }
+  __syncthreads();
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < g.n; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t i = base + threadIdx.x;
+    int32_t c = -1, lr = 0;
+    uint32_t h = 0;
+    if (i < g.n) {
+      if (gid && !keep[gid[i]]) {
+        lab[i] = -1;
+      } else {
+        c = newid[C[i]];
+        lab[i] = c;
+        h = hslot(c, __builtin_ctz(TS));
+        while (true) {
+          const int32_t k = skey[h];
+          if (k == c) break;
+          if (k == kEmpty) {
+            const int32_t old = atomicCAS(&skey[h], kEmpty, c);
+            if (old == kEmpty || old == c) break;
+          }
+          h = (h + 1u) & mask;
+        }
+        lr = atomicAdd(&scnt[h], 1);
+        const int32_t d = g.degree(i);
+        if (d) atomicAdd(&scap[h], d);
+      }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < TS; s += kBlock) {
+      const int32_t k = skey[s];
+      if (k != kEmpty) {
+        const int32_t n = scnt[s];
+        scnt[s] = atomicAdd(&cnt[k], n);  // the block's first slot
+        if (scap[s]) atomicAdd(&cap[k], scap[s]);
+      }
+    }
+    __syncthreads();
+    if (c >= 0) rank[i] = scnt[h] + lr;
+    __syncthreads();
+    for (int s = threadIdx.x; s < TS; s += kBlock) { skey[s] = kEmpty; scnt[s] = 0; scap[s] = 0; }
+    __syncthreads();
   }
 }
 void agg_count(hipStream_t st, const GraphDesc& gd, const int32_t* C, const int32_t* newid, int32_t* lab,
                int32_t* rank, int32_t* cnt, int32_t* cap, const int32_t* gid, const uint8_t* keep) {
   if (gd.n <= 0) return;
   GraphView<float> g{gd.n, gd.off, gd.deg, gd.idx, nullptr};
-  hipLaunchKernelGGL(k_agg_count<float>, dim3(grid_n(gd.n)), dim3(kBlock), 0, st, g, C, newid, lab, rank,
-                     cnt, cap, gid, keep);
+  hipLaunchKernelGGL(k_agg_count<float>, dim3(grid_n(gd.n, kBlock, 4096)), dim3(kBlock), 0, st, g, C, newid, lab,
+                     rank, cnt, cap, gid, keep);
 }
 
 __global__ void k_agg_fill(const int32_t* lab, const int32_t* rank, const int32_t* coff, int64_t n,
