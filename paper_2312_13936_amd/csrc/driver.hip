@@ -276,13 +276,13 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
 
     // Decisions of one group: short rows by the binned kernels, hubs by the
     // chunked path (batch by batch through the table region).
-    auto decide_group = [&](int grp, int phase) {
+    // (bx, lx: the short-row bins and their list, thinned during refinement;
+    // the hubs always come from bins and ws.list)
+    auto decide_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       if (phase == kMove)
-        launch_decide_move(st, cur, a, ws.list, bins.count[grp], bins.start[grp], det, grid_cap, 0,
-                           &S->scan_launches);
+        launch_decide_move(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
       else
-        launch_decide_refine(st, cur, a, ws.list, bins.count[grp], bins.start[grp], det, grid_cap, 0,
-                             &S->scan_launches);
+        launch_decide_refine(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
       for (const HubBatch& hb : plan.groups[grp]) {
         tstate.ensure(st, ws, hb.tend - hb.tbase);
         hargs.tbase = hb.tbase;
@@ -290,12 +290,12 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
                    &S->scan_launches);
       }
     };
-    auto commit_group = [&](int grp, int phase) {
+    auto commit_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       CommitLaunch cl;
       memset(&cl, 0, sizeof(cl));
-      const int32_t n0 = bins.gend[grp] - bins.gstart[grp];  // bins 0 .. kHubBin-1 of the group
-      const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];  // rows of at most kBinMax[4] arcs
-      cl.l0 = ws.list + bins.gstart[grp];
+      const int32_t n0 = bx.gend[grp] - bx.gstart[grp];  // bins 0 .. kHubBin-1 of the group
+      const int32_t n0s = bx.start[grp][5] - bx.gstart[grp];  // rows of at most kBinMax[4] arcs
+      cl.l0 = lx + bx.gstart[grp];
       cl.l2 = ws.list + bins.start[grp][kHubBin];
       cl.n2 = bins.count[grp][kHubBin];
       if (phase == kMove) {
@@ -323,12 +323,12 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         if (sync_mv) hk = tm.begin(kEvScanMoveK);
         a.ident_after = (pass == 0 && it == 0) ? grp : -1;
-        decide_group(grp, kMove);
+        decide_group(grp, kMove, bins, ws.list);
         a.ident_after = -1;
         if (sync_mv) {
           tm.end(hk);
           a.mark_after = (it == 0) ? grp : INT32_MAX;
-          commit_group(grp, kMove);
+          commit_group(grp, kMove, bins, ws.list);
           a.mark_after = INT32_MAX;
         }
       }
@@ -369,15 +369,18 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       fill_i32(st, ws.targeted, 0, nn);
       pack_labels(st, ws.C, ws.CB, ws.CP, nn);
     }
+    BinInfo rbins;  // after the first sweep: the short-row bins thinned to lone vertices
+    const BinInfo* rb = &bins;
+    const int32_t* rl = ws.list;
     for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
       a.rnd = opt->refine_random;
       a.sweep = sw;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         a.stamp = sw * bins.S + grp + 1;
         const int hk = tm.begin(kEvScanRefineK);
-        decide_group(grp, kRefine);
+        decide_group(grp, kRefine, *rb, rl);
         tm.end(hk);
-        commit_group(grp, kRefine);
+        commit_group(grp, kRefine, *rb, rl);
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
@@ -387,6 +390,12 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       pd.refine_movers.push_back((int64_t)mv);
       refine_moved += (int64_t)mv;
       if (mv == 0) break;
+      if (sw == 0 && sw + 1 < opt->refine_sweeps) {
+        s = thin_refine_bins(ctx, ws, bins, rbins);
+        if (s != GVL_OK) return s;
+        rb = &rbins;
+        rl = ws.list2;
+      }
     }
     tm.end(h);
     // ---- 4. count communities; stop on convergence or low shrink

@@ -45,6 +45,7 @@ struct Workspace {
   uint8_t* flag;
   int32_t* targeted;
   int2* CP;
+  int32_t* list2;  // refinement: the thinned short-row bins
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
   TblSlot* tbl;
@@ -106,6 +107,7 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.flag = (uint8_t*)take(N);
   w.targeted = (int32_t*)take(4 * N);
   w.CP = (int2*)take(8 * N);
+  w.list2 = (int32_t*)take(4 * N);
   for (int b = 0; b < 2; ++b) {
     w.off[b] = (int32_t*)take(4 * (N + 1));
     w.deg[b] = (int32_t*)take(4 * N);
@@ -277,6 +279,42 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
   HIP_TRY(hipMemcpyAsync(ws.bb->cursors, ctx->hbins->cursors, sizeof(int32_t) * S * kNumBins,
                          hipMemcpyHostToDevice, st));
   bin_scatter(st, off, deg, n, S, wide, gid, vbase, ws.bb, ws.list);
+  return GVL_OK;
+}
+
+// Refinement (Alg. 3) after a sweep: the short-row bins of `bins` (in
+// ws.list) reduced to their vertices still alone in their refined community,
+// in ws.list2 with the same group-major layout; `rb` describes them (its hub
+// bins are those of `bins`, still in ws.list).
+gvl_status thin_refine_bins(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, BinInfo& rb) {
+  hipStream_t st = ctx->stream;
+  BinBuf* hb = ctx->hbins;
+  memset(hb, 0, sizeof(BinBuf));
+  for (int g = 0; g < bins.S; ++g)
+    for (int b = 0; b < kHubBin; ++b) {
+      hb->cursors[g * kNumBins + b] = bins.start[g][b];
+      hb->counts[g * kNumBins + b] = bins.count[g][b];
+    }
+  HIP_TRY(hipMemcpyAsync(ws.bb, hb, sizeof(BinBuf), hipMemcpyHostToDevice, st));
+  thin_count(st, ws.list, ws.bb, bins.S, ws.C, ws.size, ws.K);
+  HIP_TRY(hipMemcpyAsync(hb->kept, ws.bb->kept, sizeof(hb->kept), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  rb = bins;
+  int32_t acc = 0;
+  for (int g = 0; g < bins.S; ++g) {
+    rb.gstart[g] = acc;
+    for (int b = 0; b < kHubBin; ++b) {
+      const int s = g * kNumBins + b;
+      rb.count[g][b] = hb->kept[s];
+      rb.start[g][b] = acc;
+      hb->nstart[s] = acc;
+      acc += hb->kept[s];
+    }
+    rb.gend[g] = acc;
+  }
+  rb.gstart[bins.S] = acc;
+  HIP_TRY(hipMemcpyAsync(ws.bb->nstart, hb->nstart, sizeof(hb->nstart), hipMemcpyHostToDevice, st));
+  thin_scatter(st, ws.list, ws.bb, bins.S, ws.C, ws.size, ws.K, ws.list2);
   return GVL_OK;
 }
 

@@ -54,6 +54,63 @@ __global__ void k_pack_labels(const int32_t* C, const int32_t* CB, int2* CP, int
 void pack_labels(hipStream_t st, const int32_t* C, const int32_t* CB, int2* CP, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_pack_labels, dim3(grid_n(n)), dim3(kBlock), 0, st, C, CB, CP, n);
 }
+// ------------------------------------------------- refinement thinning ---
+// Alg. 3 moves only vertices alone in their refined community, and a
+// refined community never drops back to one member (only lone vertices
+// leave theirs), so a vertex that has company stays out for the rest of the
+// refinement.
+__device__ __forceinline__ bool still_alone(const int32_t* C, const int32_t* size, const double* K, int32_t i) {
+  return size[C[i]] == 1 && K[i] > 0.0;
+}
+constexpr int kThinTiles = 64;  // workgroups per segment
+__global__ __launch_bounds__(kBlock) void k_thin_count(const int32_t* list, BinBuf* bb, const int32_t* C,
+                                                       const int32_t* size, const double* K) {
+  const int s = (int)(blockIdx.y / kHubBin) * kNumBins + (int)(blockIdx.y % kHubBin);
+  const int32_t beg = bb->cursors[s], cnt = bb->counts[s];
+  int32_t mine = 0;
+  for (int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x); k < cnt; k += kThinTiles * kBlock)
+    mine += still_alone(C, size, K, list[beg + k]) ? 1 : 0;
+  __shared__ int32_t red[kBlock / kWave];
+  const int32_t tot = block_sum<int32_t>(mine, red);
+  if (threadIdx.x == 0 && tot) atomicAdd(&bb->kept[s], tot);
+}
+__global__ __launch_bounds__(kBlock) void k_thin_scatter(const int32_t* list, BinBuf* bb, const int32_t* C,
+                                                         const int32_t* size, const double* K, int32_t* out) {
+  const int s = (int)(blockIdx.y / kHubBin) * kNumBins + (int)(blockIdx.y % kHubBin);
+  const int32_t beg = bb->cursors[s], cnt = bb->counts[s], dst = bb->nstart[s], lim = bb->kept[s];
+  __shared__ int32_t s_w[kBlock / kWave];
+  __shared__ int32_t s_base;
+  for (int32_t k0 = (int32_t)(blockIdx.x * kBlock); k0 < cnt; k0 += kThinTiles * kBlock) {  // uniform
+    const int32_t k = k0 + (int32_t)threadIdx.x;
+    const int32_t i = (k < cnt) ? list[beg + k] : -1;
+    const bool keep = i >= 0 && still_alone(C, size, K, i);
+    const u64 bal = __ballot(keep);
+    const int wv = threadIdx.x / kWave;
+    const int lr = __popcll(bal & ((1ull << lane_id()) - 1ull));
+    if (lane_id() == 0) s_w[wv] = __popcll(bal);
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) {
+      if (q < wv) before += s_w[q];
+      total += s_w[q];
+    }
+    if (threadIdx.x == 0) s_base = total ? atomicAdd(&bb->ncur[s], total) : 0;
+    __syncthreads();
+    const int32_t q = s_base + before + lr;
+    if (keep && q < lim) out[dst + q] = i;  // (the count pass saw the same state: q < lim always)
+    __syncthreads();  // s_w / s_base are rewritten by the next tile
+  }
+}
+void thin_count(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
+                const double* K) {
+  hipLaunchKernelGGL(k_thin_count, dim3(kThinTiles, S * kHubBin), dim3(kBlock), 0, st, list, bb, C, size, K);
+}
+void thin_scatter(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
+                  const double* K, int32_t* out) {
+  hipLaunchKernelGGL(k_thin_scatter, dim3(kThinTiles, S * kHubBin), dim3(kBlock), 0, st, list, bb, C, size, K,
+                     out);
+}
+
 void copy_f64(hipStream_t st, double* d, const double* s, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_copy<double>, dim3(grid_n(n)), dim3(kBlock), 0, st, d, s, n);
 }

@@ -66,6 +66,10 @@ struct BinBuf {
   int32_t maxsize[kNumBins];
   int32_t cursors[kMaxGroups * kNumBins];
   int32_t pad;
+  // refinement thinning: kept items, their new bin starts, placement cursors
+  int32_t kept[kMaxGroups * kNumBins];
+  int32_t nstart[kMaxGroups * kNumBins];
+  int32_t ncur[kMaxGroups * kNumBins];
 };
 
 // Per-graph constants of a fused batch (several graphs in one union graph).
@@ -333,6 +337,13 @@ void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64
 void iota_i32(hipStream_t st, int32_t* p, int64_t n);
 void copy_i32(hipStream_t st, int32_t* dst, const int32_t* src, int64_t n);
 void pack_labels(hipStream_t st, const int32_t* C, const int32_t* CB, int2* CP, int64_t n);
+// Refinement: the items of the non-hub bins (segment s = g * kNumBins + b,
+// b < kHubBin: list[cursors[s] .. + counts[s])) still alone in their refined
+// community, counted into bb->kept, then placed from bb->nstart into out.
+void thin_count(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
+                const double* K);
+void thin_scatter(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
+                  const double* K, int32_t* out);
 void copy_f64(hipStream_t st, double* dst, const double* src, int64_t n);
 void set_size_one(hipStream_t st, int32_t* size, int64_t n);
 
