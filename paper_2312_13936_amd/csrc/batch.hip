@@ -325,13 +325,13 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     fill_u8(st, ws.flag, 1, nn);
     fill_i32(st, ws.target, -1, nn);
 
-    auto decide_group = [&](int grp, int phase) {
+    // (bx, lx: the short-row bins and their list, thinned during refinement;
+    // the hubs always come from bins and ws.list)
+    auto decide_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       if (phase == kMove)
-        launch_decide_move(st, cur, a, ws.list, bins.count[grp], bins.start[grp], det, grid_cap, 0,
-                           &dummy_launches);
+        launch_decide_move(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
       else
-        launch_decide_refine(st, cur, a, ws.list, bins.count[grp], bins.start[grp], det, grid_cap, 0,
-                             &dummy_launches);
+        launch_decide_refine(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
       for (const HubBatch& hb : plan.groups[grp]) {
         tstate.ensure(st, ws, hb.tend - hb.tbase);
         hargs.tbase = hb.tbase;
@@ -339,12 +339,12 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
                    &dummy_launches);
       }
     };
-    auto commit_group = [&](int grp, int phase) {
+    auto commit_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       CommitLaunch cl;
       memset(&cl, 0, sizeof(cl));
-      const int32_t n0 = bins.gend[grp] - bins.gstart[grp];  // bins 0 .. kHubBin-1 of the group
-      const int32_t n0s = bins.start[grp][5] - bins.gstart[grp];  // rows of at most kBinMax[4] arcs
-      cl.l0 = ws.list + bins.gstart[grp];
+      const int32_t n0 = bx.gend[grp] - bx.gstart[grp];  // bins 0 .. kHubBin-1 of the group
+      const int32_t n0s = bx.start[grp][5] - bx.gstart[grp];  // rows of at most kBinMax[4] arcs
+      cl.l0 = lx + bx.gstart[grp];
       cl.l2 = ws.list + bins.start[grp][kHubBin];
       cl.n2 = bins.count[grp][kHubBin];
       if (phase == kMove) {
@@ -367,8 +367,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       if (det) fill_u64(st, B.dqg128, 0ull, 2 * (int64_t)K);
       else fill_f64(st, B.dqg, 0.0, K);
       for (int32_t grp = 0; grp < bins.S; ++grp) {
-        decide_group(grp, kMove);
-        if (sync_mv) commit_group(grp, kMove);
+        decide_group(grp, kMove, bins, ws.list);
+        if (sync_mv) commit_group(grp, kMove, bins, ws.list);
       }
       bool any = false, stopped = false;
       if (det) {
@@ -411,19 +411,28 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     s = readback(ctx, ws.sc);
     if (s != GVL_OK) return s;
     moves_before = counter(ctx->host, 3);
+    BinInfo rbins;  // after the first sweep: the short-row bins thinned to lone vertices
+    const BinInfo* rb = &bins;
+    const int32_t* rl = ws.list;
     for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
       a.rnd = opt->refine_random;
       a.sweep = sw;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         a.stamp = sw * bins.S + grp + 1;
-        decide_group(grp, kRefine);
-        commit_group(grp, kRefine);
+        decide_group(grp, kRefine, *rb, rl);
+        commit_group(grp, kRefine, *rb, rl);
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
       const unsigned long long mv = counter(ctx->host, 3) - moves_before;
       moves_before = counter(ctx->host, 3);
       if (mv == 0) break;
+      if (sw == 0 && sw + 1 < opt->refine_sweeps) {
+        s = thin_refine_bins(ctx, ws, bins, rbins);
+        if (s != GVL_OK) return s;
+        rb = &rbins;
+        rl = ws.list2;
+      }
     }
     std::vector<unsigned long long> hmv;
     if ((s = download(st, hmv, B.mvg, K)) != GVL_OK) return s;
