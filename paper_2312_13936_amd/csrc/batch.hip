@@ -332,12 +332,13 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
         launch_decide_move(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
       else
         launch_decide_refine(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
-      for (const HubBatch& hb : plan.groups[grp]) {
-        tstate.ensure(st, ws, hb.tend - hb.tbase);
-        hargs.tbase = hb.tbase;
-        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
-                   &dummy_launches);
-      }
+      if (bx.count[grp][kHubBin] > 0)  // (thinned refinement: no lone hub left in the group)
+        for (const HubBatch& hb : plan.groups[grp]) {
+          tstate.ensure(st, ws, hb.tend - hb.tbase);
+          hargs.tbase = hb.tbase;
+          hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
+                     &dummy_launches);
+        }
     };
     auto commit_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       CommitLaunch cl;
@@ -346,7 +347,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       const int32_t n0s = bx.start[grp][5] - bx.gstart[grp];  // rows of at most kBinMax[4] arcs
       cl.l0 = lx + bx.gstart[grp];
       cl.l2 = ws.list + bins.start[grp][kHubBin];
-      cl.n2 = bins.count[grp][kHubBin];
+      cl.n2 = bx.count[grp][kHubBin] > 0 ? bins.count[grp][kHubBin] : 0;
       if (phase == kMove) {
         cl.n0 = n0s;
         cl.l1 = cl.l0 + n0s;

@@ -283,12 +283,13 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         launch_decide_move(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
       else
         launch_decide_refine(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
-      for (const HubBatch& hb : plan.groups[grp]) {
-        tstate.ensure(st, ws, hb.tend - hb.tbase);
-        hargs.tbase = hb.tbase;
-        hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
-                   &S->scan_launches);
-      }
+      if (bx.count[grp][kHubBin] > 0)  // (thinned refinement: no lone hub left in the group)
+        for (const HubBatch& hb : plan.groups[grp]) {
+          tstate.ensure(st, ws, hb.tend - hb.tbase);
+          hargs.tbase = hb.tbase;
+          hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
+                     &S->scan_launches);
+        }
     };
     auto commit_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       CommitLaunch cl;
@@ -297,7 +298,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       const int32_t n0s = bx.start[grp][5] - bx.gstart[grp];  // rows of at most kBinMax[4] arcs
       cl.l0 = lx + bx.gstart[grp];
       cl.l2 = ws.list + bins.start[grp][kHubBin];
-      cl.n2 = bins.count[grp][kHubBin];
+      cl.n2 = bx.count[grp][kHubBin] > 0 ? bins.count[grp][kHubBin] : 0;
       if (phase == kMove) {
         cl.n0 = n0s;
         cl.l1 = cl.l0 + n0s;

@@ -285,13 +285,13 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
 // Refinement (Alg. 3) after a sweep: the short-row bins of `bins` (in
 // ws.list) reduced to their vertices still alone in their refined community,
 // in ws.list2 with the same group-major layout; `rb` describes them (its hub
-// bins are those of `bins`, still in ws.list).
+// counts are the lone hubs, which stay where `bins` has them, in ws.list).
 gvl_status thin_refine_bins(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, BinInfo& rb) {
   hipStream_t st = ctx->stream;
   BinBuf* hb = ctx->hbins;
   memset(hb, 0, sizeof(BinBuf));
   for (int g = 0; g < bins.S; ++g)
-    for (int b = 0; b < kHubBin; ++b) {
+    for (int b = 0; b < kNumBins; ++b) {
       hb->cursors[g * kNumBins + b] = bins.start[g][b];
       hb->counts[g * kNumBins + b] = bins.count[g][b];
     }
@@ -311,6 +311,7 @@ gvl_status thin_refine_bins(gvl_ctx* ctx, Workspace& ws, const BinInfo& bins, Bi
       acc += hb->kept[s];
     }
     rb.gend[g] = acc;
+    rb.count[g][kHubBin] = hb->kept[g * kNumBins + kHubBin];  // lone hubs (they stay in ws.list)
   }
   rb.gstart[bins.S] = acc;
   HIP_TRY(hipMemcpyAsync(ws.bb->nstart, hb->nstart, sizeof(hb->nstart), hipMemcpyHostToDevice, st));

@@ -65,7 +65,7 @@ __device__ __forceinline__ bool still_alone(const int32_t* C, const int32_t* siz
 constexpr int kThinTiles = 64;  // workgroups per segment
 __global__ __launch_bounds__(kBlock) void k_thin_count(const int32_t* list, BinBuf* bb, const int32_t* C,
                                                        const int32_t* size, const double* K) {
-  const int s = (int)(blockIdx.y / kHubBin) * kNumBins + (int)(blockIdx.y % kHubBin);
+  const int s = (int)blockIdx.y;  // every bin, hubs included (they are counted, not moved)
   const int32_t beg = bb->cursors[s], cnt = bb->counts[s];
   int32_t mine = 0;
   for (int32_t k = (int32_t)(blockIdx.x * kBlock + threadIdx.x); k < cnt; k += kThinTiles * kBlock)
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_thin_scatter(const int32_t* list, Bi
 }
 void thin_count(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
                 const double* K) {
-  hipLaunchKernelGGL(k_thin_count, dim3(kThinTiles, S * kHubBin), dim3(kBlock), 0, st, list, bb, C, size, K);
+  hipLaunchKernelGGL(k_thin_count, dim3(kThinTiles, S * kNumBins), dim3(kBlock), 0, st, list, bb, C, size, K);
 }
 void thin_scatter(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
                   const double* K, int32_t* out) {

@@ -337,9 +337,10 @@ void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64
 void iota_i32(hipStream_t st, int32_t* p, int64_t n);
 void copy_i32(hipStream_t st, int32_t* dst, const int32_t* src, int64_t n);
 void pack_labels(hipStream_t st, const int32_t* C, const int32_t* CB, int2* CP, int64_t n);
-// Refinement: the items of the non-hub bins (segment s = g * kNumBins + b,
-// b < kHubBin: list[cursors[s] .. + counts[s])) still alone in their refined
-// community, counted into bb->kept, then placed from bb->nstart into out.
+// Refinement: the items of the bins (segment s = g * kNumBins + b:
+// list[cursors[s] .. + counts[s])) still alone in their refined community,
+// counted into bb->kept; those of the non-hub bins are then placed from
+// bb->nstart into out.
 void thin_count(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
                 const double* K);
 void thin_scatter(hipStream_t st, const int32_t* list, BinBuf* bb, int S, const int32_t* C, const int32_t* size,
