@@ -3,13 +3,15 @@
 // hundreds of thousands of arcs, and a single workgroup per hub would leave
 // the GPU idle behind them.
 //
-// Every hub's arcs are cut into chunks of kHubChunk.  One workgroup per chunk
-// pre-aggregates the chunk in an LDS table and merges the distinct
-// (community, weight) pairs into the hub's global table with atomics.  The
-// table is then read back in slices by several workgroups: for the scan each
-// slice computes its best candidate (Eq. 2) and the last slice to finish
-// reduces the partial bests and applies the decision; for the aggregation
-// each slice appends its entries to the super-vertex row.
+// Every item's arcs are cut into chunks of kHubChunk, and one workgroup per
+// chunk pre-aggregates the chunk in an LDS table.  Vertex hubs of up to
+// kPartMaxDeg arcs and every giant community are split by key partitions:
+// the chunk's distinct (community, weight) pairs are sorted by partition and
+// staged at the chunk's arc positions, and one workgroup per partition sums
+// its runs in LDS, then (scan) computes its best candidate (Eq. 2), the last
+// partition to finish reducing the partial bests and applying the decision,
+// or (aggregation) appends its entries to the super-vertex row.  Longer
+// vertex hubs merge the chunks into a global table read back in slices.
 #include "scan_kernels.hpp"
 
 namespace gvl {

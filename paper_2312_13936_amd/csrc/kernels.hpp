@@ -138,19 +138,19 @@ struct ScanArgs {
 };
 
 // Hub path (vertices with more than kBinMax[kHubBin - 1] arcs, communities
-// with more than kBinMax[5] member arcs).  Their
-// arcs are cut into chunks of kHubChunk; each chunk is pre-aggregated in an
-// LDS table by one workgroup and merged into the item's global table (Alg. 2
-// scanCommunities / Alg. 4 row accumulation), which is then read back in
-// slices of kHubSlice slots by several workgroups.  Global tables hold
+// with more than kBinMax[kAggLastBin] member arcs).  Their arcs are cut into
+// chunks of kHubChunk, each pre-aggregated in an LDS table by one workgroup.
+// Vertex hubs of more than kPartMaxDeg arcs merge the chunks into the
+// hub's global table (Alg. 2 scanCommunities), read back in slices of
+// kHubSlice slots by several workgroups; global tables hold
 // max(1024, next_pow2(2 min(arcs, |V'|))) slots, allocated in units of 1024.
 constexpr int kHubChunk = 2048;
 constexpr int kHubGatherLg = 12;      // LDS pre-aggregation table: 4096 slots
 constexpr int kHubSlice = 8192;
 constexpr int kTblUnit = 1024;
-// Vertex hubs of up to kPartMaxDeg arcs are scanned partitioned instead,
-// with P = next_pow2(ceil(deg / kPartKeys)) partitions of the neighbour
-// communities (wide_part mod P).  The chunk pass sums each chunk's
+// Vertex hubs of up to kPartMaxDeg arcs, and giant communities of any size
+// (Alg. 4 rows, agg_parts), are split instead into P = next_pow2(ceil(deg /
+// kPartKeys)) partitions of the neighbour communities (wide_part mod P).  The chunk pass sums each chunk's
 // candidates (community, weight) in an LDS table, sorts the distinct ones by
 // partition and stores them at the chunk's own arc positions in lbuf / wbuf,
 // with the chunk's partition
