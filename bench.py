@@ -409,8 +409,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(graphs would shard by vertex ranges; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (independent graphs "
+              "would go to different GPUs, one large graph would shard by vertex ranges)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
