@@ -52,7 +52,8 @@ typedef struct gvl_ctx* gvl_ctx_t;
  * tolerance 0.01, tolerance drop 10, aggregation tolerance 0.8, at most 20
  * iterations per local-moving phase; passes are capped at 20. */
 typedef struct {
-  int32_t mode;                  /* GVL_MODE_FAST: asynchronous local-moving (Sec. 4.1);
+  int32_t mode;                  /* GVL_MODE_FAST: FP64 gains, FP32 super-vertex weights (Sec. 5.1.2),
+                                    local-moving schedule chosen by sync_moves;
                                     GVL_MODE_DET: synchronous moves, exact integer gains,
                                     lowest-id ties -- bit-reproducible */
   double tolerance;              /* initial per-iteration tolerance tau (Alg. 2 convergence) */
