@@ -290,3 +290,22 @@ def test_invalid_inputs(eng):
     # the engine still works after the errors
     mem2, q, _ = run(eng, g, gvl.GVL_MODE_DET)
     assert q == oracle.leiden(g, mode=oracle.DET_SYNC).q
+
+
+# The medium and heavy variants of Sec. 4.1: no threshold scaling, and
+# additionally no aggregation tolerance.
+VARIANTS = {"medium": dict(tolerance_drop=1.0), "heavy": dict(tolerance_drop=1.0, aggregation_tolerance=1.0)}
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("name", ["ring10xK5", "planted-small", "grid64-w100", "rmat-s12"])
+def test_medium_heavy_variants_det_bit_exact(eng, name, variant):
+    g = graph(name)
+    kw = VARIANTS[variant]
+    print("det parity, %s variant:" % variant, name, g.n, g.m, flush=True)
+    mem, q, st = run(eng, g, gvl.GVL_MODE_DET, **kw)
+    o = oracle.leiden(g, mode=oracle.DET_SYNC, **kw)
+    assert st.passes == len(o.passes)
+    assert np.array_equal(mem, o.membership)
+    assert q == o.q
+    assert st.termination == o.termination
