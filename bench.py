@@ -27,7 +27,7 @@ METRIC = "Leiden edges/s at matched modularity; batched graphs/s vs plain; p99 l
 # mode), valid while the kernel sources are unchanged
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "leiden_rmat_s24_fast_counters.md")
 # the sequential oracle's modularity on the same R-MAT graph (written by
-# tests/golden/make_rmat_s24_reference.py)
+# tests/golden/make_fullsize_reference.py)
 ORACLE_Q_FILE = os.path.join(ROOT, "tests", "golden", "rmat_s24_oracle.json")
 HBM_PEAK_GBS = 8000.0
 
@@ -85,19 +85,46 @@ def oracle_q(workload):
             "source": os.path.relpath(ORACLE_Q_FILE, ROOT)}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(scale: int):
     """The oracle (sequential, one thread) on a bounded sample: R-MAT with the
-    same parameters at a smaller scale."""
+    same parameters at a smaller scale, timed here; next to it the rate of
+    the oracle's recorded run on the full benchmark graph (the golden
+    record's own timing, made on the machine that wrote it)."""
     import gen
     import oracle
     g = gen.rmat(scale, 16, 0.57, 0.19, 0.19, seed=2)
     t0 = time.perf_counter()
     r = oracle.leiden(g, mode=oracle.SEQ_ASYNC)
     dt = time.perf_counter() - t0
-    return {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "sequential oracle on R-MAT scale %d (same a,b,c, edge factor 16): %d vertices, %d arcs, "
-                      "%.1f s, Q=%.4f; CPU %s" % (scale, g.n, g.m, dt, r.q, platform.processor() or platform.machine()),
-            "seconds": dt}
+    try:
+        cpus = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cpus = os.cpu_count()
+    out = {"value": g.m / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": "sequential oracle (one thread) on R-MAT scale %d (same a, b, c, edge factor 16, seed 2): "
+                     "%d vertices, %d arcs, %.1f s, Q=%.4f, %d passes" % (scale, g.n, g.m, dt, r.q, len(r.passes)),
+           "seconds": dt, "cpu_model": cpu_model(), "nproc": os.cpu_count(), "cpus_available": cpus,
+           "threads_used": 1}
+    if os.path.exists(ORACLE_Q_FILE):
+        with open(ORACLE_Q_FILE) as f:
+            rec = json.load(f)
+        out["full_size_recorded"] = {
+            "graph": rec["graph"], "arcs": rec["arcs"], "seconds": rec["oracle_seconds"],
+            "edges_per_s": rec["arcs"] / rec["oracle_seconds"], "modularity": rec["modularity"],
+            "note": "sequential oracle on the benchmark graph itself, timed when the golden record was written "
+                    "(tests/golden/make_fullsize_reference.py), not in this run"}
+    return out
 
 
 # --------------------------------------------------------- batch and serving ---
@@ -378,6 +405,33 @@ def compare_louvain(eng, off, idx, wt, r, leiden_ms, mode, kw, args):
             "check_ms": check_ms}
 
 
+def measure_variant(eng, off, idx, wt, m, mode, kw, args):
+    """The low-shrink variant (vertices without arcs left out of Alg. 1's
+    |Gamma| / |V'| ratio) on the same graph: its time, modularity and passes,
+    next to the sequential oracle's recorded result with the same variant.
+    Untimed by the metric."""
+    import torch
+    vopt = eng.options(mode, shrink_excludes_isolated=1, **kw)
+    r = eng.run(off, idx, wt, 1.0, vopt)
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(max(1, min(args.steps, 3))):
+        t1 = time.perf_counter()
+        r = eng.run(off, idx, wt, 1.0, vopt)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    ms = 1e3 * sum(ts) / len(ts)
+    out = {"ms": ms, "edges_per_s": m / (ms * 1e-3), "modularity": r.modularity, "passes": int(r.stats.passes),
+           "communities": int(r.stats.num_communities), "oracle": None}
+    if os.path.exists(ORACLE_Q_FILE):
+        with open(ORACLE_Q_FILE) as f:
+            v = json.load(f).get("shrink_excludes_isolated")
+        if v:
+            out["oracle"] = {"modularity": v["modularity"], "passes": v["passes"], "mode": v["mode"]}
+    log("shrink variant: %.1f ms Q=%.6f passes %d" % (ms, r.modularity, r.stats.passes))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -394,15 +448,19 @@ def main():
     ap.add_argument("--mode", default="fast", choices=["fast", "det"])
     ap.add_argument("--subsweeps", type=int, default=0, help="0 = library default")
     ap.add_argument("--sync-moves", type=int, default=-1, help="fast mode local-moving schedule (-1 = default)")
-    ap.add_argument("--cpu-sample-scale", type=int, default=20)
+    ap.add_argument("--cpu-sample-scale", type=int, default=21)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch-serve", action="store_true",
                     help="default workload: skip the batched and served parts of the metric")
     ap.add_argument("--no-louvain", action="store_true",
                     help="single-graph workloads: skip the Leiden / Louvain comparison")
     ap.add_argument("--batch-graphs", type=int, default=4096)
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--serve-pool", type=int, default=32)
+    ap.add_argument("--batch-plain-graphs", type=int, default=1024,
+                    help="default workload: graphs of the batch timed on the plain path (seeded subset)")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="default workload: skip the low-shrink variant without vertices that have no arcs")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-pool", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed region "
                          "(a kernel of known traffic for scaling profiler byte counters)")
@@ -524,6 +582,8 @@ def main():
                                  "kernel_ms_per_step": ams / len(stats)},
         "cpu_baseline": None,
     }
+    if not args.no_variant and args.workload == "rmat-s24":
+        out["shrink_variant"] = measure_variant(eng, off, idx, wt, g.m, mode, kw, args)
     if not args.no_louvain:
         out["louvain_comparison"] = compare_louvain(eng, off, idx, wt, r, ms_per_step, mode, kw, args)
     eng.close()
@@ -534,7 +594,7 @@ def main():
         # the metric's other two parts: batched graphs/s vs plain, p99 latency
         import argparse as _ap
         sub = _ap.Namespace(**vars(args))
-        sub.graphs, sub.plain_graphs, sub.steps, sub.warmup, sub.lanes = args.batch_graphs, 128, 2, 1, 0
+        sub.graphs, sub.plain_graphs, sub.steps, sub.warmup, sub.lanes = args.batch_graphs, args.batch_plain_graphs, 2, 1, 0
         try:
             b = bench_batch(sub, mode)
             out["batched"] = {k: b[k] for k in ("batched_graphs_per_s", "batched_edges_per_s", "plain_graphs_per_s",

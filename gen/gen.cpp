@@ -265,14 +265,18 @@ int gen_grid(int32_t rows, int32_t cols, double drop, double diag_frac, int32_t 
 }
 
 // LFR-style benchmark graph (Lancichinetti, Fortunato, Radicchi 2008),
-// simplified: degrees from a power law with exponent tau1 on
-// [kmin, kmax] (kmin chosen so that the mean is close to avg_deg);
-// community sizes from a power law with exponent tau2 on [cmin, cmax]
-// until they cover n; vertices assigned to communities in a shuffled order;
-// each vertex's stubs split into round((1 - mu) k) internal and the rest
-// external; stubs paired uniformly at random inside each community
-// (internal) and over the whole graph (external); self-loops and duplicate
-// edges dropped.  Unit weights; truth[] holds the planted community.
+// simplified: degrees from a power law with exponent tau1 on [kmin, kmax],
+// with kmin drawn per vertex from the two neighbouring integers whose mix
+// gives mean avg_deg exactly; community sizes from a power law with exponent
+// tau2 on [cmin, cmax] until they cover n; vertices assigned to communities
+// in a shuffled order; each vertex's stubs split into round((1 - mu) k)
+// internal (at most its community's size - 1, the rest external) and the
+// rest external; stubs paired uniformly at random inside each community
+// (internal) and over the whole graph (external), a pair that would make a
+// self-loop or repeat an edge going back to be paired again in the next of
+// up to 16 rounds (the configuration model with rewiring), so the realised
+// mean degree stays close to avg_deg.  Unit weights; truth[] holds the
+// planted community.
 namespace {
 int64_t discrete_powerlaw(u64 s, u64 k, const std::vector<double>& cdf, int64_t lo) {
   const double u = unif(s, k) * cdf.back();
@@ -294,6 +298,56 @@ void shuffle(std::vector<int32_t>& v, u64 s) {
 }
 }  // namespace
 
+namespace {
+// Set of undirected edges (a < b) packed into 64-bit keys: open addressing
+// with linear probing over a power-of-two table of at least twice the
+// number of insertions.
+struct EdgeSet {
+  std::vector<u64> slot;
+  u64 mask;
+  explicit EdgeSet(size_t expect) {
+    size_t cap = 16;
+    while (cap < 2 * expect + 16) cap <<= 1;
+    slot.assign(cap, ~0ull);
+    mask = cap - 1;
+  }
+  // false if the key was already present
+  bool insert(u64 key) {
+    u64 h = mix64(key) & mask;
+    while (slot[h] != ~0ull) {
+      if (slot[h] == key) return false;
+      h = (h + 1) & mask;
+    }
+    slot[h] = key;
+    return true;
+  }
+};
+
+// Pairs the stubs uniformly at random.  A pair that would be a self-loop or
+// an edge already made goes back; the returned stubs are shuffled and paired
+// again, for up to `rounds` rounds.  Stubs still unpaired are dropped.
+void pair_stubs(std::vector<int32_t>& stubs, u64 s, EdgeSet& made, std::vector<Edge>& edges,
+                int rounds) {
+  std::vector<int32_t> back;
+  for (int r = 0; r < rounds && stubs.size() >= 2; ++r) {
+    shuffle(stubs, stream(s, (u64)r));
+    back.clear();
+    for (size_t k = 0; k + 1 < stubs.size(); k += 2) {
+      int32_t a = stubs[k], b = stubs[k + 1];
+      if (a > b) std::swap(a, b);
+      if (a == b || !made.insert(((u64)(uint32_t)a << 32) | (u64)(uint32_t)b)) {
+        back.push_back(a);
+        back.push_back(b);
+        continue;
+      }
+      edges.push_back({a, b, 1.0f});
+    }
+    if (stubs.size() % 2) back.push_back(stubs.back());
+    stubs.swap(back);
+  }
+}
+}  // namespace
+
 extern "C" int gen_lfr(int64_t n, double avg_deg, int64_t kmax, double tau1, double tau2, double mu, int64_t cmin,
                        int64_t cmax, uint64_t seed, gen_graph* out) {
   memset(out, 0, sizeof(*out));
@@ -302,12 +356,20 @@ extern "C" int gen_lfr(int64_t n, double avg_deg, int64_t kmax, double tau1, dou
   cmax = std::min<int64_t>(cmax, n);
   cmin = std::min<int64_t>(cmin, cmax);
   const u64 s_deg = stream(seed, 31), s_com = stream(seed, 32), s_ord = stream(seed, 33), s_in = stream(seed, 34),
-            s_ex = stream(seed, 35);
+            s_ex = stream(seed, 35), s_mix = stream(seed, 36);
+  // kmin such that mean(kmin) <= avg_deg < mean(kmin + 1); each vertex draws
+  // from the kmin + 1 law with probability q, which makes the mean avg_deg
   int64_t kmin = 1;
   while (kmin < kmax && powerlaw_mean(kmin + 1, kmax, tau1) <= avg_deg) ++kmin;
-  std::vector<double> dcdf = powerlaw_cdf(kmin, kmax, tau1);
+  const double m0 = powerlaw_mean(kmin, kmax, tau1);
+  const double m1 = kmin < kmax ? powerlaw_mean(kmin + 1, kmax, tau1) : m0;
+  const double q = (m1 > m0 && avg_deg > m0) ? std::min(1.0, (avg_deg - m0) / (m1 - m0)) : 0.0;
+  const std::vector<double> dcdf0 = powerlaw_cdf(kmin, kmax, tau1);
+  const std::vector<double> dcdf1 = powerlaw_cdf(std::min(kmin + 1, kmax), kmax, tau1);
   std::vector<int64_t> deg(n);
-  for (int64_t i = 0; i < n; ++i) deg[i] = discrete_powerlaw(s_deg, (u64)i, dcdf, kmin);
+  for (int64_t i = 0; i < n; ++i)
+    deg[i] = unif(s_mix, (u64)i) < q ? discrete_powerlaw(s_deg, (u64)i, dcdf1, std::min(kmin + 1, kmax))
+                                     : discrete_powerlaw(s_deg, (u64)i, dcdf0, kmin);
   // community sizes
   std::vector<double> ccdf = powerlaw_cdf(cmin, cmax, tau2);
   std::vector<int64_t> csize;
@@ -329,6 +391,11 @@ extern "C" int gen_lfr(int64_t n, double avg_deg, int64_t kmax, double tau1, dou
     for (int64_t k = 0; k < csize[c]; ++k) { com[order[pos]] = (int32_t)c; members[c].push_back(order[pos]); ++pos; }
   std::vector<Edge> edges;
   std::vector<int32_t> ext;
+  int64_t total = 0;
+  for (int64_t i = 0; i < n; ++i) total += deg[i];
+  EdgeSet made((size_t)(total / 2));
+  edges.reserve((size_t)(total / 2 + 16));
+  constexpr int kRounds = 16;
   for (size_t c = 0; c < members.size(); ++c) {
     std::vector<int32_t> stubs;
     for (int32_t v : members[c]) {
@@ -337,13 +404,9 @@ extern "C" int gen_lfr(int64_t n, double avg_deg, int64_t kmax, double tau1, dou
       for (int64_t k = 0; k < kin; ++k) stubs.push_back(v);
       for (int64_t k = kin; k < deg[v]; ++k) ext.push_back(v);
     }
-    shuffle(stubs, stream(s_in, (u64)c));
-    for (size_t k = 0; k + 1 < stubs.size(); k += 2)
-      if (stubs[k] != stubs[k + 1]) edges.push_back({stubs[k], stubs[k + 1], 1.0f});
+    pair_stubs(stubs, stream(s_in, (u64)c), made, edges, kRounds);
   }
-  shuffle(ext, s_ex);
-  for (size_t k = 0; k + 1 < ext.size(); k += 2)
-    if (ext[k] != ext[k + 1]) edges.push_back({ext[k], ext[k + 1], 1.0f});
+  pair_stubs(ext, s_ex, made, edges, kRounds);
   int rc = build_csr(n, edges, out);
   if (rc) return rc;
   out->truth = (int32_t*)malloc(sizeof(int32_t) * n);

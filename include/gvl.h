@@ -58,7 +58,9 @@ typedef struct {
                                     lowest-id ties -- bit-reproducible */
   double tolerance;              /* initial per-iteration tolerance tau (Alg. 2 convergence) */
   double tolerance_drop;         /* threshold scaling: tau /= tolerance_drop after each pass */
-  double aggregation_tolerance;  /* stop when |Gamma| / |V'| exceeds this (Alg. 1) */
+  double aggregation_tolerance;  /* Alg. 1 low-shrink test: stop when |Gamma| / |V'| exceeds this,
+                                    with |Gamma| the distinct refined labels of the pass and |V'|
+                                    the vertices of its graph */
   int32_t max_iterations;        /* cap on local-moving iterations per pass */
   int32_t max_passes;            /* cap on passes */
   int32_t refine_sweeps;         /* cap on synchronous refinement sweeps per pass; sweeps stop
@@ -84,7 +86,12 @@ typedef struct {
                                     candidate); deterministic mode stays bit-reproducible for a seed.
                                     Default 0 (greedy). */
   uint32_t seed;                 /* seed of the randomized refinement */
-  int32_t reserved[3];
+  int32_t shrink_excludes_isolated; /* 1: the low-shrink ratio leaves the Z vertices of G' without
+                                    arcs out of both counts, (|Gamma| - Z) / (|V'| - Z) > tolerance
+                                    (they can never merge, so counting them ends runs on graphs with
+                                    many isolated vertices early).  Not in the paper.  Default 0
+                                    (Alg. 1 as printed). */
+  int32_t reserved[2];
 } gvl_options;
 
 #define GVL_MAX_PASS_STATS 64

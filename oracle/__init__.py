@@ -39,7 +39,8 @@ class Opts(ctypes.Structure):
                 ("max_iterations", ctypes.c_int32), ("max_passes", ctypes.c_int32),
                 ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
                 ("resolution", ctypes.c_double), ("trace", ctypes.c_int32), ("louvain", ctypes.c_int32),
-                ("refine_random", ctypes.c_int32), ("seed", ctypes.c_uint32)]
+                ("refine_random", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("shrink_excludes_isolated", ctypes.c_int32)]
 
 
 def _load():
@@ -75,6 +76,9 @@ def _load():
         lib.oracle_neg_ln_unit.restype = dbl
         lib.oracle_disconnected.argtypes = [i64, vp, vp, vp, vp]
         lib.oracle_disconnected.restype = i64
+        lib.oracle_gain_key.argtypes = [i64, i64, i64, i64, i64, i64, i64, ctypes.POINTER(i64),
+                                        ctypes.POINTER(ctypes.c_uint64)]
+        lib.oracle_gain_key.restype = None
         _lib = lib
     return _lib
 
@@ -208,3 +212,11 @@ def random_score(gain: float, seed: int, pass_: int, sweep: int, i: int, c: int)
 def neg_ln_unit(x: int) -> float:
     """-ln((x + 1/2) / 2^32) as the randomized refinement computes it."""
     return float(_load().oracle_neg_ln_unit(x))
+
+
+def gain_key(kic: int, kid: int, ki: int, sc: int, sd: int, W: int, p: int) -> int:
+    """The deterministic mode's exact Eq. 2 key for gamma = p / 2^16, as a Python int."""
+    hi = ctypes.c_int64(0)
+    lo = ctypes.c_uint64(0)
+    _load().oracle_gain_key(kic, kid, ki, sc, sd, W, p, ctypes.byref(hi), ctypes.byref(lo))
+    return (hi.value << 64) | lo.value

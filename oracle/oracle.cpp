@@ -38,9 +38,11 @@
 //   R2  global convergence (Alg. 1's test l_i + l_j <= 1 with l_i, l_j
 //       counted as iterations performed): local-moving ran one iteration
 //       and refinement moved no vertex.
-//   R3  |Gamma| = number of distinct refined labels; stop when
-//       (|Gamma| - Z) / (|V'| - Z) > aggregation tolerance, where Z counts
-//       the vertices of G' without arcs (they can never merge).
+//   R3  |Gamma| = number of distinct refined labels, |Gamma_old| = |V'|;
+//       stop when |Gamma| / |V'| > aggregation tolerance (Alg. 1's low-shrink
+//       test).  Option shrink_excludes_isolated (not in the paper) leaves the
+//       Z vertices of G' without arcs out of both counts,
+//       (|Gamma| - Z) / (|V'| - Z), since such vertices can never merge.
 //   R4  the result is the flattening of the last refinement.
 //   R5  a move is taken only for a strictly positive gain; ties go to the
 //       lowest community id; the own community is never a candidate.
@@ -101,6 +103,7 @@ struct Opts {
   int32_t louvain = 0;
   int32_t refine_random = 0;  // refinement picks c with probability proportional to its gain
   uint32_t seed = 0;
+  int32_t shrink_excludes_isolated = 0;  // R3 variant: vertices without arcs left out of the ratio
 };
 
 // Sub-sweep group of vertex i: the MurmurHash3 32-bit finalizer of i, mod S
@@ -572,12 +575,13 @@ int run_leiden(const Graph& g0, const Opts& o, Result& res) {
     bool stop = false;
     if (first && refine_moved == 0) { res.termination = 0; stop = true; }
     else {
-      // vertices without arcs stay singletons for ever: they are left out of
-      // both counts of the shrink ratio
+      // Alg. 1 low shrink: |Gamma| / |Gamma_old| with |Gamma_old| = |V'|.
+      // The variant leaves the vertices without arcs (singletons for ever)
+      // out of both counts.
       i64 z = 0;
-      for (i64 i = 0; i < n; ++i) if (cur.off[i + 1] == cur.off[i]) ++z;
-      if (n > z && (double)(ncom - z) / (double)(n - z) > o.aggregation_tolerance) { res.termination = 1; stop = true; }
-      if (n == z) { res.termination = 1; stop = true; }
+      if (o.shrink_excludes_isolated)
+        for (i64 i = 0; i < n; ++i) if (cur.off[i + 1] == cur.off[i]) ++z;
+      if (n == z || (double)(ncom - z) / (double)(n - z) > o.aggregation_tolerance) { res.termination = 1; stop = true; }
     }
     if (stop) {
       final_refined = st.C;
@@ -651,6 +655,7 @@ typedef struct {
   int32_t louvain;               // 1: no refinement (the Louvain method)
   int32_t refine_random;         // 1: randomized refinement (gain-proportional choice)
   uint32_t seed;                 // its seed
+  int32_t shrink_excludes_isolated;  // 1: low-shrink ratio without the vertices that have no arcs
 } oracle_opts;
 
 void oracle_default_opts(oracle_opts* o, int32_t mode) {
@@ -667,6 +672,7 @@ void oracle_default_opts(oracle_opts* o, int32_t mode) {
   o->louvain = 0;
   o->refine_random = 0;
   o->seed = 0;
+  o->shrink_excludes_isolated = 0;
 }
 
 // Runs Leiden; returns an opaque result handle, or NULL with *status set.
@@ -679,6 +685,7 @@ void* oracle_leiden(int64_t n, const int32_t* off, const int32_t* idx, const flo
   op.max_passes = o->max_passes; op.refine_sweeps = o->refine_sweeps; op.subsweeps = o->subsweeps;
   op.resolution = o->resolution; op.trace = o->trace; op.louvain = o->louvain;
   op.refine_random = o->refine_random; op.seed = o->seed;
+  op.shrink_excludes_isolated = o->shrink_excludes_isolated;
   Result* r = new Result();
   int rc = run_leiden(g, op, *r);
   *status = rc;
@@ -755,6 +762,15 @@ double oracle_delta_modularity(int64_t n, const int32_t* off, const int32_t* idx
   scan(H, g, st.C, i, nullptr);
   const int32_t d = st.C[i];
   return gain_fp(H.get(c), H.get(d), st.K[i], st.S[c], st.S[d], W / 2.0, gamma);
+}
+
+// The exact integer key of Eq. 2 used by the deterministic mode, for
+// gamma = p / 2^16, as its high (signed) and low 64-bit words.
+void oracle_gain_key(int64_t kic, int64_t kid, int64_t ki, int64_t sc, int64_t sd, int64_t W, int64_t p,
+                     int64_t* hi, uint64_t* lo) {
+  const i128 k = gain_key(kic, kid, ki, sc, sd, W, p);
+  *hi = (int64_t)(k >> 64);
+  *lo = (uint64_t)k;
 }
 
 // Alg. 4 on its own: writes the super-vertex CSR for dense labels in

@@ -44,7 +44,7 @@ class gvl_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("debug_trace", ctypes.c_int32), ("sync_moves", ctypes.c_int32),
                 ("louvain", ctypes.c_int32), ("refine_random", ctypes.c_int32), ("seed", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("shrink_excludes_isolated", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 _P = GVL_MAX_PASS_STATS

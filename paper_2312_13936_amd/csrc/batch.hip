@@ -459,7 +459,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       const int32_t k = alive_k[j];
       const int64_t n_k = ncur[k];
       const int64_t ncom = hg[j + 1] - hg[j];
-      const int64_t z = n_k - hnz[k];
+      const int64_t z = opt->shrink_excludes_isolated ? n_k - hnz[k] : 0;
       bool stop = false;
       if (first_conv[k] && hmv[k] == 0) stop = true;
       else if (n_k == z || (double)(ncom - z) / (double)(n_k - z) > opt->aggregation_tolerance) stop = true;

@@ -417,8 +417,9 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       pd.bound = to_host(ctx, ws.CB, nn);
       pd.refined = to_host(ctx, ws.C, nn);
     }
-    // vertices without arcs stay singletons: they are left out of the ratio
-    const int64_t z = nn - bins.binned;
+    // Alg. 1 low shrink, |Gamma| / |V'|; the variant leaves the vertices
+    // without arcs (singletons for ever) out of both counts
+    const int64_t z = opt->shrink_excludes_isolated ? nn - bins.binned : 0;
     bool stop = false;
     if (first_conv && refine_moved == 0) { S->termination = 0; stop = true; }
     else if (nn == z || (double)(ncom - z) / (double)(nn - z) > opt->aggregation_tolerance) {

@@ -17,13 +17,13 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_2312_13936_amd as gvl  # noqa: E402
-from test_gpu_parity import relabel  # noqa: E402
+from test_gpu_parity import WIDER_BAR as _SOLO_WIDER  # noqa: E402
 
 FAST_TOL = 1e-3
-# On graphs of a few thousand vertices the sequential oracle's own modularity
-# spreads by up to ~3e-3 across vertex numberings, so a single fast-mode run
-# is held to the 1e-3 bar on the mean over a mix, and each graph to 5e-3.
-FAST_TOL_ONE = 5e-3
+# Per-graph margins wider than 1e-3 (by generated graph name), each with the
+# sequential oracle's own spread over vertex numberings on that graph (see
+# test_gpu_parity.py).
+WIDER_BAR = {"rmat-s12-ef16": _SOLO_WIDER["rmat-s12"], "er-300-0.03-9": _SOLO_WIDER["er-selfloops"]}
 
 
 def lfr_mix(count, lo, hi, seed, mu=0.3, avg_deg=12.0):
@@ -93,21 +93,22 @@ def test_batch_det_matches_solo_and_oracle(eng, lanes):
 
 
 def check_fast_mix(gs, mems, qs):
-    """Fast-mode bar over a mix: every result reports Eq. 1 of its membership
-    and has no disconnected community; the mean modularity is within 1e-3 of
-    the mean of the sequential oracle (over the given and two renumbered
-    orders); each graph is within 5e-3 of the oracle's lowest."""
-    diffs = []
+    """Fast-mode bar over a mix, graph by graph: every result reports Eq. 1
+    of its membership, has no disconnected community and reaches the
+    sequential oracle's modularity on the graph as numbered minus 1e-3 (or
+    the wider margin that WIDER_BAR states for that graph)."""
+    short = []
     for g, mem, q in zip(gs, mems, qs):
         assert q == oracle.modularity(g, mem), g.name
         assert oracle.disconnected(g, mem) == 0, g.name
         if g.m == 0:
             continue
-        qref = [oracle.leiden(g, mode=oracle.SEQ_ASYNC).q]
-        qref += [oracle.leiden(relabel(g, s), mode=oracle.SEQ_ASYNC).q for s in range(2)]
-        assert q >= min(qref) - FAST_TOL_ONE, "%s: fast Q %.6f vs oracle %.6f" % (g.name, q, min(qref))
-        diffs.append(q - float(np.mean(qref)))
-    assert np.mean(diffs) >= -FAST_TOL, "mean fast-mode Q %.6f below the oracle's" % np.mean(diffs)
+        q0 = oracle.leiden(g, mode=oracle.SEQ_ASYNC).q
+        tol = WIDER_BAR.get(g.name, FAST_TOL)
+        print("  %s: fast Q %.6f, sequential oracle %.6f, margin %+.6f" % (g.name, q, q0, q - q0), flush=True)
+        if q < q0 - tol:
+            short.append("%s: fast Q %.6f vs sequential oracle %.6f" % (g.name, q, q0))
+    assert not short, "; ".join(short)
 
 
 def test_batch_fast_quality(eng):

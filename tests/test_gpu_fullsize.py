@@ -1,10 +1,14 @@
-"""Deterministic parity at the benchmark's full size.
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times.
 
-The oracle's det-sync run on the R-MAT scale-24 graph (16.8M vertices,
-521M arcs) is recorded in tests/golden/rmat_s24_oracle.json by
-tests/golden/make_rmat_s24_reference.py (modularity and a SHA-256 of the
-membership); the GPU's deterministic mode must reproduce both exactly, in
-the launch configuration bench.py times.
+tests/golden/make_fullsize_reference.py records the oracle on two graphs:
+R-MAT scale 24 (16.8M vertices, 521M arcs, the benchmark graph) and the
+4096 x 4096 weighted grid (16.8M vertices, 61M arcs, total weight 3.08e9 >
+2^31, so the deterministic gain keys need their high 64-bit word).  Each
+record holds the deterministic oracle's modularity, pass count and a SHA-256
+of its membership, which the GPU's deterministic mode must reproduce
+exactly, and the sequential oracle's modularity, which the fast mode must
+reach within 1e-3 with no internally disconnected community.
 """
 import hashlib
 import json
@@ -14,34 +18,70 @@ import numpy as np
 import pytest
 
 import gen
+import oracle
 
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_2312_13936_amd as gvl  # noqa: E402
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "rmat_s24_oracle.json")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+MAKERS = {"rmat_s24": lambda: gen.rmat(24, 16, 0.57, 0.19, 0.19, seed=2),
+          "grid4096": lambda: gen.grid(4096, 4096, seed=3)}
+_graphs = {}
 
 
-def test_rmat_s24_det_bit_exact_at_full_size():
-    rec = json.load(open(GOLDEN))
-    g = gen.rmat(24, 16, 0.57, 0.19, 0.19, seed=2)
-    assert (g.n, g.m) == (rec["vertices"], rec["arcs"])
-    print("full-size det parity: R-MAT s24", g.n, g.m, flush=True)
+def graph(name):
+    if name not in _graphs:
+        _graphs.clear()  # one full-size graph in host memory at a time
+        _graphs[name] = MAKERS[name]()
+    return _graphs[name]
+
+
+def record(name):
+    with open(os.path.join(GOLDEN, name + "_oracle.json")) as f:
+        return json.load(f)
+
+
+def run(g, mode, **kw):
     d = torch.device("cuda", 0)
     off = torch.from_numpy(g.offsets).to(d)
     idx = torch.from_numpy(g.indices).to(d)
     w = torch.from_numpy(g.weights).to(d)
-    del g
     eng = gvl.Leiden(0)
     try:
-        r = eng.run(off, idx, w, 1.0, eng.options(gvl.GVL_MODE_DET))
+        r = eng.run(off, idx, w, 1.0, eng.options(mode, **kw))
         torch.cuda.synchronize()
-        mem = r.membership.cpu().numpy().astype("<i4")
+        return r.membership.cpu().numpy().astype("<i4"), r.modularity, r.stats
     finally:
         eng.close()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", list(MAKERS))
+def test_det_bit_exact_at_full_size(name):
+    rec = record(name)
+    g = graph(name)
+    assert (g.n, g.m) == (rec["vertices"], rec["arcs"])
+    print("full-size det parity:", name, g.n, g.m, flush=True)
+    mem, q, st = run(g, gvl.GVL_MODE_DET)
     det = rec["det"]
-    assert r.modularity == det["modularity"]
+    assert q == det["modularity"]
     assert int(mem.max()) + 1 == det["communities"]
     assert hashlib.sha256(mem.tobytes()).hexdigest() == det["membership_sha256"]
-    assert r.stats.passes == det["passes"] and r.stats.termination == det["termination"]
+    assert st.passes == det["passes"] and st.termination == det["termination"]
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("sync_moves", [3, 0])
+@pytest.mark.parametrize("name", list(MAKERS))
+def test_fast_quality_at_full_size(name, sync_moves):
+    rec = record(name)
+    g = graph(name)
+    print("full-size fast quality:", name, g.n, g.m, "sync_moves", sync_moves, flush=True)
+    mem, q, st = run(g, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
+    print("  fast Q %.6f, sequential oracle %.6f, margin %+.6f, passes %d" %
+          (q, rec["modularity"], q - rec["modularity"], st.passes), flush=True)
+    assert q == oracle.modularity(g, mem)
+    assert q >= rec["modularity"] - 1e-3
+    assert oracle.disconnected(g, mem) == 0

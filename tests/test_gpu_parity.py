@@ -144,18 +144,23 @@ def relabel(g, seed):
     return gen.from_edges(g.n, e, g.weights[keep], name=g.name + "-perm%d" % seed)
 
 
-def oracle_reference_q(g, orders=4):
-    """Oracle modularity: the sequential run on the given numbering, and the
-    lowest the oracle reaches over that numbering and `orders` seeded
-    renumberings, in either of its modes (sequential, group-synchronous).
-    Leiden's result depends on the visiting order, so on graphs with weak
-    structure (R-MAT, Q ~ 0.1) the oracle's own spread exceeds 1e-3."""
+def fast_bar(g, name):
+    """The fast mode's quality bar: the sequential oracle's modularity on the
+    graph as numbered, minus 1e-3, or minus the wider margin of WIDER_BAR
+    for the graphs listed there."""
     q0 = oracle.leiden(g, mode=oracle.SEQ_ASYNC).q
-    qs = [q0, oracle.leiden(g, mode=oracle.DET_SYNC).q]
-    for s in range(orders):
-        h = relabel(g, s)
-        qs += [oracle.leiden(h, mode=oracle.SEQ_ASYNC).q, oracle.leiden(h, mode=oracle.DET_SYNC).q]
-    return q0, min(qs)
+    return q0, q0 - WIDER_BAR.get(name, FAST_TOL)
+
+
+# Graphs on which the sequential oracle's own result moves by far more than
+# 1e-3 when only the vertex numbering changes (max - min over the given and
+# seven seeded renumberings): a parallel schedule visits the vertices in yet
+# another order, and the group-synchronous one lands below the given
+# numbering's sequential result by more than 1e-3 here (deterministic-mode
+# oracle: rmat-s12 -1.1e-3, er-selfloops -1.7e-3).
+#   rmat-s12      sequential 0.0945 .. 0.1153 over numberings (given 0.1093)
+#   er-selfloops  sequential 0.3577 .. 0.3666 over numberings (given 0.3639)
+WIDER_BAR = {"rmat-s12": 2.5e-3, "er-selfloops": 2.5e-3}
 
 
 @pytest.mark.parametrize("sync_moves", [3, 0])
@@ -164,9 +169,10 @@ def test_fast_mode_quality(eng, name, sync_moves):
     g = graph(name)
     print("fast quality:", name, g.n, g.m, "sync_moves", sync_moves, flush=True)
     mem, q, st = run(eng, g, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
-    q0, qmin = oracle_reference_q(g)
+    q0, bar = fast_bar(g, name)
+    print("  fast Q %.6f, sequential oracle %.6f, margin %+.6f" % (q, q0, q - q0), flush=True)
     assert q == oracle.modularity(g, mem)  # reported Q is Eq. 1 of the returned membership
-    assert q >= qmin - FAST_TOL, "fast Q %.6f vs oracle %.6f (lowest over numberings %.6f)" % (q, q0, qmin)
+    assert q >= bar, "fast Q %.6f vs sequential oracle %.6f" % (q, q0)
     assert oracle.disconnected(g, mem) == 0
     _, first = np.unique(mem, return_index=True)
     assert np.all(np.diff(first) > 0) and mem[0] == 0  # first-occurrence labels
@@ -179,15 +185,61 @@ def test_fast_mode_sync_moves(eng, name, sync_moves):
     # (bit 0) or long rows (bit 1) only; the default is both bits
     g = graph(name)
     mem, q, st = run(eng, g, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
-    q0, qmin = oracle_reference_q(g, orders=2)
+    q0, bar = fast_bar(g, name)
+    print("  %s sync_moves %d: fast Q %.6f, sequential oracle %.6f, margin %+.6f" % (name, sync_moves, q, q0, q - q0),
+          flush=True)
     assert q == oracle.modularity(g, mem)
-    # the mixed schedules (1, 2) interleave asynchronous long-row commits
-    # with group-synchronous short rows; on R-MAT scale 14 their modularity
-    # spreads by 1e-3 from run to run (0.1017-0.1026 over six runs of
-    # schedule 1), so they are held to twice the fast-mode tolerance
-    tol = FAST_TOL if sync_moves == 0 else 2 * FAST_TOL
-    assert q >= qmin - tol, "fast Q %.6f vs oracle %.6f" % (q, qmin)
+    assert q >= bar, "fast Q %.6f vs sequential oracle %.6f" % (q, q0)
     assert oracle.disconnected(g, mem) == 0
+
+
+def _heavy(g, seed, lo=1 << 23, hi=1 << 24):
+    """The graph with integer weights drawn in [lo, hi] (the same in both
+    directions): total weights above 2^31 and gain keys above 2^64."""
+    src = np.repeat(np.arange(g.n, dtype=np.int32), np.diff(g.offsets))
+    keep = src <= g.indices
+    e = np.stack([src[keep], g.indices[keep]], 1)
+    w = np.random.default_rng(seed).integers(lo, hi + 1, len(e)).astype(np.float32)
+    return gen.from_edges(g.n, e, w, name=g.name + "-heavy")
+
+
+@pytest.mark.parametrize("name", ["planted-small", "grid64-w100", "er-selfloops", "rmat-s12"])
+def test_det_mode_int128_keys(eng, name):
+    # weights near 2^24: W ~ 10^11 > 2^31, W^2 > 2^63 and keys
+    # 2^16 W (K_ic - K_id) ~ 2^80, so the high word of every key is in use
+    g = _heavy(graph(name), 17)
+    W = float(g.weights.astype(np.float64).sum())
+    assert 2.0 ** 31 < W <= 2.0 ** 40
+    print("det parity, int128 keys:", name, g.n, g.m, "W=%.4g" % W, flush=True)
+    mem, q, st = run(eng, g, gvl.GVL_MODE_DET, debug_trace=1)
+    o = oracle.leiden(g, mode=oracle.DET_SYNC, trace=True)
+    assert st.passes == len(o.passes)
+    for p, t in enumerate(o.passes):
+        bound, refined, y_off, y_idx, y_w = gvl.gvl_debug_export_pass(eng.ctx, p)
+        assert np.array_equal(bound, t.bound) and np.array_equal(refined, t.refined), "pass %d labels" % p
+        if t.y_off is not None:
+            assert np.array_equal(y_idx, t.y_idx) and np.array_equal(y_w, t.y_w), "pass %d super-vertex CSR" % p
+    assert np.array_equal(mem, o.membership) and q == o.q
+
+
+def _with_isolated(g, extra):
+    off = np.concatenate([g.offsets, np.full(extra, g.offsets[-1], np.int32)])
+    return gen.Graph(g.n + extra, g.m, off, g.indices, g.weights, name=g.name + "+iso")
+
+
+@pytest.mark.parametrize("name", ["rmat-s14", "rmat-s16", "ring10xK5", "hubs-wide"])
+def test_det_shrink_excludes_isolated_bit_exact(eng, name):
+    # the low-shrink variant that leaves vertices without arcs out of the
+    # ratio: R-MAT has many such vertices, the ring gets 600 of them
+    g = graph(name) if name != "ring10xK5" else _with_isolated(graph(name), 600)
+    print("det parity, shrink_excludes_isolated:", name, g.n, g.m, flush=True)
+    mem, q, st = run(eng, g, gvl.GVL_MODE_DET, shrink_excludes_isolated=1)
+    o = oracle.leiden(g, mode=oracle.DET_SYNC, shrink_excludes_isolated=1)
+    p = oracle.leiden(g, mode=oracle.DET_SYNC)
+    assert st.passes == len(o.passes) and st.termination == o.termination
+    assert np.array_equal(mem, o.membership) and q == o.q
+    if name != "hubs-wide":
+        assert len(o.passes) > len(p.passes)  # the variant aggregates further
 
 
 @pytest.mark.parametrize("gamma", [0.5, 1.5, 0.25])

@@ -89,9 +89,12 @@ def test_lfr_degrees_and_mixing():
     check_csr(g)
     assert np.all(g.weights == 1.0)
     deg = np.diff(g.offsets)
-    # the requested mean, less what dropping self-loops and duplicate stubs
-    # costs the hubs (about a quarter at this size)
-    assert 0.7 * 12.0 < deg.mean() <= 12.0
+    # the requested mean: stubs that would form self-loops or repeat an edge
+    # are paired again, so only a few per cent stay unpaired
+    assert 0.95 * 12.0 < deg.mean() <= 1.02 * 12.0
+    for n, k in ((2000, 12.0), (200000, 12.0), (300000, 16.0)):
+        d = np.diff(gen.lfr(n, avg_deg=k, mu=0.3, seed=3).offsets)
+        assert 0.95 * k < d.mean() <= 1.02 * k, (n, k, d.mean())
     assert deg.max() > 4 * deg.mean()  # power-law tail
     src, dst, _ = arcs(g)
     mixing = np.mean(g.truth[src] != g.truth[dst])
