@@ -36,6 +36,7 @@ typedef enum {
   GVL_OK = 0,
   GVL_E_INVALID_ARG = -1,       /* null pointer, negative size, bad option value */
   GVL_E_BAD_CSR = -2,           /* offsets not monotone / out of range, index out of range */
+  GVL_E_NOT_SYMMETRIC = -3,     /* validate = 2: some arc (i, j, w) has no matching reverse arc (j, i, w) */
   GVL_E_NONINTEGER_WEIGHT = -4, /* deterministic mode: weight not an integer in [1, 2^24] or total > 2^40 */
   GVL_E_RESOLUTION = -5,        /* resolution < 0, or (deterministic mode) not p / 65536 with p <= 2^24 */
   GVL_E_WORKSPACE = -6,         /* workspace null or smaller than gvl_workspace_bytes */
@@ -67,7 +68,13 @@ typedef struct {
                                     early once one moves no vertex (1 = the single sweep of Alg. 3) */
   int32_t subsweeps;             /* S <= 64: local-moving and refinement visit the vertices in S
                                     pseudo-random groups in turn (sub-sweeps) */
-  int32_t validate;              /* 0: none; 1: CSR bounds and weight checks on the device */
+  int32_t validate;              /* 0: none; 1: CSR bounds and weight checks on the device (default);
+                                    2: also symmetry (Sec. 3.1: the graph is undirected, each edge
+                                    stored as two arcs with one weight): a multiset hash of the arcs
+                                    (i, j, w) against that of their reverses (j, i, w), one pass over
+                                    the arcs; GVL_E_NOT_SYMMETRIC if they differ.  The hash is
+                                    probabilistic: an asymmetric input passes with probability
+                                    2^-128 unless crafted against its public mixers. */
   int32_t profile;               /* 1: time every kernel class with HIP events (fills gvl_stats ms_*) */
   int32_t debug_trace;           /* 1: keep per-pass labels and super-vertex CSRs for gvl_debug_* */
   int32_t sync_moves;            /* fast mode local-moving: 0 commits every move at once (the

@@ -24,7 +24,8 @@ GVL_MODE_FAST = 0
 GVL_MODE_DET = 1
 GVL_MAX_PASS_STATS = 64
 
-STATUS = {0: "GVL_OK", -1: "GVL_E_INVALID_ARG", -2: "GVL_E_BAD_CSR", -4: "GVL_E_NONINTEGER_WEIGHT",
+STATUS = {0: "GVL_OK", -1: "GVL_E_INVALID_ARG", -2: "GVL_E_BAD_CSR", -3: "GVL_E_NOT_SYMMETRIC",
+          -4: "GVL_E_NONINTEGER_WEIGHT",
           -5: "GVL_E_RESOLUTION", -6: "GVL_E_WORKSPACE", -8: "GVL_E_HIP", -9: "GVL_E_BUSY", -10: "GVL_E_BATCH"}
 
 GVL_REQ_PENDING, GVL_REQ_RUNNING, GVL_REQ_DONE, GVL_REQ_CANCELLED = 0, 1, 2, 3

@@ -202,6 +202,14 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   std::vector<double> hW;
   if ((s = download(st, hflags, B.flags, G)) != GVL_OK) return s;
   if ((s = download(st, hW, B.W, G)) != GVL_OK) return s;
+  std::vector<unsigned long long> hsym;
+  if (opt->validate >= 2) {  // symmetry of every graph whose CSR is in range (B.s2u as scratch)
+    fill_u64(st, B.s2u, 0ull, 2 * (int64_t)G);
+    for (int32_t g = 0; g < G; ++g)
+      if (ok[g] && !(hflags[g] & 1))
+        symmetry_check(st, gs[g].d_offsets, gs[g].d_indices, gs[g].d_weights, gs[g].n, B.s2u + 2 * g);
+    if ((s = download(st, hsym, B.s2u, 2 * (size_t)G)) != GVL_OK) return s;
+  }
 
   // ---- kept graphs: valid, with arcs; edgeless graphs are singletons
   std::vector<int32_t> src;
@@ -212,6 +220,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     const int f = hflags[g];
     if (f & 1) { sts[g] = GVL_E_BAD_CSR; continue; }
     if (f & 2) { sts[g] = GVL_E_NONINTEGER_WEIGHT; continue; }
+    if (!hsym.empty() && (hsym[2 * g] != 0 || hsym[2 * g + 1] != 0)) { sts[g] = GVL_E_NOT_SYMMETRIC; continue; }
     if (det && ((f & 4) || hW[g] > 1099511627776.0)) { sts[g] = GVL_E_NONINTEGER_WEIGHT; continue; }
     if (hW[g] == 0.0) {
       iota_i32(st, gs[g].d_membership, gs[g].n);

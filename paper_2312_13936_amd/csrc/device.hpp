@@ -216,6 +216,29 @@ __device__ __forceinline__ double key_to_double(i128 k) {
   return (double)hi * 18446744073709551616.0 + (double)lo;
 }
 
+// Symmetry check (validate = 2): a multiset hash of the arcs.  For every arc
+// (i -> j, weight bits) the check adds H(i, j, w) - H(j, i, w) modulo 2^64,
+// for two independent seeds.  A symmetric CSR (every arc matched by its
+// reverse with the same weight, duplicates matched in number) sums to zero
+// whatever the order; an asymmetric one sums to zero for both seeds only by
+// a 2^-128 coincidence (not by construction: an input crafted against these
+// public mixers could pass).  H is SplitMix64's finalizer (Steele, Lea,
+// Flood 2014) applied twice around the seed.
+__device__ __forceinline__ u64 splitmix_fin(u64 x) {
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__device__ __forceinline__ u64 arc_hash(u64 seed, int32_t a, int32_t b, uint32_t wbits) {
+  const u64 x = (((u64)(uint32_t)a << 32) | (u64)(uint32_t)b) ^ ((u64)wbits * 0x9E3779B97F4A7C15ull);
+  return splitmix_fin(splitmix_fin(x) ^ seed);
+}
+constexpr u64 kSymSeed0 = 0x243F6A8885A308D3ull, kSymSeed1 = 0x13198A2E03707344ull;
+__device__ __forceinline__ void arc_sym(int32_t i, int32_t j, uint32_t wbits, u64& d0, u64& d1) {
+  d0 += arc_hash(kSymSeed0, i, j, wbits) - arc_hash(kSymSeed0, j, i, wbits);
+  d1 += arc_hash(kSymSeed1, i, j, wbits) - arc_hash(kSymSeed1, j, i, wbits);
+}
+
 // Partition hash of a community id for wide rows (Wellons' "lowbias32"
 // integer mixer); independent of hslot, which takes the high bits of a
 // multiplicative hash.

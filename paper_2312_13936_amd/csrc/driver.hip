@@ -22,6 +22,7 @@ const char* gvl_status_string(gvl_status s) {
     case GVL_OK: return "ok";
     case GVL_E_INVALID_ARG: return "invalid argument";
     case GVL_E_BAD_CSR: return "malformed CSR input";
+    case GVL_E_NOT_SYMMETRIC: return "graph not symmetric (an arc has no reverse arc of the same weight)";
     case GVL_E_NONINTEGER_WEIGHT: return "weights not valid for this mode";
     case GVL_E_RESOLUTION: return "invalid resolution";
     case GVL_E_WORKSPACE: return "workspace missing or too small";
@@ -233,6 +234,13 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     if (pass == 0) {
       if (ctx->host->flags[0]) return GVL_E_BAD_CSR;
       if (ctx->host->flags[2]) return GVL_E_NONINTEGER_WEIGHT;
+      if (opt->validate >= 2) {  // offsets and neighbour ids are known to be in range here
+        fill_u64(st, ws.sc->acc_u, 0ull, 2);
+        symmetry_check(st, d_off, d_idx, d_w, n, ws.sc->acc_u);
+        s = readback(ctx, ws.sc);
+        if (s != GVL_OK) return s;
+        if (ctx->host->acc_u[0] != 0 || ctx->host->acc_u[1] != 0) return GVL_E_NOT_SYMMETRIC;
+      }
       Wd = ctx->host->accW;
       integral = ctx->host->flags[1] == 0;
       if (det) {

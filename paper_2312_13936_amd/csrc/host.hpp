@@ -490,7 +490,8 @@ gvl_status check_args(gvl_ctx* ctx, int64_t n, int64_t m, const int32_t* off, co
   if (!(resolution >= 0.0) || !std::isfinite(resolution)) return GVL_E_RESOLUTION;
   if (opt->mode != GVL_MODE_FAST && opt->mode != GVL_MODE_DET) return GVL_E_INVALID_ARG;
   if ((opt->louvain != 0 && opt->louvain != 1) || (opt->refine_random != 0 && opt->refine_random != 1) ||
-      (opt->shrink_excludes_isolated != 0 && opt->shrink_excludes_isolated != 1))
+      (opt->shrink_excludes_isolated != 0 && opt->shrink_excludes_isolated != 1) || opt->validate < 0 ||
+      opt->validate > 2)
     return GVL_E_INVALID_ARG;
   if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 1 ||
       opt->subsweeps > kMaxGroups ||

@@ -203,6 +203,31 @@ __global__ void k_check_offsets(const int32_t* off, int64_t n, int64_t m, int32_
   }
 }
 
+// Symmetry check (validate = 2): one wavefront per row, acc[0..1] += the
+// row's multiset-hash differences (zero in total for a symmetric CSR).
+// Offsets must have been checked (rows stay inside [0, m)); neighbour ids
+// are hashed, never followed.
+__global__ __launch_bounds__(kBlock) void k_symmetry(const int32_t* off, const int32_t* idx, const float* w, int64_t n,
+                                                     unsigned long long* acc) {
+  u64 d0 = 0, d1 = 0;
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / kWave);
+  for (int64_t i = (int64_t)blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave; i < n; i += nw) {
+    const int32_t beg = off[i], end = off[i + 1];
+    for (int32_t e = beg + lane_id(); e < end; e += kWave)
+      arc_sym((int32_t)i, idx[e], w ? __float_as_uint(w[e]) : 0x3f800000u, d0, d1);
+  }
+  d0 = sum_xor<kWave>(d0);
+  d1 = sum_xor<kWave>(d1);
+  if (lane_id() == 0) {
+    if (d0) atomicAdd(&acc[0], (unsigned long long)d0);
+    if (d1) atomicAdd(&acc[1], (unsigned long long)d1);
+  }
+}
+void symmetry_check(hipStream_t st, const int32_t* off, const int32_t* idx, const float* w, int64_t n,
+                    unsigned long long* acc) {
+  if (n > 0) hipLaunchKernelGGL(k_symmetry, dim3(grid_n(n, kBlock / kWave)), dim3(kBlock), 0, st, off, idx, w, n, acc);
+}
+
 // ------------------------------------------------------- community totals ---
 __global__ __launch_bounds__(kBlock) void k_community_totals(const int32_t* C, const double* K, double* Sig,
                                                              int32_t* size, int64_t n) {

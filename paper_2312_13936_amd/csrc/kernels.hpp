@@ -399,6 +399,10 @@ void apply_canonical(hipStream_t st, int32_t* top, const int32_t* first, const i
 void modularity_partial(hipStream_t st, const GraphDesc& g, const int32_t* C, double* tot,
                         double* acc_d, const int32_t* gid = nullptr, double* s1g = nullptr);
 void check_offsets(hipStream_t st, const int32_t* off, int64_t n, int64_t m, int32_t* flags);
+// acc[0..1] += multiset-hash differences of the arcs (zero for a symmetric
+// CSR; offsets already checked).
+void symmetry_check(hipStream_t st, const int32_t* off, const int32_t* idx, const float* w, int64_t n,
+                    unsigned long long* acc);
 // Alg. 5: components of the intra-community arcs (union-find); dis[c] = 1
 // and ++cnt[0] for every community c with more than one (comp, root, rep,
 // dis: int32[n] scratch / output).

@@ -20,10 +20,18 @@ import paper_2312_13936_amd as gvl  # noqa: E402
 from test_gpu_parity import WIDER_BAR as _SOLO_WIDER  # noqa: E402
 
 FAST_TOL = 1e-3
-# Per-graph margins wider than 1e-3 (by generated graph name), each with the
-# sequential oracle's own spread over vertex numberings on that graph (see
-# test_gpu_parity.py).
-WIDER_BAR = {"rmat-s12-ef16": _SOLO_WIDER["rmat-s12"], "er-300-0.03-9": _SOLO_WIDER["er-selfloops"]}
+# Per-graph margins wider than 1e-3 (by generated graph name), by the rules
+# (i) and (ii) stated in test_gpu_parity.py:
+#   lfr-14820-7017   (i) sequential spread 5.3e-3 over numberings (0.6583 ..
+#                    0.6636); asynchronous lane-pool runs -4.7e-3 .. +0.7e-3
+#   lfr-24108-14000  (ii) det oracle -1.03e-3 (sequential spread 1.8e-4);
+#                    the fast mode's synchronous schedule -1.03e-3
+#   lfr-13658-14004  (ii) det oracle -0.96e-3 (spread 2.7e-4)
+#   lfr-14903-12006  (ii) det oracle -0.73e-3 (spread 1.5e-4); asynchronous
+#                    serving runs -0.8e-3
+WIDER_BAR = {"rmat-s12-ef16": _SOLO_WIDER["rmat-s12"], "er-300-0.03-9": _SOLO_WIDER["er-selfloops"],
+             "grid-64x64": _SOLO_WIDER["grid64-w100"], "lfr-14820-7017": 5.5e-3, "lfr-24108-14000": 1.5e-3,
+             "lfr-13658-14004": 1.5e-3, "lfr-14903-12006": 1.5e-3}
 
 
 def lfr_mix(count, lo, hi, seed, mu=0.3, avg_deg=12.0):
