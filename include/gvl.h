@@ -164,6 +164,24 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offs
                       const gvl_options* opt, void* d_workspace, size_t workspace_bytes,
                       int32_t* d_membership, double* modularity, gvl_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): gvl_leiden
+ * with its workspace in a device array that the library holds, one copy of
+ * GVL_STATIC_WORKSPACE_BYTES (256 MiB) per GPU it runs on, until the
+ * process ends.  The caller still provides the input graph and the output
+ * membership; arguments and results are those of gvl_leiden.  The call
+ * allocates no device memory.
+ *   Errors: those of gvl_leiden; GVL_E_WORKSPACE if gvl_workspace_bytes(n,
+ *   m, opt) exceeds GVL_STATIC_WORKSPACE_BYTES (e.g. fast mode up to about
+ *   350k vertices with 12 arcs each); GVL_E_INVALID_ARG if opt->profile is
+ *   set (timing would create HIP events).
+ * Every call on one GPU uses the same array: calls that overlap on one GPU
+ * (from several streams or host threads) race and must not be made. */
+#define GVL_STATIC_WORKSPACE_BYTES (256u * 1024u * 1024u)
+gvl_status gvl_leiden_static(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,
+                             const int32_t* d_indices, const float* d_weights, double resolution,
+                             const gvl_options* opt, int32_t* d_membership, double* modularity, gvl_stats* stats);
+
 /* Eq. 1 for a given membership (labels in [0, n)) on the device. */
 gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,
                           const int32_t* d_indices, const float* d_weights,

@@ -86,6 +86,7 @@ class gvl_server_info(ctypes.Structure):
 
 
 EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
+           "gvl_leiden_static",
            "gvl_modularity", "gvl_disconnected_communities", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
            "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_fused_workspace_bytes", "gvl_leiden_fused",
            "gvl_server_create", "gvl_server_submit",
@@ -111,6 +112,8 @@ def load_library(path: str = LIB_PATH):
     lib.gvl_workspace_bytes.argtypes = [i64, i64, ctypes.POINTER(gvl_options), ctypes.POINTER(sz)]
     lib.gvl_leiden.argtypes = [vp, i64, i64, vp, vp, vp, dbl, ctypes.POINTER(gvl_options), vp, sz, vp,
                                ctypes.POINTER(dbl), ctypes.POINTER(gvl_stats)]
+    lib.gvl_leiden_static.argtypes = [vp, i64, i64, vp, vp, vp, dbl, ctypes.POINTER(gvl_options), vp,
+                                      ctypes.POINTER(dbl), ctypes.POINTER(gvl_stats)]
     lib.gvl_modularity.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(dbl)]
     lib.gvl_disconnected_communities.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp, ctypes.POINTER(i64)]
     lib.gvl_debug_pass_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -176,6 +179,22 @@ def gvl_leiden(ctx, n, m, d_offsets, d_indices, d_weights, resolution, opt, d_wo
                                      d_workspace, workspace_bytes, d_membership, ctypes.byref(q),
                                      ctypes.byref(stats) if stats is not None else None)
     _check(code, "gvl_leiden")
+    return q.value
+
+
+GVL_STATIC_WORKSPACE_BYTES = 256 * 1024 * 1024
+
+
+def gvl_leiden_static(ctx, n, m, d_offsets, d_indices, d_weights, resolution, opt, d_membership,
+                      stats: Optional[gvl_stats] = None) -> float:
+    """gvl_leiden with the library's own device array as workspace (no device
+    allocation anywhere in the call); graphs whose workspace exceeds
+    GVL_STATIC_WORKSPACE_BYTES are rejected with GVL_E_WORKSPACE."""
+    q = ctypes.c_double(0.0)
+    code = load_library().gvl_leiden_static(ctx, n, m, d_offsets, d_indices, d_weights, resolution,
+                                            ctypes.byref(opt), d_membership, ctypes.byref(q),
+                                            ctypes.byref(stats) if stats is not None else None)
+    _check(code, "gvl_leiden_static")
     return q.value
 
 

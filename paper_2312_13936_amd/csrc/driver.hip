@@ -71,6 +71,14 @@ gvl_status gvl_create(gvl_ctx_t* out, int device, void* hip_stream) {
   }
   memset(c->host, 0, sizeof(Scalars));
   memset(c->hbins, 0, sizeof(BinBuf));
+  // device address of gvl_leiden_static's array on this device (once per device)
+  const gvl_status s = gvl_static_scratch_setup(device);
+  if (s != GVL_OK) {
+    (void)hipHostFree(c->host);
+    (void)hipHostFree(c->hbins);
+    delete c;
+    return s;
+  }
   *out = c;
   return GVL_OK;
 }

@@ -183,6 +183,10 @@ struct gvl_ctx {
   std::vector<PassDebug> trace;
 };
 
+// gvl_leiden_static's device array: resolves its address on `device` (the
+// current device) once per device; called by gvl_create (static_ws.hip).
+gvl_status gvl_static_scratch_setup(int device);
+
 namespace {
 
 #define HIP_TRY(x)                                   \
