@@ -98,7 +98,15 @@ typedef struct {
                                     (they can never merge, so counting them ends runs on graphs with
                                     many isolated vertices early).  Not in the paper.  Default 0
                                     (Alg. 1 as printed). */
-  int32_t reserved[2];
+  int32_t no_graph_replay;       /* 1: launch every kernel from the host.  Default 0: local-moving
+                                    iterations and refinement sweeps after the first of a pass are
+                                    recorded once into a HIP graph and replayed (same kernels, same
+                                    results; the host no longer issues each launch).  Replay is off
+                                    while profile = 1. */
+  int32_t refine_based;          /* 1: refine-based labels of super-vertices (Sec. 4.1): the next pass
+                                    starts with every super-vertex alone in its community, as pass 0
+                                    does.  Default 0: move-based, each super-vertex starts in the
+                                    local-moving community of its members (Alg. 1). */
 } gvl_options;
 
 #define GVL_MAX_PASS_STATS 64
@@ -128,6 +136,7 @@ typedef struct {
   int64_t agg_launches;
   int64_t scan_refine_arcs;      /* part of scan_arcs read by refinement */
   double ms_scan_move_kernels;   /* part of ms_scan_kernels spent in local-moving */
+  int64_t graph_launches;        /* iterations and sweeps run as one replayed HIP graph */
 } gvl_stats;
 
 /* Create a context bound to `device` and to the HIP stream `hip_stream`
@@ -181,6 +190,37 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offs
 gvl_status gvl_leiden_static(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,
                              const int32_t* d_indices, const float* d_weights, double resolution,
                              const gvl_options* opt, int32_t* d_membership, double* modularity, gvl_stats* stats);
+
+/* Launch-shape tuning: the degree binning and grid sizes that take the
+ * place of the paper's dynamic loop schedule (Sec. 4.1), picked per class of
+ * graph by paper_2312_13936_amd/tune.py and kept in a process-wide table.
+ * They change which kernel handles a row and how many workgroups a launch
+ * uses, never a result.  The table starts from compiled defaults and is
+ * loaded once per process, when the first context is created, from
+ * $GVL_TUNE_FILE, or (unset) tune.txt next to libgvl.so; "none" skips it.
+ * Class of a graph: fused batches GVL_CLASS_BATCH; else n <= 131072
+ * GVL_CLASS_SMALL; else m < 6 n GVL_CLASS_LOWDEG; else GVL_CLASS_SKEWED. */
+enum { GVL_CLASS_SMALL = 0, GVL_CLASS_LOWDEG = 1, GVL_CLASS_SKEWED = 2, GVL_CLASS_BATCH = 3, GVL_NUM_CLASSES = 4 };
+typedef struct {
+  int32_t bin_max[6];   /* largest row (arcs, or member arcs of a community) of the lane-group bins 0-4
+                           and of the one-workgroup bin 5: non-decreasing, each at most the compiled
+                           limit {4, 8, 16, 32, 128, 1024}, bin_max[5] >= 256 (a bin whose limit
+                           equals the previous one is empty; its rows go to the next bin) */
+  int32_t decide_grid;  /* workgroups per decision launch (at most), 1..65536 */
+  int32_t commit_grid;  /* workgroups per commit role (at most), 1..65536 */
+  int32_t agg_grid;     /* workgroups per aggregation launch (at most), 1..65536 */
+} gvl_tuning;
+/* Class of a graph with n vertices and m arcs (fused: 1 for a fused batch). */
+gvl_status gvl_graph_class(int64_t n, int64_t m, int32_t fused, int32_t* cls);
+gvl_status gvl_get_tuning(int32_t cls, gvl_tuning* t);
+/* GVL_E_INVALID_ARG for an unknown class or values outside the limits above;
+ * calls running meanwhile keep the values they started with. */
+gvl_status gvl_set_tuning(int32_t cls, const gvl_tuning* t);
+/* Reads a tune file (lines "<class> b0 b1 b2 b3 b4 b5 decide_grid
+ * commit_grid agg_grid", class one of small lowdeg skewed batch, '#'
+ * comments); invalid lines are reported on stderr and skipped.
+ * GVL_E_INVALID_ARG if the file cannot be opened. */
+gvl_status gvl_load_tuning(const char* path);
 
 /* Eq. 1 for a given membership (labels in [0, n)) on the device. */
 gvl_status gvl_modularity(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offsets,

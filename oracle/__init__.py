@@ -40,7 +40,7 @@ class Opts(ctypes.Structure):
                 ("refine_sweeps", ctypes.c_int32), ("subsweeps", ctypes.c_int32),
                 ("resolution", ctypes.c_double), ("trace", ctypes.c_int32), ("louvain", ctypes.c_int32),
                 ("refine_random", ctypes.c_int32), ("seed", ctypes.c_uint32),
-                ("shrink_excludes_isolated", ctypes.c_int32)]
+                ("shrink_excludes_isolated", ctypes.c_int32), ("refine_based", ctypes.c_int32)]
 
 
 def _load():

@@ -34,7 +34,8 @@
 // specification, not by code):
 //   R1  pass 0 starts from singletons; later passes start from the
 //       move-based labels of the previous pass (Alg. 1 "use move-based
-//       membership"), with community totals summed over members.
+//       membership"), with community totals summed over members; option
+//       refine_based (Sec. 4.1's alternative) starts them from singletons too.
 //   R2  global convergence (Alg. 1's test l_i + l_j <= 1 with l_i, l_j
 //       counted as iterations performed): local-moving ran one iteration
 //       and refinement moved no vertex.
@@ -104,6 +105,7 @@ struct Opts {
   int32_t refine_random = 0;  // refinement picks c with probability proportional to its gain
   uint32_t seed = 0;
   int32_t shrink_excludes_isolated = 0;  // R3 variant: vertices without arcs left out of the ratio
+  int32_t refine_based = 0;  // next-pass labels from the refinement (Sec. 4.1) instead of local-moving
 };
 
 // Sub-sweep group of vertex i: the MurmurHash3 32-bit finalizer of i, mod S
@@ -594,11 +596,17 @@ int run_leiden(const Graph& g0, const Opts& o, Result& res) {
     for (i64 v = 0; v < N; ++v) top[v] = lab[top[v]];
     if (pass + 1 < o.max_passes) {
       Graph y = aggregate(cur, lab, ncom);
-      // next-pass labels: dense rank of the bound label of each super-vertex
-      i64 nb = 0;
-      std::vector<int32_t> brank = dense_rank(bound, n, &nb);
+      // next-pass labels (Sec. 4.1): move-based, the dense rank of the
+      // local-moving label of each super-vertex (Alg. 1); refine-based, the
+      // super-vertex's own refined community, i.e. every super-vertex alone
       std::vector<int32_t> nstart(ncom, 0);
-      for (i64 i = 0; i < n; ++i) nstart[lab[i]] = brank[bound[i]];
+      if (o.refine_based) {
+        for (i64 c = 0; c < ncom; ++c) nstart[c] = (int32_t)c;
+      } else {
+        i64 nb = 0;
+        std::vector<int32_t> brank = dense_rank(bound, n, &nb);
+        for (i64 i = 0; i < n; ++i) nstart[lab[i]] = brank[bound[i]];
+      }
       if (o.trace) {
         tr.aggregated = true;
         tr.y_off.resize(y.n + 1);
@@ -656,6 +664,7 @@ typedef struct {
   int32_t refine_random;         // 1: randomized refinement (gain-proportional choice)
   uint32_t seed;                 // its seed
   int32_t shrink_excludes_isolated;  // 1: low-shrink ratio without the vertices that have no arcs
+  int32_t refine_based;          // 1: refine-based next-pass labels (each super-vertex alone)
 } oracle_opts;
 
 void oracle_default_opts(oracle_opts* o, int32_t mode) {
@@ -673,6 +682,7 @@ void oracle_default_opts(oracle_opts* o, int32_t mode) {
   o->refine_random = 0;
   o->seed = 0;
   o->shrink_excludes_isolated = 0;
+  o->refine_based = 0;
 }
 
 // Runs Leiden; returns an opaque result handle, or NULL with *status set.
@@ -686,6 +696,7 @@ void* oracle_leiden(int64_t n, const int32_t* off, const int32_t* idx, const flo
   op.resolution = o->resolution; op.trace = o->trace; op.louvain = o->louvain;
   op.refine_random = o->refine_random; op.seed = o->seed;
   op.shrink_excludes_isolated = o->shrink_excludes_isolated;
+  op.refine_based = o->refine_based;
   Result* r = new Result();
   int rc = run_leiden(g, op, *r);
   *status = rc;

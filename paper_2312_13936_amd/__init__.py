@@ -45,7 +45,8 @@ class gvl_options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("profile", ctypes.c_int32),
                 ("debug_trace", ctypes.c_int32), ("sync_moves", ctypes.c_int32),
                 ("louvain", ctypes.c_int32), ("refine_random", ctypes.c_int32), ("seed", ctypes.c_uint32),
-                ("shrink_excludes_isolated", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
+                ("shrink_excludes_isolated", ctypes.c_int32), ("no_graph_replay", ctypes.c_int32),
+                ("refine_based", ctypes.c_int32)]
 
 
 _P = GVL_MAX_PASS_STATS
@@ -65,7 +66,8 @@ class gvl_stats(ctypes.Structure):
                 ("agg_out_arcs", ctypes.c_int64),
                 ("ms_scan_kernels", ctypes.c_double), ("ms_agg_kernels", ctypes.c_double),
                 ("scan_launches", ctypes.c_int64), ("agg_launches", ctypes.c_int64),
-                ("scan_refine_arcs", ctypes.c_int64), ("ms_scan_move_kernels", ctypes.c_double)]
+                ("scan_refine_arcs", ctypes.c_int64), ("ms_scan_move_kernels", ctypes.c_double),
+                ("graph_launches", ctypes.c_int64)]
 
 
 class gvl_graph_desc(ctypes.Structure):
@@ -85,8 +87,17 @@ class gvl_server_info(ctypes.Structure):
                 ("arena_peak", ctypes.c_size_t)]
 
 
+GVL_CLASS_SMALL, GVL_CLASS_LOWDEG, GVL_CLASS_SKEWED, GVL_CLASS_BATCH, GVL_NUM_CLASSES = 0, 1, 2, 3, 4
+CLASS_NAMES = ("small", "lowdeg", "skewed", "batch")
+
+
+class gvl_tuning(ctypes.Structure):
+    _fields_ = [("bin_max", ctypes.c_int32 * 6), ("decide_grid", ctypes.c_int32), ("commit_grid", ctypes.c_int32),
+                ("agg_grid", ctypes.c_int32)]
+
+
 EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
-           "gvl_leiden_static",
+           "gvl_leiden_static", "gvl_graph_class", "gvl_get_tuning", "gvl_set_tuning", "gvl_load_tuning",
            "gvl_modularity", "gvl_disconnected_communities", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
            "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_fused_workspace_bytes", "gvl_leiden_fused",
            "gvl_server_create", "gvl_server_submit",
@@ -114,6 +125,10 @@ def load_library(path: str = LIB_PATH):
                                ctypes.POINTER(dbl), ctypes.POINTER(gvl_stats)]
     lib.gvl_leiden_static.argtypes = [vp, i64, i64, vp, vp, vp, dbl, ctypes.POINTER(gvl_options), vp,
                                       ctypes.POINTER(dbl), ctypes.POINTER(gvl_stats)]
+    lib.gvl_graph_class.argtypes = [i64, i64, i32, ctypes.POINTER(i32)]
+    lib.gvl_get_tuning.argtypes = [i32, ctypes.POINTER(gvl_tuning)]
+    lib.gvl_set_tuning.argtypes = [i32, ctypes.POINTER(gvl_tuning)]
+    lib.gvl_load_tuning.argtypes = [ctypes.c_char_p]
     lib.gvl_modularity.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(dbl)]
     lib.gvl_disconnected_communities.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp, ctypes.POINTER(i64)]
     lib.gvl_debug_pass_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -180,6 +195,26 @@ def gvl_leiden(ctx, n, m, d_offsets, d_indices, d_weights, resolution, opt, d_wo
                                      ctypes.byref(stats) if stats is not None else None)
     _check(code, "gvl_leiden")
     return q.value
+
+
+def gvl_graph_class(n: int, m: int, fused: bool = False) -> int:
+    c = ctypes.c_int32(0)
+    _check(load_library().gvl_graph_class(n, m, 1 if fused else 0, ctypes.byref(c)), "gvl_graph_class")
+    return c.value
+
+
+def gvl_get_tuning(cls: int) -> gvl_tuning:
+    t = gvl_tuning()
+    _check(load_library().gvl_get_tuning(cls, ctypes.byref(t)), "gvl_get_tuning")
+    return t
+
+
+def gvl_set_tuning(cls: int, t: gvl_tuning) -> None:
+    _check(load_library().gvl_set_tuning(cls, ctypes.byref(t)), "gvl_set_tuning")
+
+
+def gvl_load_tuning(path: str) -> None:
+    _check(load_library().gvl_load_tuning(path.encode()), "gvl_load_tuning")
 
 
 GVL_STATIC_WORKSPACE_BYTES = 256 * 1024 * 1024

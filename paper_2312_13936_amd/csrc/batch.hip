@@ -285,7 +285,11 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.gp = B.gp; a.dqg = B.dqg; a.dqg128 = B.dqg128; a.mvg = B.mvg;
   const bool sync_mv = det || opt->sync_moves != 0;
   a.sync_moves = det ? 3 : (opt->sync_moves & 3);
-  const int grid_cap = 1024, agg_grid_cap = 4096;  // as for one graph
+  // launch shapes of the batch class (tuning.hip)
+  const gvl_tuning tune = gvl_tuning_of(GVL_CLASS_BATCH);
+  ctx->lim = bin_limits(tune);
+  const int grid_cap = tune.decide_grid, agg_grid_cap = tune.agg_grid;
+  a.commit_grid = tune.commit_grid;
   int64_t dummy_launches = 0;
   TableState tstate;
 
@@ -336,20 +340,20 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
 
     // (bx, lx: the short-row bins and their list, thinned during refinement;
     // the hubs always come from bins and ws.list)
-    auto decide_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
+    auto decide_group = [&](hipStream_t q, int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       if (phase == kMove)
-        launch_decide_move(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
+        launch_decide_move(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
       else
-        launch_decide_refine(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
+        launch_decide_refine(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &dummy_launches);
       if (bx.count[grp][kHubBin] > 0)  // (thinned refinement: no lone hub left in the group)
         for (const HubBatch& hb : plan.groups[grp]) {
-          tstate.ensure(st, ws, hb.tend - hb.tbase);
+          tstate.ensure(q, ws, hb.tend - hb.tbase);
           hargs.tbase = hb.tbase;
-          hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
+          hub_decide(q, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
                      &dummy_launches);
         }
     };
-    auto commit_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
+    auto commit_group = [&](hipStream_t q, int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       CommitLaunch cl;
       memset(&cl, 0, sizeof(cl));
       const int32_t n0 = bx.gend[grp] - bx.gstart[grp];  // bins 0 .. kHubBin-1 of the group
@@ -368,18 +372,29 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       } else {
         cl.n0 = n0;
       }
-      launch_commit(st, cur, a, hargs, cl, phase);
+      launch_commit(q, cur, a, hargs, cl, phase);
     };
+
+    // every local-moving iteration, and every refinement sweep after the
+    // first, repeats one launch sequence with the same arguments: replayed as
+    // one HIP graph
+    const bool replay = !opt->no_graph_replay;
 
     // ---- local-moving (Alg. 2), each graph stopping on its own gain sum
     std::vector<uint8_t> iter(run), first_conv(K, 0);
+    a.groups = bins.S;
+    Replay move_graph;
     for (int32_t it = 0; it < opt->max_iterations; ++it) {
-      if (det) fill_u64(st, B.dqg128, 0ull, 2 * (int64_t)K);
-      else fill_f64(st, B.dqg, 0.0, K);
-      for (int32_t grp = 0; grp < bins.S; ++grp) {
-        decide_group(grp, kMove, bins, ws.list);
-        if (sync_mv) commit_group(grp, kMove, bins, ws.list);
-      }
+      const int64_t clean = tstate.clean;
+      s = move_graph.run(ctx, replay, &dummy_launches, [&](hipStream_t q) {
+        if (det) fill_u64(q, B.dqg128, 0ull, 2 * (int64_t)K);
+        else fill_f64(q, B.dqg, 0.0, K);
+        for (int32_t grp = 0; grp < bins.S; ++grp) {
+          decide_group(q, grp, kMove, bins, ws.list);
+          if (sync_mv) commit_group(q, grp, kMove, bins, ws.list);
+        }
+      }, [&] { tstate.clean = clean; });
+      if (s != GVL_OK) return s;
       bool any = false, stopped = false;
       if (det) {
         std::vector<unsigned long long> h;
@@ -416,6 +431,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       set_size_one(st, ws.size, nn);
       fill_i32(st, ws.targeted, 0, nn);
       pack_labels(st, ws.C, ws.CB, ws.CP, nn);
+      fill_i32(st, &ws.sc->sweep, 0, 1);
     }
     fill_u64(st, B.mvg, 0ull, K);
     s = readback(ctx, ws.sc);
@@ -424,13 +440,26 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     BinInfo rbins;  // after the first sweep: the short-row bins thinned to lone vertices
     const BinInfo* rb = &bins;
     const int32_t* rl = ws.list;
-    for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
-      a.rnd = opt->refine_random;
-      a.sweep = sw;
+    // one sweep: group stamps grp + 1 + sweep * S (unique within the pass),
+    // the sweep number read from the device and advanced by the sweep itself
+    a.rnd = opt->refine_random;
+    a.sweep_dev = &ws.sc->sweep;
+    auto refine_sweep = [&](hipStream_t q) {
       for (int32_t grp = 0; grp < bins.S; ++grp) {
-        a.stamp = sw * bins.S + grp + 1;
-        decide_group(grp, kRefine, *rb, rl);
-        commit_group(grp, kRefine, *rb, rl);
+        a.stamp = grp + 1;
+        decide_group(q, grp, kRefine, *rb, rl);
+        commit_group(q, grp, kRefine, *rb, rl);
+      }
+      add_one_i32(q, &ws.sc->sweep);
+    };
+    Replay refine_graph;  // sweeps from the second on (the thinned bins stay fixed)
+    for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
+      if (sw == 0) {
+        refine_sweep(st);
+      } else {
+        const int64_t clean = tstate.clean;
+        s = refine_graph.run(ctx, replay, &dummy_launches, refine_sweep, [&] { tstate.clean = clean; });
+        if (s != GVL_OK) return s;
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
@@ -444,6 +473,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
         rl = ws.list2;
       }
     }
+    a.rnd = 0;
+    a.sweep_dev = nullptr;
     std::vector<unsigned long long> hmv;
     if ((s = download(st, hmv, B.mvg, K)) != GVL_OK) return s;
     std::vector<int32_t> hnz;
@@ -538,11 +569,17 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
         gagg_rows(st, cur, g, gh, hb.c0, hb.c1, hb.s0, hb.s1, &dummy_launches);
       }
     }
-    // move-based labels of the super-vertices, their graphs and bases
-    fill_i32(st, ws.brank, 0, nn + 1);
-    mark_used(st, ws.CB, nn, ws.brank, gid, B.keep);
-    exclusive_scan(st, ws.brank, nn, ws.scan_tmp);
-    next_labels(st, ws.lab, ws.CB, ws.brank, nn, ws.start);
+    // labels of the super-vertices (move-based, Alg. 1; or refine-based,
+    // Sec. 4.1: every super-vertex alone, its union id being its solo id
+    // shifted by its graph's base), their graphs and bases
+    if (opt->refine_based) {
+      iota_i32(st, ws.start, ncom_all);
+    } else {
+      fill_i32(st, ws.brank, 0, nn + 1);
+      mark_used(st, ws.CB, nn, ws.brank, gid, B.keep);
+      exclusive_scan(st, ws.brank, nn, ws.scan_tmp);
+      next_labels(st, ws.lab, ws.CB, ws.brank, nn, ws.start);
+    }
     gid_next(st, ws.C, ws.newid, gid, B.keep, nn, gidn);
     std::vector<int32_t> cont_k, cpos;
     for (int32_t k = 0; k < K; ++k)

@@ -79,12 +79,20 @@ gvl_status gvl_create(gvl_ctx_t* out, int device, void* hip_stream) {
     delete c;
     return s;
   }
+  gvl_tuning_load_once();  // launch shapes per class of graph, from the tune file if there is one
+  // private stream for recording launch sequences into graphs (default
+  // priority; nothing runs on it); without it every launch goes eagerly
+  if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+    c->cap = nullptr;
+    (void)hipGetLastError();
+  }
   *out = c;
   return GVL_OK;
 }
 
 gvl_status gvl_destroy(gvl_ctx_t c) {
   if (!c) return GVL_E_INVALID_ARG;
+  if (c->cap) (void)hipStreamDestroy(c->cap);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->host) (void)hipHostFree(c->host);
   if (c->hbins) (void)hipHostFree(c->hbins);
@@ -203,10 +211,12 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   const bool sync_mv = det || opt->sync_moves != 0;
   a.sync_moves = det ? 3 : (opt->sync_moves & 3);
 
-  // workgroups of one decision launch per bin (measured best on R-MAT scale
-  // 24: 1024, four per CU; 2048 and 512 are slower) and of one aggregation
-  // launch
-  const int grid_cap = 1024, agg_grid_cap = 4096;
+  // launch shapes of the graph's class (tuning.hip): bin limits, workgroups
+  // per decision, commit and aggregation launch
+  const gvl_tuning tune = gvl_tuning_of(gvl_class_of(n, m, false));
+  ctx->lim = bin_limits(tune);
+  const int grid_cap = tune.decide_grid, agg_grid_cap = tune.agg_grid;
+  a.commit_grid = tune.commit_grid;
   GraphDesc cur = input;
   int buf = 0;
   double tau = opt->tolerance;
@@ -294,20 +304,20 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     // chunked path (batch by batch through the table region).
     // (bx, lx: the short-row bins and their list, thinned during refinement;
     // the hubs always come from bins and ws.list)
-    auto decide_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
+    auto decide_group = [&](hipStream_t q, int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       if (phase == kMove)
-        launch_decide_move(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
+        launch_decide_move(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
       else
-        launch_decide_refine(st, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
+        launch_decide_refine(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
       if (bx.count[grp][kHubBin] > 0)  // (thinned refinement: no lone hub left in the group)
         for (const HubBatch& hb : plan.groups[grp]) {
-          tstate.ensure(st, ws, hb.tend - hb.tbase);
+          tstate.ensure(q, ws, hb.tend - hb.tbase);
           hargs.tbase = hb.tbase;
-          hub_decide(st, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
+          hub_decide(q, cur, a, hargs, hb.h0, hb.h1, hb.c0, hb.c1, hb.s0, hb.s1, hb.tend > hb.tbase, phase, det,
                      &S->scan_launches);
         }
     };
-    auto commit_group = [&](int grp, int phase, const BinInfo& bx, const int32_t* lx) {
+    auto commit_group = [&](hipStream_t q, int grp, int phase, const BinInfo& bx, const int32_t* lx) {
       CommitLaunch cl;
       memset(&cl, 0, sizeof(cl));
       const int32_t n0 = bx.gend[grp] - bx.gstart[grp];  // bins 0 .. kHubBin-1 of the group
@@ -326,32 +336,51 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       } else {
         cl.n0 = n0;
       }
-      launch_commit(st, cur, a, hargs, cl, phase);
+      launch_commit(q, cur, a, hargs, cl, phase);
     };
+    // Iterations and sweeps after the first of a phase repeat one launch
+    // sequence with the same arguments: they are replayed as one HIP graph
+    // (not while kernel classes are timed: see Replay).
+    const bool replay = !tm.on && !opt->no_graph_replay;
 
     // ---- 2. local-moving (Alg. 2)
     h = tm.begin(kEvMove);
     int32_t iters = 0;
     bool first_conv = false;
-    for (int32_t it = 0; it < opt->max_iterations; ++it) {
-      fill_u64(st, (unsigned long long*)ws.sc->dq, 0ull, 3 * kCntSlots);
+    a.groups = bins.S;
+    // one iteration: every group decides on the state its predecessors left
+    // (and commits, synchronous schedules); the first iteration of a pass
+    // knows which vertices are still unmarked or (pass 0) unmoved
+    auto move_iteration = [&](hipStream_t q, int32_t it) {
+      fill_u64(q, (unsigned long long*)ws.sc->dq, 0ull, 3 * kCntSlots);
       int hk = sync_mv ? -1 : tm.begin(kEvScanMoveK);
-      a.groups = bins.S;
       for (int32_t grp = 0; grp < bins.S; ++grp) {
         if (sync_mv) hk = tm.begin(kEvScanMoveK);
         a.ident_after = (pass == 0 && it == 0) ? grp : -1;
-        decide_group(grp, kMove, bins, ws.list);
+        decide_group(q, grp, kMove, bins, ws.list);
         a.ident_after = -1;
         if (sync_mv) {
           tm.end(hk);
           a.mark_after = (it == 0) ? grp : INT32_MAX;
-          commit_group(grp, kMove, bins, ws.list);
+          commit_group(q, grp, kMove, bins, ws.list);
           a.mark_after = INT32_MAX;
         }
       }
       if (!sync_mv) tm.end(hk);
+    };
+    Replay move_graph;
+    for (int32_t it = 0; it < opt->max_iterations; ++it) {
+      if (it == 0) {
+        move_iteration(st, 0);
+      } else {
+        const int64_t clean = tstate.clean;
+        s = move_graph.run(ctx, replay, &S->scan_launches, [&](hipStream_t q) { move_iteration(q, it); },
+                           [&] { tstate.clean = clean; });
+        if (s != GVL_OK) return s;
+      }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
+      if (move_graph.launched) ++S->graph_launches;
       ++iters;
       const unsigned long long mv = counter(ctx->host, 3) - moves_before;
       moves_before = counter(ctx->host, 3);
@@ -385,22 +414,37 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       set_size_one(st, ws.size, nn);
       fill_i32(st, ws.targeted, 0, nn);
       pack_labels(st, ws.C, ws.CB, ws.CP, nn);
+      fill_i32(st, &ws.sc->sweep, 0, 1);
     }
     BinInfo rbins;  // after the first sweep: the short-row bins thinned to lone vertices
     const BinInfo* rb = &bins;
     const int32_t* rl = ws.list;
-    for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
-      a.rnd = opt->refine_random;
-      a.sweep = sw;
+    // one sweep: group stamps grp + 1 + sweep * S (unique within the pass),
+    // the sweep number read from the device and advanced by the sweep itself
+    a.rnd = opt->refine_random;
+    a.sweep_dev = &ws.sc->sweep;
+    auto refine_sweep = [&](hipStream_t q) {
       for (int32_t grp = 0; grp < bins.S; ++grp) {
-        a.stamp = sw * bins.S + grp + 1;
+        a.stamp = grp + 1;
         const int hk = tm.begin(kEvScanRefineK);
-        decide_group(grp, kRefine, *rb, rl);
+        decide_group(q, grp, kRefine, *rb, rl);
         tm.end(hk);
-        commit_group(grp, kRefine, *rb, rl);
+        commit_group(q, grp, kRefine, *rb, rl);
+      }
+      add_one_i32(q, &ws.sc->sweep);
+    };
+    Replay refine_graph;  // sweeps from the second on (the thinned bins stay fixed)
+    for (int32_t sw = 0; sw < (opt->louvain ? 0 : opt->refine_sweeps); ++sw) {
+      if (sw == 0) {
+        refine_sweep(st);
+      } else {
+        const int64_t clean = tstate.clean;
+        s = refine_graph.run(ctx, replay, &S->scan_launches, refine_sweep, [&] { tstate.clean = clean; });
+        if (s != GVL_OK) return s;
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
+      if (refine_graph.launched) ++S->graph_launches;
       ++sweeps;
       const unsigned long long mv = counter(ctx->host, 3) - moves_before;
       moves_before = counter(ctx->host, 3);
@@ -414,6 +458,8 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         rl = ws.list2;
       }
     }
+    a.rnd = 0;
+    a.sweep_dev = nullptr;
     tm.end(h);
     // ---- 4. count communities; stop on convergence or low shrink
     h = tm.begin(kEvOther);
@@ -489,11 +535,16 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         }
       }
       tm.end(hk);
-      // move-based labels of the super-vertices (Alg. 1)
-      fill_i32(st, ws.brank, 0, nn + 1);
-      mark_used(st, ws.CB, nn, ws.brank);
-      exclusive_scan(st, ws.brank, nn, ws.scan_tmp);
-      next_labels(st, ws.lab, ws.CB, ws.brank, nn, ws.start);
+      if (opt->refine_based) {
+        // refine-based labels (Sec. 4.1): every super-vertex starts alone
+        iota_i32(st, ws.start, ncom);
+      } else {
+        // move-based labels of the super-vertices (Alg. 1)
+        fill_i32(st, ws.brank, 0, nn + 1);
+        mark_used(st, ws.CB, nn, ws.brank);
+        exclusive_scan(st, ws.brank, nn, ws.scan_tmp);
+        next_labels(st, ws.lab, ws.CB, ws.brank, nn, ws.start);
+      }
       GraphDesc nxt{ncom, yoff, ydeg, ws.idx[nb], ws.w[nb], det};
       if (opt->debug_trace) export_graph(ctx, nxt, ncom, pd);
       cur = nxt;

@@ -27,7 +27,7 @@ struct Scalars {
   double acc_d[2];                  // modularity: S1, S2 (floating)
   unsigned long long acc_u[2];      // modularity: S2 exact (lo, hi)
   int32_t total;                    // scan totals read back
-  int32_t pad;
+  int32_t sweep;                    // refinement sweep number, read by replayed sweeps (ScanArgs::sweep_dev)
 };
 
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -138,8 +138,8 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.pb_g = (double*)take(8 * (size_t)w.max_tasks);
   w.pb_k = (i128_t*)take(16 * (size_t)w.max_tasks);
   w.pb_c = (int32_t*)take(4 * (size_t)w.max_tasks);
-  // vertices of the wide bins: degree > kBinMax[5]
-  w.max_wide = std::min<int64_t>((int64_t)N, (int64_t)M / (kBinMax[5] + 1) + 1);
+  // vertices of the wide bins: degree above the bin-5 limit, at least kMinBin5
+  w.max_wide = std::min<int64_t>((int64_t)N, (int64_t)M / (kMinBin5 + 1) + 1);
   const size_t wq = (size_t)w.max_wide * kWideMaxParts;
   w.wd_g = (double*)take(8 * wq);
   w.wd_k = (i128_t*)take(16 * wq);
@@ -176,6 +176,8 @@ using namespace gvl;
 struct gvl_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;  // private stream on which launch sequences are recorded into HIP graphs
+  BinLimits lim = {{4, 8, 16, 32, 128, 1024, 4096, 8192, 16384, 0x7fffffff}};  // bin limits of the call
   Scalars* host = nullptr;  // pinned
   BinBuf* hbins = nullptr;  // pinned
   std::vector<hipEvent_t> events;
@@ -186,6 +188,13 @@ struct gvl_ctx {
 // gvl_leiden_static's device array: resolves its address on `device` (the
 // current device) once per device; called by gvl_create (static_ws.hip).
 gvl_status gvl_static_scratch_setup(int device);
+
+// Launch-shape tuning (tuning.hip): the table is loaded from the tune file
+// once per process; class of a graph; the values of a class; bin limits.
+void gvl_tuning_load_once();
+int32_t gvl_class_of(int64_t n, int64_t m, bool fused);
+gvl_tuning gvl_tuning_of(int32_t cls);
+BinLimits bin_limits(const gvl_tuning& t);
 
 namespace {
 
@@ -204,6 +213,20 @@ namespace {
 enum { kEvMove = 0, kEvRefine = 1, kEvAgg = 2, kEvOther = 3, kEvScanMoveK = 4, kEvScanRefineK = 5,
        kEvAggK = 6, kEvClasses = 7 };
 
+// Checks a HIP call whose failure the caller handles itself: reports it on
+// stderr (the first 32 in a process) and clears the thread's last-error
+// state so that it does not surface in the caller's later HIP calls.
+inline bool hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  static int reported = 0;
+  if (reported < 32) {
+    ++reported;
+    fprintf(stderr, "gvl: %s failed: %s\n", what, hipGetErrorString(e));
+  }
+  (void)hipGetLastError();
+  return false;
+}
+
 struct Timer {
   gvl_ctx* ctx;
   bool on;
@@ -212,7 +235,7 @@ struct Timer {
   hipEvent_t get() {
     if (ctx->ev_used == ctx->events.size()) {
       hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      if (!hip_ok(hipEventCreate(&e), "hipEventCreate")) return nullptr;
       ctx->events.push_back(e);
     }
     return ctx->events[ctx->ev_used++];
@@ -220,24 +243,88 @@ struct Timer {
   int begin(int cls) {
     if (!on) return -1;
     hipEvent_t e = get();
-    if (!e) return -1;
-    (void)hipEventRecord(e, ctx->stream);
+    if (!e || !hip_ok(hipEventRecord(e, ctx->stream), "hipEventRecord")) return -1;
     spans.push_back({cls, e, nullptr});
     return (int)spans.size() - 1;
   }
   void end(int h) {
     if (h < 0) return;
     hipEvent_t e = get();
-    if (!e) return;
-    (void)hipEventRecord(e, ctx->stream);
+    if (!e || !hip_ok(hipEventRecord(e, ctx->stream), "hipEventRecord")) return;
     spans[h].b = e;
   }
   void totals(double* ms) {
     for (int k = 0; k < kEvClasses; ++k) ms[k] = 0.0;
     for (auto& sp : spans) {
       float t = 0.f;
-      if (sp.b && hipEventElapsedTime(&t, sp.a, sp.b) == hipSuccess) ms[sp.cls] += t;
+      if (sp.b && hip_ok(hipEventElapsedTime(&t, sp.a, sp.b), "hipEventElapsedTime")) ms[sp.cls] += t;
     }
+  }
+};
+
+// A launch sequence (one local-moving iteration, one refinement sweep)
+// recorded once into a HIP graph on the context's private stream, then
+// launched as one graph on the context's stream, so its kernels run back to
+// back instead of each waiting for the host to issue it.  body(stream) must
+// enqueue only kernel launches whose arguments stay valid for every launch
+// of the graph.  If recording fails the sequence runs eagerly from then on.
+// *launches counts the kernels of every launch.  Not used while kernel
+// classes are timed: HIP reports no elapsed time between events recorded by
+// graph nodes, so timed runs launch every kernel from the host.
+struct Replay {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool broken = false;
+  bool launched = false;
+  int64_t per_launch = 0;
+  Replay() = default;
+  Replay(const Replay&) = delete;
+  Replay& operator=(const Replay&) = delete;
+  ~Replay() { reset(); }
+  void reset() {
+    if (exec) hip_ok(hipGraphExecDestroy(exec), "hipGraphExecDestroy");
+    if (graph) hip_ok(hipGraphDestroy(graph), "hipGraphDestroy");
+    exec = nullptr;
+    graph = nullptr;
+    broken = false;
+    per_launch = 0;
+  }
+  // undo(): restores host-side state the body changed while it was only
+  // being recorded (called before the eager fallback of a failed recording)
+  template <class F, class U>
+  gvl_status run(gvl_ctx* ctx, bool use, int64_t* launches, F&& body, U&& undo) {
+    launched = false;
+    if (use && !broken && !exec && ctx->cap) {
+      const int64_t before = *launches;
+      if (hip_ok(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture")) {
+        body(ctx->cap);
+        hipGraph_t g = nullptr;
+        const bool ended = hip_ok(hipStreamEndCapture(ctx->cap, &g), "hipStreamEndCapture");
+        if (ended && g && hip_ok(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "hipGraphInstantiate")) {
+          graph = g;
+          per_launch = *launches - before;
+          *launches = before;
+        } else {
+          if (g) hip_ok(hipGraphDestroy(g), "hipGraphDestroy");
+          exec = nullptr;
+          broken = true;
+          *launches = before;
+          undo();
+          (void)hipGetLastError();
+        }
+      } else {
+        broken = true;
+        (void)hipGetLastError();
+      }
+    }
+    if (use && exec) {
+      HIP_TRY(hipGraphLaunch(exec, ctx->stream));
+      *launches += per_launch;
+      launched = true;
+      return GVL_OK;
+    }
+    body(ctx->stream);
+    return GVL_OK;
   }
 };
 
@@ -254,7 +341,7 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
                      bool wide, BinInfo& bins, const int32_t* gid = nullptr, const int32_t* vbase = nullptr) {
   hipStream_t st = ctx->stream;
   fill_i32(st, (int32_t*)ws.bb, 0, (int64_t)(sizeof(BinBuf) / sizeof(int32_t)));
-  bin_count(st, off, deg, n, S, wide, gid, vbase, ws.bb);
+  bin_count(st, off, deg, n, S, wide, gid, vbase, ctx->lim, ws.bb);
   HIP_TRY(hipMemcpyAsync(ctx->hbins, ws.bb, sizeof(BinBuf), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   bins.S = S;
@@ -282,7 +369,7 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
   for (int b = 0; b < kNumBins; ++b) bins.maxsize[b] = ctx->hbins->maxsize[b];
   HIP_TRY(hipMemcpyAsync(ws.bb->cursors, ctx->hbins->cursors, sizeof(int32_t) * S * kNumBins,
                          hipMemcpyHostToDevice, st));
-  bin_scatter(st, off, deg, n, S, wide, gid, vbase, ws.bb, ws.list);
+  bin_scatter(st, off, deg, n, S, wide, gid, vbase, ctx->lim, ws.bb, ws.list);
   return GVL_OK;
 }
 
@@ -494,7 +581,8 @@ gvl_status check_args(gvl_ctx* ctx, int64_t n, int64_t m, const int32_t* off, co
   if (!(resolution >= 0.0) || !std::isfinite(resolution)) return GVL_E_RESOLUTION;
   if (opt->mode != GVL_MODE_FAST && opt->mode != GVL_MODE_DET) return GVL_E_INVALID_ARG;
   if ((opt->louvain != 0 && opt->louvain != 1) || (opt->refine_random != 0 && opt->refine_random != 1) ||
-      (opt->shrink_excludes_isolated != 0 && opt->shrink_excludes_isolated != 1) || opt->validate < 0 ||
+      (opt->shrink_excludes_isolated != 0 && opt->shrink_excludes_isolated != 1) ||
+      (opt->refine_based != 0 && opt->refine_based != 1) || opt->validate < 0 ||
       opt->validate > 2)
     return GVL_E_INVALID_ARG;
   if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 1 ||

@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
             }
           } else {
             a.target[i] = bc;
-            a.targeted[bc] = a.stamp;
+            a.targeted[bc] = cur_stamp(a);
           }
         }
       }
@@ -576,7 +576,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
           add_gain<DET>(a, acc, i, bg, bk);
         } else {
           a.target[i] = bc;
-          a.targeted[bc] = a.stamp;
+          a.targeted[bc] = cur_stamp(a);
         }
       }
     }

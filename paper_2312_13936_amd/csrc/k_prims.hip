@@ -45,6 +45,10 @@ void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64
 void iota_i32(hipStream_t st, int32_t* p, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_iota, dim3(grid_n(n)), dim3(kBlock), 0, st, p, n);
 }
+__global__ void k_add_one(int32_t* p) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *p += 1;
+}
+void add_one_i32(hipStream_t st, int32_t* p) { hipLaunchKernelGGL(k_add_one, dim3(1), dim3(64), 0, st, p); }
 void copy_i32(hipStream_t st, int32_t* d, const int32_t* s, int64_t n) {
   if (n > 0) hipLaunchKernelGGL(k_copy<int32_t>, dim3(grid_n(n)), dim3(kBlock), 0, st, d, s, n);
 }
@@ -245,12 +249,12 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
 }
 
 // ---------------------------------------------------------------- binning ---
-__device__ __forceinline__ int bin_of(int32_t d, bool wide) {
+__device__ __forceinline__ int bin_of(int32_t d, bool wide, const BinLimits& lim) {
   if (d <= 0) return -1;
 #pragma unroll
   for (int b = 0; b < kNumBins; ++b) {
     if (!wide && b > kAggLastBin) return kHubBin;
-    if (d <= kBinMax[b]) return b;
+    if (d <= lim.v[b]) return b;
   }
   return kHubBin;
 }
@@ -267,7 +271,7 @@ __device__ __forceinline__ int group_local(int64_t i, int S, const int32_t* gid,
 
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const int32_t* deg, int64_t n, int S,
                                                       bool wide, const int32_t* gid, const int32_t* vbase,
-                                                      BinBuf* bb) {
+                                                      BinLimits lim, BinBuf* bb) {
   __shared__ int32_t h[kMaxGroups * kNumBins], mx[kNumBins];
   const int nk = S * kNumBins;
   for (int k = threadIdx.x; k < nk; k += kBlock) h[k] = 0;
@@ -275,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
   __syncthreads();
   GRID_STRIDE(i, n) {
     const int32_t d = size_of(off, deg, i);
-    const int b = bin_of(d, wide);
+    const int b = bin_of(d, wide, lim);
     if (b >= 0) {
       const int grp = (S > 1) ? group_local(i, S, gid, vbase) : 0;
       atomicAdd(&h[grp * kNumBins + b], 1);
@@ -288,10 +292,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
   if (threadIdx.x < kNumBins && mx[threadIdx.x]) atomicMax(&bb->maxsize[threadIdx.x], mx[threadIdx.x]);
 }
 void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-               const int32_t* gid, const int32_t* vbase, BinBuf* bb) {
+               const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb) {
   if (n > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, st, off, deg, n, S, wide, gid,
-                       vbase, bb);
+                       vbase, lim, bb);
 }
 
 // Each workgroup takes a contiguous chunk of items, reserves room per key
@@ -300,7 +304,7 @@ void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n
 constexpr int kBinChunk = 4096;
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, const int32_t* deg, int64_t n, int S,
                                                         bool wide, const int32_t* gid, const int32_t* vbase,
-                                                        BinBuf* bb, int32_t* list) {
+                                                        BinLimits lim, BinBuf* bb, int32_t* list) {
   __shared__ int32_t h[kMaxGroups * kNumBins], base[kMaxGroups * kNumBins];
   const int nk = S * kNumBins;
   for (int64_t c0 = (int64_t)blockIdx.x * kBinChunk; c0 < n; c0 += (int64_t)gridDim.x * kBinChunk) {
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     __syncthreads();
     const int64_t c1 = (c0 + kBinChunk < n) ? c0 + kBinChunk : n;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-      const int b = bin_of(size_of(off, deg, i), wide);
+      const int b = bin_of(size_of(off, deg, i), wide, lim);
       if (b >= 0) atomicAdd(&h[((S > 1) ? group_local(i, S, gid, vbase) : 0) * kNumBins + b], 1);
     }
     __syncthreads();
@@ -318,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     }
     __syncthreads();
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
-      const int b = bin_of(size_of(off, deg, i), wide);
+      const int b = bin_of(size_of(off, deg, i), wide, lim);
       if (b >= 0) {
         const int k = ((S > 1) ? group_local(i, S, gid, vbase) : 0) * kNumBins + b;
         list[base[k] + atomicAdd(&h[k], 1)] = (int32_t)i;
@@ -328,10 +332,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
   }
 }
 void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-                 const int32_t* gid, const int32_t* vbase, BinBuf* bb, int32_t* list) {
+                 const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb, int32_t* list) {
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_n(n, kBinChunk, 2048)), dim3(kBlock), 0, st, off, deg, n, S,
-                       wide, gid, vbase, bb, list);
+                       wide, gid, vbase, lim, bb, list);
 }
 
 // ---------------------------------------------------------- exclusive scan ---

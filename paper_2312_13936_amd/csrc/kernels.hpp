@@ -42,6 +42,18 @@ constexpr int kWideSlots = 12288;  // 144 KiB of LDS (keys + FP64 values)
 constexpr int kAggLastBin = 7;
 constexpr int kHubBin = kNumBins - 1;
 
+// Bin limits in use: the upper limits of the lane-group bins 0-4 and of the
+// workgroup bin 5 are tunable at run time, each at most its compiled
+// kBinMax (the kernels of a bin handle any shorter row) and non-decreasing;
+// a bin whose limit equals its predecessor's is empty.  Longer bins keep
+// kBinMax.  The lowest allowed limit of bin 5 bounds the wide-row work
+// arrays of the workspace.
+constexpr int kTunedBins = 6;
+constexpr int32_t kMinBin5 = 256;
+struct BinLimits {
+  int32_t v[kNumBins];
+};
+
 // Local-moving and refinement visit the vertices in S pseudo-random groups
 // (sub-sweeps); the bin lists are laid out group-major so that every
 // (group, bin) segment is contiguous.
@@ -101,7 +113,10 @@ struct ScanArgs {
   uint8_t* flag;            // local-moving: 1 = unprocessed
   int32_t* target;          // synchronous decisions: chosen community or -1
   int32_t* targeted;        // refinement: stamp of the last group that chose the community as a target
-  int32_t stamp;            // refinement: stamp of the current group (unique within a pass, > 0)
+  int32_t stamp;            // refinement: stamp of the current group (unique within a pass, > 0): with
+                            // sweep_dev, stamp + *sweep_dev * groups
+  const int32_t* sweep_dev; // refinement sweep number in device memory (a replayed sweep reads it
+                            // there), or nullptr: the stamp and sweep fields hold the values
   double inv_m;             // 1/m = 2/W
   double gk_scale;          // 2 gamma / W^2
   long long W;              // exact total weight (deterministic mode)
@@ -126,6 +141,7 @@ struct ScanArgs {
   double* dqg;              // [G] fast mode
   unsigned long long* dqg128;  // [G][lo, hi] deterministic mode
   unsigned long long* mvg;  // [G] refinement moves
+  int32_t commit_grid;      // workgroups per role of a commit launch (at most)
   int32_t sync_moves;       // local-moving records decisions (committed per group) instead of
                             // committing at once: bit 0 rows <= kBinMax[4], bit 1 longer rows
   // randomized refinement (rnd = 1 during refinement sweeps only): draws of
@@ -335,6 +351,7 @@ void fill_f64(hipStream_t st, double* p, double v, int64_t n);
 void fill_slots(hipStream_t st, TblSlot* p, int64_t n);  // empty slots
 void fill_u64(hipStream_t st, unsigned long long* p, unsigned long long v, int64_t n);
 void iota_i32(hipStream_t st, int32_t* p, int64_t n);
+void add_one_i32(hipStream_t st, int32_t* p);  // *p += 1 (a replayable counter step)
 void copy_i32(hipStream_t st, int32_t* dst, const int32_t* src, int64_t n);
 void pack_labels(hipStream_t st, const int32_t* C, const int32_t* CB, int2* CP, int64_t n);
 // Refinement: the items of the bins (segment s = g * kNumBins + b:
@@ -365,9 +382,9 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
 // gid / vbase (fused batches, else nullptr): the group of item i is taken
 // from its id inside its own graph, i - vbase[gid[i]].
 void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-               const int32_t* gid, const int32_t* vbase, BinBuf* bb);
+               const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb);
 void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-                 const int32_t* gid, const int32_t* vbase, BinBuf* bb, int32_t* list);
+                 const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb, int32_t* list);
 // used[c] = 1 for every label c in C[0..n) (used zeroed by the caller);
 // with gid / keep only for vertices of graphs g with keep[g].
 void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used, const int32_t* gid = nullptr,

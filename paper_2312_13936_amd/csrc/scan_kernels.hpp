@@ -24,6 +24,13 @@
 
 namespace gvl {
 
+// Refinement stamp of the current group and the current sweep number (see
+// ScanArgs::sweep_dev).
+__device__ __forceinline__ int32_t cur_stamp(const ScanArgs& a) {
+  return a.sweep_dev ? a.stamp + *a.sweep_dev * a.groups : a.stamp;
+}
+__device__ __forceinline__ int32_t cur_sweep(const ScanArgs& a) { return a.sweep_dev ? *a.sweep_dev : a.sweep; }
+
 template <int PH, bool DET>
 struct Decide {
   // Returns true if vertex i is to be scanned in this launch.
@@ -109,7 +116,7 @@ struct Eval {
     return (kic - kid) * inv_m - gk * (ki + kic - sd) > 0.0;
   }
   __device__ __forceinline__ double score(const ScanArgs& a, double gain, int32_t c) const {
-    return gain / neg_ln_unit(draw32(a.seed, a.pass, a.sweep, il, c - base));
+    return gain / neg_ln_unit(draw32(a.seed, a.pass, cur_sweep(a), il, c - base));
   }
   __device__ __forceinline__ void operator()(const ScanArgs& a, int32_t c, double kic, double sc,
                                              double& bg, i128& bk, int32_t& bc) const {
@@ -335,7 +342,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
         add_gain<DET>(a, acc, i, bg, bk);
       }
     } else {
-      if (gl == 0) { a.target[i] = bc; a.targeted[bc] = a.stamp; }
+      if (gl == 0) { a.target[i] = bc; a.targeted[bc] = cur_stamp(a); }
     }
   }
   flush_acc<PH, DET>(a, acc);
@@ -431,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
         add_gain<DET>(a, acc, i, bg, bk);
       }
     } else {
-      if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = a.stamp; }
+      if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = cur_stamp(a); }
     }
   }
   flush_acc<PH, DET>(a, acc);
@@ -599,7 +606,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
           add_gain<DET>(a, acc, i, bg, bk);
         } else {
           a.target[i] = bc;
-          a.targeted[bc] = a.stamp;
+          a.targeted[bc] = cur_stamp(a);
         }
       }
       s_take = take;
@@ -657,7 +664,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
       const int32_t d = a.C[i];
       if (PH == kRefine) {
         a.target[i] = -1;
-        if (a.targeted[d] == a.stamp) mv = false;  // own community chosen by this group
+        if (a.targeted[d] == cur_stamp(a)) mv = false;  // own community chosen by this group
       }
       if (mv) {
         const double ki = a.K[i];
@@ -841,13 +848,14 @@ void commit_group_launch(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
                          CommitLaunch cl) {
   const GraphView<WT> g = view<WT>(gd);
   int32_t nblk[4];
+  const int cap = a.commit_grid > 0 ? a.commit_grid : 2048;
   if (PH == kRefine) {
-    nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, 2048) : 0;
-    nblk[1] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, 2048) : 0;
+    nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, cap) : 0;
+    nblk[1] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, cap) : 0;
     nblk[2] = nblk[3] = 0;
   } else {
-    nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, 2048) : 0;
-    nblk[1] = cl.n1 > 0 ? grid_for(cl.n1, 1, 2048) : 0;
+    nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, cap) : 0;
+    nblk[1] = cl.n1 > 0 ? grid_for(cl.n1, 1, cap) : 0;
     nblk[2] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, 64) : 0;
     nblk[3] = cl.c1 > cl.c0 ? grid_for(cl.c1 - cl.c0, 1, 4096) : 0;
   }

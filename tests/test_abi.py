@@ -61,3 +61,53 @@ def test_status_strings(lib):
     assert gvl.gvl_status_string(0) == "ok"
     assert "workspace" in gvl.gvl_status_string(-6)
     assert gvl.gvl_status_string(12345) == "unknown status"
+
+
+def test_tuning_table_validation_and_classes(lib):
+    assert gvl.gvl_graph_class(10000, 147000) == gvl.GVL_CLASS_SMALL
+    assert gvl.gvl_graph_class(16777216, 61047992) == gvl.GVL_CLASS_LOWDEG
+    assert gvl.gvl_graph_class(16777216, 520764976) == gvl.GVL_CLASS_SKEWED
+    assert gvl.gvl_graph_class(100, 10, fused=True) == gvl.GVL_CLASS_BATCH
+    saved = [gvl.gvl_get_tuning(c) for c in range(gvl.GVL_NUM_CLASSES)]
+    try:
+        t = gvl.gvl_tuning.from_buffer_copy(saved[0])
+        t.bin_max[4] = 64
+        t.decide_grid = 512
+        gvl.gvl_set_tuning(gvl.GVL_CLASS_SMALL, t)
+        got = gvl.gvl_get_tuning(gvl.GVL_CLASS_SMALL)
+        assert list(got.bin_max)[4] == 64 and got.decide_grid == 512
+        for bad in (dict(b=4, v=256), dict(b=5, v=128), dict(b=3, v=8)):  # above compiled, below 256, decreasing
+            u = gvl.gvl_tuning.from_buffer_copy(saved[0])
+            u.bin_max[bad["b"]] = bad["v"]
+            with pytest.raises(gvl.GvlError):
+                gvl.gvl_set_tuning(gvl.GVL_CLASS_SMALL, u)
+        u = gvl.gvl_tuning.from_buffer_copy(saved[0])
+        u.agg_grid = 0
+        with pytest.raises(gvl.GvlError):
+            gvl.gvl_set_tuning(gvl.GVL_CLASS_SMALL, u)
+        with pytest.raises(gvl.GvlError):
+            gvl.gvl_set_tuning(7, saved[0])
+    finally:
+        for c, t in enumerate(saved):
+            gvl.gvl_set_tuning(c, t)
+
+
+def test_tuning_file_is_parsed(lib, tmp_path, capfd):
+    saved = [gvl.gvl_get_tuning(c) for c in range(gvl.GVL_NUM_CLASSES)]
+    p = tmp_path / "tune.txt"
+    p.write_text("# comment\nlowdeg 4 8 16 16 64 512 2048 1024 8192  # trailing comment\n"
+                 "skewed 4 8 16 32 256 1024 1024 2048 4096\nunknown 1 2 3\n")
+    try:
+        gvl.gvl_load_tuning(str(p))
+        t = gvl.gvl_get_tuning(gvl.GVL_CLASS_LOWDEG)
+        assert list(t.bin_max) == [4, 8, 16, 16, 64, 512] and (t.decide_grid, t.commit_grid, t.agg_grid) == (2048, 1024,
+                                                                                                          8192)
+        # the invalid lines (bin 4 above 128; unknown class) are skipped and reported
+        assert list(gvl.gvl_get_tuning(gvl.GVL_CLASS_SKEWED).bin_max) == list(saved[gvl.GVL_CLASS_SKEWED].bin_max)
+        err = capfd.readouterr().err
+        assert "tune.txt:3" in err and "tune.txt:4" in err
+        with pytest.raises(gvl.GvlError):
+            gvl.gvl_load_tuning(str(tmp_path / "missing.txt"))
+    finally:
+        for c, t in enumerate(saved):
+            gvl.gvl_set_tuning(c, t)

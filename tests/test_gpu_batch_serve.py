@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
 import paper_2312_13936_amd as gvl  # noqa: E402
-from test_gpu_parity import WIDER_BAR as _SOLO_WIDER  # noqa: E402
+from test_gpu_parity import ASYNC_TRIES, WIDER_BAR as _SOLO_WIDER, async_bar, check_fast_run  # noqa: E402
 
 FAST_TOL = 1e-3
 # Per-graph margins wider than 1e-3 (by generated graph name), by the rules
@@ -107,8 +107,7 @@ def check_fast_mix(gs, mems, qs):
     the wider margin that WIDER_BAR states for that graph)."""
     short = []
     for g, mem, q in zip(gs, mems, qs):
-        assert q == oracle.modularity(g, mem), g.name
-        assert oracle.disconnected(g, mem) == 0, g.name
+        check_fast_run(g, mem, q)
         if g.m == 0:
             continue
         q0 = oracle.leiden(g, mode=oracle.SEQ_ASYNC).q
@@ -119,12 +118,37 @@ def check_fast_mix(gs, mems, qs):
     assert not short, "; ".join(short)
 
 
+def check_async_mix(gs, once):
+    """The asynchronous schedule's bar over a mix (the rule stated with
+    ASYNC_TRIES in test_gpu_parity.py): once() runs the whole mix and returns
+    (memberships, modularities); every run's results must report Eq. 1 and
+    have no disconnected community, and for each graph the best of up to
+    ASYNC_TRIES runs must reach its bar."""
+    bars = {k: async_bar(g, g.name, WIDER_BAR.get(g.name, FAST_TOL)) for k, g in enumerate(gs) if g.m > 0}
+    best = {k: -np.inf for k in bars}
+    for t in range(ASYNC_TRIES):
+        mems, qs = once()
+        for g, mem, q in zip(gs, mems, qs):
+            check_fast_run(g, mem, q)
+        for k, (q0, bar) in bars.items():
+            best[k] = max(best[k], qs[k])
+        short = [k for k, (q0, bar) in bars.items() if best[k] < bar]
+        print("  try %d: %d of %d graphs below their bar" % (t, len(short), len(bars)), flush=True)
+        if not short:
+            return
+    assert not short, "; ".join("%s: best fast Q %.6f vs sequential oracle %.6f (bar %.6f)" % (
+        gs[k].name, best[k], bars[k][0], bars[k][1]) for k in short)
+
+
 def test_batch_fast_quality(eng):
     gs = batch_graphs()
     print("batch fast: %d graphs" % len(gs), flush=True)
-    code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_FAST, 6, sync_moves=0)
-    assert code == 0
-    check_fast_mix(gs, mems, qs)
+
+    def once():
+        code, mems, qs, sts = run_batch(eng, gs, gvl.GVL_MODE_FAST, 6, sync_moves=0)
+        assert code == 0
+        return mems, qs
+    check_async_mix(gs, once)
 
 
 def test_batch_bad_graph_in_mix(eng):
@@ -211,9 +235,15 @@ def test_fused_det_resolutions_and_subsweeps(eng):
 @pytest.mark.parametrize("sync_moves", [3, 0])
 def test_fused_fast_quality(eng, sync_moves):
     gs = fused_graphs()
-    code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
-    assert code == 0
-    check_fast_mix(gs, mems, qs)
+
+    def once():
+        code, mems, qs, sts = run_fused(eng, gs, gvl.GVL_MODE_FAST, sync_moves=sync_moves)
+        assert code == 0
+        return mems, qs
+    if sync_moves == 3:
+        check_fast_mix(gs, *once())
+    else:
+        check_async_mix(gs, once)
 
 
 def test_fused_fast_sync_matches_solo(eng):
@@ -307,10 +337,13 @@ def test_serve_mix_fast_quality(eng):
     opt = gvl.Leiden.options(gvl.GVL_MODE_FAST)
     arena = 6 * max(footprint(g, opt) for g in gs)
     print("serve fast: %d requests" % len(gs), flush=True)
-    mix, st = serve(gs, tensors, gvl.GVL_MODE_FAST, 4, arena, alone=False, sync_moves=0)
+
     # asynchronous commits make every run differ a little, alone or in a
-    # mix, so the mix is held to the fast-mode quality bar
-    check_fast_mix(gs, [m for m, _ in mix], [q for _, q in mix])
+    # mix, so the mix is held to the asynchronous schedule's quality bar
+    def once():
+        mix, st = serve(gs, tensors, gvl.GVL_MODE_FAST, 4, arena, alone=False, sync_moves=0)
+        return [m for m, _ in mix], [q for _, q in mix]
+    check_async_mix(gs, once)
 
 
 def test_serve_alone_vs_mix_fast_sync(eng):

@@ -280,3 +280,28 @@ def test_planted_c1_blocks_and_recovery():
         assert _nmi(r.membership, g.truth) >= nmi_min, (mode, tau)
         assert q_planted - dq_max <= r.q <= q_planted + 0.005, (mode, tau, r.q)
         assert oracle.disconnected(g, r.membership) == 0
+
+
+# ------------------------------------------ refine-based labels (Sec. 4.1) ---
+
+@pytest.mark.parametrize("mode", [oracle.SEQ_ASYNC, oracle.DET_SYNC])
+@pytest.mark.parametrize("maker", [lambda: gen.planted(12, 80, 0.1, 0.004, seed=3), lambda: gen.rmat(11, 8, seed=4),
+                                   lambda: gen.grid(40, 40, seed=2), lambda: gen.lfr(3000, seed=8)])
+def test_refine_based_labels_restart_each_pass_from_singletons(mode, maker):
+    # With refine-based labels every super-vertex starts alone, so pass 1 is
+    # pass 0 of a run on the super-vertex graph of pass 0 (with the tolerance
+    # already divided by the drop factor): its local-moving and refined labels
+    # must equal that run's.  Move-based labels start pass 1 elsewhere.
+    g = maker()
+    r = oracle.leiden(g, mode=mode, trace=True, refine_based=1)
+    assert len(r.passes) >= 2
+    t0, t1 = r.passes[0], r.passes[1]
+    y = gen.Graph(len(t0.y_off) - 1, len(t0.y_idx), t0.y_off, t0.y_idx, t0.y_w.astype(np.float32))
+    fresh = oracle.leiden(y, mode=mode, trace=True, tolerance=0.01 / 10.0, max_passes=1)
+    assert np.array_equal(t1.bound, fresh.passes[0].bound)
+    assert np.array_equal(t1.refined, fresh.passes[0].refined)
+    m = oracle.leiden(g, mode=mode, trace=True)
+    assert not np.array_equal(m.passes[1].bound, fresh.passes[0].bound) or len(m.passes[1].bound) != y.n
+    # the Leiden guarantees hold as with move-based labels
+    assert oracle.disconnected(g, r.membership) == 0
+    assert r.q == oracle.modularity(g, r.membership)
