@@ -114,15 +114,24 @@ def test_louvain_det_bit_exact(eng, name):
     assert st.termination == o.termination
 
 
+# Per-graph margin wider than 1e-3, by rule (i) of test_gpu_parity.py:
+#   rmat-s14  the sequential Louvain oracle's spread over the given and seven
+#             seeded numberings is 3.07e-3 (0.100831 .. 0.103904); its
+#             group-synchronous run (exact arithmetic) lands 2.45e-3 below
+#             the given numbering's sequential result
+LOUVAIN_WIDER = {"rmat-s14": 3.1e-3}
+
+
 @pytest.mark.parametrize("name", ["rmat-s14", "planted-C1", "grid200-w100", "hubs-wide"])
 def test_louvain_fast_quality(eng, name):
     g = graph(name)
     mem, q, _ = run(eng, g, gvl.GVL_MODE_FAST, louvain=1)
-    assert q == pytest.approx(oracle.modularity(g, mem), abs=1e-9)
-    # the fast-mode bar of the Leiden runs: the lower of the oracle's
-    # sequential and synchronous schedules, minus 1e-3
-    ref = min(oracle.leiden(g, mode=m, louvain=1).q for m in (oracle.SEQ_ASYNC, oracle.DET_SYNC))
-    assert q >= ref - 1e-3, (q, ref)
+    assert q == oracle.modularity(g, mem)  # reported Q is Eq. 1 of the returned membership
+    # the fast-mode bar: the sequential oracle (Louvain too) on the graph as
+    # numbered, minus 1e-3 (or LOUVAIN_WIDER's margin)
+    ref = oracle.leiden(g, mode=oracle.SEQ_ASYNC, louvain=1).q
+    print("  louvain %s: fast Q %.6f, sequential oracle %.6f, margin %+.6f" % (name, q, ref, q - ref), flush=True)
+    assert q >= ref - LOUVAIN_WIDER.get(name, 1e-3), (q, ref)
 
 
 def test_louvain_fused_matches_solo(eng):
@@ -177,9 +186,13 @@ def test_random_refinement_fused_matches_oracle(eng):
 def test_random_refinement_fast_quality(eng, name):
     g = graph(name)
     mem, q, _ = run(eng, g, gvl.GVL_MODE_FAST, refine_random=1, seed=7)
-    assert q == pytest.approx(oracle.modularity(g, mem), abs=1e-9)
+    assert q == oracle.modularity(g, mem)
     assert check(eng, g, mem)[0] == 0
-    ref = min(oracle.leiden(g, mode=m, refine_random=1, seed=7).q for m in (oracle.SEQ_ASYNC, oracle.DET_SYNC))
+    # the sequential oracle with the same randomized refinement and seed, on
+    # the graph as numbered, minus 1e-3
+    ref = oracle.leiden(g, mode=oracle.SEQ_ASYNC, refine_random=1, seed=7).q
+    print("  random refinement %s: fast Q %.6f, sequential oracle %.6f, margin %+.6f" % (name, q, ref, q - ref),
+          flush=True)
     assert q >= ref - 1e-3, (q, ref)
 
 
