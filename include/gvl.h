@@ -42,7 +42,10 @@ typedef enum {
   GVL_E_WORKSPACE = -6,         /* workspace null or smaller than gvl_workspace_bytes */
   GVL_E_HIP = -8,               /* a HIP runtime call failed */
   GVL_E_BUSY = -9,              /* serving: request not in a state that allows the call */
-  GVL_E_BATCH = -10             /* batch: at least one graph failed (see its status) */
+  GVL_E_BATCH = -10,            /* batch: at least one graph failed (see its status) */
+  GVL_E_TABLE_OVERFLOW = -11    /* deterministic mode: a key partition of a wide row or hub held more
+                                   distinct neighbour communities than its LDS table (gvl_stats.
+                                   table_overflows); the decision could not be computed exactly */
 } gvl_status;
 
 enum { GVL_MODE_FAST = 0, GVL_MODE_DET = 1 };
@@ -67,7 +70,9 @@ typedef struct {
   int32_t refine_sweeps;         /* cap on synchronous refinement sweeps per pass; sweeps stop
                                     early once one moves no vertex (1 = the single sweep of Alg. 3) */
   int32_t subsweeps;             /* S <= 64: local-moving and refinement visit the vertices in S
-                                    pseudo-random groups in turn (sub-sweeps) */
+                                    pseudo-random groups in turn (sub-sweeps).  0 (fast mode only,
+                                    its default): S = 8 if no vertex of the input has more than 128
+                                    arcs, else 32 (deterministic mode default: 32) */
   int32_t validate;              /* 0: none; 1: CSR bounds and weight checks on the device (default);
                                     2: also symmetry (Sec. 3.1: the graph is undirected, each edge
                                     stored as two arcs with one weight): a multiset hash of the arcs
@@ -137,6 +142,9 @@ typedef struct {
   int64_t scan_refine_arcs;      /* part of scan_arcs read by refinement */
   double ms_scan_move_kernels;   /* part of ms_scan_kernels spent in local-moving */
   int64_t graph_launches;        /* iterations and sweeps run as one replayed HIP graph */
+  int64_t table_overflows;       /* decisions of wide rows and hubs whose key partition overflowed its
+                                    LDS table: the vertex stays put (fast mode); deterministic mode
+                                    returns GVL_E_TABLE_OVERFLOW instead */
 } gvl_stats;
 
 /* Create a context bound to `device` and to the HIP stream `hip_stream`
@@ -292,8 +300,10 @@ gvl_status gvl_leiden_batch(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_d
  * workspace holds the largest run.  statuses: host gvl_status[num_graphs]
  * (per-graph input errors as gvl_leiden reports them); modularities: host
  * double[num_graphs].  Returns GVL_E_BATCH if any graph failed, the others
- * are still computed.  Work already queued on ctx's stream comes first; the
- * call returns when every membership is written. */
+ * are still computed; in deterministic mode a partition table overflow in
+ * any graph fails the whole call with GVL_E_TABLE_OVERFLOW.  Work already
+ * queued on ctx's stream comes first; the call returns when every
+ * membership is written. */
 gvl_status gvl_fused_workspace_bytes(int32_t num_graphs, const gvl_graph_desc* graphs, const gvl_options* opt,
                                      size_t* bytes);
 gvl_status gvl_leiden_fused(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_desc* graphs, const gvl_options* opt,

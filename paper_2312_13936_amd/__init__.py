@@ -26,7 +26,8 @@ GVL_MAX_PASS_STATS = 64
 
 STATUS = {0: "GVL_OK", -1: "GVL_E_INVALID_ARG", -2: "GVL_E_BAD_CSR", -3: "GVL_E_NOT_SYMMETRIC",
           -4: "GVL_E_NONINTEGER_WEIGHT",
-          -5: "GVL_E_RESOLUTION", -6: "GVL_E_WORKSPACE", -8: "GVL_E_HIP", -9: "GVL_E_BUSY", -10: "GVL_E_BATCH"}
+          -5: "GVL_E_RESOLUTION", -6: "GVL_E_WORKSPACE", -8: "GVL_E_HIP", -9: "GVL_E_BUSY", -10: "GVL_E_BATCH",
+          -11: "GVL_E_TABLE_OVERFLOW"}
 
 GVL_REQ_PENDING, GVL_REQ_RUNNING, GVL_REQ_DONE, GVL_REQ_CANCELLED = 0, 1, 2, 3
 
@@ -67,7 +68,7 @@ class gvl_stats(ctypes.Structure):
                 ("ms_scan_kernels", ctypes.c_double), ("ms_agg_kernels", ctypes.c_double),
                 ("scan_launches", ctypes.c_int64), ("agg_launches", ctypes.c_int64),
                 ("scan_refine_arcs", ctypes.c_int64), ("ms_scan_move_kernels", ctypes.c_double),
-                ("graph_launches", ctypes.c_int64)]
+                ("graph_launches", ctypes.c_int64), ("table_overflows", ctypes.c_int64)]
 
 
 class gvl_graph_desc(ctypes.Structure):

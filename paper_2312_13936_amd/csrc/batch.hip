@@ -43,7 +43,7 @@ struct BatchArea {
   const float** w;
   int32_t** out;
   int64_t *n, *m, *vb, *ub, *uab;
-  int32_t *src, *flags, *vcur, *pos, *gath, *goff0, *nz, *cb;
+  int32_t *src, *flags, *vcur, *pos, *gath, *goff0, *nz, *cb, *gsh;
   double *W, *dqg, *s1g, *s2d;
   unsigned long long *dqg128, *mvg, *s2u;
   GraphParam* gp;
@@ -77,6 +77,7 @@ BatchArea carve_batch(int64_t G, int64_t N, int64_t M, char* base) {
   b.src = (int32_t*)take(4 * g);
   b.flags = (int32_t*)take(4 * g);
   b.vcur = (int32_t*)take(4 * g);
+  b.gsh = (int32_t*)take(4 * g);
   b.pos = (int32_t*)take(4 * (g + 1));
   b.gath = (int32_t*)take(4 * (g + 1));
   b.goff0 = (int32_t*)take(4 * (g + 1));
@@ -265,6 +266,21 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   goff0[K] = (int32_t)N0;
   if ((s = upload(st, B.gp, hgp)) != GVL_OK) return s;
   if ((s = upload(st, B.goff0, goff0)) != GVL_OK) return s;
+  // sub-sweep groups: the option, or per graph by its longest row; a graph
+  // with fewer groups than the union puts its group k into union group
+  // k << gsh (its groups run in the same order as alone)
+  int S_union = opt->subsweeps;
+  std::vector<int32_t> gsh(K, 0);
+  if (opt->subsweeps == 0) {
+    S_union = kAutoFewGroups;
+    for (int32_t k = 0; k < K; ++k)
+      if (hflags[src[k]] & 8) S_union = kAutoGroups;
+    for (int32_t k = 0; k < K; ++k) {
+      const int Sg = (hflags[src[k]] & 8) ? kAutoGroups : kAutoFewGroups;
+      while ((Sg << gsh[k]) < S_union) ++gsh[k];
+    }
+  }
+  if ((s = upload(st, B.gsh, gsh)) != GVL_OK) return s;
 
   // ---- state of the pass loop
   fill_u64(st, (unsigned long long*)ws.sc, 0ull, sizeof(Scalars) / 8);
@@ -280,6 +296,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.ident_after = -1;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
+  a.ovf = &ws.sc->ovf;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
   a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
   a.gp = B.gp; a.dqg = B.dqg; a.dqg128 = B.dqg128; a.mvg = B.mvg;
@@ -316,7 +333,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     a.rnd = 0;
     // ---- bins, hub plan, K', initial labels
     BinInfo bins;
-    s = make_bins(ctx, ws, cur.off, cur.deg, nn, opt->subsweeps, true, bins, gid, B.vcur);
+    s = make_bins(ctx, ws, cur.off, cur.deg, nn, S_union, true, bins, gid, B.vcur, B.gsh);
     if (s != GVL_OK) return s;
     HubPlan plan;
     s = build_hub_plan(ctx, ws, bins, false, cur, nullptr, 0, plan);
@@ -436,6 +453,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     fill_u64(st, B.mvg, 0ull, K);
     s = readback(ctx, ws.sc);
     if (s != GVL_OK) return s;
+    if (det && ctx->host->ovf) return GVL_E_TABLE_OVERFLOW;
     moves_before = counter(ctx->host, 3);
     BinInfo rbins;  // after the first sweep: the short-row bins thinned to lone vertices
     const BinInfo* rb = &bins;
@@ -463,6 +481,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
+      if (det && ctx->host->ovf) return GVL_E_TABLE_OVERFLOW;
       const unsigned long long mv = counter(ctx->host, 3) - moves_before;
       moves_before = counter(ctx->host, 3);
       if (mv == 0) break;
@@ -660,8 +679,9 @@ gvl_status gvl_leiden_fused(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_d
   if (!ctx || !opt || num_graphs < 0 || (num_graphs > 0 && (!graphs || !modularities || !statuses)))
     return GVL_E_INVALID_ARG;
   if (opt->mode != GVL_MODE_FAST && opt->mode != GVL_MODE_DET) return GVL_E_INVALID_ARG;
-  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 1 ||
-      opt->subsweeps > kMaxGroups || !(opt->tolerance_drop > 0.0))
+  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 0 ||
+      (opt->subsweeps == 0 && opt->mode == GVL_MODE_DET) || opt->subsweeps > kMaxGroups ||
+      !(opt->tolerance_drop > 0.0))
     return GVL_E_INVALID_ARG;
   size_t need = 0;
   gvl_status s = gvl_fused_workspace_bytes(num_graphs, graphs, opt, &need);

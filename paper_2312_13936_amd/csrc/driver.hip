@@ -19,6 +19,7 @@ const char* gvl_status_string(gvl_status s) {
   switch (s) {
     case GVL_E_BUSY: return "request busy";
     case GVL_E_BATCH: return "some graphs of the batch failed";
+    case GVL_E_TABLE_OVERFLOW: return "a key partition of a wide row or hub overflowed its table";
     case GVL_OK: return "ok";
     case GVL_E_INVALID_ARG: return "invalid argument";
     case GVL_E_BAD_CSR: return "malformed CSR input";
@@ -41,7 +42,9 @@ gvl_status gvl_default_options(gvl_options* o, int32_t mode) {
   o->max_iterations = 20;
   o->max_passes = 20;
   o->refine_sweeps = 20;
-  o->subsweeps = 32;
+  // deterministic mode: 32 groups, as the oracle's default; fast mode: 8 or
+  // 32 by the longest row of the input (kAutoShortRow)
+  o->subsweeps = mode == GVL_MODE_DET ? kAutoGroups : 0;
   o->validate = 1;
   // group-synchronous local-moving (faster and higher modularity than
   // committing every move at once on the R-MAT benchmark graph)
@@ -206,6 +209,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   a.ident_after = -1;
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
+  a.ovf = &ws.sc->ovf;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
   a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
   const bool sync_mv = det || opt->sync_moves != 0;
@@ -231,6 +235,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   tm.end(h);
 
   a.seed = opt->seed;
+  int S_run = opt->subsweeps > 0 ? opt->subsweeps : kAutoGroups;  // sub-sweep groups of every pass
   for (pass = 0; pass < opt->max_passes; ++pass) {
     a.pass = pass;
     a.rnd = 0;
@@ -240,8 +245,17 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     // ---- 1. degree bins, hub plan, vertex weights K', initial labels
     h = tm.begin(kEvOther);
     BinInfo bins;
-    s = make_bins(ctx, ws, cur.off, cur.deg, nn, opt->subsweeps, true, bins);
+    s = make_bins(ctx, ws, cur.off, cur.deg, nn, S_run, true, bins);
     if (s != GVL_OK) return s;
+    if (pass == 0 && opt->subsweeps == 0) {  // automatic S: by the longest row of the input
+      int32_t longest = 0;
+      for (int b = 0; b < kNumBins; ++b) longest = std::max(longest, bins.maxsize[b]);
+      if (longest <= kAutoShortRow) {
+        S_run = kAutoFewGroups;
+        s = make_bins(ctx, ws, cur.off, cur.deg, nn, S_run, true, bins);
+        if (s != GVL_OK) return s;
+      }
+    }
     HubPlan plan;
     s = build_hub_plan(ctx, ws, bins, false, cur, nullptr, 0, plan);
     if (s != GVL_OK) return s;
@@ -380,6 +394,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
+      if (det && ctx->host->ovf) return GVL_E_TABLE_OVERFLOW;
       if (move_graph.launched) ++S->graph_launches;
       ++iters;
       const unsigned long long mv = counter(ctx->host, 3) - moves_before;
@@ -444,6 +459,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       }
       s = readback(ctx, ws.sc);
       if (s != GVL_OK) return s;
+      if (det && ctx->host->ovf) return GVL_E_TABLE_OVERFLOW;
       if (refine_graph.launched) ++S->graph_launches;
       ++sweeps;
       const unsigned long long mv = counter(ctx->host, 3) - moves_before;
@@ -577,6 +593,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   S->agg_arcs = (int64_t)counter(ctx->host, 5);
   S->agg_out_arcs = (int64_t)counter(ctx->host, 6);
   S->scan_refine_arcs = (int64_t)counter(ctx->host, 7);
+  S->table_overflows = (int64_t)ctx->host->ovf;
   if (tm.on) {
     double ms[kEvClasses];
     tm.totals(ms);

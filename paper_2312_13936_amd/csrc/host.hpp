@@ -28,6 +28,7 @@ struct Scalars {
   unsigned long long acc_u[2];      // modularity: S2 exact (lo, hi)
   int32_t total;                    // scan totals read back
   int32_t sweep;                    // refinement sweep number, read by replayed sweeps (ScanArgs::sweep_dev)
+  unsigned long long ovf;           // decisions cancelled by a partition table overflow (cumulative)
 };
 
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -338,10 +339,11 @@ gvl_status readback(gvl_ctx* ctx, Scalars* dev) {
 // `list`: bins 0..kHubBin-1 of every group (group-major), then the hub bin
 // of every group in group order.
 gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int32_t* deg, int64_t n, int S,
-                     bool wide, BinInfo& bins, const int32_t* gid = nullptr, const int32_t* vbase = nullptr) {
+                     bool wide, BinInfo& bins, const int32_t* gid = nullptr, const int32_t* vbase = nullptr,
+                     const int32_t* gsh = nullptr) {
   hipStream_t st = ctx->stream;
   fill_i32(st, (int32_t*)ws.bb, 0, (int64_t)(sizeof(BinBuf) / sizeof(int32_t)));
-  bin_count(st, off, deg, n, S, wide, gid, vbase, ctx->lim, ws.bb);
+  bin_count(st, off, deg, n, S, wide, gid, vbase, gsh, ctx->lim, ws.bb);
   HIP_TRY(hipMemcpyAsync(ctx->hbins, ws.bb, sizeof(BinBuf), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   bins.S = S;
@@ -369,7 +371,7 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
   for (int b = 0; b < kNumBins; ++b) bins.maxsize[b] = ctx->hbins->maxsize[b];
   HIP_TRY(hipMemcpyAsync(ws.bb->cursors, ctx->hbins->cursors, sizeof(int32_t) * S * kNumBins,
                          hipMemcpyHostToDevice, st));
-  bin_scatter(st, off, deg, n, S, wide, gid, vbase, ctx->lim, ws.bb, ws.list);
+  bin_scatter(st, off, deg, n, S, wide, gid, vbase, gsh, ctx->lim, ws.bb, ws.list);
   return GVL_OK;
 }
 
@@ -585,8 +587,8 @@ gvl_status check_args(gvl_ctx* ctx, int64_t n, int64_t m, const int32_t* off, co
       (opt->refine_based != 0 && opt->refine_based != 1) || opt->validate < 0 ||
       opt->validate > 2)
     return GVL_E_INVALID_ARG;
-  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 1 ||
-      opt->subsweeps > kMaxGroups ||
+  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 0 ||
+      (opt->subsweeps == 0 && opt->mode == GVL_MODE_DET) || opt->subsweeps > kMaxGroups ||
       !(opt->tolerance_drop > 0.0) || !(opt->aggregation_tolerance >= 0.0))
     return GVL_E_INVALID_ARG;
   size_t need = 0;

@@ -32,7 +32,8 @@ __device__ __forceinline__ int32_t graph_of(const int64_t* base, int32_t G, int6
 // graph g = graph_of(vb, v)): offsets start at 0, never decrease and end at
 // m_g; neighbours lie in [0, n_g); weights are positive and finite (flag
 // bit 1 otherwise), integers in [1, 2^24] (bit 2 otherwise); W[g] += row
-// sums.  flags bit 0: bad CSR.
+// sums.  flags bit 0: bad CSR; bit 3: a row of more than kAutoShortRow arcs
+// (the automatic sub-sweep count).
 __global__ __launch_bounds__(kBlock) void k_batch_validate(BatchDesc d, int32_t G, int64_t total, int32_t* flags,
                                                            double* W) {
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < total; base += (int64_t)gridDim.x * kBlock) {
@@ -52,6 +53,7 @@ __global__ __launch_bounds__(kBlock) void k_batch_validate(BatchDesc d, int32_t 
           (k == n - 1 && (int64_t)end != d.m[g]))
         f |= 1;
       deg = (f & 1) ? 0 : end - beg;
+      if (deg > kAutoShortRow) f |= 8;
     }
     double s = 0.0;
     const float* w = on ? d.w[g] : nullptr;

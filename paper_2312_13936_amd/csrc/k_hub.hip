@@ -435,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
 // min-label rule and the sign test, and commits (fast local-moving) or
 // records the decision.  A partition whose keys overflow the table
 // (statistically out of reach: at most kPartKeys expected per kPartSlots
-// slots) reports kOverflow and cancels the hub's move.
+// slots) reports kOverflow, cancels the hub's move and counts it in *a.ovf.
 constexpr int32_t kOverflow = -2;
 template <class WT, int PH, bool DET>
 __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g, ScanArgs a, HubArgs h, int32_t s0,
@@ -560,6 +560,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
     if (threadIdx.x == 0) {
       h.done[p] = 0;
       ++acc.nv;
+      if (ovf) atomicAdd(a.ovf, 1ull);
       const bool take = !ovf && accept<PH, DET>(a, d, bc, bg, bk);
       s_take = take ? 1 : 0;
       if (take) {

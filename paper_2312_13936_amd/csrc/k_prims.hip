@@ -265,13 +265,17 @@ __device__ __forceinline__ int32_t size_of(const int32_t* off, const int32_t* de
 
 // Binning key of item i: group_of(i, S) * kNumBins + bin(size).  Counts
 // per key and the largest size per bin go to bb.
-__device__ __forceinline__ int group_local(int64_t i, int S, const int32_t* gid, const int32_t* vbase) {
-  return group_of(gid ? i - vbase[gid[i]] : i, S);
+__device__ __forceinline__ int group_local(int64_t i, int S, const int32_t* gid, const int32_t* vbase,
+                                           const int32_t* gsh) {
+  if (!gid) return group_of(i, S);
+  const int32_t g = gid[i];
+  const int sh = gsh ? gsh[g] : 0;
+  return group_of(i - vbase[g], S >> sh) << sh;
 }
 
 __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const int32_t* deg, int64_t n, int S,
                                                       bool wide, const int32_t* gid, const int32_t* vbase,
-                                                      BinLimits lim, BinBuf* bb) {
+                                                      const int32_t* gsh, BinLimits lim, BinBuf* bb) {
   __shared__ int32_t h[kMaxGroups * kNumBins], mx[kNumBins];
   const int nk = S * kNumBins;
   for (int k = threadIdx.x; k < nk; k += kBlock) h[k] = 0;
@@ -281,7 +285,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
     const int32_t d = size_of(off, deg, i);
     const int b = bin_of(d, wide, lim);
     if (b >= 0) {
-      const int grp = (S > 1) ? group_local(i, S, gid, vbase) : 0;
+      const int grp = (S > 1) ? group_local(i, S, gid, vbase, gsh) : 0;
       atomicAdd(&h[grp * kNumBins + b], 1);
       atomicMax(&mx[b], d);
     }
@@ -292,10 +296,10 @@ __global__ __launch_bounds__(kBlock) void k_bin_count(const int32_t* off, const 
   if (threadIdx.x < kNumBins && mx[threadIdx.x]) atomicMax(&bb->maxsize[threadIdx.x], mx[threadIdx.x]);
 }
 void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-               const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb) {
+               const int32_t* gid, const int32_t* vbase, const int32_t* gsh, const BinLimits& lim, BinBuf* bb) {
   if (n > 0)
     hipLaunchKernelGGL(k_bin_count, dim3(grid_n(n, kBlock, 2048)), dim3(kBlock), 0, st, off, deg, n, S, wide, gid,
-                       vbase, lim, bb);
+                       vbase, gsh, lim, bb);
 }
 
 // Each workgroup takes a contiguous chunk of items, reserves room per key
@@ -304,7 +308,8 @@ void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n
 constexpr int kBinChunk = 4096;
 __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, const int32_t* deg, int64_t n, int S,
                                                         bool wide, const int32_t* gid, const int32_t* vbase,
-                                                        BinLimits lim, BinBuf* bb, int32_t* list) {
+                                                        const int32_t* gsh, BinLimits lim, BinBuf* bb,
+                                                        int32_t* list) {
   __shared__ int32_t h[kMaxGroups * kNumBins], base[kMaxGroups * kNumBins];
   const int nk = S * kNumBins;
   for (int64_t c0 = (int64_t)blockIdx.x * kBinChunk; c0 < n; c0 += (int64_t)gridDim.x * kBinChunk) {
@@ -313,7 +318,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     const int64_t c1 = (c0 + kBinChunk < n) ? c0 + kBinChunk : n;
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
       const int b = bin_of(size_of(off, deg, i), wide, lim);
-      if (b >= 0) atomicAdd(&h[((S > 1) ? group_local(i, S, gid, vbase) : 0) * kNumBins + b], 1);
+      if (b >= 0) atomicAdd(&h[((S > 1) ? group_local(i, S, gid, vbase, gsh) : 0) * kNumBins + b], 1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < nk; k += kBlock) {
@@ -324,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
     for (int64_t i = c0 + threadIdx.x; i < c1; i += kBlock) {
       const int b = bin_of(size_of(off, deg, i), wide, lim);
       if (b >= 0) {
-        const int k = ((S > 1) ? group_local(i, S, gid, vbase) : 0) * kNumBins + b;
+        const int k = ((S > 1) ? group_local(i, S, gid, vbase, gsh) : 0) * kNumBins + b;
         list[base[k] + atomicAdd(&h[k], 1)] = (int32_t)i;
       }
     }
@@ -332,10 +337,11 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const int32_t* off, cons
   }
 }
 void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-                 const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb, int32_t* list) {
+                 const int32_t* gid, const int32_t* vbase, const int32_t* gsh, const BinLimits& lim, BinBuf* bb,
+                 int32_t* list) {
   if (n > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3(grid_n(n, kBinChunk, 2048)), dim3(kBlock), 0, st, off, deg, n, S,
-                       wide, gid, vbase, lim, bb, list);
+                       wide, gid, vbase, gsh, lim, bb, list);
 }
 
 // ---------------------------------------------------------- exclusive scan ---

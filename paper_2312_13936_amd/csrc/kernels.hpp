@@ -58,6 +58,14 @@ struct BinLimits {
 // (sub-sweeps); the bin lists are laid out group-major so that every
 // (group, bin) segment is contiguous.
 constexpr int kMaxGroups = 64;
+// Fast mode with subsweeps = 0 picks S per input graph: kAutoFewGroups when
+// no row has more than kAutoShortRow arcs, else kAutoGroups.  In a fused
+// batch a graph with fewer groups than the union puts its group k into
+// union group k << shift (shift = log2 of the ratio), so its groups run in
+// the same order as alone.
+constexpr int kAutoGroups = 32;
+constexpr int kAutoFewGroups = 8;
+constexpr int32_t kAutoShortRow = 128;
 
 // List layout: for every group its bins 0..kHubBin-1 (group-major), then the
 // hub bin of every group, so that all hubs form one region [H0, H0 + H).
@@ -125,6 +133,7 @@ struct ScanArgs {
   unsigned long long* dq128;  // deterministic mode: exact int128 sums of move keys [kCntSlots][lo, hi]
   unsigned long long* cnt;  // [kCntSlots][8]: [0] vertices scanned, [1] arcs, [2] candidates,
                             // [3] moves, [4..6] aggregation, [7] arcs scanned by refinement
+  unsigned long long* ovf;  // decisions of wide rows and hubs cancelled by a partition table overflow
   // wide rows: partial bests of the partitions of each vertex of a launch
   // ([vertex][kWideMaxParts]) and the partitions finished per vertex
   double* wd_g;
@@ -380,11 +389,13 @@ void community_totals(hipStream_t st, const int32_t* C, const double* K, double*
 // wide = false (aggregation capacities) stops at bin kAggLastBin: larger
 // capacities go to the hub bin.
 // gid / vbase (fused batches, else nullptr): the group of item i is taken
-// from its id inside its own graph, i - vbase[gid[i]].
+// from its id inside its own graph, i - vbase[gid[i]]; gsh (nullable): per
+// graph, the group is group_of(id, S >> gsh) << gsh.
 void bin_count(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-               const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb);
+               const int32_t* gid, const int32_t* vbase, const int32_t* gsh, const BinLimits& lim, BinBuf* bb);
 void bin_scatter(hipStream_t st, const int32_t* off, const int32_t* deg, int64_t n, int S, bool wide,
-                 const int32_t* gid, const int32_t* vbase, const BinLimits& lim, BinBuf* bb, int32_t* list);
+                 const int32_t* gid, const int32_t* vbase, const int32_t* gsh, const BinLimits& lim, BinBuf* bb,
+                 int32_t* list);
 // used[c] = 1 for every label c in C[0..n) (used zeroed by the caller);
 // with gid / keep only for vertices of graphs g with keep[g].
 void mark_used(hipStream_t st, const int32_t* C, int64_t n, int32_t* used, const int32_t* gid = nullptr,

@@ -457,7 +457,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
 // clears) the pruning flag: the others scan regardless, and the decision
 // follows partition 0.  A partition whose keys overflow the table (more than
 // kWideSlots distinct; statistically out of reach for rows of at most 8192 P
-// arcs) cancels the move of its vertex.
+// arcs, but ids can be chosen to put every neighbour into one partition)
+// cancels the move of its vertex and is counted in *a.ovf.
 constexpr int kWideThreads = 1024;
 constexpr int64_t kWideGrid = 256;  // persistent workgroups: one per CU (the LDS table fits once)
 static_assert(kWideSlots % kWideThreads == 0, "wide table: whole slots per thread");
@@ -590,6 +591,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       if (ok0) {
         ++acc.nv;
         acc.na += (unsigned long long)deg;
+        if (ovf_any) atomicAdd(a.ovf, 1ull);
         take = (!ovf_any && accept<PH, DET>(a, d, bc, bg, bk)) ? 1 : 0;
       }
       if (take) {

@@ -38,7 +38,8 @@ def test_default_options(lib):
     for o in (fast, det):
         assert o.tolerance == 0.01 and o.tolerance_drop == 10.0
         assert o.aggregation_tolerance == 0.8 and o.max_iterations == 20 and o.max_passes == 20
-    assert fast.mode == 0 and det.mode == 1 and det.subsweeps == 32 and fast.subsweeps == 32
+    # sub-sweep groups: deterministic 32 (the oracle's default); fast 0 = by the longest row
+    assert fast.mode == 0 and det.mode == 1 and det.subsweeps == 32 and fast.subsweeps == 0
     assert fast.sync_moves == 3 and fast.refine_sweeps == 20 and fast.max_passes == 20
     with pytest.raises(gvl.GvlError):
         gvl.gvl_default_options(7)

@@ -624,3 +624,72 @@ def test_refine_based_labels_fused_matches_oracle(eng):
     for k, g in enumerate(gs):
         o = oracle.leiden(g, mode=oracle.DET_SYNC, refine_based=1)
         assert np.array_equal(mems[k].cpu().numpy(), o.membership) and qs[k] == o.q, g.name
+
+
+# ---------------------------------------------- partition table overflow ---
+
+def _mix32(x, m1, s1, m2):
+    x &= 0xFFFFFFFF
+    x ^= x >> 16
+    x = (x * m1) & 0xFFFFFFFF
+    x ^= x >> s1
+    x = (x * m2) & 0xFFFFFFFF
+    return x ^ (x >> 16)
+
+
+def _wide_part(c):  # the key-partition mixer of wide rows (lowbias32)
+    return _mix32(c, 0x7feb352d, 15, 0x846ca68b)
+
+
+def _group_of(i, s):  # the sub-sweep group of a vertex (murmur3 finalizer)
+    return _mix32(i, 0x85ebca6b, 13, 0xc2b2ae35) % s
+
+
+def _overflow_star(leaves=13000):
+    """A star whose hub (sub-sweep group 0: it decides before any leaf has
+    moved) has 13000 leaves, all with an even partition hash: a row of
+    8192 < deg <= 16384 arcs is split over two key partitions of 12288 LDS
+    slots each, and every distinct neighbour community falls into partition
+    0.  The remaining ids are vertices without arcs."""
+    hub = next(i for i in range(1000) if _group_of(i, 32) == 0)
+    ids = []
+    j = 0
+    while len(ids) < leaves:
+        if j != hub and _wide_part(j) & 1 == 0:
+            ids.append(j)
+        j += 1
+    return gen.from_edges(j, [(hub, x) for x in ids], name="overflow-star")
+
+
+def test_partition_table_overflow_is_reported(eng):
+    g = _overflow_star()
+    assert 8192 < np.diff(g.offsets).max() <= 16384
+    # deterministic mode: the hub's decision cannot be computed exactly
+    with pytest.raises(gvl.GvlError) as e:
+        run(eng, g, gvl.GVL_MODE_DET)
+    assert gvl.STATUS[e.value.code] == "GVL_E_TABLE_OVERFLOW"
+    # fast mode: the hub stays put, the run completes and counts the overflow
+    mem, q, st = run(eng, g, gvl.GVL_MODE_FAST)
+    assert st.table_overflows >= 1
+    assert q == oracle.modularity(g, mem) and oracle.disconnected(g, mem) == 0
+    # an ordinary graph reports none
+    mem, q, st = run(eng, graph("hubs-wide"), gvl.GVL_MODE_DET)
+    assert st.table_overflows == 0
+
+
+# ------------------------------------------------ automatic sub-sweeps ---
+
+@pytest.mark.parametrize("name,groups", [("grid200-w100", 8), ("planted-C1", 8), ("path", 8), ("ring30xK3", 8),
+                                         ("er-selfloops", 8), ("rmat-s14", 32), ("hubs-wide", 32), ("star", 32)])
+def test_automatic_subsweeps(eng, name, groups):
+    # Fast mode's default (subsweeps = 0) takes 8 groups when no row has
+    # more than 128 arcs, else 32.  The group-synchronous schedule is
+    # reproducible with integer weights, so the default run equals the run
+    # with that count given explicitly.
+    g = graph(name)
+    assert (int(np.diff(g.offsets).max()) <= 128) == (groups == 8)
+    m0, q0, _ = run(eng, g, gvl.GVL_MODE_FAST)
+    m1, q1, _ = run(eng, g, gvl.GVL_MODE_FAST, subsweeps=groups)
+    assert np.array_equal(m0, m1) and q0 == q1
+    with pytest.raises(gvl.GvlError):  # deterministic mode needs an explicit count (the oracle's)
+        run(eng, g, gvl.GVL_MODE_DET, subsweeps=0)
