@@ -27,8 +27,11 @@
 //          paper): vertices are split into S pseudo-random groups visited in
 //          turn; inside a group every active vertex decides from the state at
 //          the start of the group and the moves are applied together; ties
-//          go to the lowest community id, and every sum and gain is an exact
-//          integer (gains are int128 keys).  Used for bit-exact parity.
+//          go to the lowest community id, two adjacent vertices of a group
+//          that chose each other's community do not both move, a vertex
+//          bouncing between two communities stops (swap and bounce rules in
+//          move_det), and every sum and gain is an exact integer (gains are
+//          int128 keys).  Used for bit-exact parity.
 //
 // Readings of points the paper leaves open (all shared with the GPU path by
 // specification, not by code):
@@ -115,6 +118,10 @@ uint32_t fmix32(uint32_t h) {
   return h;
 }
 int32_t group_of(i64 i, int32_t S) { return (int32_t)(fmix32((uint32_t)i) % (uint32_t)S); }
+
+// Rows longer than this never yield under the swap rule of the synchronous
+// local-moving (move_det) and win against shorter ones.
+const i64 kSwapRowMax = 128;
 
 // ---------------------------------------------- randomized refinement ---
 // The alternative refinement of Sec. 4.1 (Traag's original rule): among the
@@ -310,6 +317,9 @@ int32_t move_det(const Graph& g, State& st, double tau, const Opts& o, i64 W, i6
   std::vector<char> unprocessed(n, 1);
   std::vector<int32_t> target(n, -1);
   std::vector<i128> key(n, 0);
+  // last move of each vertex: the community it left and the iteration, and
+  // the iteration of the move before (bounce rule)
+  std::vector<int32_t> left(n, -1), left_it(n, -3), prev_it(n, -3);
   Table H(n);
   int32_t it = 0;
   *first = 0;
@@ -337,18 +347,43 @@ int32_t move_det(const Graph& g, State& st, double tau, const Opts& o, i64 W, i6
         H.clear();
         if (best < 0 || !(bk > 0)) continue;
         if (st.size[d] == 1 && st.size[best] == 1 && best > d) continue;  // min-label rule
+        // Bounce rule: a vertex that moved in each of the two previous
+        // iterations does not go straight back to the community it left in
+        // the last one (it is cycling with a neighbour of its group).
+        if (best == left[i] && left_it[i] == it - 1 && prev_it[i] == it - 2) continue;
         target[i] = best; key[i] = bk;
         group.push_back(i);
       }
-      for (i64 i : group) {  // apply the group's moves together
+      // Swap rule: two adjacent vertices of the group that chose each
+      // other's community (i: d -> c while j: c -> d) would trade places and
+      // trade back in the next iteration; only one of them moves: the
+      // lower id, or the one with more than kSwapRowMax arcs (such rows
+      // never yield).  Decided on the state before the group's moves.
+      std::vector<i64> go;
+      for (i64 i : group) {
+        bool yield = false;
+        if (g.off[i + 1] - g.off[i] <= kSwapRowMax) {
+          const int32_t d = st.C[i], c = target[i];
+          for (i64 e = g.off[i]; e < g.off[i + 1] && !yield; ++e) {
+            const i64 j = g.idx[e];
+            if (j == i || group_of(j, S) != sub || target[j] != d || st.C[j] != c) continue;
+            yield = j < i || g.off[j + 1] - g.off[j] > kSwapRowMax;
+          }
+        }
+        if (!yield) go.push_back(i);
+      }
+      for (i64 i : go) {  // apply the group's moves together
         const int32_t d = st.C[i], c = target[i];
+        prev_it[i] = left_it[i];
+        left[i] = d;
+        left_it[i] = it;
         st.S[d] -= st.K[i]; st.S[c] += st.K[i];
         st.size[d] -= 1; st.size[c] += 1;
         st.C[i] = c;
         sum += key[i];
         ++moved;
       }
-      for (i64 i : group)
+      for (i64 i : go)
         for (i64 e = g.off[i]; e < g.off[i + 1]; ++e)
           if (g.idx[e] != i) unprocessed[g.idx[e]] = 1;
     }

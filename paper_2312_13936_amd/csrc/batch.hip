@@ -288,6 +288,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   fill_i32(st, ws.hp_lcnt, 0, ch.n);
   fill_i32(st, ws.wd_done, 0, ws.max_wide);
   fill_i32(st, ws.wd_ctr, 0, 2);
+  fill_u8(st, ws.yld, 0, ch.n);
+  fill_u8(st, ws.cand, 0, ch.n);
   ScanArgs a;
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
@@ -297,6 +299,10 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.ovf = &ws.sc->ovf;
+  a.gainf = ws.gainf; a.gaink = ws.gaink; a.yld = ws.yld; a.last = ws.last; a.it_dev = &ws.sc->iter;
+  a.cand = ws.cand;
+  if (!scan_state_ready(a, det)) return GVL_E_INVALID_ARG;
+  a.gsh = B.gsh;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
   a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
   a.gp = B.gp; a.dqg = B.dqg; a.dqg128 = B.dqg128; a.mvg = B.mvg;
@@ -354,6 +360,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     HubArgs hargs = hub_args(ws, bins);
     fill_u8(st, ws.flag, 1, nn);
     fill_i32(st, ws.target, -1, nn);
+    fill_i32(st, (int32_t*)ws.last, -3, 4 * nn);  // no vertex has moved in this pass
+    fill_i32(st, &ws.sc->iter, 0, 1);
 
     // (bx, lx: the short-row bins and their list, thinned during refinement;
     // the hubs always come from bins and ws.list)
@@ -407,9 +415,14 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
         if (det) fill_u64(q, B.dqg128, 0ull, 2 * (int64_t)K);
         else fill_f64(q, B.dqg, 0.0, K);
         for (int32_t grp = 0; grp < bins.S; ++grp) {
+          a.grp = grp;
           decide_group(q, grp, kMove, bins, ws.list);
-          if (sync_mv) commit_group(q, grp, kMove, bins, ws.list);
+          if (sync_mv) {
+            launch_swap_check(q, cur, a, ws.list + bins.gstart[grp], swap_bound(bins, grp, ctx->lim));
+            commit_group(q, grp, kMove, bins, ws.list);
+          }
         }
+        add_one_i32(q, &ws.sc->iter);
       }, [&] { tstate.clean = clean; });
       if (s != GVL_OK) return s;
       bool any = false, stopped = false;

@@ -29,6 +29,7 @@ struct Scalars {
   int32_t total;                    // scan totals read back
   int32_t sweep;                    // refinement sweep number, read by replayed sweeps (ScanArgs::sweep_dev)
   unsigned long long ovf;           // decisions cancelled by a partition table overflow (cumulative)
+  int32_t iter;                     // local-moving iteration of the pass, read by the kernels (ScanArgs::it_dev)
 };
 
 static inline size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -47,6 +48,13 @@ struct Workspace {
   int32_t* targeted;
   int2* CP;
   int32_t* list2;  // refinement: the thinned short-row bins
+  // synchronous local-moving: decided gains (FP64, or exact keys in
+  // deterministic mode), swap-rule yield flags, last move of each vertex
+  double* gainf;
+  i128_t* gaink;
+  uint8_t* yld;
+  int4* last;
+  uint8_t* cand;  // swap-rule candidates (ScanArgs::cand)
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
   TblSlot* tbl;
@@ -109,6 +117,10 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.targeted = (int32_t*)take(4 * N);
   w.CP = (int2*)take(8 * N);
   w.list2 = (int32_t*)take(4 * N);
+  if (det) w.gaink = (i128_t*)take(16 * N); else w.gainf = (double*)take(8 * N);
+  w.yld = (uint8_t*)take(N);
+  w.last = (int4*)take(16 * N);
+  w.cand = (uint8_t*)take(N);
   for (int b = 0; b < 2; ++b) {
     w.off[b] = (int32_t*)take(4 * (N + 1));
     w.deg[b] = (int32_t*)take(4 * N);
@@ -373,6 +385,21 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
                          hipMemcpyHostToDevice, st));
   bin_scatter(st, off, deg, n, S, wide, gid, vbase, gsh, ctx->lim, ws.bb, ws.list);
   return GVL_OK;
+}
+
+// Every per-vertex array the synchronous local-moving kernels write or read
+// (gains, yield and candidate flags, last moves, iteration counter) is set.
+static inline bool scan_state_ready(const ScanArgs& a, bool det) {
+  return a.yld && a.cand && a.last && a.it_dev && (det ? a.gaink != nullptr : a.gainf != nullptr);
+}
+
+// Entries of group grp's segment of the bin list that can be swap-rule
+// candidates: its rows of at most kSwapRowMax arcs (the lane-group bins,
+// and bin 5 when its tuned lower limit is lower).
+static inline int32_t swap_bound(const BinInfo& bins, int grp, const BinLimits& lim) {
+  int32_t b = bins.start[grp][5] - bins.gstart[grp];
+  if (lim.v[4] < kSwapRowMax) b += bins.count[grp][5];
+  return b;
 }
 
 // Refinement (Alg. 3) after a sweep: the short-row bins of `bins` (in

@@ -381,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
         h.done[p] = 0;
         h.lcnt[p] = 0;
         ++nv;
-        const bool take = accept<PH, DET>(a, d, bc, bg, bk);
+        const bool take = accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 2));
         s_take = take ? 1 : 0;
         if (take) {
           if (PH == kMove && !DET && !(a.sync_moves & 2)) {
@@ -561,7 +561,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
       h.done[p] = 0;
       ++acc.nv;
       if (ovf) atomicAdd(a.ovf, 1ull);
-      const bool take = !ovf && accept<PH, DET>(a, d, bc, bg, bk);
+      const bool take = !ovf && accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 2));
       s_take = take ? 1 : 0;
       if (take) {
         if (PH == kMove && !DET && !(a.sync_moves & 2)) {

@@ -152,6 +152,26 @@ __device__ __forceinline__ void add_gain(const ScanArgs& a, Acc& acc, int32_t i,
   }
 }
 
+// Records the gain of a synchronous local-moving decision of a row of at
+// most kSwapRowMax arcs; the commit adds it if the move is applied.
+template <bool DET>
+__device__ __forceinline__ void store_gain(const ScanArgs& a, int32_t i, double bg, i128 bk) {
+  if (DET) a.gaink[i] = bk; else a.gainf[i] = bg;
+}
+
+// Sub-sweep group of neighbour j of a vertex whose graph starts at vbase
+// (group shift sh in a fused batch).
+__device__ __forceinline__ int group_in_pass(const ScanArgs& a, int32_t j, int32_t vbase, int sh) {
+  return group_of(j - vbase, a.groups >> sh) << sh;
+}
+
+template <int G>
+__device__ __forceinline__ int or_lanes(int f) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) f |= __shfl_xor(f, o, G);
+  return f;
+}
+
 // Workgroup argmax of (gain or key, id) over NW wavefronts; the result is
 // valid in every thread.
 template <bool DET, int NW = kBlock / kWave>
@@ -174,13 +194,25 @@ __device__ __forceinline__ bool mark_needed(const ScanArgs& a, int32_t j) {
   return a.mark_after == INT32_MAX || group_of(j, a.groups) <= a.mark_after;
 }
 
-// After the argmax: apply the min-label rule and the sign test.
+// Bounce rule of the synchronous local-moving: a vertex that moved in each
+// of the two previous iterations does not go straight back to the community
+// it left in the last one (it is cycling with a neighbour of its group).
+__device__ __forceinline__ bool bounces(const ScanArgs& a, int32_t i, int32_t bc) {
+  const int32_t it = *a.it_dev;
+  const int4 l = a.last[i];
+  return l.x == bc && l.y == it - 1 && l.z == it - 2;
+}
+
+// After the argmax: apply the min-label rule, the sign test and, for a
+// synchronous local-moving decision (sync), the bounce rule.
 template <int PH, bool DET>
-__device__ __forceinline__ bool accept(const ScanArgs& a, int32_t d, int32_t bc, double bg, i128 bk) {
+__device__ __forceinline__ bool accept(const ScanArgs& a, int32_t i, int32_t d, int32_t bc, double bg, i128 bk,
+                                       bool sync) {
   if (bc < 0) return false;
   if (DET ? !(bk > 0) : !(bg > 0.0)) return false;
   if (PH == kMove) {
     if (a.size[d] == 1 && a.size[bc] == 1 && bc > d) return false;
+    if (sync && bounces(a, i, bc)) return false;
   } else {
     if (a.size[bc] == 1 && bc > d) return false;
   }
@@ -319,7 +351,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     if (DET) argmax_k<G>(bk, bc); else argmax_f<G>(bg, bc);
     wave_sync();
     if (gl == 0) { ++acc.nv; acc.na += (unsigned long long)deg; }
-    int take = (gl == 0) ? (int)accept<PH, DET>(a, d, bc, bg, bk) : 0;
+    int take = (gl == 0) ? (int)accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 1)) : 0;
     take = __shfl(take, 0, G);
     if (!take) continue;
     if (PH == kMove && !DET && !(a.sync_moves & 1)) {
@@ -339,8 +371,19 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     } else if (PH == kMove) {
       if (gl == 0) {
         a.target[i] = bc;
-        add_gain<DET>(a, acc, i, bg, bk);
+        store_gain<DET>(a, i, bg, bk);
       }
+      // swap-rule candidate if the target holds a neighbour of the group
+      // (labels do not change during the decisions of a group)
+      const int32_t vb = a.gid ? a.vbase[a.gid[i]] : 0;
+      const int sh = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
+      int f = 0;
+      for (int32_t e = gl; e < deg; e += G) {
+        const int32_t j = g.idx[beg + e];
+        if (j != i && group_in_pass(a, j, vb, sh) == a.grp && a.C[j] == bc) f = 1;
+      }
+      f = or_lanes<G>(f);
+      if (gl == 0 && f) a.cand[i] = 1;
     } else {
       if (gl == 0) { a.target[i] = bc; a.targeted[bc] = cur_stamp(a); }
     }
@@ -413,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     if (threadIdx.x == 0) {
       ++acc.nv;
       acc.na += (unsigned long long)deg;
-      s_take = (int)accept<PH, DET>(a, d, bc, bg, bk);
+      s_take = (int)accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 2));
     }
     __syncthreads();  // table and s_* reads done; s_take published
     const int take = s_take;
@@ -435,7 +478,18 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     } else if (PH == kMove) {
       if (threadIdx.x == 0) {
         a.target[i] = bc;
-        add_gain<DET>(a, acc, i, bg, bk);
+        store_gain<DET>(a, i, bg, bk);
+      }
+      if (deg <= kSwapRowMax) {  // uniform (only with a tuned lane-group limit below kSwapRowMax)
+        const int32_t vb = a.gid ? a.vbase[a.gid[i]] : 0;
+        const int sh = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
+        int f = 0;
+        for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
+          const int32_t j = g.idx[beg + e];
+          if (j != i && group_in_pass(a, j, vb, sh) == a.grp && a.C[j] == bc) f = 1;
+        }
+        f = __syncthreads_or(f);
+        if (threadIdx.x == 0 && f) a.cand[i] = 1;
       }
     } else {
       if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = cur_stamp(a); }
@@ -592,7 +646,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
         ++acc.nv;
         acc.na += (unsigned long long)deg;
         if (ovf_any) atomicAdd(a.ovf, 1ull);
-        take = (!ovf_any && accept<PH, DET>(a, d, bc, bg, bk)) ? 1 : 0;
+        take = (!ovf_any && accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 2))) ? 1 : 0;
       }
       if (take) {
         if (PH == kMove && !DET && !(a.sync_moves & 2)) {
@@ -605,7 +659,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
           ++acc.nm;
         } else if (PH == kMove) {
           a.target[i] = bc;
-          add_gain<DET>(a, acc, i, bg, bk);
+          store_gain<DET>(a, i, bg, bk);
         } else {
           a.target[i] = bc;
           a.targeted[bc] = cur_stamp(a);
@@ -641,6 +695,29 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
 // marked unprocessed; the workgroup lays its movers' rows end to end and
 // every lane marks one arc per step.  Without MARK (long rows, hubs) the
 // targets stay for the marking kernels.
+// Summed gains of the applied synchronous moves of one thread.
+struct CommitGain {
+  double f = 0.0;
+  i128 k = 0;
+};
+
+// An applied local-moving move of vertex i out of community d: its record
+// for the bounce rule, and (take_gain) its gain added to the iteration's sum
+// (per graph in a fused batch, else per thread and reduced at kernel end).
+__device__ __forceinline__ void note_move(const ScanArgs& a, int32_t i, int32_t d) {
+  const int4 l = a.last[i];
+  a.last[i] = make_int4(d, *a.it_dev, l.y, 0);
+}
+__device__ __forceinline__ void take_gain(const ScanArgs& a, int32_t i, CommitGain& G) {
+  if (a.gaink) {
+    const i128 k = a.gaink[i];
+    if (a.gid) atomic_add_i128(a.dqg128 + 2 * a.gid[i], k); else G.k += k;
+  } else {
+    const double x = a.gainf[i];
+    if (a.gid) atomicAdd(a.dqg + a.gid[i], x); else G.f += x;
+  }
+}
+
 // Shared memory of the commit roles.
 struct CommitLds {
   KeyedLds<kBlock> kt;
@@ -653,7 +730,7 @@ struct CommitLds {
 template <class WT, int PH, bool MARK>
 __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& g, const ScanArgs& a,
                                                            const int32_t* __restrict__ list, int32_t count,
-                                                           int32_t bid, int32_t nb, CommitLds& L) {
+                                                           int32_t bid, int32_t nb, CommitLds& L, CommitGain& G) {
   unsigned long long nm = 0;
   for (int64_t base = (int64_t)bid * kBlock; base < count; base += (int64_t)nb * kBlock) {
     const int64_t k = base + threadIdx.x;
@@ -662,7 +739,13 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
     if (k < count) t = a.target[i];
     bool mv = t >= 0;
     if (mv) {
-      if (PH == kMove && MARK) a.target[i] = -1;
+      if (PH == kMove && MARK) {
+        a.target[i] = -1;
+        if (a.yld[i]) {  // swap rule: the neighbour takes this vertex's place
+          a.yld[i] = 0;
+          mv = false;
+        }
+      }
       const int32_t d = a.C[i];
       if (PH == kRefine) {
         a.target[i] = -1;
@@ -674,6 +757,10 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
         keyed_put(L.kt, t, ki, 1);
         a.C[i] = t;
         if (PH == kRefine && a.CP) a.CP[i].x = t;
+        if (PH == kMove) {
+          note_move(a, i, d);
+          if (MARK) take_gain(a, i, G);  // (hubs, MARK = false, added theirs when deciding)
+        }
         ++nm;
         if (PH == kRefine && a.gid) atomicAdd(&a.mvg[a.gid[i]], 1ull);
       }
@@ -720,7 +807,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
 template <class WT>
 __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g, const ScanArgs& a,
                                                           const int32_t* __restrict__ list, int32_t count,
-                                                          int32_t bid, int32_t nb, CommitLds& L) {
+                                                          int32_t bid, int32_t nb, CommitLds& L, CommitGain& G) {
   unsigned long long nm = 0;
   for (int64_t k = bid; k < count; k += nb) {
     const int32_t i = list[k];
@@ -729,14 +816,21 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
       L.mv = t >= 0;
       if (t >= 0) {
         a.target[i] = -1;
-        const int32_t d = a.C[i];
-        const double ki = a.K[i];
-        atomicAdd(&a.Sig[d], -ki);
-        atomicAdd(&a.Sig[t], ki);
-        atomicSub(&a.size[d], 1);
-        atomicAdd(&a.size[t], 1);
-        a.C[i] = t;
-        ++nm;
+        if (a.yld[i]) {  // swap rule
+          a.yld[i] = 0;
+          L.mv = 0;
+        } else {
+          const int32_t d = a.C[i];
+          const double ki = a.K[i];
+          atomicAdd(&a.Sig[d], -ki);
+          atomicAdd(&a.Sig[t], ki);
+          atomicSub(&a.size[d], 1);
+          atomicAdd(&a.size[t], 1);
+          a.C[i] = t;
+          note_move(a, i, d);
+          take_gain(a, i, G);
+          ++nm;
+        }
       }
     }
     __syncthreads();
@@ -757,6 +851,9 @@ template <class WT, int PH>
 __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, HubArgs h, CommitLaunch cl) {
   __shared__ CommitLds L;
   __shared__ unsigned long long red_u[16];
+  __shared__ double red_d[16];
+  __shared__ i128 red_k[16];
+  CommitGain G;
   keyed_clear(L.kt);
   const int32_t x = (int32_t)blockIdx.x;
   int r = 0;
@@ -764,14 +861,14 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
   const int32_t bid = x - cl.b[r], nb = cl.b[r + 1] - cl.b[r];
   unsigned long long nm = 0;
   if (PH == kRefine) {
-    if (r == 0) nm = commit_tiles<WT, kRefine, false>(g, a, cl.l0, cl.n0, bid, nb, L);
-    else nm = commit_tiles<WT, kRefine, false>(g, a, cl.l2, cl.n2, bid, nb, L);
+    if (r == 0) nm = commit_tiles<WT, kRefine, false>(g, a, cl.l0, cl.n0, bid, nb, L, G);
+    else nm = commit_tiles<WT, kRefine, false>(g, a, cl.l2, cl.n2, bid, nb, L, G);
   } else if (r == 0) {
-    nm = commit_tiles<WT, kMove, true>(g, a, cl.l0, cl.n0, bid, nb, L);
+    nm = commit_tiles<WT, kMove, true>(g, a, cl.l0, cl.n0, bid, nb, L, G);
   } else if (r == 1) {
-    nm = commit_long<WT>(g, a, cl.l1, cl.n1, bid, nb, L);
+    nm = commit_long<WT>(g, a, cl.l1, cl.n1, bid, nb, L, G);
   } else if (r == 2) {
-    nm = commit_tiles<WT, kMove, false>(g, a, cl.l2, cl.n2, bid, nb, L);
+    nm = commit_tiles<WT, kMove, false>(g, a, cl.l2, cl.n2, bid, nb, L, G);
   } else {
     for (int64_t t = cl.c0 + (int64_t)bid; t < cl.c1; t += nb) {
       const int2 task = h.chunk_tasks[t];
@@ -788,6 +885,92 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
   }
   nm = block_sum<unsigned long long>(nm, red_u);
   if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
+  if (PH == kMove && !a.gid) {  // the applied moves' gains (fused batches added theirs per graph)
+    if (a.gaink) {
+      const i128 k = block_sum_i128(G.k, red_k);
+      if (threadIdx.x == 0 && k != 0) atomic_add_i128(a.dq128 + 2 * cslot(), k);
+    } else {
+      const double x = block_sum<double>(G.f, red_d);
+      if (threadIdx.x == 0 && x != 0.0) atomicAdd(a.dq + cslot(), x);
+    }
+  }
+}
+
+// ---------------------------------------------------------- swap check ---
+// Swap rule of the synchronous local-moving, between a group's decisions
+// and its commit: a recorded move of vertex i (community d, target t) of a
+// row of at most kSwapRowMax arcs yields if an adjacent vertex j of the
+// same group chose d while in t, and j has the lower id or more than
+// kSwapRowMax arcs (such rows never yield).  Two such vertices would trade
+// places and trade back in the next iteration.  A move can only yield if
+// its target holds a neighbour of the group; the decision kernels flag
+// exactly those (cand), and this kernel, walking the group's rows of at
+// most kSwapRowMax arcs, clears the flags and checks only the flagged rows.
+// Only targets and labels are read, which nothing changes before the
+// commit, so the result does not depend on the order of the workgroups; a
+// yielding vertex gets a flag the commit consumes.  A workgroup lays the
+// rows of the candidates among kBlock list entries end to end and every
+// lane takes one arc per step.
+__device__ __forceinline__ bool swap_partner(const ScanArgs& a, int32_t j, int32_t i, int32_t d, int32_t t,
+                                             int32_t vbase, int sh) {
+  if (j == i || group_in_pass(a, j, vbase, sh) != a.grp) return false;
+  return a.target[j] == d && a.C[j] == t;
+}
+
+template <class WT>
+__global__ __launch_bounds__(kBlock) void k_swap_check(GraphView<WT> g, ScanArgs a, const int32_t* __restrict__ list,
+                                                       int32_t count) {
+  __shared__ int32_t off[kBlock + 1], beg[kBlock], vi[kBlock], vd[kBlock], vt[kBlock], vb[kBlock], vs[kBlock];
+  __shared__ int32_t hit[kBlock], wsum[kBlock / kWave];
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = base + threadIdx.x;
+    const int32_t i = (k < count) ? list[k] : 0;
+    bool c = false;
+    if (k < count && a.cand[i]) {
+      c = true;
+      a.cand[i] = 0;
+    }
+    const int32_t t = c ? a.target[i] : -1;
+    const int32_t deg = (t >= 0) ? g.degree(i) : 0;
+    int incl = deg;
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+      const int x = __shfl_up(incl, o);
+      if (lane_id() >= o) incl += x;
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) wsum[w] = incl;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int q = 0; q < kBlock / kWave; ++q) {
+      if (q < w) before += wsum[q];
+      total += wsum[q];
+    }
+    off[threadIdx.x] = before + incl - deg;
+    if (threadIdx.x == 0) off[kBlock] = total;
+    beg[threadIdx.x] = (t >= 0) ? g.begin(i) : 0;
+    vi[threadIdx.x] = i;
+    vd[threadIdx.x] = (t >= 0) ? a.C[i] : kEmpty;
+    vt[threadIdx.x] = t;
+    vb[threadIdx.x] = a.gid ? a.vbase[a.gid[i]] : 0;
+    vs[threadIdx.x] = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
+    hit[threadIdx.x] = 0;
+    __syncthreads();
+    for (int32_t q = threadIdx.x; q < total; q += kBlock) {
+      int lo = 0, hi = kBlock;  // off[lo] <= q < off[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= q) lo = mid; else hi = mid;
+      }
+      const int32_t j = g.idx[(int64_t)beg[lo] + (q - off[lo])];
+      const int32_t me = vi[lo];
+      if (swap_partner(a, j, me, vd[lo], vt[lo], vb[lo], vs[lo]) && (j < me || g.degree(j) > kSwapRowMax))
+        hit[lo] = 1;  // (every writer stores 1)
+    }
+    __syncthreads();
+    if (t >= 0 && hit[threadIdx.x]) a.yld[i] = 1;
+    __syncthreads();  // the tile's LDS is rewritten by the next tile
+  }
 }
 
 // ------------------------------------------------------------- launchers ---
@@ -803,6 +986,15 @@ inline int grid_for(int64_t items, int per_block, int cap) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (int)b;
+}
+
+template <class WT>
+void swap_check_launch(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count) {
+  if (count <= 0) return;
+  const GraphView<WT> g = view<WT>(gd);
+  const int cap = a.commit_grid > 0 ? a.commit_grid : 2048;
+  hipLaunchKernelGGL((k_swap_check<WT>), dim3(grid_for(count, kBlock, cap)), dim3(kBlock), 0, st, g, a, list,
+                     count);
 }
 
 template <class WT, int PH, bool DET>
