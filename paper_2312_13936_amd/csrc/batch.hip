@@ -288,8 +288,6 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   fill_i32(st, ws.hp_lcnt, 0, ch.n);
   fill_i32(st, ws.wd_done, 0, ws.max_wide);
   fill_i32(st, ws.wd_ctr, 0, 2);
-  fill_u8(st, ws.yld, 0, ch.n);
-  fill_u8(st, ws.cand, 0, ch.n);
   ScanArgs a;
   memset(&a, 0, sizeof(a));
   a.C = ws.C; a.CB = ws.CB; a.Sig = ws.Sig; a.size = ws.size; a.K = ws.K; a.flag = ws.flag;
@@ -299,8 +297,7 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.ovf = &ws.sc->ovf;
-  a.gainf = ws.gainf; a.gaink = ws.gaink; a.yld = ws.yld; a.last = ws.last; a.it_dev = &ws.sc->iter;
-  a.cand = ws.cand;
+  a.gainf = ws.gainf; a.gaink = ws.gaink; a.last = ws.last; a.mv = ws.mv; a.it_dev = &ws.sc->iter;
   if (!scan_state_ready(a, det)) return GVL_E_INVALID_ARG;
   a.gsh = B.gsh;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
@@ -360,7 +357,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     HubArgs hargs = hub_args(ws, bins);
     fill_u8(st, ws.flag, 1, nn);
     fill_i32(st, ws.target, -1, nn);
-    fill_i32(st, (int32_t*)ws.last, -3, 4 * nn);  // no vertex has moved in this pass
+    fill_i32(st, (int32_t*)ws.last, kNoLastMove, 2 * nn);  // no vertex has moved in this pass
+    fill_i32(st, (int32_t*)ws.mv, 0, 4 * nn);     // no move recorded (stamps start at 1)
     fill_i32(st, &ws.sc->iter, 0, 1);
 
     // (bx, lx: the short-row bins and their list, thinned during refinement;
@@ -418,7 +416,6 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
           a.grp = grp;
           decide_group(q, grp, kMove, bins, ws.list);
           if (sync_mv) {
-            launch_swap_check(q, cur, a, ws.list + bins.gstart[grp], swap_bound(bins, grp, ctx->lim));
             commit_group(q, grp, kMove, bins, ws.list);
           }
         }
@@ -692,7 +689,8 @@ gvl_status gvl_leiden_fused(gvl_ctx_t ctx, int32_t num_graphs, const gvl_graph_d
   if (!ctx || !opt || num_graphs < 0 || (num_graphs > 0 && (!graphs || !modularities || !statuses)))
     return GVL_E_INVALID_ARG;
   if (opt->mode != GVL_MODE_FAST && opt->mode != GVL_MODE_DET) return GVL_E_INVALID_ARG;
-  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 0 ||
+  if (opt->max_iterations < 1 || opt->max_iterations > kMaxIterationsSync || opt->max_passes < 1 ||
+      opt->refine_sweeps < 1 || opt->subsweeps < 0 ||
       (opt->subsweeps == 0 && opt->mode == GVL_MODE_DET) || opt->subsweeps > kMaxGroups ||
       !(opt->tolerance_drop > 0.0))
     return GVL_E_INVALID_ARG;

@@ -194,8 +194,6 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   fill_i32(st, ws.hp_lcnt, 0, n);
   fill_i32(st, ws.wd_done, 0, ws.max_wide);
   fill_i32(st, ws.wd_ctr, 0, 2);
-  fill_u8(st, ws.yld, 0, n);
-  fill_u8(st, ws.cand, 0, n);
   if (opt->validate) {
     check_offsets(st, d_off, n, m, ws.sc->flags);
     s = readback(ctx, ws.sc);
@@ -212,8 +210,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
   a.target = ws.target; a.targeted = ws.targeted;
   a.dq = ws.sc->dq; a.dq128 = &ws.sc->dq128[0][0]; a.cnt = &ws.sc->cnt[0][0];
   a.ovf = &ws.sc->ovf;
-  a.gainf = ws.gainf; a.gaink = ws.gaink; a.yld = ws.yld; a.last = ws.last; a.it_dev = &ws.sc->iter;
-  a.cand = ws.cand;
+  a.gainf = ws.gainf; a.gaink = ws.gaink; a.last = ws.last; a.mv = ws.mv; a.it_dev = &ws.sc->iter;
   if (!scan_state_ready(a, det)) return GVL_E_INVALID_ARG;
   a.wd_g = ws.wd_g; a.wd_k = ws.wd_k; a.wd_c = ws.wd_c; a.wd_ok = ws.wd_ok; a.wd_done = ws.wd_done;
   a.wd_next = ws.wd_ctr; a.wd_exit = ws.wd_ctr + 1;
@@ -317,7 +314,8 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     HubArgs hargs = hub_args(ws, bins);
     fill_u8(st, ws.flag, 1, nn);
     fill_i32(st, ws.target, -1, nn);
-    fill_i32(st, (int32_t*)ws.last, -3, 4 * nn);  // no vertex has moved in this pass
+    fill_i32(st, (int32_t*)ws.last, kNoLastMove, 2 * nn);  // no vertex has moved in this pass
+    fill_i32(st, (int32_t*)ws.mv, 0, 4 * nn);     // no move recorded (stamps start at 1)
     fill_i32(st, &ws.sc->iter, 0, 1);
     tm.end(h);
 
@@ -383,7 +381,6 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
         a.ident_after = -1;
         if (sync_mv) {
           tm.end(hk);
-          launch_swap_check(q, cur, a, ws.list + bins.gstart[grp], swap_bound(bins, grp, ctx->lim));
           a.mark_after = (it == 0) ? grp : INT32_MAX;
           commit_group(q, grp, kMove, bins, ws.list);
           a.mark_after = INT32_MAX;

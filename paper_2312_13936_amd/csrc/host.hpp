@@ -49,12 +49,11 @@ struct Workspace {
   int2* CP;
   int32_t* list2;  // refinement: the thinned short-row bins
   // synchronous local-moving: decided gains (FP64, or exact keys in
-  // deterministic mode), swap-rule yield flags, last move of each vertex
+  // deterministic mode), last move of each vertex, move records (ScanArgs)
   double* gainf;
   i128_t* gaink;
-  uint8_t* yld;
-  int4* last;
-  uint8_t* cand;  // swap-rule candidates (ScanArgs::cand)
+  int2* last;
+  int4* mv;
   int32_t *off[2], *deg[2], *idx[2];
   void* w[2];
   TblSlot* tbl;
@@ -118,9 +117,8 @@ static Workspace carve(int64_t n, int64_t m, bool det, char* base, int64_t tbl_n
   w.CP = (int2*)take(8 * N);
   w.list2 = (int32_t*)take(4 * N);
   if (det) w.gaink = (i128_t*)take(16 * N); else w.gainf = (double*)take(8 * N);
-  w.yld = (uint8_t*)take(N);
-  w.last = (int4*)take(16 * N);
-  w.cand = (uint8_t*)take(N);
+  w.last = (int2*)take(8 * N);
+  w.mv = (int4*)take(16 * N);
   for (int b = 0; b < 2; ++b) {
     w.off[b] = (int32_t*)take(4 * (N + 1));
     w.deg[b] = (int32_t*)take(4 * N);
@@ -388,18 +386,9 @@ gvl_status make_bins(gvl_ctx* ctx, Workspace& ws, const int32_t* off, const int3
 }
 
 // Every per-vertex array the synchronous local-moving kernels write or read
-// (gains, yield and candidate flags, last moves, iteration counter) is set.
+// (gains, last moves, move records, iteration counter) is set.
 static inline bool scan_state_ready(const ScanArgs& a, bool det) {
-  return a.yld && a.cand && a.last && a.it_dev && (det ? a.gaink != nullptr : a.gainf != nullptr);
-}
-
-// Entries of group grp's segment of the bin list that can be swap-rule
-// candidates: its rows of at most kSwapRowMax arcs (the lane-group bins,
-// and bin 5 when its tuned lower limit is lower).
-static inline int32_t swap_bound(const BinInfo& bins, int grp, const BinLimits& lim) {
-  int32_t b = bins.start[grp][5] - bins.gstart[grp];
-  if (lim.v[4] < kSwapRowMax) b += bins.count[grp][5];
-  return b;
+  return a.last && a.mv && a.it_dev && (det ? a.gaink != nullptr : a.gainf != nullptr);
 }
 
 // Refinement (Alg. 3) after a sweep: the short-row bins of `bins` (in
@@ -614,7 +603,8 @@ gvl_status check_args(gvl_ctx* ctx, int64_t n, int64_t m, const int32_t* off, co
       (opt->refine_based != 0 && opt->refine_based != 1) || opt->validate < 0 ||
       opt->validate > 2)
     return GVL_E_INVALID_ARG;
-  if (opt->max_iterations < 1 || opt->max_passes < 1 || opt->refine_sweeps < 1 || opt->subsweeps < 0 ||
+  if (opt->max_iterations < 1 || opt->max_iterations > kMaxIterationsSync || opt->max_passes < 1 ||
+      opt->refine_sweeps < 1 || opt->subsweeps < 0 ||
       (opt->subsweeps == 0 && opt->mode == GVL_MODE_DET) || opt->subsweeps > kMaxGroups ||
       !(opt->tolerance_drop > 0.0) || !(opt->aggregation_tolerance >= 0.0))
     return GVL_E_INVALID_ARG;

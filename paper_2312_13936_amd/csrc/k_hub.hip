@@ -394,6 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
             ++nm;
           } else if (PH == kMove) {
             a.target[i] = bc;
+            record_move(a, i, d, bc, -1);
             if (a.gid) {
               if (DET) atomic_add_i128(a.dqg128 + 2 * a.gid[i], bk); else atomicAdd(a.dqg + a.gid[i], bg);
             } else {
@@ -574,6 +575,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
           ++acc.nm;
         } else if (PH == kMove) {
           a.target[i] = bc;
+          record_move(a, i, d, bc, -1);
           add_gain<DET>(a, acc, i, bg, bk);
         } else {
           a.target[i] = bc;

@@ -16,11 +16,6 @@ void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, c
   }
 }
 
-void launch_swap_check(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list, int32_t count) {
-  if (g.w_double) swap_check_launch<double>(st, g, a, list, count);
-  else swap_check_launch<float>(st, g, a, list, count);
-}
-
 void launch_commit(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, const CommitLaunch& cl,
                    int phase) {
   if (phase == kMove) {

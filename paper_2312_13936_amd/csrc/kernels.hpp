@@ -70,6 +70,10 @@ constexpr int32_t kAutoShortRow = 128;
 // under the swap rule and win against shorter rows (a cycle among them is
 // stopped by the bounce rule).
 constexpr int32_t kSwapRowMax = 128;
+// last-move entry of a vertex that has not moved in the pass: no community,
+// iterations -3 and -3 (16 bits each); iterations of a pass fit 16 bits
+constexpr int32_t kNoLastMove = (int32_t)0xFFFDFFFDu;
+constexpr int32_t kMaxIterationsSync = 32767;
 static_assert(kSwapRowMax <= kBinMax[4], "rows of the swap rule sit in the lane-group bins or bin 5");
 
 // List layout: for every group its bins 0..kHubBin-1 (group-major), then the
@@ -139,24 +143,24 @@ struct ScanArgs {
   unsigned long long* cnt;  // [kCntSlots][8]: [0] vertices scanned, [1] arcs, [2] candidates,
                             // [3] moves, [4..6] aggregation, [7] arcs scanned by refinement
   unsigned long long* ovf;  // decisions of wide rows and hubs cancelled by a partition table overflow
-  // synchronous local-moving (the swap and bounce rules): the gain of each
-  // recorded decision of a non-hub row, added to the iteration's sum by the
-  // commit if the move is applied (gaink in deterministic mode, else gainf;
-  // hubs add theirs when they decide);
-  // yield flags set by the swap check (zero outside a group's check ->
-  // commit); each vertex's last move (community left, iteration, iteration
-  // of the move before); the pass's iteration number in device memory
+  // synchronous local-moving (the swap and bounce rules): decisions add
+  // their gains to the iteration's sum; a swap-rule candidate (its target
+  // stored as -2 - target) also keeps its gain here, which the commit takes
+  // back if the move yields (gaink in deterministic mode, else gainf); each
+  // vertex's last move (community left; iteration of that move in the low
+  // and of the move before in the high 16 bits); the move records the
+  // swap rule reads: (community, target, stamp of the iteration and group,
+  // 0), written by the decisions of every row longer than kSwapRowMax and
+  // of the shorter rows whose target holds a neighbour of the same group,
+  // and only read by the commits (stamps are reset every pass); the pass's
+  // iteration number in device memory
   double* gainf;
   i128_t* gaink;
-  uint8_t* yld;
-  int4* last;
+  int2* last;
+  int4* mv;
   const int32_t* it_dev;
   int32_t grp;              // the group deciding (swap rule)
   const int32_t* gsh;       // fused batches: per-graph group shift (see kAutoFewGroups), or nullptr
-  // swap-rule candidates: recorded moves of rows of at most kSwapRowMax arcs
-  // whose target holds a neighbour of the same group (1; cleared by the
-  // group's swap check)
-  uint8_t* cand;
   // wide rows: partial bests of the partitions of each vertex of a launch
   // ([vertex][kWideMaxParts]) and the partitions finished per vertex
   double* wd_g;
@@ -306,10 +310,6 @@ struct CommitLaunch {
 
 void launch_commit(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, const CommitLaunch& cl,
                    int phase);
-// Swap rule of the synchronous local-moving over the candidates the group's
-// decisions flagged among list[0..count) (its rows of at most kSwapRowMax
-// arcs), between its decisions and its commit; a.grp is the group.
-void launch_swap_check(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list, int32_t count);
 
 // ---- aggregation (k_aggregate.hip)
 void launch_agg_rows(hipStream_t st, const GraphDesc& g, const AggArgs& a, const int32_t* list,

@@ -165,10 +165,26 @@ __device__ __forceinline__ int group_in_pass(const ScanArgs& a, int32_t j, int32
   return group_of(j - vbase, a.groups >> sh) << sh;
 }
 
+// Stamp of the current (iteration, group) of the synchronous local-moving,
+// unique within a pass and > 0; and the move record of a decision: partner
+// = the one neighbour of the group in the target (a row of at most
+// kSwapRowMax arcs), -2 for several (the commit reads the row), -1 for a
+// row that never yields.
+__device__ __forceinline__ int32_t move_stamp(const ScanArgs& a) { return *a.it_dev * a.groups + a.grp + 1; }
+__device__ __forceinline__ void record_move(const ScanArgs& a, int32_t i, int32_t d, int32_t t, int32_t partner) {
+  a.mv[i] = make_int4(d, t, move_stamp(a), partner);
+}
+
 template <int G>
-__device__ __forceinline__ int or_lanes(int f) {
+__device__ __forceinline__ int sum_lanes(int f) {
 #pragma unroll
-  for (int o = 1; o < G; o <<= 1) f |= __shfl_xor(f, o, G);
+  for (int o = 1; o < G; o <<= 1) f += __shfl_xor(f, o, G);
+  return f;
+}
+template <int G>
+__device__ __forceinline__ int max_lanes(int f) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) f = max(f, __shfl_xor(f, o, G));
   return f;
 }
 
@@ -199,8 +215,8 @@ __device__ __forceinline__ bool mark_needed(const ScanArgs& a, int32_t j) {
 // it left in the last one (it is cycling with a neighbour of its group).
 __device__ __forceinline__ bool bounces(const ScanArgs& a, int32_t i, int32_t bc) {
   const int32_t it = *a.it_dev;
-  const int4 l = a.last[i];
-  return l.x == bc && l.y == it - 1 && l.z == it - 2;
+  const int2 l = a.last[i];
+  return l.x == bc && (int16_t)(l.y & 0xFFFF) == it - 1 && (int16_t)((uint32_t)l.y >> 16) == it - 2;
 }
 
 // After the argmax: apply the min-label rule, the sign test and, for a
@@ -224,9 +240,11 @@ __device__ __forceinline__ bool accept(const ScanArgs& a, int32_t i, int32_t d, 
 // whose slot would otherwise take an atomic per intra-community arc), every
 // other neighbour community goes to ins(c, w).  U arcs per round, with their
 // index, weight, label (and bound) loads issued together.
-template <int U, int NT, int PH, class WT, class Ins>
+// note(u, j, c) sees arc u of the lane's round (j: neighbour, c: its label,
+// kEmpty past the row or outside the bound).
+template <int U, int NT, int PH, class WT, class Ins, class Note>
 __device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArgs& a, int32_t i, int32_t beg,
-                                           int32_t deg, int32_t e0, int32_t d, int32_t bi, Ins ins) {
+                                           int32_t deg, int32_t e0, int32_t d, int32_t bi, Ins ins, Note note) {
   double kid = 0.0;
   for (int32_t base = e0; base < deg; base += U * NT) {
     int32_t j[U];
@@ -256,12 +274,18 @@ __device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArg
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      note(u, j[u], c[u]);
       if (c[u] == kEmpty) continue;
       if (c[u] == d) kid += w[u];
       else ins(c[u], w[u]);
     }
   }
   return kid;
+}
+template <int U, int NT, int PH, class WT, class Ins>
+__device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArgs& a, int32_t i, int32_t beg,
+                                           int32_t deg, int32_t e0, int32_t d, int32_t bi, Ins ins) {
+  return scan_row<U, NT, PH>(g, a, i, beg, deg, e0, d, bi, ins, [](int, int32_t, int32_t) {});
 }
 
 // Evaluates the table slots s0, s0 + NT, ... < ts (no slot holds d) and
@@ -338,9 +362,15 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     // table of next_pow2(2 deg) <= TS slots: at most deg distinct keys
     const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
-    constexpr int UA = (BMAX + G - 1) / G;
-    double kid = scan_row<UA, G, PH>(g, a, i, beg, deg, gl, d, bi,
-                                     [&](int32_t c, double w) { lds_insert(keys, vals, lg, c, w); });
+    constexpr int UA = (BMAX + G - 1) / G;  // (one round: the row's arcs gl, gl + G, ... stay in registers)
+    // labels of the lane's arcs gl + u G (kEmpty past the row: a lane whose
+    // first arc lies past it sees none), kept for the swap-rule candidate test
+    int32_t rc[UA];
+#pragma unroll
+    for (int u = 0; u < UA; ++u) rc[u] = kEmpty;
+    double kid = scan_row<UA, G, PH>(
+        g, a, i, beg, deg, gl, d, bi, [&](int32_t c, double w) { lds_insert(keys, vals, lg, c, w); },
+        [&](int u, int32_t, int32_t c) { rc[u] = c; });
     kid = sum_xor<G>(kid);
     wave_sync();
     const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
@@ -369,21 +399,32 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
         if (j != i) a.flag[j] = 1;
       }
     } else if (PH == kMove) {
-      if (gl == 0) {
-        a.target[i] = bc;
-        store_gain<DET>(a, i, bg, bk);
-      }
-      // swap-rule candidate if the target holds a neighbour of the group
-      // (labels do not change during the decisions of a group)
+      // swap-rule candidate if the target holds a neighbour of the group:
+      // its move record names that neighbour (-2: several)
       const int32_t vb = a.gid ? a.vbase[a.gid[i]] : 0;
       const int sh = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
-      int f = 0;
-      for (int32_t e = gl; e < deg; e += G) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i && group_in_pass(a, j, vb, sh) == a.grp && a.C[j] == bc) f = 1;
+      int np = 0, pj = -1;
+#pragma unroll
+      for (int u = 0; u < UA; ++u)
+        if (rc[u] == bc) {  // (bc is not the own community, so the arc is not a self-loop)
+          const int32_t j = g.idx[beg + gl + u * G];
+          if (group_in_pass(a, j, vb, sh) == a.grp) {
+            ++np;
+            pj = j;
+          }
+        }
+      np = sum_lanes<G>(np);
+      pj = max_lanes<G>(pj);
+      if (gl == 0) {
+        add_gain<DET>(a, acc, i, bg, bk);
+        if (np > 0) {
+          a.target[i] = -2 - bc;
+          store_gain<DET>(a, i, bg, bk);
+          record_move(a, i, d, bc, np == 1 ? pj : -2);
+        } else {
+          a.target[i] = bc;
+        }
       }
-      f = or_lanes<G>(f);
-      if (gl == 0 && f) a.cand[i] = 1;
     } else {
       if (gl == 0) { a.target[i] = bc; a.targeted[bc] = cur_stamp(a); }
     }
@@ -477,19 +518,15 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
       }
     } else if (PH == kMove) {
       if (threadIdx.x == 0) {
-        a.target[i] = bc;
-        store_gain<DET>(a, i, bg, bk);
-      }
-      if (deg <= kSwapRowMax) {  // uniform (only with a tuned lane-group limit below kSwapRowMax)
-        const int32_t vb = a.gid ? a.vbase[a.gid[i]] : 0;
-        const int sh = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
-        int f = 0;
-        for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
-          const int32_t j = g.idx[beg + e];
-          if (j != i && group_in_pass(a, j, vb, sh) == a.grp && a.C[j] == bc) f = 1;
+        add_gain<DET>(a, acc, i, bg, bk);
+        if (deg <= kSwapRowMax) {  // (only with a tuned lane-group limit below kSwapRowMax) a candidate
+          a.target[i] = -2 - bc;
+          store_gain<DET>(a, i, bg, bk);
+          record_move(a, i, d, bc, -2);
+        } else {  // a possible partner
+          a.target[i] = bc;
+          record_move(a, i, d, bc, -1);
         }
-        f = __syncthreads_or(f);
-        if (threadIdx.x == 0 && f) a.cand[i] = 1;
       }
     } else {
       if (threadIdx.x == 0) { a.target[i] = bc; a.targeted[bc] = cur_stamp(a); }
@@ -659,7 +696,8 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
           ++acc.nm;
         } else if (PH == kMove) {
           a.target[i] = bc;
-          store_gain<DET>(a, i, bg, bk);
+          add_gain<DET>(a, acc, i, bg, bk);
+          record_move(a, i, d, bc, -1);
         } else {
           a.target[i] = bc;
           a.targeted[bc] = cur_stamp(a);
@@ -695,27 +733,63 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
 // marked unprocessed; the workgroup lays its movers' rows end to end and
 // every lane marks one arc per step.  Without MARK (long rows, hubs) the
 // targets stay for the marking kernels.
-// Summed gains of the applied synchronous moves of one thread.
+// Gains taken back from the iteration's sum for the moves that yield (one
+// thread).
 struct CommitGain {
   double f = 0.0;
   i128 k = 0;
 };
 
 // An applied local-moving move of vertex i out of community d: its record
-// for the bounce rule, and (take_gain) its gain added to the iteration's sum
-// (per graph in a fused batch, else per thread and reduced at kernel end).
+// for the bounce rule.  A move that yields under the swap rule takes its
+// gain back out of the iteration's sum (per graph in a fused batch, else per
+// thread and reduced at kernel end).
 __device__ __forceinline__ void note_move(const ScanArgs& a, int32_t i, int32_t d) {
-  const int4 l = a.last[i];
-  a.last[i] = make_int4(d, *a.it_dev, l.y, 0);
+  const int2 l = a.last[i];
+  a.last[i] = make_int2(d, (int32_t)(((uint32_t)l.y << 16) | ((uint32_t)*a.it_dev & 0xFFFFu)));
 }
-__device__ __forceinline__ void take_gain(const ScanArgs& a, int32_t i, CommitGain& G) {
+__device__ __forceinline__ void untake_gain(const ScanArgs& a, int32_t i, CommitGain& G) {
   if (a.gaink) {
-    const i128 k = a.gaink[i];
+    const i128 k = -a.gaink[i];
     if (a.gid) atomic_add_i128(a.dqg128 + 2 * a.gid[i], k); else G.k += k;
   } else {
-    const double x = a.gainf[i];
+    const double x = -a.gainf[i];
     if (a.gid) atomicAdd(a.dqg + a.gid[i], x); else G.f += x;
   }
+}
+
+// Swap rule of the synchronous local-moving, in the commit of a group: a
+// recorded move of vertex i (community d, target t) of a row of at most
+// kSwapRowMax arcs yields if an adjacent vertex j of the same group chose d
+// while in t (its move record of this iteration and group), and j has the
+// lower id or more than kSwapRowMax arcs (such rows never yield).  Two such
+// vertices would trade places and trade back in the next iteration.  The
+// records are written by the decisions only, so the answer does not depend
+// on which moves of the group were applied before.  Only candidates (their
+// target holds a neighbour of the group; target stored as -2 - t) can have
+// such a partner.
+template <class WT>
+__device__ __forceinline__ bool swap_yields(const GraphView<WT>& g, const ScanArgs& a, int32_t i, int32_t d,
+                                            int32_t t) {
+  const int32_t stamp = move_stamp(a);
+  const int4 own = a.mv[i];
+  if (own.z != stamp || own.w == -1) return false;
+  if (own.w >= 0) {  // the one neighbour of the group in the target
+    const int32_t j = own.w;
+    if ((int64_t)j >= g.n) return false;
+    const int4 r = a.mv[j];
+    return r.z == stamp && r.x == t && r.y == d && (j < i || g.degree(j) > kSwapRowMax);
+  }
+  const int32_t beg = g.begin(i), deg = g.degree(i);
+  const int32_t vb = a.gid ? a.vbase[a.gid[i]] : 0;
+  const int sh = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
+  for (int32_t e = 0; e < deg; ++e) {
+    const int32_t j = g.idx[beg + e];
+    if (j == i || group_in_pass(a, j, vb, sh) != a.grp) continue;
+    const int4 r = a.mv[j];
+    if (r.z == stamp && r.x == t && r.y == d && (j < i || g.degree(j) > kSwapRowMax)) return true;
+  }
+  return false;
 }
 
 // Shared memory of the commit roles.
@@ -737,16 +811,18 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
     const int32_t i = (k < count) ? list[k] : 0;
     int32_t t = -1;
     if (k < count) t = a.target[i];
+    const bool cand = PH == kMove && MARK && t <= -2;
+    if (cand) t = -2 - t;
     bool mv = t >= 0;
     if (mv) {
+      const int32_t d = a.C[i];
       if (PH == kMove && MARK) {
         a.target[i] = -1;
-        if (a.yld[i]) {  // swap rule: the neighbour takes this vertex's place
-          a.yld[i] = 0;
+        if (cand && swap_yields(g, a, i, d, t)) {  // the neighbour takes this vertex's place
           mv = false;
+          untake_gain(a, i, G);
         }
       }
-      const int32_t d = a.C[i];
       if (PH == kRefine) {
         a.target[i] = -1;
         if (a.targeted[d] == cur_stamp(a)) mv = false;  // own community chosen by this group
@@ -757,10 +833,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
         keyed_put(L.kt, t, ki, 1);
         a.C[i] = t;
         if (PH == kRefine && a.CP) a.CP[i].x = t;
-        if (PH == kMove) {
-          note_move(a, i, d);
-          if (MARK) take_gain(a, i, G);  // (hubs, MARK = false, added theirs when deciding)
-        }
+        if (PH == kMove) note_move(a, i, d);
         ++nm;
         if (PH == kRefine && a.gid) atomicAdd(&a.mvg[a.gid[i]], 1ull);
       }
@@ -812,15 +885,17 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
   for (int64_t k = bid; k < count; k += nb) {
     const int32_t i = list[k];
     if (threadIdx.x == 0) {
-      const int32_t t = a.target[i];
+      int32_t t = a.target[i];
+      const bool cand = t <= -2;  // (rows of bin 5 up to kSwapRowMax arcs, with a tuned lane-group limit)
+      if (cand) t = -2 - t;
       L.mv = t >= 0;
       if (t >= 0) {
         a.target[i] = -1;
-        if (a.yld[i]) {  // swap rule
-          a.yld[i] = 0;
+        const int32_t d = a.C[i];
+        if (cand && swap_yields(g, a, i, d, t)) {
           L.mv = 0;
+          untake_gain(a, i, G);
         } else {
-          const int32_t d = a.C[i];
           const double ki = a.K[i];
           atomicAdd(&a.Sig[d], -ki);
           atomicAdd(&a.Sig[t], ki);
@@ -828,7 +903,6 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
           atomicAdd(&a.size[t], 1);
           a.C[i] = t;
           note_move(a, i, d);
-          take_gain(a, i, G);
           ++nm;
         }
       }
@@ -885,7 +959,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
   }
   nm = block_sum<unsigned long long>(nm, red_u);
   if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
-  if (PH == kMove && !a.gid) {  // the applied moves' gains (fused batches added theirs per graph)
+  if (PH == kMove && !a.gid) {  // gains of the moves that yielded, taken back (fused batches: per graph)
     if (a.gaink) {
       const i128 k = block_sum_i128(G.k, red_k);
       if (threadIdx.x == 0 && k != 0) atomic_add_i128(a.dq128 + 2 * cslot(), k);
@@ -893,83 +967,6 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
       const double x = block_sum<double>(G.f, red_d);
       if (threadIdx.x == 0 && x != 0.0) atomicAdd(a.dq + cslot(), x);
     }
-  }
-}
-
-// ---------------------------------------------------------- swap check ---
-// Swap rule of the synchronous local-moving, between a group's decisions
-// and its commit: a recorded move of vertex i (community d, target t) of a
-// row of at most kSwapRowMax arcs yields if an adjacent vertex j of the
-// same group chose d while in t, and j has the lower id or more than
-// kSwapRowMax arcs (such rows never yield).  Two such vertices would trade
-// places and trade back in the next iteration.  A move can only yield if
-// its target holds a neighbour of the group; the decision kernels flag
-// exactly those (cand), and this kernel, walking the group's rows of at
-// most kSwapRowMax arcs, clears the flags and checks only the flagged rows.
-// Only targets and labels are read, which nothing changes before the
-// commit, so the result does not depend on the order of the workgroups; a
-// yielding vertex gets a flag the commit consumes.  A workgroup lays the
-// rows of the candidates among kBlock list entries end to end and every
-// lane takes one arc per step.
-__device__ __forceinline__ bool swap_partner(const ScanArgs& a, int32_t j, int32_t i, int32_t d, int32_t t,
-                                             int32_t vbase, int sh) {
-  if (j == i || group_in_pass(a, j, vbase, sh) != a.grp) return false;
-  return a.target[j] == d && a.C[j] == t;
-}
-
-template <class WT>
-__global__ __launch_bounds__(kBlock) void k_swap_check(GraphView<WT> g, ScanArgs a, const int32_t* __restrict__ list,
-                                                       int32_t count) {
-  __shared__ int32_t off[kBlock + 1], beg[kBlock], vi[kBlock], vd[kBlock], vt[kBlock], vb[kBlock], vs[kBlock];
-  __shared__ int32_t hit[kBlock], wsum[kBlock / kWave];
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < count; base += (int64_t)gridDim.x * kBlock) {
-    const int64_t k = base + threadIdx.x;
-    const int32_t i = (k < count) ? list[k] : 0;
-    bool c = false;
-    if (k < count && a.cand[i]) {
-      c = true;
-      a.cand[i] = 0;
-    }
-    const int32_t t = c ? a.target[i] : -1;
-    const int32_t deg = (t >= 0) ? g.degree(i) : 0;
-    int incl = deg;
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-      const int x = __shfl_up(incl, o);
-      if (lane_id() >= o) incl += x;
-    }
-    const int w = threadIdx.x / kWave;
-    if (lane_id() == kWave - 1) wsum[w] = incl;
-    __syncthreads();
-    int before = 0, total = 0;
-    for (int q = 0; q < kBlock / kWave; ++q) {
-      if (q < w) before += wsum[q];
-      total += wsum[q];
-    }
-    off[threadIdx.x] = before + incl - deg;
-    if (threadIdx.x == 0) off[kBlock] = total;
-    beg[threadIdx.x] = (t >= 0) ? g.begin(i) : 0;
-    vi[threadIdx.x] = i;
-    vd[threadIdx.x] = (t >= 0) ? a.C[i] : kEmpty;
-    vt[threadIdx.x] = t;
-    vb[threadIdx.x] = a.gid ? a.vbase[a.gid[i]] : 0;
-    vs[threadIdx.x] = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
-    hit[threadIdx.x] = 0;
-    __syncthreads();
-    for (int32_t q = threadIdx.x; q < total; q += kBlock) {
-      int lo = 0, hi = kBlock;  // off[lo] <= q < off[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (off[mid] <= q) lo = mid; else hi = mid;
-      }
-      const int32_t j = g.idx[(int64_t)beg[lo] + (q - off[lo])];
-      const int32_t me = vi[lo];
-      if (swap_partner(a, j, me, vd[lo], vt[lo], vb[lo], vs[lo]) && (j < me || g.degree(j) > kSwapRowMax))
-        hit[lo] = 1;  // (every writer stores 1)
-    }
-    __syncthreads();
-    if (t >= 0 && hit[threadIdx.x]) a.yld[i] = 1;
-    __syncthreads();  // the tile's LDS is rewritten by the next tile
   }
 }
 
@@ -986,15 +983,6 @@ inline int grid_for(int64_t items, int per_block, int cap) {
   if (b < 1) b = 1;
   if (b > cap) b = cap;
   return (int)b;
-}
-
-template <class WT>
-void swap_check_launch(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list, int32_t count) {
-  if (count <= 0) return;
-  const GraphView<WT> g = view<WT>(gd);
-  const int cap = a.commit_grid > 0 ? a.commit_grid : 2048;
-  hipLaunchKernelGGL((k_swap_check<WT>), dim3(grid_for(count, kBlock, cap)), dim3(kBlock), 0, st, g, a, list,
-                     count);
 }
 
 template <class WT, int PH, bool DET>

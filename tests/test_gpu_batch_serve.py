@@ -24,8 +24,7 @@ FAST_TOL = 1e-3
 # (i) and (ii) stated in test_gpu_parity.py:
 #   lfr-14820-7017   (i) sequential spread 5.3e-3 over numberings (0.6583 ..
 #                    0.6636); asynchronous lane-pool runs -4.7e-3 .. +0.7e-3
-#   lfr-24108-14000  (ii) det oracle -1.03e-3 (sequential spread 1.8e-4);
-#                    the fast mode's synchronous schedule -1.03e-3
+#   lfr-24108-14000  (ii) det oracle -0.97e-3 (sequential spread 1.8e-4)
 #   lfr-13658-14004  (ii) det oracle -0.96e-3 (spread 2.7e-4)
 #   lfr-14903-12006  (ii) det oracle -0.73e-3 (spread 1.5e-4); asynchronous
 #                    serving runs -0.8e-3

@@ -167,14 +167,15 @@ def fast_bar(g, name):
 # (ii) the oracle run with the GPU's group-synchronous schedule (its
 #      deterministic mode: exact arithmetic) itself lands more than 7e-4
 #      below the sequential result; margin 1.5e-3.
-# Measured (sequential spread over numberings; deterministic oracle and GPU
-# runs relative to the given numbering's sequential result):
-#   rmat-s12      spread 2.1e-2 (0.0945 .. 0.1153); det -1.1e-3; asynchronous
-#                 schedule -3.3e-3 .. +0.9e-3 over five runs
-#   er-selfloops  spread 8.9e-3 (0.3577 .. 0.3666); det -1.7e-3; asynchronous
-#                 -5.1e-3 (five runs)
-#   grid64-w100   spread 1.4e-3 (0.9274 .. 0.9289); asynchronous -0.9e-3 ..
-#                 -0.3e-3
+# Measured (sequential spread over numberings; deterministic oracle with the
+# default sub-sweep count and asynchronous GPU runs, relative to the given
+# numbering's sequential result):
+#   rmat-s12      spread 2.1e-2 (0.0945 .. 0.1153); det -0.1e-3 (32 groups);
+#                 asynchronous schedule -3.3e-3 .. +0.9e-3 over five runs
+#   er-selfloops  spread 8.9e-3 (0.3577 .. 0.3666); det +0.7e-3 (8 groups);
+#                 asynchronous -5.1e-3 (five runs)
+#   grid64-w100   spread 1.4e-3 (0.9274 .. 0.9289); det -1.0e-3 (8 groups);
+#                 asynchronous -0.9e-3 .. -0.3e-3
 WIDER_BAR = {"rmat-s12": 4e-3, "er-selfloops": 6e-3, "grid64-w100": 1.5e-3}
 
 # With an asynchronous schedule (sync_moves 0, 1 or 2: some or all commits
