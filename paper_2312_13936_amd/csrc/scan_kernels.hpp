@@ -733,28 +733,21 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
 // marked unprocessed; the workgroup lays its movers' rows end to end and
 // every lane marks one arc per step.  Without MARK (long rows, hubs) the
 // targets stay for the marking kernels.
-// Gains taken back from the iteration's sum for the moves that yield (one
-// thread).
-struct CommitGain {
-  double f = 0.0;
-  i128 k = 0;
-};
-
 // An applied local-moving move of vertex i out of community d: its record
-// for the bounce rule.  A move that yields under the swap rule takes its
-// gain back out of the iteration's sum (per graph in a fused batch, else per
-// thread and reduced at kernel end).
+// for the bounce rule.  A move that yields under the swap rule (rare) takes
+// its gain back out of the iteration's sum with one atomic (per graph in a
+// fused batch).
 __device__ __forceinline__ void note_move(const ScanArgs& a, int32_t i, int32_t d) {
   const int2 l = a.last[i];
   a.last[i] = make_int2(d, (int32_t)(((uint32_t)l.y << 16) | ((uint32_t)*a.it_dev & 0xFFFFu)));
 }
-__device__ __forceinline__ void untake_gain(const ScanArgs& a, int32_t i, CommitGain& G) {
+__device__ __forceinline__ void untake_gain(const ScanArgs& a, int32_t i) {
   if (a.gaink) {
     const i128 k = -a.gaink[i];
-    if (a.gid) atomic_add_i128(a.dqg128 + 2 * a.gid[i], k); else G.k += k;
+    atomic_add_i128(a.gid ? a.dqg128 + 2 * a.gid[i] : a.dq128 + 2 * cslot(), k);
   } else {
     const double x = -a.gainf[i];
-    if (a.gid) atomicAdd(a.dqg + a.gid[i], x); else G.f += x;
+    atomicAdd(a.gid ? a.dqg + a.gid[i] : a.dq + cslot(), x);
   }
 }
 
@@ -804,7 +797,7 @@ struct CommitLds {
 template <class WT, int PH, bool MARK>
 __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& g, const ScanArgs& a,
                                                            const int32_t* __restrict__ list, int32_t count,
-                                                           int32_t bid, int32_t nb, CommitLds& L, CommitGain& G) {
+                                                           int32_t bid, int32_t nb, CommitLds& L) {
   unsigned long long nm = 0;
   for (int64_t base = (int64_t)bid * kBlock; base < count; base += (int64_t)nb * kBlock) {
     const int64_t k = base + threadIdx.x;
@@ -820,7 +813,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
         a.target[i] = -1;
         if (cand && swap_yields(g, a, i, d, t)) {  // the neighbour takes this vertex's place
           mv = false;
-          untake_gain(a, i, G);
+          untake_gain(a, i);
         }
       }
       if (PH == kRefine) {
@@ -880,7 +873,7 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
 template <class WT>
 __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g, const ScanArgs& a,
                                                           const int32_t* __restrict__ list, int32_t count,
-                                                          int32_t bid, int32_t nb, CommitLds& L, CommitGain& G) {
+                                                          int32_t bid, int32_t nb, CommitLds& L) {
   unsigned long long nm = 0;
   for (int64_t k = bid; k < count; k += nb) {
     const int32_t i = list[k];
@@ -894,7 +887,7 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
         const int32_t d = a.C[i];
         if (cand && swap_yields(g, a, i, d, t)) {
           L.mv = 0;
-          untake_gain(a, i, G);
+          untake_gain(a, i);
         } else {
           const double ki = a.K[i];
           atomicAdd(&a.Sig[d], -ki);
@@ -925,9 +918,6 @@ template <class WT, int PH>
 __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, HubArgs h, CommitLaunch cl) {
   __shared__ CommitLds L;
   __shared__ unsigned long long red_u[16];
-  __shared__ double red_d[16];
-  __shared__ i128 red_k[16];
-  CommitGain G;
   keyed_clear(L.kt);
   const int32_t x = (int32_t)blockIdx.x;
   int r = 0;
@@ -935,14 +925,14 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
   const int32_t bid = x - cl.b[r], nb = cl.b[r + 1] - cl.b[r];
   unsigned long long nm = 0;
   if (PH == kRefine) {
-    if (r == 0) nm = commit_tiles<WT, kRefine, false>(g, a, cl.l0, cl.n0, bid, nb, L, G);
-    else nm = commit_tiles<WT, kRefine, false>(g, a, cl.l2, cl.n2, bid, nb, L, G);
+    if (r == 0) nm = commit_tiles<WT, kRefine, false>(g, a, cl.l0, cl.n0, bid, nb, L);
+    else nm = commit_tiles<WT, kRefine, false>(g, a, cl.l2, cl.n2, bid, nb, L);
   } else if (r == 0) {
-    nm = commit_tiles<WT, kMove, true>(g, a, cl.l0, cl.n0, bid, nb, L, G);
+    nm = commit_tiles<WT, kMove, true>(g, a, cl.l0, cl.n0, bid, nb, L);
   } else if (r == 1) {
-    nm = commit_long<WT>(g, a, cl.l1, cl.n1, bid, nb, L, G);
+    nm = commit_long<WT>(g, a, cl.l1, cl.n1, bid, nb, L);
   } else if (r == 2) {
-    nm = commit_tiles<WT, kMove, false>(g, a, cl.l2, cl.n2, bid, nb, L, G);
+    nm = commit_tiles<WT, kMove, false>(g, a, cl.l2, cl.n2, bid, nb, L);
   } else {
     for (int64_t t = cl.c0 + (int64_t)bid; t < cl.c1; t += nb) {
       const int2 task = h.chunk_tasks[t];
@@ -959,15 +949,6 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
   }
   nm = block_sum<unsigned long long>(nm, red_u);
   if (threadIdx.x == 0 && nm) atomicAdd(&cnt_of(a.cnt)[3], nm);
-  if (PH == kMove && !a.gid) {  // gains of the moves that yielded, taken back (fused batches: per graph)
-    if (a.gaink) {
-      const i128 k = block_sum_i128(G.k, red_k);
-      if (threadIdx.x == 0 && k != 0) atomic_add_i128(a.dq128 + 2 * cslot(), k);
-    } else {
-      const double x = block_sum<double>(G.f, red_d);
-      if (threadIdx.x == 0 && x != 0.0) atomicAdd(a.dq + cslot(), x);
-    }
-  }
 }
 
 // ------------------------------------------------------------- launchers ---

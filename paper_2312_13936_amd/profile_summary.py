@@ -1,15 +1,20 @@
 """Summaries of rocprofv3 output for the profiles/ folder.
 
-    python -m paper_2312_13936_amd.profile_summary stats  <kernel_stats.csv> <bench.json> <out.md> <command>
-    python -m paper_2312_13936_amd.profile_summary counters <fetch.csv> <write.csv> <calib_bytes> <out.md> <command>
+    python -m paper_2312_13936_amd.profile_summary stats  <kernel_stats.csv> <bench.json> <calls> <out.md> <command>
+    python -m paper_2312_13936_amd.profile_summary counters <fetch.csv> <write.csv> <calib_bytes> <calls> <out.md> <command>
+    python -m paper_2312_13936_amd.profile_summary pmc <calls> <out.md> <command> <counter_collection.csv>...
 
 `stats` writes the per-kernel time table of a `--kernel-trace --stats` run
-grouped into the scan and aggregation classes.  `counters` sums FETCH_SIZE
-and WRITE_SIZE (KiB per dispatch) over the dispatches of each class, scales
-each counter by what it reads for the device-to-device copy of
-`calib_bytes` bytes that the benchmark runs first, and records the result
-with a digest of the kernel sources; bench.py reports it as the roofline's
-`traffic` only while that digest matches the current sources.
+(`calls` gvl_leiden calls) grouped into the scan and aggregation classes,
+per call beside the bench line's HIP-event times.  `counters` sums FETCH_SIZE
+and WRITE_SIZE (KiB per dispatch) over the dispatches of each class, divides
+by the number of gvl_leiden calls the run made, scales each counter by what
+it reads for the device-to-device copy of `calib_bytes` bytes that the
+benchmark runs first, and records the result with a digest of the kernel
+sources; bench.py reports it as the roofline's `traffic` only while that
+digest matches the current sources.  `pmc` tabulates any other counters
+(one csv per rocprofv3 pass) per call, by kernel class and for the kernels
+that take the most time.
 """
 from __future__ import annotations
 
@@ -45,7 +50,8 @@ def short(name: str) -> str:
     return name
 
 
-def stats(stats_csv, bench_json, out, command):
+def stats(stats_csv, bench_json, calls, out, command):
+    calls = int(calls)
     rows = list(csv.DictReader(open(stats_csv)))
     bench = json.loads(open(bench_json).read().strip().splitlines()[-1])
     tot = sum(float(r["TotalDurationNs"]) for r in rows) / 1e6
@@ -61,13 +67,14 @@ def stats(stats_csv, bench_json, out, command):
              "Command (from the repository root on the MI355X box):", "", "```", command, "```", "",
              "One gvl_leiden call: %.1f ms wall, Q = %.4f, %d passes, %s mode." % (
                  bench["ms_per_step"], bench["modularity"], bench["passes"], bench["config"]["mode"]), "",
-             "| kernel class | rocprofv3 total (ms) | HIP-event total in bench.py (ms) |", "|---|---|---|",
+             "| kernel class | rocprofv3, per call (ms) | HIP events in bench.py, per call (ms) |", "|---|---|---|",
              "| neighbour-community scan (`k_decide_*`, `k_hub_prep/gather/eval/part_eval`) | %.1f | %.1f |" % (
-                 cls["scan"], ph.get("scan_kernels_ms", float("nan"))),
+                 cls["scan"] / calls, ph.get("scan_kernels_ms", float("nan"))),
              "| aggregation rows (`k_agg_*`, `k_gagg_*`, `k_member_degrees`) | %.1f | %.1f |" % (
-                 cls["agg"], ph.get("agg_kernels_ms", float("nan"))),
-             "| all kernels | %.1f | |" % tot, "",
-             "The HIP-event spans bracket every launch of a class and the short gaps between them.", "",
+                 cls["agg"] / calls, ph.get("agg_kernels_ms", float("nan"))),
+             "| all kernels | %.1f | |" % (tot / calls), "",
+             "Per call = the run's total over its %d gvl_leiden calls.  The HIP-event spans bracket every" % calls,
+             "launch of a class and the short gaps between them.  The table below is the whole run.", "",
              "| total ms | calls | avg us | % | kernel |", "|---|---|---|---|---|"]
     for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:25]:
         lines.append("| %.2f | %s | %.1f | %.1f | `%s` |" % (
@@ -86,8 +93,9 @@ def _sum(path, counter):
     return per
 
 
-def counters(fetch_csv, write_csv, calib_bytes, out, command):
+def counters(fetch_csv, write_csv, calib_bytes, calls, out, command):
     calib_bytes = int(calib_bytes)
+    calls = int(calls)
     f = _sum(fetch_csv, "FETCH_SIZE")
     w = _sum(write_csv, "WRITE_SIZE")
     fc = [v for k, v in f.items() if COPY.search(k)]
@@ -96,16 +104,18 @@ def counters(fetch_csv, write_csv, calib_bytes, out, command):
         raise SystemExit("no copy kernel found for the calibration")
     kf = calib_bytes / (max(fc) * 1024.0)   # bytes per counted KiB
     kw = calib_bytes / (max(wc) * 1024.0)
-    res = {"digest": source_digest(), "calib_bytes": calib_bytes, "fetch_scale": kf, "write_scale": kw}
+    res = {"digest": source_digest(), "calib_bytes": calib_bytes, "calls": calls, "fetch_scale": kf,
+           "write_scale": kw}
     for name, rx in (("scan", SCAN), ("agg", AGG)):
-        fb = sum(v for k, v in f.items() if rx.search(k)) * 1024.0 * kf
-        wb = sum(v for k, v in w.items() if rx.search(k)) * 1024.0 * kw
+        fb = sum(v for k, v in f.items() if rx.search(k)) * 1024.0 * kf / calls
+        wb = sum(v for k, v in w.items() if rx.search(k)) * 1024.0 * kw / calls
         res[name + "_fetch_bytes"] = fb
         res[name + "_write_bytes"] = wb
     lines = ["# HBM traffic of the Leiden kernel classes (rocprofv3 counters)", "",
              "Commands (from the repository root on the MI355X box), one counter per run:", "", "```",
              command, "```", "",
-             "FETCH_SIZE and WRITE_SIZE are summed over the dispatches of each class in one step and",
+             "FETCH_SIZE and WRITE_SIZE are summed over the dispatches of each class, divided by the",
+             "%d gvl_leiden calls of the run (bytes per call) and" % calls,
              "scaled by what each counter reads for a device-to-device copy of %d bytes run first" % calib_bytes,
              "(fetch x%.4f, write x%.4f per counted byte)." % (kf, kw), "",
              "| class | fetched (GB) | written (GB) |", "|---|---|---|",
@@ -113,6 +123,40 @@ def counters(fetch_csv, write_csv, calib_bytes, out, command):
                                                              res["scan_write_bytes"] / 1e9),
              "| aggregation rows | %.2f | %.2f |" % (res["agg_fetch_bytes"] / 1e9, res["agg_write_bytes"] / 1e9),
              "", "counters-json: " + json.dumps(res), ""]
+    open(out, "w").write("\n".join(lines))
+
+
+def pmc(calls, out, command, *csvs):
+    """Per-call totals of every counter in the given counter_collection.csv
+    files, by kernel class and for the 12 kernels with the largest
+    SQ_BUSY_CYCLES (or the first counter)."""
+    calls = int(calls)
+    per = collections.defaultdict(lambda: collections.defaultdict(float))
+    names = []
+    for path in csvs:
+        for r in csv.DictReader(open(path)):
+            c = r["Counter_Name"]
+            if c not in names:
+                names.append(c)
+            per[short(r["Kernel_Name"].split("(")[0]).replace("void ", "")][c] += float(r["Counter_Value"]) / calls
+    key = "SQ_BUSY_CYCLES" if "SQ_BUSY_CYCLES" in names else names[0]
+    cls = collections.defaultdict(lambda: collections.defaultdict(float))
+    for k, v in per.items():
+        for name, rx in (("neighbour-community scan", SCAN), ("aggregation rows", AGG)):
+            if rx.search(k):
+                for c, x in v.items():
+                    cls[name][c] += x
+    def row(label, v):
+        return "| %s | " % label + " | ".join("%.3g" % v.get(c, 0.0) for c in names) + " |"
+    lines = ["# Hardware counters per gvl_leiden call (rocprofv3 --pmc)", "",
+             "Commands (from the repository root on the MI355X box), one pass per counter group:", "", "```",
+             command, "```", "", "Totals per call (the run made %d calls)." % calls, "",
+             "| kernel / class | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
+    for name in ("neighbour-community scan", "aggregation rows"):
+        lines.append(row("**%s**" % name, cls[name]))
+    for k in sorted(per, key=lambda k: -per[k].get(key, 0.0))[:12]:
+        lines.append(row("`%s`" % k[:70], per[k]))
+    lines += ["", "Kernel sources digest: %s" % source_digest(), ""]
     open(out, "w").write("\n".join(lines))
 
 
@@ -130,10 +174,12 @@ def recorded_traffic(path):
 
 
 if __name__ == "__main__":
-    if len(sys.argv) >= 6 and sys.argv[1] == "stats":
-        stats(*sys.argv[2:6])
-    elif len(sys.argv) >= 7 and sys.argv[1] == "counters":
-        counters(*sys.argv[2:7])
+    if len(sys.argv) >= 7 and sys.argv[1] == "stats":
+        stats(*sys.argv[2:7])
+    elif len(sys.argv) >= 8 and sys.argv[1] == "counters":
+        counters(*sys.argv[2:8])
+    elif len(sys.argv) >= 6 and sys.argv[1] == "pmc":
+        pmc(*sys.argv[2:])
     else:
         print(__doc__)
         sys.exit(2)
