@@ -432,6 +432,34 @@ def measure_variant(eng, off, idx, wt, m, mode, kw, args):
     return out
 
 
+def gather_ceiling(eng, idx, n, scan_arcs, scan_ms, reps=5):
+    """The device's random-gather rate over this graph's neighbour array
+    (one 4-byte label per arc, the access the scan makes at C'[j]), measured
+    with gvl_gather_probe and HIP events on the library's stream, beside the
+    rate at which the scan kernels of one call read labels: the arcs they
+    scan (each arc of a scanned row is one label read) over their kernel
+    time.  The scan's later passes read a super-vertex graph, not this
+    array, so the ratio is a guide, not an exact bound."""
+    import torch
+    import paper_2312_13936_amd as gvl
+    table = torch.zeros(max(n, 1), dtype=torch.int32, device=idx.device)
+    sink = torch.zeros(1, dtype=torch.int64, device=idx.device)
+    for _ in range(2):
+        gvl.gvl_gather_probe(eng.ctx, idx.data_ptr(), idx.numel(), table.data_ptr(), max(n, 1), sink.data_ptr())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(eng.stream)
+    for _ in range(reps):
+        gvl.gvl_gather_probe(eng.ctx, idx.data_ptr(), idx.numel(), table.data_ptr(), max(n, 1), sink.data_ptr())
+    e1.record(eng.stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    probe = idx.numel() / (ms * 1e-3)
+    scan = scan_arcs / (scan_ms * 1e-3) if scan_ms > 0 else 0.0
+    return {"probe_gathers_per_s": probe, "probe_ms": ms, "scan_label_gathers_per_s": scan,
+            "frac": scan / probe if probe > 0 else 0.0,
+            "probe": "sum of table[idx[e]] over the graph's %d arcs (int32 table of %d entries)" % (idx.numel(), n)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -605,6 +633,10 @@ def main():
                                  "kernel_ms_per_step": ams / len(stats)},
         "cpu_baseline": None,
     }
+    out["gather_ceiling"] = gather_ceiling(eng, idx, g.n, last.scan_arcs, sms / len(stats))
+    log("gather probe: %.1f G gathers/s; scan kernels read labels at %.1f G/s (%.0f %%)" % (
+        out["gather_ceiling"]["probe_gathers_per_s"] / 1e9, out["gather_ceiling"]["scan_label_gathers_per_s"] / 1e9,
+        100 * out["gather_ceiling"]["frac"]))
     if not args.no_variant and args.workload == "rmat-s24":
         out["shrink_variant"] = measure_variant(eng, off, idx, wt, g.m, mode, kw, args)
     if not args.no_louvain:

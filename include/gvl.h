@@ -190,7 +190,7 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_offs
  * allocates no device memory.
  *   Errors: those of gvl_leiden; GVL_E_WORKSPACE if gvl_workspace_bytes(n,
  *   m, opt) exceeds GVL_STATIC_WORKSPACE_BYTES (e.g. fast mode up to about
- *   350k vertices with 12 arcs each); GVL_E_INVALID_ARG if opt->profile is
+ *   330k vertices with 12 arcs each); GVL_E_INVALID_ARG if opt->profile is
  *   set (timing would create HIP events).
  * Every call on one GPU uses the same array: calls that overlap on one GPU
  * (from several streams or host threads) race and must not be made. */
@@ -248,6 +248,17 @@ gvl_status gvl_disconnected_communities(gvl_ctx_t ctx, int64_t n, int64_t m, con
                                         const int32_t* d_indices, const int32_t* d_membership,
                                         void* d_workspace, size_t workspace_bytes, int32_t* d_flags,
                                         int64_t* count);
+
+/* Measurement aid (not part of Leiden): enqueues on ctx's stream a kernel
+ * that sums d_table[d_idx[e]] for e in [0, n_idx) into *d_sink (device,
+ * caller-zeroed unsigned 64-bit), four loads in flight per lane, so that
+ * the caller can time the device's random-gather rate over an index array
+ * (the neighbour-community scan reads one label per arc at the arc's
+ * neighbour id, Alg. 2 and Alg. 3).  An index outside [0, n_table) reads
+ * entry 0.  Returns without waiting.  Errors: GVL_E_INVALID_ARG (null
+ * pointer, n_idx < 0, n_table < 1), GVL_E_HIP. */
+gvl_status gvl_gather_probe(gvl_ctx_t ctx, const int32_t* d_idx, int64_t n_idx, const int32_t* d_table,
+                            int64_t n_table, unsigned long long* d_sink);
 
 /* Debug export of the last gvl_leiden run made with debug_trace = 1.
  * For pass p: n_out = |V'|, m_out = arcs of the super-vertex graph built in

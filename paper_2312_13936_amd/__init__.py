@@ -99,7 +99,7 @@ class gvl_tuning(ctypes.Structure):
 
 EXPORTS = ["gvl_create", "gvl_destroy", "gvl_default_options", "gvl_workspace_bytes", "gvl_leiden",
            "gvl_leiden_static", "gvl_graph_class", "gvl_get_tuning", "gvl_set_tuning", "gvl_load_tuning",
-           "gvl_modularity", "gvl_disconnected_communities", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
+           "gvl_modularity", "gvl_disconnected_communities", "gvl_gather_probe", "gvl_debug_pass_info", "gvl_debug_export_pass", "gvl_debug_pass_movers",
            "gvl_batch_workspace_bytes", "gvl_leiden_batch", "gvl_fused_workspace_bytes", "gvl_leiden_fused",
            "gvl_server_create", "gvl_server_submit",
            "gvl_server_poll", "gvl_server_wait", "gvl_server_cancel", "gvl_server_release",
@@ -131,6 +131,7 @@ def load_library(path: str = LIB_PATH):
     lib.gvl_set_tuning.argtypes = [i32, ctypes.POINTER(gvl_tuning)]
     lib.gvl_load_tuning.argtypes = [ctypes.c_char_p]
     lib.gvl_modularity.argtypes = [vp, i64, i64, vp, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(dbl)]
+    lib.gvl_gather_probe.argtypes = [vp, i64, i64, vp, i64, vp]
     lib.gvl_disconnected_communities.argtypes = [vp, i64, i64, vp, vp, vp, vp, sz, vp, ctypes.POINTER(i64)]
     lib.gvl_debug_pass_info.argtypes = [vp, i32, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.gvl_debug_export_pass.argtypes = [vp, i32, vp, vp, vp, vp, vp]
@@ -241,6 +242,12 @@ def gvl_modularity(ctx, n, m, d_offsets, d_indices, d_weights, d_membership, res
                                          d_workspace, workspace_bytes, ctypes.byref(q))
     _check(code, "gvl_modularity")
     return q.value
+
+
+def gvl_gather_probe(ctx, d_idx, n_idx, d_table, n_table, d_sink) -> None:
+    """Enqueues the random-gather probe (sum of d_table[d_idx[e]] into the
+    device uint64 *d_sink) on the context's stream."""
+    _check(load_library().gvl_gather_probe(ctx, d_idx, n_idx, d_table, n_table, d_sink), "gvl_gather_probe")
 
 
 def gvl_disconnected_communities(ctx, n, m, d_offsets, d_indices, d_membership, d_workspace, workspace_bytes,

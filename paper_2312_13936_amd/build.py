@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgvl.so")
 SOURCES = ["k_prims.hip", "k_scan_move.hip", "k_scan_refine.hip", "k_aggregate.hip", "k_hub.hip", "k_batch.hip",
-           "k_check.hip", "driver.hip", "batch.hip", "serve.hip", "static_ws.hip", "tuning.hip"]
+           "k_check.hip", "driver.hip", "batch.hip", "serve.hip", "static_ws.hip", "tuning.hip", "probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

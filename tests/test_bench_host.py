@@ -52,14 +52,14 @@ def test_counters_scale_by_the_copy_and_sum_per_class(tmp_path):
     _counter_csv(fp, "FETCH_SIZE", fetch)
     _counter_csv(wp, "WRITE_SIZE", write)
     out = tmp_path / "c.md"
-    ps.counters(str(fp), str(wp), str(calib), str(out), "cmd")
+    ps.counters(str(fp), str(wp), str(calib), "2", str(out), "cmd")  # the run made two calls
     rec = ps.recorded_traffic(str(out))
-    assert rec is not None and rec["digest"] == ps.source_digest()
+    assert rec is not None and rec["digest"] == ps.source_digest() and rec["calls"] == 2
     assert rec["fetch_scale"] == pytest.approx(2.0) and rec["write_scale"] == pytest.approx(1.0)
-    assert rec["scan_fetch_bytes"] == pytest.approx(1500.0 * 1024 * 2)
-    assert rec["agg_fetch_bytes"] == pytest.approx(400.0 * 1024 * 2)
-    assert rec["scan_write_bytes"] == pytest.approx(10.0 * 1024)
-    assert rec["agg_write_bytes"] == pytest.approx(20.0 * 1024)
+    assert rec["scan_fetch_bytes"] == pytest.approx(1500.0 * 1024 * 2 / 2)
+    assert rec["agg_fetch_bytes"] == pytest.approx(400.0 * 1024 * 2 / 2)
+    assert rec["scan_write_bytes"] == pytest.approx(10.0 * 1024 / 2)
+    assert rec["agg_write_bytes"] == pytest.approx(20.0 * 1024 / 2)
 
 
 def test_recorded_traffic_is_dropped_when_sources_change(tmp_path):

@@ -201,3 +201,24 @@ def test_option_values_checked(eng):
     for kw in ({"louvain": 2}, {"refine_random": -1}):
         with pytest.raises(gvl.GvlError):
             run(eng, g, gvl.GVL_MODE_FAST, **kw)
+
+
+# ------------------------------------------------------------ gather probe ---
+
+def test_gather_probe_sums_the_gathered_entries(eng):
+    # the measurement aid bench.py times: sum of table[idx[e]]
+    g = graph("rmat-s12")
+    idx = torch.from_numpy(g.indices.astype(np.int32)).cuda()
+    table = torch.randint(0, 1000, (g.n,), dtype=torch.int32, device="cuda",
+                          generator=torch.Generator(device="cuda").manual_seed(5))
+    sink = torch.zeros(1, dtype=torch.int64, device="cuda")
+    gvl.gvl_gather_probe(eng.ctx, idx.data_ptr(), idx.numel(), table.data_ptr(), g.n, sink.data_ptr())
+    torch.cuda.synchronize()
+    assert int(sink.item()) == int(table.long()[idx.long()].sum().item())
+    bad = torch.tensor([g.n, -1, 5], dtype=torch.int32, device="cuda")  # outside the table: entry 0
+    sink.zero_()
+    gvl.gvl_gather_probe(eng.ctx, bad.data_ptr(), 3, table.data_ptr(), g.n, sink.data_ptr())
+    torch.cuda.synchronize()
+    assert int(sink.item()) == 2 * int(table[0].item()) + int(table[5].item())
+    with pytest.raises(gvl.GvlError):
+        gvl.gvl_gather_probe(eng.ctx, idx.data_ptr(), -1, table.data_ptr(), g.n, sink.data_ptr())
