@@ -59,13 +59,19 @@ typedef struct {
   int32_t mode;                  /* GVL_MODE_FAST: FP64 gains, FP32 super-vertex weights (Sec. 5.1.2),
                                     local-moving schedule chosen by sync_moves;
                                     GVL_MODE_DET: synchronous moves, exact integer gains,
-                                    lowest-id ties -- bit-reproducible */
+                                    lowest-id ties -- bit-reproducible.  Synchronous local-moving
+                                    (both modes) also applies two rules against move cycles: of two
+                                    adjacent vertices of a group that chose each other's community,
+                                    a row of at most 128 arcs yields to the lower id or the longer
+                                    row (swap rule), and a vertex that moved in each of the two
+                                    previous iterations does not go straight back to the community
+                                    it left in the last one (bounce rule) */
   double tolerance;              /* initial per-iteration tolerance tau (Alg. 2 convergence) */
   double tolerance_drop;         /* threshold scaling: tau /= tolerance_drop after each pass */
   double aggregation_tolerance;  /* Alg. 1 low-shrink test: stop when |Gamma| / |V'| exceeds this,
                                     with |Gamma| the distinct refined labels of the pass and |V'|
                                     the vertices of its graph */
-  int32_t max_iterations;        /* cap on local-moving iterations per pass */
+  int32_t max_iterations;        /* cap on local-moving iterations per pass (1 .. 32767) */
   int32_t max_passes;            /* cap on passes */
   int32_t refine_sweeps;         /* cap on synchronous refinement sweeps per pass; sweeps stop
                                     early once one moves no vertex (1 = the single sweep of Alg. 3) */
