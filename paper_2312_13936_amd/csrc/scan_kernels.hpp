@@ -213,10 +213,12 @@ __device__ __forceinline__ bool mark_needed(const ScanArgs& a, int32_t j) {
 // Bounce rule of the synchronous local-moving: a vertex that moved in each
 // of the two previous iterations does not go straight back to the community
 // it left in the last one (it is cycling with a neighbour of its group).
-__device__ __forceinline__ bool bounces(const ScanArgs& a, int32_t i, int32_t bc) {
-  const int32_t it = *a.it_dev;
-  const int2 l = a.last[i];
+// (l: the vertex's last-move entry, it: the current iteration)
+__device__ __forceinline__ bool bounced(int2 l, int32_t bc, int32_t it) {
   return l.x == bc && (int16_t)(l.y & 0xFFFF) == it - 1 && (int16_t)((uint32_t)l.y >> 16) == it - 2;
+}
+__device__ __forceinline__ bool bounces(const ScanArgs& a, int32_t i, int32_t bc) {
+  return bounced(a.last[i], bc, *a.it_dev);
 }
 
 // After the argmax: apply the min-label rule, the sign test and, for a
@@ -233,6 +235,47 @@ __device__ __forceinline__ bool accept(const ScanArgs& a, int32_t i, int32_t d, 
     if (a.size[bc] == 1 && bc > d) return false;
   }
   return true;
+}
+
+// The state of vertex i (own community d) that the tests after the argmax
+// read, loaded before the scan so that the only load left between the
+// argmax and the decision is size[c*] for a singleton (see accept_pre).
+// sync: synchronous local-moving (the bounce rule applies); it: the
+// iteration (read once per launch).
+struct Pre {
+  int32_t size_d = 0;
+  int2 last = make_int2(kEmpty, 0);
+  int32_t it = 0;
+};
+template <int PH>
+__device__ __forceinline__ Pre prefetch_state(const ScanArgs& a, int32_t i, int32_t d, bool sync, int32_t it) {
+  Pre p;
+  if (PH == kMove) {
+    p.size_d = a.size[d];
+    if (sync) p.last = a.last[i];
+    p.it = it;
+  }
+  return p;
+}
+// accept() on prefetched state: the same tests in an order that reads
+// size[bc] only where it decides.
+template <int PH, bool DET>
+__device__ __forceinline__ bool accept_pre(const ScanArgs& a, const Pre& p, int32_t d, int32_t bc, double bg,
+                                           i128 bk, bool sync) {
+  if (bc < 0) return false;
+  if (DET ? !(bk > 0) : !(bg > 0.0)) return false;
+  if (PH == kMove) {
+    if (p.size_d == 1 && bc > d && a.size[bc] == 1) return false;
+    if (sync && bounced(p.last, bc, p.it)) return false;
+  } else {
+    if (bc > d && a.size[bc] == 1) return false;
+  }
+  return true;
+}
+// The iteration number for the bounce rule, once per launch (sync only).
+template <int PH>
+__device__ __forceinline__ int32_t launch_iteration(const ScanArgs& a, bool sync) {
+  return (PH == kMove && sync) ? *a.it_dev : 0;
 }
 
 // Accumulates the arcs e0, e0 + NT, ... of row i: arcs to the vertex's own
@@ -348,17 +391,23 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
   for (int s = gl; s < TS; s += G) { keys[s] = kEmpty; vals[s] = 0.0; }
   wave_sync();
   Acc acc;
+  const bool sync = DET || (a.sync_moves & 1);
+  const int32_t it = launch_iteration<PH>(a, sync);
   for (int64_t v = (int64_t)bid * GPB + gb; v < count; v += (int64_t)nb * GPB) {
     const int32_t i = list[v];
+    // the loads that need only i go out together with the eligibility test
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
     // One lane reads the (possibly concurrently updated) eligibility state.
     int ok = (gl == 0) ? (int)Decide<PH, DET>::eligible(a, i) : 0;
     ok = __shfl(ok, 0, G);
     if (!ok) continue;
     if (PH == kMove && gl == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
-    const int32_t beg = g.begin(i), deg = g.degree(i);
-    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
+    // and those that need d, before the scan's
+    const double sd = a.Sig[d];
+    const Pre pre = prefetch_state<PH>(a, i, d, sync, it);
     // table of next_pow2(2 deg) <= TS slots: at most deg distinct keys
     const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
@@ -373,7 +422,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
         [&](int u, int32_t, int32_t c) { rc[u] = c; });
     kid = sum_xor<G>(kid);
     wave_sync();
-    const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, kid, ki, sd);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
@@ -381,7 +430,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     if (DET) argmax_k<G>(bk, bc); else argmax_f<G>(bg, bc);
     wave_sync();
     if (gl == 0) { ++acc.nv; acc.na += (unsigned long long)deg; }
-    int take = (gl == 0) ? (int)accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 1)) : 0;
+    int take = (gl == 0) ? (int)accept_pre<PH, DET>(a, pre, d, bc, bg, bk, sync) : 0;
     take = __shfl(take, 0, G);
     if (!take) continue;
     if (PH == kMove && !DET && !(a.sync_moves & 1)) {
@@ -467,27 +516,34 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
   for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
   __syncthreads();
   Acc acc;
+  const bool sync = DET || (a.sync_moves & 2);
+  const int32_t it = launch_iteration<PH>(a, sync);
   for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
     const int32_t i = list[v];
+    // the loads that need only i go out together with the eligibility test
+    const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
     if (threadIdx.x == 0) s_flag = (int)Decide<PH, DET>::eligible(a, i);
     __syncthreads();
     const int ok = s_flag;
     __syncthreads();
     if (!ok) continue;  // uniform over the workgroup
     if (PH == kMove && threadIdx.x == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
-    const int32_t beg = g.begin(i), deg = g.degree(i);
-    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
     const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
+    // and those that need d, before the scan's
+    const double sd = a.Sig[d];
+    Pre pre;
+    if (threadIdx.x == 0) pre = prefetch_state<PH>(a, i, d, sync, it);
     double kid = scan_row<4, kBlock, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
       lds_insert(keys, vals, lg, c, w);
     });
     kid = block_sum<double>(kid, s_g);
     if (threadIdx.x == 0) s_kid = kid;
     __syncthreads();
-    const Eval<DET> ev(a, i, s_kid, ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, s_kid, ki, sd);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
@@ -497,7 +553,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     if (threadIdx.x == 0) {
       ++acc.nv;
       acc.na += (unsigned long long)deg;
-      s_take = (int)accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 2));
+      s_take = (int)accept_pre<PH, DET>(a, pre, d, bc, bg, bk, sync);
     }
     __syncthreads();  // table and s_* reads done; s_take published
     const int take = s_take;
@@ -576,6 +632,8 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
   // what it reads, and nothing is inserted for a skipped vertex)
   for (int s = threadIdx.x; s < TS; s += kWideThreads) { keys[s] = kEmpty; vals[s] = 0.0; }
   Acc acc;
+  const bool sync = DET || (a.sync_moves & 2);
+  const int32_t it = launch_iteration<PH>(a, sync);
   // persistent workgroups take tasks from a counter, so a vertex that is
   // skipped (not flagged, not isolated) costs a few loads, not a dispatch
   for (;;) {
@@ -599,7 +657,10 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
     const int part = b & (P - 1);
     r += vloc;
     const int32_t i = list[wl.start[k] + vloc];
+    // the loads that need only i go out together with the eligibility test
     const int32_t beg = g.begin(i), deg = g.degree(i);
+    const int32_t d = a.C[i];
+    const double ki = a.K[i];
     // P == 1: 2 deg slots (whole multiples of the workgroup), at most TS
     int ts = TS;
     if (P == 1) {
@@ -619,9 +680,11 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
+    Pre pre;
     if (ok) {  // uniform
+      // the loads that need d, before the scan's
+      const double sd = a.Sig[d];
+      if (threadIdx.x == 0) pre = prefetch_state<PH>(a, i, d, sync, it);
       const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
       double kid = scan_row<4, kWideThreads, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
         if ((int)(wide_part(c) & (uint32_t)(P - 1)) != part) return;
@@ -631,7 +694,7 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       if (threadIdx.x == 0) s_d[0] = kid;
       __syncthreads();
       kid = s_d[0];
-      const Eval<DET> ev(a, i, kid, ki, a.Sig[d]);
+      const Eval<DET> ev(a, i, kid, ki, sd);
       eval_table<TS / kWideThreads / 2, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
       block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
     }
@@ -683,7 +746,8 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
         ++acc.nv;
         acc.na += (unsigned long long)deg;
         if (ovf_any) atomicAdd(a.ovf, 1ull);
-        take = (!ovf_any && accept<PH, DET>(a, i, d, bc, bg, bk, DET || (a.sync_moves & 2))) ? 1 : 0;
+        // (with ok0 set, the last partition scanned and loaded pre too)
+        take = (!ovf_any && accept_pre<PH, DET>(a, pre, d, bc, bg, bk, sync)) ? 1 : 0;
       }
       if (take) {
         if (PH == kMove && !DET && !(a.sync_moves & 2)) {
