@@ -261,8 +261,10 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     HubPlan plan;
     s = build_hub_plan(ctx, ws, bins, false, cur, nullptr, 0, plan);
     if (s != GVL_OK) return s;
+    // K' of the input here; of a super-vertex graph, written by the
+    // aggregation that built it (its community totals)
     fill_f64(st, &ws.sc->accW, 0.0, 1);
-    graph_weights(ctx, ws, cur, pass == 0 ? m : 0, bins, plan, pass == 0 ? opt->validate : 0);
+    if (pass == 0) graph_weights(ctx, ws, cur, m, bins, plan, opt->validate);
     s = readback(ctx, ws.sc);
     if (s != GVL_OK) return s;
     if (pass == 0) {
@@ -530,6 +532,9 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
       fill_i32(st, ws.cnt, 0, ncom + 1);
       fill_i32(st, yoff, 0, ncom + 1);
       agg_count(st, cur, ws.C, ws.newid, ws.lab, ws.rank, ws.cnt, yoff);
+      // K' of the next pass: each super-vertex row sums its members' rows
+      // (no later step of this pass reads K')
+      next_weights(st, ws.Sig, ws.newid, nn, ws.K);
       exclusive_scan(st, ws.cnt, ncom, ws.scan_tmp);
       exclusive_scan(st, yoff, ncom, ws.scan_tmp);
       agg_fill(st, ws.lab, ws.rank, ws.cnt, nn, ws.cv);

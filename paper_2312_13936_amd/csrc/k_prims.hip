@@ -546,6 +546,15 @@ void agg_fill(hipStream_t st, const int32_t* lab, const int32_t* rank, const int
   if (n > 0) hipLaunchKernelGGL(k_agg_fill, dim3(grid_n(n)), dim3(kBlock), 0, st, lab, rank, coff, n, cv);
 }
 
+// K' of the next pass: super-vertex newid[c] is community c, and its row
+// (self-loop included) sums the rows of c's members, i.e. Sigma'_c.
+__global__ void k_next_weights(const double* Sig, const int32_t* newid, int64_t n, double* K) {
+  GRID_STRIDE(c, n) if (newid[c + 1] != newid[c]) K[newid[c]] = Sig[c];
+}
+void next_weights(hipStream_t st, const double* Sig, const int32_t* newid, int64_t n, double* K) {
+  if (n > 0) hipLaunchKernelGGL(k_next_weights, dim3(grid_n(n)), dim3(kBlock), 0, st, Sig, newid, n, K);
+}
+
 __global__ void k_next_labels(const int32_t* lab, const int32_t* CB, const int32_t* brank, int64_t n,
                               int32_t* start) {
   GRID_STRIDE(i, n) if (lab[i] >= 0) start[lab[i]] = brank[CB[i]];

@@ -441,6 +441,9 @@ void agg_count(hipStream_t st, const GraphDesc& g, const int32_t* C, const int32
 void agg_fill(hipStream_t st, const int32_t* lab, const int32_t* rank, const int32_t* coff, int64_t n,
               int32_t* cv);
 // start[lab[i]] = brank[CB[i]] (move-based labels of super-vertices).
+// K'[newid[c]] = Sigma'[c] for every used label c of [0, n) (newid: the
+// exclusive scan of the used flags, n + 1 entries); K' may not alias Sig.
+void next_weights(hipStream_t st, const double* Sig, const int32_t* newid, int64_t n, double* K);
 void next_labels(hipStream_t st, const int32_t* lab, const int32_t* CB, const int32_t* brank,
                  int64_t n, int32_t* start);
 // Canonical relabelling by first occurrence over v = 0..N-1.
