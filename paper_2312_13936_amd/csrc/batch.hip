@@ -341,7 +341,9 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     HubPlan plan;
     s = build_hub_plan(ctx, ws, bins, false, cur, nullptr, 0, plan);
     if (s != GVL_OK) return s;
-    graph_weights(ctx, ws, cur, pass == 0 ? M0 : 0, bins, plan, 0);
+    // K' of the inputs here; of a super-vertex graph, written by the
+    // aggregation that built it (its community totals)
+    if (pass == 0) graph_weights(ctx, ws, cur, M0, bins, plan, 0);
     fill_i32(st, B.nz, 0, K);
     graph_nonzero(st, cur, gid, B.nz);
     if (pass > 0) {
@@ -568,6 +570,8 @@ gvl_status fused_chunk(gvl_ctx* ctx, int32_t G, const gvl_graph_desc* gs, const 
     fill_i32(st, ws.cnt, 0, ncom_all + 1);
     fill_i32(st, yoff, 0, ncom_all + 1);
     agg_count(st, cur, ws.C, ws.newid, ws.lab, ws.rank, ws.cnt, yoff, gid, B.keep);
+    // K' of the next pass: each super-vertex row sums its members' rows
+    next_weights(st, ws.Sig, ws.newid, nn, ws.K);
     exclusive_scan(st, ws.cnt, ncom_all, ws.scan_tmp);
     exclusive_scan(st, yoff, ncom_all, ws.scan_tmp);
     agg_fill(st, ws.lab, ws.rank, ws.cnt, nn, ws.cv);
