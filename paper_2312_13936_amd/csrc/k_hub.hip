@@ -407,13 +407,8 @@ __global__ __launch_bounds__(kBlock) void k_hub_eval(GraphView<WT> g, ScanArgs a
         }
       }
       __syncthreads();
-      if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) {
-        const int32_t beg = g.begin(i), deg = g.degree(i);
-        for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
-          const int32_t j = g.idx[beg + e];
-          if (j != i) a.flag[j] = 1;
-        }
-      }
+      if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take)
+        mark_row(g, a, i, g.begin(i), g.degree(i), threadIdx.x, kBlock, false);
     }
     __syncthreads();
   }
@@ -584,12 +579,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
       }
     }
     __syncthreads();
-    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) {
-      for (int32_t e = threadIdx.x; e < deg; e += NT) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i) a.flag[j] = 1;
-      }
-    }
+    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) mark_row(g, a, i, beg, deg, threadIdx.x, NT, false);
   }
   flush_acc<PH, DET>(a, acc);  // (the arcs were counted by the chunk pass)
 }

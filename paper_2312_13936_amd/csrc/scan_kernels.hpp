@@ -210,6 +210,39 @@ __device__ __forceinline__ bool mark_needed(const ScanArgs& a, int32_t j) {
   return a.mark_after == INT32_MAX || group_of(j, a.groups) <= a.mark_after;
 }
 
+// Marks the neighbours j != i of a moved vertex i as unprocessed (Alg. 2):
+// the arcs e0, e0 + nt, ... < deg of its row, kMarkUnroll per thread per
+// step with their index loads issued together (the marks do not depend on
+// each other, so a row costs deg / (nt kMarkUnroll) load latencies rather
+// than deg / nt).  check (synchronous commits): only where mark_needed,
+// and a flag is read before it is written: a vertex with many moving
+// neighbours is marked by each of them, and the read of a set flag stays
+// in the cache where each store would travel to memory.  (No flag is
+// cleared while a commit runs, so a skipped store is never needed; the
+// asynchronous schedule clears flags concurrently and always stores.)
+constexpr int kMarkUnroll = 8;
+template <class WT>
+__device__ __forceinline__ void mark_row(const GraphView<WT>& g, const ScanArgs& a, int32_t i, int32_t beg,
+                                         int32_t deg, int32_t e0, int32_t nt, bool check) {
+  for (int32_t base = e0; base < deg; base += kMarkUnroll * nt) {
+    int32_t j[kMarkUnroll];
+    uint8_t f[kMarkUnroll];
+#pragma unroll
+    for (int u = 0; u < kMarkUnroll; ++u) {
+      const int32_t e = base + u * nt;
+      j[u] = (e < deg) ? g.idx[beg + e] : i;
+    }
+#pragma unroll
+    for (int u = 0; u < kMarkUnroll; ++u) {
+      const bool want = j[u] != i && (!check || mark_needed(a, j[u]));
+      f[u] = !want ? 1 : (check ? a.flag[j[u]] : 0);
+    }
+#pragma unroll
+    for (int u = 0; u < kMarkUnroll; ++u)
+      if (f[u] == 0) a.flag[j[u]] = 1;
+  }
+}
+
 // Bounce rule of the synchronous local-moving: a vertex that moved in each
 // of the two previous iterations does not go straight back to the community
 // it left in the last one (it is cycling with a neighbour of its group).
@@ -443,10 +476,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
         add_gain<DET>(a, acc, i, bg, bk);
         ++acc.nm;
       }
-      for (int32_t e = gl; e < deg; e += G) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i) a.flag[j] = 1;
-      }
+      mark_row(g, a, i, beg, deg, gl, G, false);
     } else if (PH == kMove) {
       // swap-rule candidate if the target holds a neighbour of the group:
       // its move record names that neighbour (-2: several)
@@ -568,10 +598,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
         add_gain<DET>(a, acc, i, bg, bk);
         ++acc.nm;
       }
-      for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i) a.flag[j] = 1;
-      }
+      mark_row(g, a, i, beg, deg, threadIdx.x, kBlock, false);
     } else if (PH == kMove) {
       if (threadIdx.x == 0) {
         add_gain<DET>(a, acc, i, bg, bk);
@@ -770,12 +797,8 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       s_take = take;
     }
     __syncthreads();
-    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take) {
-      for (int32_t e = threadIdx.x; e < deg; e += kWideThreads) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i) a.flag[j] = 1;
-      }
-    }
+    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take)
+      mark_row(g, a, i, beg, deg, threadIdx.x, kWideThreads, false);
   }
   // the last workgroup out resets the task counter for the next launch
   if (threadIdx.x == 0) {
@@ -917,14 +940,29 @@ __device__ __forceinline__ unsigned long long commit_tiles(const GraphView<WT>& 
       L.beg[threadIdx.x] = mv ? g.begin(i) : 0;
       L.vi[threadIdx.x] = i;
       __syncthreads();
-      for (int32_t q = threadIdx.x; q < total; q += kBlock) {
-        int lo = 0, hi = kBlock;  // off[lo] <= q < off[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (L.off[mid] <= q) lo = mid; else hi = mid;
+      for (int32_t q0 = threadIdx.x; q0 < total; q0 += kMarkUnroll * kBlock) {  // (as mark_row)
+        int32_t j[kMarkUnroll], v[kMarkUnroll];
+#pragma unroll
+        for (int u = 0; u < kMarkUnroll; ++u) {
+          const int32_t q = q0 + u * kBlock;
+          j[u] = 0;
+          v[u] = 0;  // (j == v: no mark)
+          if (q < total) {
+            int lo = 0, hi = kBlock;  // off[lo] <= q < off[hi]
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (L.off[mid] <= q) lo = mid; else hi = mid;
+            }
+            j[u] = g.idx[(int64_t)L.beg[lo] + (q - L.off[lo])];
+            v[u] = L.vi[lo];
+          }
         }
-        const int32_t j = g.idx[(int64_t)L.beg[lo] + (q - L.off[lo])];
-        if (j != L.vi[lo] && mark_needed(a, j)) a.flag[j] = 1;
+        uint8_t f[kMarkUnroll];
+#pragma unroll
+        for (int u = 0; u < kMarkUnroll; ++u) f[u] = (j[u] != v[u] && mark_needed(a, j[u])) ? a.flag[j[u]] : 1;
+#pragma unroll
+        for (int u = 0; u < kMarkUnroll; ++u)
+          if (f[u] == 0) a.flag[j[u]] = 1;
       }
       __syncthreads();  // L.* are rewritten by the next entries
     }
@@ -965,13 +1003,7 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
       }
     }
     __syncthreads();
-    if (L.mv) {
-      const int32_t beg = g.begin(i), deg = g.degree(i);
-      for (int32_t e = threadIdx.x; e < deg; e += kBlock) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i && mark_needed(a, j)) a.flag[j] = 1;
-      }
-    }
+    if (L.mv) mark_row(g, a, i, g.begin(i), g.degree(i), threadIdx.x, kBlock, true);
     __syncthreads();
   }
   return nm;
@@ -1005,10 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
       const int32_t beg = g.begin(i), deg = g.degree(i);
       const int32_t e0 = task.y * kHubChunk;
       const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
-      for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-        const int32_t j = g.idx[beg + e];
-        if (j != i && mark_needed(a, j)) a.flag[j] = 1;
-      }
+      mark_row(g, a, i, beg + e0, e1 - e0, threadIdx.x, kBlock, true);
     }
   }
   nm = block_sum<unsigned long long>(nm, red_u);
