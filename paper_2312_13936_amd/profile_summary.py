@@ -154,8 +154,26 @@ def pmc(calls, out, command, *csvs):
              "| kernel / class | " + " | ".join(names) + " |", "|---" * (len(names) + 1) + "|"]
     for name in ("neighbour-community scan", "aggregation rows"):
         lines.append(row("**%s**" % name, cls[name]))
-    for k in sorted(per, key=lambda k: -per[k].get(key, 0.0))[:12]:
+    top = sorted(per, key=lambda k: -per[k].get(key, 0.0))[:12]
+    for k in top:
         lines.append(row("`%s`" % k[:70], per[k]))
+    # ratios of counter pairs that were both collected
+    ratios = [("L2 hit rate", "TCC_HIT_sum", ("TCC_HIT_sum", "TCC_MISS_sum")),
+              ("wave-cycles waiting", "SQ_WAIT_ANY", ("SQ_WAVE_CYCLES",)),
+              ("wave-cycles waiting to issue", "SQ_WAIT_INST_ANY", ("SQ_WAVE_CYCLES",)),
+              ("mean EA read latency (cycles)", "TCC_EA0_RDREQ_LEVEL_sum", ("TCC_EA0_RDREQ_sum",)),
+              ("mean EA write latency (cycles)", "TCC_EA0_WRREQ_LEVEL_sum", ("TCC_EA0_WRREQ_sum",)),
+              ("mean EA atomic latency (cycles)", "TCC_EA0_ATOMIC_LEVEL_sum", ("TCC_EA0_ATOMIC_sum",))]
+    ratios = [r for r in ratios if r[1] in names and all(c in names for c in r[2])]
+    if ratios:
+        def ratio(v, num, den):
+            d = sum(v.get(c, 0.0) for c in den)
+            return "%.3g" % (v.get(num, 0.0) / d) if d > 0 else "-"
+        lines += ["", "Derived (ratios of the totals above):", "",
+                  "| kernel / class | " + " | ".join(r[0] for r in ratios) + " |", "|---" * (len(ratios) + 1) + "|"]
+        for label, v in [("**%s**" % n, cls[n]) for n in ("neighbour-community scan", "aggregation rows")] + \
+                        [("`%s`" % k[:70], per[k]) for k in top]:
+            lines.append("| %s | " % label + " | ".join(ratio(v, r[1], r[2]) for r in ratios) + " |")
     lines += ["", "Kernel sources digest: %s" % source_digest(), ""]
     open(out, "w").write("\n".join(lines))
 
