@@ -324,36 +324,47 @@ __device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArg
   double kid = 0.0;
   for (int32_t base = e0; base < deg; base += U * NT) {
     int32_t j[U];
-    double w[U];
+    WT wr[U];  // raw weights: converted where used, so the round's loads are all in flight first
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int32_t e = base + u * NT;
-      j[u] = (e < deg) ? g.idx[beg + e] : i;
-      w[u] = (e < deg) ? g.weight(beg + e) : 0.0;
+      j[u] = i;
+      wr[u] = WT(1);
+      if (e < deg) {
+        j[u] = g.idx[beg + e];
+        if (g.w) wr[u] = g.w[beg + e];
+      }
+    }
+    // The label loads of the round go out first and land in registers
+    // nothing else writes (a value merged into a load's register from
+    // another branch would make the compiler wait for that load there).
+    int2 cb[U];  // (label, bound label) of each neighbour
+    bool own[U];  // label known without a load (its id)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool ok = j[u] != i;
+      own[u] = PH == kMove && a.ident_after >= 0 && ok && group_of(j[u], a.groups) > a.ident_after;
+      cb[u] = make_int2(kEmpty, bi);
+      if (PH == kRefine && a.CP) {
+        if (ok) cb[u] = a.CP[j[u]];
+      } else if (ok && !own[u]) {
+        cb[u].x = a.C[j[u]];
+        if (PH == kRefine) cb[u].y = a.CB[j[u]];
+      }
     }
     int32_t c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const bool ok = j[u] != i;
-      if (PH == kRefine && a.CP) {
-        const int2 cb = ok ? a.CP[j[u]] : make_int2(kEmpty, bi);
-        c[u] = (cb.y == bi) ? cb.x : kEmpty;
-      } else if (PH == kMove && a.ident_after >= 0 && ok && group_of(j[u], a.groups) > a.ident_after) {
-        c[u] = j[u];
-      } else {
-        c[u] = ok ? a.C[j[u]] : kEmpty;
-        if (PH == kRefine) {
-          const int32_t b = ok ? a.CB[j[u]] : bi;
-          if (b != bi) c[u] = kEmpty;
-        }
-      }
+      c[u] = own[u] ? j[u] : cb[u].x;
+      if (PH == kRefine && cb[u].y != bi) c[u] = kEmpty;
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       note(u, j[u], c[u]);
       if (c[u] == kEmpty) continue;
-      if (c[u] == d) kid += w[u];
-      else ins(c[u], w[u]);
+      const double w = (double)wr[u];
+      if (c[u] == d) kid += w;
+      else ins(c[u], w);
     }
   }
   return kid;
