@@ -30,7 +30,16 @@ struct GraphView {
   __device__ __forceinline__ int32_t degree(int64_t i) const {
     return deg ? deg[i] : off[i + 1] - off[i];
   }
-  __device__ __forceinline__ double weight(int64_t e) const { return w ? (double)w[e] : 1.0; }
+  // Weight of arc e (1 for an unweighted graph) in the graph's own type.
+  // Loops that issue several loads keep it in that type and widen it to
+  // FP64 where it is used: a conversion next to its load, inside the
+  // branch on w, makes the compiler wait for that load before the next
+  // load of the round goes out.
+  __device__ __forceinline__ WT weight(int64_t e) const {
+    WT x = WT(1);
+    if (w) x = w[e];
+    return x;
+  }
 };
 
 // ------------------------------------------------------------ wave helpers ---

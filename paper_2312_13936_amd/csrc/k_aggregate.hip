@@ -16,6 +16,10 @@
 
 namespace gvl {
 
+// Arcs per lane per round in the row loops: their index, weight and label
+// loads are all in flight before the LDS inserts of the round.
+constexpr int kAggUnroll = 4;
+
 template <class WTin, class WTout, int G, int LG>
 __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs a,
                                                       const int32_t* __restrict__ list,
@@ -46,10 +50,27 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
       ++nv;
       if (deg >= G) continue;
       na += (unsigned long long)deg;
-      for (int32_t e = 0; e < deg; ++e) {
-        const int32_t d = a.lab[g.idx[beg + e]];
-        if (d == c) self += g.weight(beg + e);
-        else lds_insert(keys, vals, LG, d, g.weight(beg + e));
+      for (int32_t e0 = 0; e0 < deg; e0 += kAggUnroll) {
+        int32_t j[kAggUnroll];
+        WTin wr[kAggUnroll];
+#pragma unroll
+        for (int u = 0; u < kAggUnroll; ++u) {
+          j[u] = 0;  // (past the row: an unused, valid label load)
+          wr[u] = WTin(0);
+          if (e0 + u < deg) {
+            j[u] = g.idx[beg + e0 + u];
+            wr[u] = g.weight(beg + e0 + u);
+          }
+        }
+        int32_t d[kAggUnroll];
+#pragma unroll
+        for (int u = 0; u < kAggUnroll; ++u) d[u] = a.lab[j[u]];
+#pragma unroll
+        for (int u = 0; u < kAggUnroll; ++u) {
+          if (e0 + u >= deg) continue;
+          if (d[u] == c) self += (double)wr[u];
+          else lds_insert(keys, vals, LG, d[u], (double)wr[u]);
+        }
       }
     }
     // members with long rows: the whole group
@@ -64,10 +85,27 @@ __global__ __launch_bounds__(kBlock) void k_agg_group(GraphView<WTin> g, AggArgs
         const int32_t ii = __shfl(i, q, G);
         const int32_t beg = g.begin(ii), deg = g.degree(ii);
         if (gl == 0) na += (unsigned long long)deg;
-        for (int32_t e = gl; e < deg; e += G) {
-          const int32_t d = a.lab[g.idx[beg + e]];
-          if (d == c) self += g.weight(beg + e);
-          else lds_insert(keys, vals, LG, d, g.weight(beg + e));
+        for (int32_t e0 = gl; e0 < deg; e0 += kAggUnroll * G) {
+          int32_t j[kAggUnroll];
+          WTin wr[kAggUnroll];
+#pragma unroll
+          for (int u = 0; u < kAggUnroll; ++u) {
+            j[u] = 0;  // (past the row: an unused, valid label load)
+            wr[u] = WTin(0);
+            if (e0 + u * G < deg) {
+              j[u] = g.idx[beg + e0 + u * G];
+              wr[u] = g.weight(beg + e0 + u * G);
+            }
+          }
+          int32_t d[kAggUnroll];
+#pragma unroll
+          for (int u = 0; u < kAggUnroll; ++u) d[u] = a.lab[j[u]];
+#pragma unroll
+          for (int u = 0; u < kAggUnroll; ++u) {
+            if (e0 + u * G >= deg) continue;
+            if (d[u] == c) self += (double)wr[u];
+            else lds_insert(keys, vals, LG, d[u], (double)wr[u]);
+          }
         }
       }
     }
@@ -173,17 +211,35 @@ __global__ __launch_bounds__(NT) void k_agg_rows(GraphView<WTin> g, AggArgs a, c
       s_beg[t] = beg;
       __syncthreads();
       na += (unsigned long long)deg;
-      for (int32_t q = t; q < total; q += NT) {
-        int lo = 0, hi = NT;  // s_off[lo] <= q < s_off[hi]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (s_off[mid] <= q) lo = mid; else hi = mid;
+      for (int32_t q0 = t; q0 < total; q0 += kAggUnroll * NT) {  // uniform
+        int32_t j[kAggUnroll];
+        WTin wr[kAggUnroll];
+#pragma unroll
+        for (int u = 0; u < kAggUnroll; ++u) {
+          const int32_t q = q0 + u * NT;
+          j[u] = 0;  // (past the arcs: an unused, valid label load)
+          wr[u] = WTin(0);
+          if (q < total) {
+            int lo = 0, hi = NT;  // s_off[lo] <= q < s_off[hi]
+            while (hi - lo > 1) {
+              const int mid = (lo + hi) >> 1;
+              if (s_off[mid] <= q) lo = mid; else hi = mid;
+            }
+            const int64_t e = (int64_t)s_beg[lo] + (q - s_off[lo]);
+            j[u] = g.idx[e];
+            wr[u] = g.weight(e);
+          }
         }
-        const int64_t e = (int64_t)s_beg[lo] + (q - s_off[lo]);
-        const int32_t d = a.lab[g.idx[e]];
-        const double wt = g.weight(e);
-        if (d == c) self += wt;
-        else lds_insert_sized(keys, vals, (uint32_t)ts, d, wt);
+        int32_t d[kAggUnroll];
+#pragma unroll
+        for (int u = 0; u < kAggUnroll; ++u) d[u] = a.lab[j[u]];
+#pragma unroll
+        for (int u = 0; u < kAggUnroll; ++u) {
+          if (q0 + u * NT >= total) continue;
+          const double wt = (double)wr[u];
+          if (d[u] == c) self += wt;
+          else lds_insert_sized(keys, vals, (uint32_t)ts, d[u], wt);
+        }
       }
     }
     self = block_sum<double>(self, s_red);

@@ -682,10 +682,27 @@ __global__ __launch_bounds__(kBlock) void k_hub_modularity(GraphView<WT> g, HubA
     const int32_t e0 = task.y * kHubChunk;
     const int32_t e1 = (deg - e0 < kHubChunk) ? deg : e0 + kHubChunk;
     double k = 0.0, sc = 0.0;
-    for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
-      const double w = g.weight(beg + e);
-      k += w;
-      if (C[g.idx[beg + e]] == ci) sc += w;
+    constexpr int U = 8;  // arcs per thread per round, their loads issued together
+    for (int32_t eb = e0 + threadIdx.x; eb < e1; eb += U * kBlock) {
+      int32_t j[U];
+      WT w[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        j[u] = i;  // (past the chunk: an unused, valid label load)
+        w[u] = WT(0);
+        if (eb + u * kBlock < e1) {
+          j[u] = g.idx[beg + eb + u * kBlock];
+          w[u] = g.weight(beg + eb + u * kBlock);
+        }
+      }
+      int32_t cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) cj[u] = C[j[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        k += (double)w[u];
+        if (eb + u * kBlock < e1 && cj[u] == ci) sc += (double)w[u];
+      }
     }
     k = block_sum<double>(k, red);
     if (threadIdx.x == 0) atomicAdd(&tot[ci], k);
@@ -805,13 +822,15 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     }
     double self = 0.0;  // arcs inside c: the super-vertex's self-loop
     int32_t j[PER];
-    double w[PER];
+    WT w[PER];  // widened where used (see GraphView::weight)
+    bool in[PER];
 #pragma unroll
     for (int x = 0; x < PER; ++x) {
       const int64_t q = A0 + (int64_t)x * kBlock + threadIdx.x;
-      j[x] = -1;
-      w[x] = 0.0;
-      if (q < A1) {
+      in[x] = q < A1;
+      j[x] = 0;  // (past the chunk: an unused, valid label load)
+      w[x] = WT(0);
+      if (in[x]) {
         int lo = 0, hi = nm;  // s_mo[lo] <= q < s_mo[hi] (s_mo[nm] taken as A1)
         while (hi - lo > 1) {
           const int mid = (lo + hi) >> 1;
@@ -824,12 +843,12 @@ __global__ __launch_bounds__(kBlock) void k_gagg_gather(GraphView<WT> g, AggArgs
     }
     int32_t dl[PER];
 #pragma unroll
-    for (int x = 0; x < PER; ++x) dl[x] = (j[x] >= 0) ? a.lab[j[x]] : kEmpty;
+    for (int x = 0; x < PER; ++x) dl[x] = a.lab[j[x]];
 #pragma unroll
     for (int x = 0; x < PER; ++x) {
-      if (dl[x] == kEmpty) continue;
-      if (dl[x] == c) self += w[x];
-      else lds_insert(skeys, svals, kHubGatherLg, dl[x], w[x]);
+      if (!in[x] || dl[x] == kEmpty) continue;
+      if (dl[x] == c) self += (double)w[x];
+      else lds_insert(skeys, svals, kHubGatherLg, dl[x], (double)w[x]);
     }
     na += (unsigned long long)((A1 - A0 + kBlock - 1 - threadIdx.x) / kBlock);
     self = block_sum<double>(self, s_red);

@@ -140,35 +140,40 @@ __global__ __launch_bounds__(kBlock) void k_vertex_weights(GraphView<WT> g, int6
       if (validate && (deg < 0 || beg < 0 || (int64_t)beg + deg > m)) { bad_csr = 1; deg = 0; }
       if (deg > kBinMax[kHubBin - 1]) deg = 0;  // hub rows: hub_weights
     }
-    double s = 0.0;
-    if (deg < kWave) {
-      for (int32_t e = 0; e < deg; ++e) {
-        const double w = g.weight(beg + e);
-        if (validate) {
-          const int32_t j = g.idx[beg + e];
-          if (j < 0 || j >= n) bad_csr = 1;
+    // four arcs per step, their loads issued before the first use
+    constexpr int U = 4;
+    auto step = [&](int32_t b0, int32_t e0, int32_t stride, int32_t end, double& acc) {
+      WT wr[U];
+      int32_t j[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        wr[u] = WT(1);
+        j[u] = 0;
+        if (e0 + u * stride < end) {
+          wr[u] = g.weight(b0 + e0 + u * stride);
+          if (validate) j[u] = g.idx[b0 + e0 + u * stride];
         }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (e0 + u * stride >= end) continue;
+        const double w = (double)wr[u];
+        if (validate && (j[u] < 0 || j[u] >= n)) bad_csr = 1;
         if (!(w >= 1.0 && w <= 16777216.0 && w == floor(w))) bad_w = 1;
         if (!(w > 0.0 && w < INFINITY)) bad_sign = 1;
-        s += w;
+        acc += w;
       }
-    }
+    };
+    double s = 0.0;
+    if (deg < kWave)
+      for (int32_t e = 0; e < deg; e += U) step(beg, e, 1, deg, s);
     u64 mask = __ballot(i < n && deg >= kWave);
     while (mask) {
       const int q = __ffsll((unsigned long long)mask) - 1;
       mask &= mask - 1;
       const int32_t bq = __shfl(beg, q), dq = __shfl(deg, q);
       double part = 0.0;
-      for (int32_t e = lane_id(); e < dq; e += kWave) {
-        const double w = g.weight(bq + e);
-        if (validate) {
-          const int32_t j = g.idx[bq + e];
-          if (j < 0 || j >= n) bad_csr = 1;
-        }
-        if (!(w >= 1.0 && w <= 16777216.0 && w == floor(w))) bad_w = 1;
-        if (!(w > 0.0 && w < INFINITY)) bad_sign = 1;
-        part += w;
-      }
+      for (int32_t e = lane_id(); e < dq; e += U * kWave) step(bq, e, kWave, dq, part);
       part = sum_xor<kWave>(part);
       if (lane_id() == q) s = part;
     }
@@ -601,25 +606,40 @@ __global__ __launch_bounds__(kBlock) void k_mod_partial(GraphView<WT> g, const i
     int32_t beg = 0, deg = 0, ci = -1;
     if (i < n) { beg = g.begin(i); deg = g.degree(i); ci = C[i]; }
     if (deg > kBinMax[kHubBin - 1]) deg = 0;  // hub rows: hub_modularity
-    double k = 0.0, sg = 0.0;
-    if (deg < kWave) {
-      for (int32_t e = 0; e < deg; ++e) {
-        const double w = g.weight(beg + e);
-        k += w;
-        if (C[g.idx[beg + e]] == ci) sg += w;
+    // four arcs per step: index and weight loads, then the label loads, all
+    // issued before the first use
+    constexpr int U = 4;
+    auto step = [&](int32_t b0, int32_t e0, int32_t stride, int32_t end, int32_t cc, double& kk, double& ss) {
+      WT wr[U];
+      int32_t j[U], cj[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        wr[u] = WT(0);
+        j[u] = 0;  // (past the row: an unused, valid label load)
+        if (e0 + u * stride < end) {
+          wr[u] = g.weight(b0 + e0 + u * stride);
+          j[u] = g.idx[b0 + e0 + u * stride];
+        }
       }
-    }
+#pragma unroll
+      for (int u = 0; u < U; ++u) cj[u] = C[j[u]];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (e0 + u * stride >= end) continue;
+        kk += (double)wr[u];
+        if (cj[u] == cc) ss += (double)wr[u];
+      }
+    };
+    double k = 0.0, sg = 0.0;
+    if (deg < kWave)
+      for (int32_t e = 0; e < deg; e += U) step(beg, e, 1, deg, ci, k, sg);
     u64 mask = __ballot(i < n && deg >= kWave);
     while (mask) {
       const int q = __ffsll((unsigned long long)mask) - 1;
       mask &= mask - 1;
       const int32_t bq = __shfl(beg, q), dq = __shfl(deg, q), cq = __shfl(ci, q);
       double pk = 0.0, ps = 0.0;
-      for (int32_t e = lane_id(); e < dq; e += kWave) {
-        const double w = g.weight(bq + e);
-        pk += w;
-        if (C[g.idx[bq + e]] == cq) ps += w;
-      }
+      for (int32_t e = lane_id(); e < dq; e += U * kWave) step(bq, e, kWave, dq, cq, pk, ps);
       pk = sum_xor<kWave>(pk);
       ps = sum_xor<kWave>(ps);
       if (lane_id() == q) { k = pk; sg = ps; }
@@ -681,13 +701,13 @@ __global__ __launch_bounds__(kBlock) void k_mod_rows(GraphView<WT> g, const int3
     __syncthreads();
     for (int32_t qb = 0; qb < total; qb += U * kBlock) {  // uniform over the workgroup
       int32_t row[U], j[U];
-      double w[U];
+      WT w[U];  // widened where used (see GraphView::weight)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const int32_t q = qb + u * kBlock + t;
         row[u] = -1;
         j[u] = 0;
-        w[u] = 0.0;
+        w[u] = WT(0);
         if (q < total) {
           int lo = 0, hi = kBlock;  // s_off[lo] <= q < s_off[hi]
           while (hi - lo > 1) {
@@ -702,11 +722,11 @@ __global__ __launch_bounds__(kBlock) void k_mod_rows(GraphView<WT> g, const int3
       }
       int32_t cj[U];
 #pragma unroll
-      for (int u = 0; u < U; ++u) cj[u] = (row[u] >= 0) ? C[j[u]] : -1;
+      for (int u = 0; u < U; ++u) cj[u] = C[j[u]];  // (j = 0 past the rows: an unused, valid load)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (row[u] >= 0 && cj[u] == s_c[row[u]]) s1 += w[u];
-        double v = w[u];
+        double v = (double)w[u];  // (0 past the rows)
+        if (row[u] >= 0 && cj[u] == s_c[row[u]]) s1 += v;
         const int32_t r = row[u];
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {

@@ -332,7 +332,7 @@ __device__ __forceinline__ double scan_row(const GraphView<WT>& g, const ScanArg
       wr[u] = WT(1);
       if (e < deg) {
         j[u] = g.idx[beg + e];
-        if (g.w) wr[u] = g.w[beg + e];
+        wr[u] = g.weight(beg + e);
       }
     }
     // The label loads of the round go out first and land in registers
