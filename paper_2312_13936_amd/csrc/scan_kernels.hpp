@@ -270,6 +270,33 @@ __device__ __forceinline__ bool accept(const ScanArgs& a, int32_t i, int32_t d, 
   return true;
 }
 
+// A row's own state, loaded ahead of its scan: row bounds, bound label
+// (refinement), label, K', and the pruning flag (local-moving).  Only the
+// loads go out here; nothing waits for them.
+struct RowState {
+  int32_t beg = 0, deg = 0, bi = 0, d = 0;
+  double ki = 0.0;
+  uint8_t flag = 0;
+};
+template <int PH, class WT>
+__device__ __forceinline__ RowState load_row_state(const GraphView<WT>& g, const ScanArgs& a, int32_t i) {
+  RowState r;
+  r.beg = g.begin(i);
+  r.deg = g.degree(i);
+  if (PH == kRefine) r.bi = a.CB[i];
+  r.d = a.C[i];
+  r.ki = a.K[i];
+  if (PH == kMove) r.flag = a.flag[i];
+  return r;
+}
+// Decide::eligible on a loaded state (refinement reads the size of the own
+// community here: the row's label is already loaded).
+template <int PH>
+__device__ __forceinline__ bool row_eligible(const ScanArgs& a, const RowState& r) {
+  if (PH == kMove) return r.flag != 0;
+  return a.size[r.d] == 1 && r.ki > 0.0;
+}
+
 // The state of vertex i (own community d) that the tests after the argmax
 // read, loaded before the scan so that the only load left between the
 // argmax and the decision is size[c*] for a singleton (see accept_pre).
@@ -437,15 +464,27 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
   Acc acc;
   const bool sync = DET || (a.sync_moves & 1);
   const int32_t it = launch_iteration<PH>(a, sync);
-  for (int64_t v = (int64_t)bid * GPB + gb; v < count; v += (int64_t)nb * GPB) {
-    const int32_t i = list[v];
-    // the loads that need only i go out together with the eligibility test
-    const int32_t beg = g.begin(i), deg = g.degree(i);
-    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
-    // One lane reads the (possibly concurrently updated) eligibility state.
-    int ok = (gl == 0) ? (int)Decide<PH, DET>::eligible(a, i) : 0;
+  // rows software pipelined as in k_decide_block: a row's state is loaded
+  // while the row before it is scanned, its list entry one row earlier
+  const int64_t step = (int64_t)nb * GPB;
+  const int64_t v0 = (int64_t)bid * GPB + gb;
+  int32_t i_next = 0, i_after = 0;
+  RowState nx;
+  if (v0 < count) {
+    i_next = list[v0];
+    if (v0 + step < count) i_after = list[v0 + step];
+    nx = load_row_state<PH>(g, a, i_next);
+  }
+  for (int64_t v = v0; v < count; v += step) {
+    const int32_t i = i_next;
+    const RowState cur = nx;
+    if (v + step < count) nx = load_row_state<PH>(g, a, i_after);
+    i_next = i_after;
+    if (v + 2 * step < count) i_after = list[v + 2 * step];
+    const int32_t beg = cur.beg, deg = cur.deg, bi = cur.bi, d = cur.d;
+    const double ki = cur.ki;
+    // One lane decides on the (possibly concurrently updated) eligibility state.
+    int ok = (gl == 0) ? (int)row_eligible<PH>(a, cur) : 0;
     ok = __shfl(ok, 0, G);
     if (!ok) continue;
     if (PH == kMove && gl == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
@@ -559,14 +598,27 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
   Acc acc;
   const bool sync = DET || (a.sync_moves & 2);
   const int32_t it = launch_iteration<PH>(a, sync);
-  for (int64_t v = blockIdx.x; v < count; v += gridDim.x) {
-    const int32_t i = list[v];
-    // the loads that need only i go out together with the eligibility test
-    const int32_t beg = g.begin(i), deg = g.degree(i);
-    const int32_t bi = (PH == kRefine) ? a.CB[i] : 0;
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
-    if (threadIdx.x == 0) s_flag = (int)Decide<PH, DET>::eligible(a, i);
+  // The workgroup's rows v = blockIdx.x + r gridDim.x are software
+  // pipelined: a row's own state is loaded while the row before it is
+  // scanned, and its list entry one row earlier still, so that neither
+  // sits on the path from one row's scan to the next.
+  const int64_t step = gridDim.x;
+  int32_t i_next = 0, i_after = 0;
+  RowState nx;
+  if ((int64_t)blockIdx.x < count) {
+    i_next = list[blockIdx.x];
+    if ((int64_t)blockIdx.x + step < count) i_after = list[blockIdx.x + step];
+    nx = load_row_state<PH>(g, a, i_next);
+  }
+  for (int64_t v = blockIdx.x; v < count; v += step) {
+    const int32_t i = i_next;
+    const RowState cur = nx;
+    if (v + step < count) nx = load_row_state<PH>(g, a, i_after);
+    i_next = i_after;
+    if (v + 2 * step < count) i_after = list[v + 2 * step];
+    const int32_t beg = cur.beg, deg = cur.deg, bi = cur.bi, d = cur.d;
+    const double ki = cur.ki;
+    if (threadIdx.x == 0) s_flag = (int)row_eligible<PH>(a, cur);
     __syncthreads();
     const int ok = s_flag;
     __syncthreads();
