@@ -290,10 +290,13 @@ __device__ __forceinline__ RowState load_row_state(const GraphView<WT>& g, const
   return r;
 }
 // Decide::eligible on a loaded state (refinement reads the size of the own
-// community here: the row's label is already loaded).
+// community here: the row's label is already loaded).  sync: the loaded
+// pruning flag is current (no decision of a synchronous schedule sets a
+// flag); the asynchronous schedule marks neighbours while others decide,
+// so there the flag of vertex i is read again now.
 template <int PH>
-__device__ __forceinline__ bool row_eligible(const ScanArgs& a, const RowState& r) {
-  if (PH == kMove) return r.flag != 0;
+__device__ __forceinline__ bool row_eligible(const ScanArgs& a, const RowState& r, int32_t i, bool sync) {
+  if (PH == kMove) return (sync ? r.flag : a.flag[i]) != 0;
   return a.size[r.d] == 1 && r.ki > 0.0;
 }
 
@@ -484,7 +487,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     const int32_t beg = cur.beg, deg = cur.deg, bi = cur.bi, d = cur.d;
     const double ki = cur.ki;
     // One lane decides on the (possibly concurrently updated) eligibility state.
-    int ok = (gl == 0) ? (int)row_eligible<PH>(a, cur) : 0;
+    int ok = (gl == 0) ? (int)row_eligible<PH>(a, cur, i, sync) : 0;
     ok = __shfl(ok, 0, G);
     if (!ok) continue;
     if (PH == kMove && gl == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
@@ -618,7 +621,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     if (v + 2 * step < count) i_after = list[v + 2 * step];
     const int32_t beg = cur.beg, deg = cur.deg, bi = cur.bi, d = cur.d;
     const double ki = cur.ki;
-    if (threadIdx.x == 0) s_flag = (int)row_eligible<PH>(a, cur);
+    if (threadIdx.x == 0) s_flag = (int)row_eligible<PH>(a, cur, i, sync);
     __syncthreads();
     const int ok = s_flag;
     __syncthreads();
