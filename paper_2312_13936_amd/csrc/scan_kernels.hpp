@@ -213,13 +213,14 @@ __device__ __forceinline__ bool mark_needed(const ScanArgs& a, int32_t j) {
 // Marks the neighbours j != i of a moved vertex i as unprocessed (Alg. 2):
 // the arcs e0, e0 + nt, ... < deg of its row, kMarkUnroll per thread per
 // step with their index loads issued together (the marks do not depend on
-// each other, so a row costs deg / (nt kMarkUnroll) load latencies rather
-// than deg / nt).  check (synchronous commits): only where mark_needed,
-// and a flag is read before it is written: a vertex with many moving
-// neighbours is marked by each of them, and the read of a set flag stays
-// in the cache where each store would travel to memory.  (No flag is
-// cleared while a commit runs, so a skipped store is never needed; the
-// asynchronous schedule clears flags concurrently and always stores.)
+// each other).  check (synchronous commits): only where mark_needed, and a
+// flag is read before it is written: a vertex with many moving neighbours
+// is marked by each of them, and the read of a set flag stays in the cache
+// where each store would travel to memory.  (No flag is cleared while a
+// commit runs, so a skipped store is never needed; the asynchronous
+// schedule clears flags concurrently and always stores.)  The flag reads
+// are branch-guarded and so issued one at a time; reading every lane's
+// flag through a valid index instead measured no faster.
 constexpr int kMarkUnroll = 8;
 template <class WT>
 __device__ __forceinline__ void mark_row(const GraphView<WT>& g, const ScanArgs& a, int32_t i, int32_t beg,
