@@ -459,6 +459,11 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
     const int32_t i = h.items[p];
     const int32_t beg = g.begin(i), deg = g.degree(i);
     if (!hub_partitioned(deg)) continue;  // uniform: k_hub_eval
+    // the hub's own label, K', K_{i->d} and total go out before the table
+    // is filled, not after it
+    const int32_t d = a.C[i];
+    const double ki = a.K[i], kid = h.kid[p];
+    const double sd = a.Sig[d];
     const int32_t sb = h.slice_off[p], se = h.slice_off[p + 1];
     const uint32_t pm = (uint32_t)(se - sb) - 1u;  // P - 1
     const uint32_t q = (uint32_t)task.y;
@@ -516,9 +521,7 @@ __global__ __launch_bounds__(kPartThreads) void k_hub_part_eval(GraphView<WT> g,
         if (ck[u] != kEmpty && !lds_insert_sized(keys, vals, (uint32_t)TS, ck[u], cw[u])) s_ovf = 1;
     }
     __syncthreads();
-    const int32_t d = a.C[i];
-    const double ki = a.K[i];
-    const Eval<DET> ev(a, i, h.kid[p], ki, a.Sig[d]);
+    const Eval<DET> ev(a, i, kid, ki, sd);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
