@@ -71,3 +71,28 @@ def test_recorded_traffic_is_dropped_when_sources_change(tmp_path):
     assert ps.recorded_traffic(str(p)) is None
     assert ps.recorded_traffic(str(tmp_path / "missing.md")) is None
 
+
+
+def test_pmc_tables_per_call_totals_and_ratios(tmp_path):
+    a, b = tmp_path / "a.csv", tmp_path / "b.csv"
+    scan = "void gvl::k_decide_block<11, float, 0, false>(...)"
+    agg = "void gvl::k_agg_rows<float, float, 256, 2048>(...)"
+    _counter_csv(a, "SQ_WAVE_CYCLES", [(scan, 1000.0), (agg, 400.0)])
+    with open(a, "a", newline="") as f:  # a second counter of the same pass
+        csv.writer(f).writerows([[scan, "SQ_WAIT_ANY", 700.0], [agg, "SQ_WAIT_ANY", 100.0]])
+    _counter_csv(b, "TCC_EA0_RDREQ_sum", [(scan, 50.0), (agg, 20.0)])
+    with open(b, "a", newline="") as f:
+        csv.writer(f).writerows([[scan, "TCC_EA0_RDREQ_LEVEL_sum", 45000.0], [agg, "TCC_EA0_RDREQ_LEVEL_sum", 16000.0]])
+    out = tmp_path / "p.md"
+    ps.pmc("2", str(out), "cmd", str(a), str(b))  # two calls: totals halved
+    text = out.read_text()
+    totals, derived = text.split("Derived")
+    rows = {l.split("|")[1].strip(): [c.strip() for c in l.split("|")[2:-1]] for l in totals.splitlines()
+            if l.startswith("| **") or l.startswith("| `")}
+    # table of totals: SQ_WAVE_CYCLES, SQ_WAIT_ANY, TCC_EA0_RDREQ_sum, TCC_EA0_RDREQ_LEVEL_sum per call
+    assert rows["**neighbour-community scan**"][:4] == ["500", "350", "25", "2.25e+04"]
+    assert rows["**aggregation rows**"][:4] == ["200", "50", "10", "8e+03"]
+    # waiting fraction and mean latency are ratios of the per-call totals
+    assert "| **neighbour-community scan** | 0.7 | 900 |" in derived
+    assert "| **aggregation rows** | 0.25 | 800 |" in derived
+    assert "Kernel sources digest: %s" % ps.source_digest() in text
