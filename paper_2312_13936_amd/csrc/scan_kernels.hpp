@@ -501,12 +501,18 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
     constexpr int UA = (BMAX + G - 1) / G;  // (one round: the row's arcs gl, gl + G, ... stay in registers)
     // labels of the lane's arcs gl + u G (kEmpty past the row: a lane whose
     // first arc lies past it sees none), kept for the swap-rule candidate test
-    int32_t rc[UA];
+    int32_t rc[UA], rj[UA];  // (rj: the neighbour ids, set wherever rc is)
 #pragma unroll
-    for (int u = 0; u < UA; ++u) rc[u] = kEmpty;
+    for (int u = 0; u < UA; ++u) {
+      rc[u] = kEmpty;
+      rj[u] = i;
+    }
     double kid = scan_row<UA, G, PH>(
         g, a, i, beg, deg, gl, d, bi, [&](int32_t c, double w) { lds_insert(keys, vals, lg, c, w); },
-        [&](int u, int32_t, int32_t c) { rc[u] = c; });
+        [&](int u, int32_t j, int32_t c) {
+          rc[u] = c;
+          rj[u] = j;
+        });
     kid = sum_xor<G>(kid);
     wave_sync();
     const Eval<DET> ev(a, i, kid, ki, sd);
@@ -540,7 +546,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
 #pragma unroll
       for (int u = 0; u < UA; ++u)
         if (rc[u] == bc) {  // (bc is not the own community, so the arc is not a self-loop)
-          const int32_t j = g.idx[beg + gl + u * G];
+          const int32_t j = rj[u];
           if (group_in_pass(a, j, vb, sh) == a.grp) {
             ++np;
             pj = j;
