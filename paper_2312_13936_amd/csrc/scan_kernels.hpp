@@ -936,11 +936,26 @@ __device__ __forceinline__ bool swap_yields(const GraphView<WT>& g, const ScanAr
   const int32_t beg = g.begin(i), deg = g.degree(i);
   const int32_t vb = a.gid ? a.vbase[a.gid[i]] : 0;
   const int sh = (a.gid && a.gsh) ? a.gsh[a.gid[i]] : 0;
-  for (int32_t e = 0; e < deg; ++e) {
-    const int32_t j = g.idx[beg + e];
-    if (j == i || group_in_pass(a, j, vb, sh) != a.grp) continue;
-    const int4 r = a.mv[j];
-    if (r.z == stamp && r.x == t && r.y == d && (j < i || g.degree(j) > kSwapRowMax)) return true;
+  // four arcs per step: their ids, then their records (a lane without a
+  // same-group neighbour reads its own record), each batch in flight
+  // together; a row walked one arc at a time (two dependent loads per arc)
+  // could hold up a whole commit launch
+  constexpr int U = 4;
+  for (int32_t e0 = 0; e0 < deg; e0 += U) {
+    int32_t j[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) j[u] = g.idx[beg + min(e0 + u, deg - 1)];
+    bool same[U];
+    int4 r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      same[u] = e0 + u < deg && j[u] != i && group_in_pass(a, j[u], vb, sh) == a.grp;
+      r[u] = a.mv[same[u] ? j[u] : i];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (same[u] && r[u].z == stamp && r[u].x == t && r[u].y == d && (j[u] < i || g.degree(j[u]) > kSwapRowMax))
+        return true;
   }
   return false;
 }
