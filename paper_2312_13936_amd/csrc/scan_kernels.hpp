@@ -1199,7 +1199,7 @@ void commit_group_launch(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
     nblk[2] = nblk[3] = 0;
   } else {
     nblk[0] = cl.n0 > 0 ? grid_for(cl.n0, kBlock, cap) : 0;
-    nblk[1] = cl.n1 > 0 ? grid_for(cl.n1, 1, cap) : 0;
+    nblk[1] = cl.n1 > 0 ? grid_for(cl.n1, 1, 4 * cap) : 0;
     nblk[2] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, 64) : 0;
     nblk[3] = cl.c1 > cl.c0 ? grid_for(cl.c1 - cl.c0, 1, 4096) : 0;
   }
