@@ -387,6 +387,20 @@ __device__ __forceinline__ T block_sum(T v, T* red) {
   return s;
 }
 
+// Sum over the block as block_sum, with the result valid in every thread
+// (each thread adds the wavefront sums in the same order, so all agree).
+template <class T>
+__device__ __forceinline__ T block_allsum(T v, T* red) {
+  v = sum_xor<kWave>(v);
+  const int w = threadIdx.x / kWave;
+  __syncthreads();
+  if (lane_id() == 0) red[w] = v;
+  __syncthreads();
+  T s = T(0);
+  for (int k = 0; k < (int)(blockDim.x / kWave); ++k) s += red[k];
+  return s;
+}
+
 __device__ __forceinline__ i128 block_sum_i128(i128 v, i128* red) {
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) v += shfl_xor_i128<kWave>(v, o);

@@ -602,12 +602,18 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
   __shared__ i128 s_k[kBlock / kWave];
   __shared__ int32_t s_c[kBlock / kWave];
   __shared__ int s_flag, s_take;
-  __shared__ double s_kid;
   for (int s = threadIdx.x; s < TS; s += kBlock) { keys[s] = kEmpty; vals[s] = 0.0; }
   __syncthreads();
   Acc acc;
   const bool sync = DET || (a.sync_moves & 2);
   const int32_t it = launch_iteration<PH>(a, sync);
+  // stable: while this launch runs, nothing else writes a row's flag, the
+  // community sizes or the last-move entries (refinement and synchronous
+  // local-moving only record targets), so every thread reaches the
+  // eligibility and acceptance decisions from its own loads and no thread
+  // has to publish them.  The row's own flag is cleared once every
+  // wavefront has read it.
+  const bool stable = PH == kRefine || sync;
   // The workgroup's rows v = blockIdx.x + r gridDim.x are software
   // pipelined: a row's own state is loaded while the row before it is
   // scanned, and its list entry one row earlier still, so that neither
@@ -628,25 +634,30 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     if (v + 2 * step < count) i_after = list[v + 2 * step];
     const int32_t beg = cur.beg, deg = cur.deg, bi = cur.bi, d = cur.d;
     const double ki = cur.ki;
-    if (threadIdx.x == 0) s_flag = (int)row_eligible<PH>(a, cur, i, sync);
-    __syncthreads();
-    const int ok = s_flag;
-    __syncthreads();
+    int ok;
+    if (stable) {
+      ok = (int)row_eligible<PH>(a, cur, i, sync);
+    } else {
+      if (threadIdx.x == 0) s_flag = (int)row_eligible<PH>(a, cur, i, sync);
+      __syncthreads();
+      ok = s_flag;
+      __syncthreads();
+    }
     if (!ok) continue;  // uniform over the workgroup
-    if (PH == kMove && threadIdx.x == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
+    if (PH == kMove && !stable && threadIdx.x == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
     const int lg = min(LG, ceil_log2(2 * (int64_t)deg));
     const int ts = 1 << lg;
     // and those that need d, before the scan's
     const double sd = a.Sig[d];
     Pre pre;
-    if (threadIdx.x == 0) pre = prefetch_state<PH>(a, i, d, sync, it);
+    if (stable || threadIdx.x == 0) pre = prefetch_state<PH>(a, i, d, sync, it);
     double kid = scan_row<4, kBlock, PH>(g, a, i, beg, deg, threadIdx.x, d, bi, [&](int32_t c, double w) {
       lds_insert(keys, vals, lg, c, w);
     });
-    kid = block_sum<double>(kid, s_g);
-    if (threadIdx.x == 0) s_kid = kid;
-    __syncthreads();
-    const Eval<DET> ev(a, i, s_kid, ki, sd);
+    kid = block_allsum<double>(kid, s_g);
+    // Every wavefront has read this row's flag by now (it decided on it).
+    if (PH == kMove && stable && threadIdx.x == 0) a.flag[i] = 0;
+    const Eval<DET> ev(a, i, kid, ki, sd);
     int32_t bc = -1;
     double bg = 0.0;
     i128 bk = 0;
@@ -656,10 +667,15 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     if (threadIdx.x == 0) {
       ++acc.nv;
       acc.na += (unsigned long long)deg;
-      s_take = (int)accept_pre<PH, DET>(a, pre, d, bc, bg, bk, sync);
     }
-    __syncthreads();  // table and s_* reads done; s_take published
-    const int take = s_take;
+    int take;
+    if (stable) {
+      take = (int)accept_pre<PH, DET>(a, pre, d, bc, bg, bk, sync);
+    } else {
+      if (threadIdx.x == 0) s_take = (int)accept_pre<PH, DET>(a, pre, d, bc, bg, bk, sync);
+      __syncthreads();  // s_take published
+      take = s_take;
+    }
     if (!take) continue;
     if (PH == kMove && !DET && !(a.sync_moves & 2)) {
       if (threadIdx.x == 0) {
