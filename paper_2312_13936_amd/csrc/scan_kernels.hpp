@@ -441,14 +441,16 @@ __device__ __forceinline__ void eval_table(int32_t* keys, double* vals, int ts, 
 }
 
 // ------------------------------------------------ group of G lanes per vertex ---
-// Bins 0-4 in one launch: blocks [blk[b], blk[b+1]) serve bin b, each with
-// groups of G lanes per vertex (the bin's rows have at most BMAX arcs).
+// Bins 0-5 in one launch (k_decide_groups): blocks [blk[b], blk[b+1]) serve
+// bin b, bins 0-4 with groups of G lanes per vertex (the bin's rows have at
+// most BMAX arcs), bin 5 with one workgroup per vertex.
 struct GroupLaunch {
-  int32_t count[5];
-  int32_t start[5];
-  int32_t blk[6];
+  int32_t count[6];
+  int32_t start[6];
+  int32_t blk[7];
 };
-constexpr int kGroupSlots = 2048;  // LDS slots of one workgroup: the largest GPB * 2^LG of bins 0-4
+constexpr int kGroupSlots = 2048;  // LDS slots of one workgroup: the largest GPB * 2^LG of bins 0-4, bin 5's table
+static_assert(kBinLanes[5] == kBlock, "bin 5: one workgroup per vertex");
 
 // Body of one workgroup of bin (G, LG): workgroup `bid` of `nb` strides over
 // the bin's vertices; skeys / svals: the workgroup's kGroupSlots LDS slots.
@@ -571,33 +573,14 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
   flush_acc<PH, DET>(a, acc);
 }
 
-template <class WT, int PH, bool DET>
-__global__ __launch_bounds__(kBlock) void k_decide_groups(GraphView<WT> g, ScanArgs a,
-                                                          const int32_t* __restrict__ list, GroupLaunch gl) {
-  __shared__ int32_t skeys[kGroupSlots];
-  __shared__ double svals[kGroupSlots];
-  int b = 0;
-  while (b < 4 && (int32_t)blockIdx.x >= gl.blk[b + 1]) ++b;  // uniform over the workgroup
-  const int32_t bid = (int32_t)blockIdx.x - gl.blk[b], nb = gl.blk[b + 1] - gl.blk[b];
-  const int32_t* l = list + gl.start[b];
-  switch (b) {
-    case 0: decide_group_body<kBinLanes[0], 3, kBinMax[0], WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
-    case 1: decide_group_body<kBinLanes[1], 4, kBinMax[1], WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
-    case 2: decide_group_body<kBinLanes[2], 5, kBinMax[2], WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
-    case 3: decide_group_body<kBinLanes[3], 6, kBinMax[3], WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
-    default: decide_group_body<kBinLanes[4], 8, kBinMax[4], WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
-  }
-}
-
 // ------------------------------------------------ one workgroup per vertex ---
-// LDS table of 2^LG slots.
+// Body of one workgroup of bin 5: workgroup `bid` of `nb` strides over the
+// bin's vertices with an LDS table of 2^LG slots (keys, vals).
 template <int LG, class WT, int PH, bool DET>
-__global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanArgs a,
-                                                         const int32_t* __restrict__ list,
-                                                         int32_t count) {
+__device__ __forceinline__ void decide_block_body(const GraphView<WT>& g, const ScanArgs& a,
+                                                  const int32_t* __restrict__ list, int32_t count, int32_t bid,
+                                                  int32_t nb, int32_t* keys, double* vals) {
   constexpr int TS = 1 << LG;
-  __shared__ int32_t keys[TS];
-  __shared__ double vals[TS];
   __shared__ double s_g[kBlock / kWave];
   __shared__ i128 s_k[kBlock / kWave];
   __shared__ int32_t s_c[kBlock / kWave];
@@ -614,19 +597,19 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
   // has to publish them.  The row's own flag is cleared once every
   // wavefront has read it.
   const bool stable = PH == kRefine || sync;
-  // The workgroup's rows v = blockIdx.x + r gridDim.x are software
+  // The workgroup's rows v = bid + r nb are software
   // pipelined: a row's own state is loaded while the row before it is
   // scanned, and its list entry one row earlier still, so that neither
   // sits on the path from one row's scan to the next.
-  const int64_t step = gridDim.x;
+  const int64_t step = nb;
   int32_t i_next = 0, i_after = 0;
   RowState nx;
-  if ((int64_t)blockIdx.x < count) {
-    i_next = list[blockIdx.x];
-    if ((int64_t)blockIdx.x + step < count) i_after = list[blockIdx.x + step];
+  if ((int64_t)bid < count) {
+    i_next = list[bid];
+    if ((int64_t)bid + step < count) i_after = list[bid + step];
     nx = load_row_state<PH>(g, a, i_next);
   }
-  for (int64_t v = blockIdx.x; v < count; v += step) {
+  for (int64_t v = bid; v < count; v += step) {
     const int32_t i = i_next;
     const RowState cur = nx;
     if (v + step < count) nx = load_row_state<PH>(g, a, i_after);
@@ -705,6 +688,27 @@ __global__ __launch_bounds__(kBlock) void k_decide_block(GraphView<WT> g, ScanAr
     }
   }
   flush_acc<PH, DET>(a, acc);
+}
+
+// The short-row decisions of a group: bins 0-5 in one launch, so the rows of
+// bin 5 fill the CUs that the lane-group bins leave as they finish.
+template <class WT, int PH, bool DET>
+__global__ __launch_bounds__(kBlock) void k_decide_groups(GraphView<WT> g, ScanArgs a,
+                                                          const int32_t* __restrict__ list, GroupLaunch gl) {
+  __shared__ int32_t skeys[kGroupSlots];
+  __shared__ double svals[kGroupSlots];
+  int b = 0;
+  while (b < 5 && (int32_t)blockIdx.x >= gl.blk[b + 1]) ++b;  // uniform over the workgroup
+  const int32_t bid = (int32_t)blockIdx.x - gl.blk[b], nb = gl.blk[b + 1] - gl.blk[b];
+  const int32_t* l = list + gl.start[b];
+  switch (b) {
+    case 0: decide_group_body<kBinLanes[0], 3, kBinMax[0], WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
+    case 1: decide_group_body<kBinLanes[1], 4, kBinMax[1], WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
+    case 2: decide_group_body<kBinLanes[2], 5, kBinMax[2], WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
+    case 3: decide_group_body<kBinLanes[3], 6, kBinMax[3], WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
+    case 4: decide_group_body<kBinLanes[4], 8, kBinMax[4], WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
+    default: decide_block_body<11, WT, PH, DET>(g, a, l, gl.count[5], bid, nb, skeys, svals); break;
+  }
 }
 
 // ------------------------------------ wide rows: P workgroups per vertex ---
@@ -1167,24 +1171,18 @@ template <class WT, int PH, bool DET>
 void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list,
                  const int32_t* count, const int32_t* start, int grid_cap, int hub_grid, int64_t* launches) {
   const GraphView<WT> g = view<WT>(gd);
-  {  // bins 0-4: one launch
+  {  // bins 0-5: one launch
     GroupLaunch gl;
     gl.blk[0] = 0;
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < 6; ++b) {
       gl.count[b] = count[b];
       gl.start[b] = start[b];
       gl.blk[b + 1] = gl.blk[b] + (count[b] > 0 ? grid_for(count[b], kBlock / kBinLanes[b], grid_cap) : 0);
     }
-    if (gl.blk[5] > 0) {
-      hipLaunchKernelGGL((k_decide_groups<WT, PH, DET>), dim3(gl.blk[5]), dim3(kBlock), 0, st, g, a, list, gl);
+    if (gl.blk[6] > 0) {
+      hipLaunchKernelGGL((k_decide_groups<WT, PH, DET>), dim3(gl.blk[6]), dim3(kBlock), 0, st, g, a, list, gl);
       ++*launches;
     }
-  }
-  if (count[5] > 0) {
-    const int grid = grid_for(count[5], 1, grid_cap);
-    hipLaunchKernelGGL((k_decide_block<11, WT, PH, DET>), dim3(grid), dim3(kBlock), 0, st, g, a,
-                       list + start[5], count[5]);
-    ++*launches;
   }
   WideLaunch wl;
   int64_t tasks = 0;
