@@ -756,9 +756,15 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
   const int32_t it = launch_iteration<PH>(a, sync);
   // persistent workgroups take tasks from a counter, so a vertex that is
   // skipped (not flagged, not isolated) costs a few loads, not a dispatch
+  // stable: as in decide_block_body (every thread decides eligibility
+  // itself; the flag is cleared once every wavefront has read it).
+  const bool stable = PH == kRefine || sync;
   for (;;) {
     __syncthreads();
-    if (threadIdx.x == 0) s_task = atomicAdd(a.wd_next, 1);
+    if (threadIdx.x == 0) {
+      s_task = atomicAdd(a.wd_next, 1);
+      s_ovf = 0;
+    }
     __syncthreads();
     int32_t b = s_task;
     if (b >= wl.tasks) break;  // uniform
@@ -787,15 +793,19 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       const int64_t want = ((2 * (int64_t)deg + kWideThreads - 1) / kWideThreads) * kWideThreads;
       if (want < ts) ts = (int)want;
     }
-    if (threadIdx.x == 0) {
-      int ok = 1;
-      if (part == 0 || PH == kRefine) ok = (int)Decide<PH, DET>::eligible(a, i);
-      if (PH == kMove && part == 0 && ok) a.flag[i] = 0;  // processed (Alg. 2 prune)
-      s_ok = ok;
-      s_ovf = 0;
+    int ok;
+    if (stable) {
+      ok = (part == 0 || PH == kRefine) ? (int)Decide<PH, DET>::eligible(a, i) : 1;
+    } else {
+      if (threadIdx.x == 0) {
+        int o = 1;
+        if (part == 0 || PH == kRefine) o = (int)Decide<PH, DET>::eligible(a, i);
+        if (PH == kMove && part == 0 && o) a.flag[i] = 0;  // processed (Alg. 2 prune)
+        s_ok = o;
+      }
+      __syncthreads();
+      ok = s_ok;
     }
-    __syncthreads();
-    const int ok = s_ok;
     if (!ok && P == 1) continue;  // uniform: nothing to decide, nothing to combine
     int32_t bc = -1;
     double bg = 0.0;
@@ -810,10 +820,8 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
         if ((int)(wide_part(c) & (uint32_t)(P - 1)) != part) return;
         if (!lds_insert_sized(keys, vals, (uint32_t)ts, c, w)) s_ovf = 1;
       });
-      kid = block_sum<double>(kid, s_d);
-      if (threadIdx.x == 0) s_d[0] = kid;
-      __syncthreads();
-      kid = s_d[0];
+      kid = block_allsum<double>(kid, s_d);
+      if (PH == kMove && stable && part == 0 && threadIdx.x == 0) a.flag[i] = 0;  // processed (Alg. 2 prune)
       const Eval<DET> ev(a, i, kid, ki, sd);
       eval_table<TS / kWideThreads / 2, kWideThreads, DET>(keys, vals, ts, threadIdx.x, a, ev, acc, bg, bk, bc);
       block_argmax<DET, NW>(bg, bk, bc, s_g, s_k, s_c);
@@ -889,9 +897,10 @@ __global__ __launch_bounds__(kWideThreads) void k_decide_wide(GraphView<WT> g, S
       }
       s_take = take;
     }
-    __syncthreads();
-    if (PH == kMove && !DET && !(a.sync_moves & 2) && s_take)
-      mark_row(g, a, i, beg, deg, threadIdx.x, kWideThreads, false);
+    if (!stable) {
+      __syncthreads();
+      if (PH == kMove && s_take) mark_row(g, a, i, beg, deg, threadIdx.x, kWideThreads, false);
+    }
   }
   // the last workgroup out resets the task counter for the next launch
   if (threadIdx.x == 0) {
