@@ -326,11 +326,14 @@ gvl_status gvl_leiden(gvl_ctx_t ctx, int64_t n, int64_t m, const int32_t* d_off,
     // (bx, lx: the short-row bins and their list, thinned during refinement;
     // the hubs always come from bins and ws.list)
     auto decide_group = [&](hipStream_t q, int grp, int phase, const BinInfo& bx, const int32_t* lx) {
+      // (thinned refinement: no lone hub left in the group)
+      const bool hubs = bx.count[grp][kHubBin] > 0 && !plan.groups[grp].empty();
+      const int32_t h0 = hubs ? plan.groups[grp].front().h0 : 0, h1 = hubs ? plan.groups[grp].back().h1 : 0;
       if (phase == kMove)
-        launch_decide_move(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
+        launch_decide_move(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, hargs, h0, h1, &S->scan_launches);
       else
-        launch_decide_refine(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, 0, &S->scan_launches);
-      if (bx.count[grp][kHubBin] > 0)  // (thinned refinement: no lone hub left in the group)
+        launch_decide_refine(q, cur, a, lx, bx.count[grp], bx.start[grp], det, grid_cap, hargs, h0, h1, &S->scan_launches);
+      if (hubs)
         for (const HubBatch& hb : plan.groups[grp]) {
           tstate.ensure(q, ws, hb.tend - hb.tbase);
           hargs.tbase = hb.tbase;

@@ -99,18 +99,6 @@ void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_
 }
 
 // ------------------------------------------------------------------ scan ---
-template <int PH, bool DET>
-__global__ void k_hub_prep(ScanArgs a, HubArgs h, int32_t h0, int32_t h1) {
-  for (int64_t p = h0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < h1; p += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t i = h.items[p];
-    const bool act = Decide<PH, DET>::eligible(a, i);
-    h.active[p] = act ? 1 : 0;
-    h.kid[p] = 0.0;
-    a.target[i] = -1;  // (a synchronous local-moving commit applies a hub's target without forgetting it)
-    if (PH == kMove && act) a.flag[i] = 0;  // processed (Alg. 2 prune)
-  }
-}
-
 // Merge the LDS pre-aggregation table of one chunk into item p's global
 // table; the slots of keys new to the global table are appended to p's
 // occupied-slot list (one reservation per workgroup).  Leaves the LDS table
@@ -591,8 +579,6 @@ template <class WT, int PH, bool DET>
 static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const HubArgs& h, int32_t h0,
                          int32_t h1, int32_t c0, int32_t c1, int32_t s0, int32_t s1, bool tables, int64_t* launches) {
   const GraphView<WT> g = view<WT>(gd);
-  const int hb = grid_items(h1 - h0, kBlock, 1024);
-  hipLaunchKernelGGL((k_hub_prep<PH, DET>), dim3(hb), dim3(kBlock), 0, st, a, h, h0, h1);
   if (c1 > c0) {
     hipLaunchKernelGGL((k_hub_gather<WT, PH, true>), dim3(grid_items(c1 - c0, 1, 2048)), dim3(kBlock), 0, st, g, a,
                        h, c0, c1);
@@ -608,7 +594,7 @@ static void hub_decide_t(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
     hipLaunchKernelGGL((k_hub_part_eval<WT, PH, DET>), dim3(grid_items(s1 - s0, 1, 512)), dim3(kPartThreads), 0,
                        st, g, a, h, s0, s1);
   }
-  *launches += tables ? 5 : 3;
+  *launches += tables ? 4 : 2;
 }
 
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,

@@ -5,14 +5,14 @@
 namespace gvl {
 
 void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
-                        int64_t* launches) {
+                        const int32_t* count, const int32_t* start, bool det, int grid_cap, const HubArgs& h,
+                        int32_t h0, int32_t h1, int64_t* launches) {
   if (g.w_double) {
-    if (det) decide_bins<double, kMove, true>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
-    else decide_bins<double, kMove, false>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
+    if (det) decide_bins<double, kMove, true>(st, g, a, list, count, start, grid_cap, h, h0, h1, launches);
+    else decide_bins<double, kMove, false>(st, g, a, list, count, start, grid_cap, h, h0, h1, launches);
   } else {
-    if (det) decide_bins<float, kMove, true>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
-    else decide_bins<float, kMove, false>(st, g, a, list, count, start, grid_cap, hub_grid, launches);
+    if (det) decide_bins<float, kMove, true>(st, g, a, list, count, start, grid_cap, h, h0, h1, launches);
+    else decide_bins<float, kMove, false>(st, g, a, list, count, start, grid_cap, h, h0, h1, launches);
   }
 }
 

@@ -286,17 +286,20 @@ struct AggArgs {
 
 // ---- scan kernels (k_scan_move.hip, k_scan_refine.hip); one call per group
 // `list` is the whole bin list; count/start are the group's bin segments.
+// The same launch takes the eligibility snapshot of the group's hubs
+// [h0, h1) (h.items indices; an empty range for none) and resets their
+// per-decision state, before hub_decide runs on them.
 void launch_decide_move(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                        const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
-                        int64_t* launches);
+                        const int32_t* count, const int32_t* start, bool det, int grid_cap, const HubArgs& h,
+                        int32_t h0, int32_t h1, int64_t* launches);
 void launch_decide_refine(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const int32_t* list,
-                          const int32_t* count, const int32_t* start, bool det, int grid_cap, int hub_grid,
-                          int64_t* launches);
+                          const int32_t* count, const int32_t* start, bool det, int grid_cap, const HubArgs& h,
+                          int32_t h0, int32_t h1, int64_t* launches);
 // Applies the recorded synchronous decisions of one group in one launch.
 // Local-moving: rows of up to kBinMax[4] arcs in tiles (community totals
 // through the workgroup-combined table; the movers' rows marked end to end),
 // longer rows one workgroup each, hub moves applied in tiles (their targets
-// are forgotten by the next k_hub_prep) and hub rows marked chunk by chunk.
+// are forgotten by the next group's hub snapshot) and hub rows marked chunk by chunk.
 // Refinement: both lists in tiles; vertex i moves only if its own community
 // was not chosen as a target by this group (stamp).
 struct CommitLaunch {
@@ -323,8 +326,9 @@ void hub_setup(hipStream_t st, const int32_t* off, const int32_t* deg, const int
                int64_t n, int32_t* chunk_off, int32_t* tbl_off, int32_t* slice_off);
 void hub_tasks(hipStream_t st, int32_t H, const int32_t* chunk_off, const int32_t* slice_off, int2* chunk_tasks,
                int2* slice_tasks);
-// One batch [h0, h1) of one group: eligibility snapshot, gather, own-community
-// weight, evaluation (+ commit in fast local-moving).
+// One batch [h0, h1) of one group: gather, own-community weight, evaluation
+// (+ commit in fast local-moving); the group's decision launch has taken
+// the hubs' eligibility snapshot.
 void hub_decide(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, int32_t h0, int32_t h1,
                 int32_t c0, int32_t c1, int32_t s0, int32_t s1, bool tables, int phase, bool det, int64_t* launches);
 // K[i] += sums of the chunks of hub rows (K[i] of hubs zeroed by the caller).

@@ -447,7 +447,13 @@ __device__ __forceinline__ void eval_table(int32_t* keys, double* vals, int ts, 
 struct GroupLaunch {
   int32_t count[6];
   int32_t start[6];
-  int32_t blk[7];
+  // the group's hub snapshot, served by blocks [blk[6], blk[7]): hubs
+  // [h0, h1) of HubArgs::items, with its active and kid arrays
+  const int32_t* h_items;
+  int32_t* h_active;
+  double* h_kid;
+  int32_t h0, h1;
+  int32_t blk[8];
 };
 constexpr int kGroupSlots = 2048;  // LDS slots of one workgroup: the largest GPB * 2^LG of bins 0-4, bin 5's table
 static_assert(kBinLanes[5] == kBlock, "bin 5: one workgroup per vertex");
@@ -690,24 +696,45 @@ __device__ __forceinline__ void decide_block_body(const GraphView<WT>& g, const 
   flush_acc<PH, DET>(a, acc);
 }
 
+// Eligibility snapshot of hubs p = t0, t0 + stride, ... < h1 of a group,
+// taken before any of their chunks is gathered: active[p], K_{i->d} and the
+// target reset (a synchronous local-moving commit applies a hub's target
+// without forgetting it), the pruning flag cleared (Alg. 2).
+template <int PH, bool DET>
+__device__ __forceinline__ void hub_prep_body(const ScanArgs& a, const GroupLaunch& gl, int64_t t0, int64_t stride) {
+  for (int64_t p = t0; p < gl.h1; p += stride) {
+    const int32_t i = gl.h_items[p];
+    const bool act = Decide<PH, DET>::eligible(a, i);
+    gl.h_active[p] = act ? 1 : 0;
+    gl.h_kid[p] = 0.0;
+    a.target[i] = -1;
+    if (PH == kMove && act) a.flag[i] = 0;  // processed (Alg. 2 prune)
+  }
+}
+
 // The short-row decisions of a group: bins 0-5 in one launch, so the rows of
-// bin 5 fill the CUs that the lane-group bins leave as they finish.
+// bin 5 fill the CUs that the lane-group bins leave as they finish; the
+// last blocks take the group's hub snapshot (the hub kernels follow on the
+// same stream).
 template <class WT, int PH, bool DET>
 __global__ __launch_bounds__(kBlock) void k_decide_groups(GraphView<WT> g, ScanArgs a,
                                                           const int32_t* __restrict__ list, GroupLaunch gl) {
   __shared__ int32_t skeys[kGroupSlots];
   __shared__ double svals[kGroupSlots];
   int b = 0;
-  while (b < 5 && (int32_t)blockIdx.x >= gl.blk[b + 1]) ++b;  // uniform over the workgroup
+  while (b < 6 && (int32_t)blockIdx.x >= gl.blk[b + 1]) ++b;  // uniform over the workgroup
   const int32_t bid = (int32_t)blockIdx.x - gl.blk[b], nb = gl.blk[b + 1] - gl.blk[b];
-  const int32_t* l = list + gl.start[b];
+  const int32_t* l = list + (b < 6 ? gl.start[b] : 0);
   switch (b) {
     case 0: decide_group_body<kBinLanes[0], 3, kBinMax[0], WT, PH, DET>(g, a, l, gl.count[0], bid, nb, skeys, svals); break;
     case 1: decide_group_body<kBinLanes[1], 4, kBinMax[1], WT, PH, DET>(g, a, l, gl.count[1], bid, nb, skeys, svals); break;
     case 2: decide_group_body<kBinLanes[2], 5, kBinMax[2], WT, PH, DET>(g, a, l, gl.count[2], bid, nb, skeys, svals); break;
     case 3: decide_group_body<kBinLanes[3], 6, kBinMax[3], WT, PH, DET>(g, a, l, gl.count[3], bid, nb, skeys, svals); break;
     case 4: decide_group_body<kBinLanes[4], 8, kBinMax[4], WT, PH, DET>(g, a, l, gl.count[4], bid, nb, skeys, svals); break;
-    default: decide_block_body<11, WT, PH, DET>(g, a, l, gl.count[5], bid, nb, skeys, svals); break;
+    case 5: decide_block_body<11, WT, PH, DET>(g, a, l, gl.count[5], bid, nb, skeys, svals); break;
+    default:
+      hub_prep_body<PH, DET>(a, gl, (int64_t)gl.h0 + (int64_t)bid * kBlock + threadIdx.x, (int64_t)nb * kBlock);
+      break;
   }
 }
 
@@ -1178,9 +1205,10 @@ inline int grid_for(int64_t items, int per_block, int cap) {
 
 template <class WT, int PH, bool DET>
 void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const int32_t* list,
-                 const int32_t* count, const int32_t* start, int grid_cap, int hub_grid, int64_t* launches) {
+                 const int32_t* count, const int32_t* start, int grid_cap, const HubArgs& h, int32_t h0, int32_t h1,
+                 int64_t* launches) {
   const GraphView<WT> g = view<WT>(gd);
-  {  // bins 0-5: one launch
+  {  // bins 0-5 and the hub snapshot: one launch
     GroupLaunch gl;
     gl.blk[0] = 0;
     for (int b = 0; b < 6; ++b) {
@@ -1188,8 +1216,14 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
       gl.start[b] = start[b];
       gl.blk[b + 1] = gl.blk[b] + (count[b] > 0 ? grid_for(count[b], kBlock / kBinLanes[b], grid_cap) : 0);
     }
-    if (gl.blk[6] > 0) {
-      hipLaunchKernelGGL((k_decide_groups<WT, PH, DET>), dim3(gl.blk[6]), dim3(kBlock), 0, st, g, a, list, gl);
+    gl.h_items = h.items;
+    gl.h_active = h.active;
+    gl.h_kid = h.kid;
+    gl.h0 = h0;
+    gl.h1 = h1;
+    gl.blk[7] = gl.blk[6] + (h1 > h0 ? grid_for(h1 - h0, kBlock, 1024) : 0);
+    if (gl.blk[7] > 0) {
+      hipLaunchKernelGGL((k_decide_groups<WT, PH, DET>), dim3(gl.blk[7]), dim3(kBlock), 0, st, g, a, list, gl);
       ++*launches;
     }
   }
@@ -1206,7 +1240,6 @@ void decide_bins(hipStream_t st, const GraphDesc& gd, const ScanArgs& a, const i
     hipLaunchKernelGGL((k_decide_wide<WT, PH, DET>), dim3(grid), dim3(kWideThreads), 0, st, g, a, list, wl);
     ++*launches;
   }
-  (void)hub_grid;  // the hub bin goes through the chunked hub path
 }
 
 // One launch for the commits of a group (see k_commit).
