@@ -186,8 +186,11 @@ WIDER_BAR = {"rmat-s12": 4e-3, "er-selfloops": 6e-3, "grid64-w100": 1.5e-3}
 # the sequential oracle's modularity minus the wider of the fixed margin and
 # its own spread over the given and seven seeded numberings, and the best of
 # up to ASYNC_TRIES runs must reach it.  Every run must still report Eq. 1 of
-# its membership and leave no community disconnected.
-ASYNC_TRIES = 3
+# its membership and leave no community disconnected.  (planted-small, 40 runs
+# each with three library builds: 33 to 37 runs reached the bar, and three
+# misses in a row did occur; eight tries leave a chance of about 3e-7 for a
+# schedule whose runs reach it 85 % of the time.)
+ASYNC_TRIES = 8
 _SPREAD = {}
 
 
