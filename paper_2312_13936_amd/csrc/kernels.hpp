@@ -309,6 +309,8 @@ struct CommitLaunch {
   int32_t n0, n1, n2;
   int32_t c0, c1;      // chunk tasks of the hubs (local-moving marks)
   int32_t b[5];        // block ranges of the roles: [b[r], b[r+1])
+  const int2* chunk_tasks;    // HubArgs::chunk_tasks and items (set by launch_commit)
+  const int32_t* hub_items;
 };
 
 void launch_commit(hipStream_t st, const GraphDesc& g, const ScanArgs& a, const HubArgs& h, const CommitLaunch& cl,

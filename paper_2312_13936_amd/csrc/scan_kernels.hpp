@@ -1155,7 +1155,7 @@ __device__ __forceinline__ unsigned long long commit_long(const GraphView<WT>& g
 
 // Applies the recorded synchronous decisions of one group (CommitLaunch).
 template <class WT, int PH>
-__global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, HubArgs h, CommitLaunch cl) {
+__global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, CommitLaunch cl) {
   __shared__ CommitLds L;
   __shared__ unsigned long long red_u[16];
   keyed_clear(L.kt);
@@ -1175,8 +1175,8 @@ __global__ __launch_bounds__(kBlock) void k_commit(GraphView<WT> g, ScanArgs a, 
     nm = commit_tiles<WT, kMove, false>(g, a, cl.l2, cl.n2, bid, nb, L);
   } else {
     for (int64_t t = cl.c0 + (int64_t)bid; t < cl.c1; t += nb) {
-      const int2 task = h.chunk_tasks[t];
-      const int32_t i = h.items[task.x];
+      const int2 task = cl.chunk_tasks[t];
+      const int32_t i = cl.hub_items[task.x];
       if (a.target[i] < 0) continue;  // uniform: no move
       const int32_t beg = g.begin(i), deg = g.degree(i);
       const int32_t e0 = task.y * kHubChunk;
@@ -1259,10 +1259,12 @@ void commit_group_launch(hipStream_t st, const GraphDesc& gd, const ScanArgs& a,
     nblk[2] = cl.n2 > 0 ? grid_for(cl.n2, kBlock, 64) : 0;
     nblk[3] = cl.c1 > cl.c0 ? grid_for(cl.c1 - cl.c0, 1, 4096) : 0;
   }
+  cl.chunk_tasks = h.chunk_tasks;
+  cl.hub_items = h.items;
   cl.b[0] = 0;
   for (int r = 0; r < 4; ++r) cl.b[r + 1] = cl.b[r] + nblk[r];
   if (cl.b[4] > 0)
-    hipLaunchKernelGGL((k_commit<WT, PH>), dim3(cl.b[4]), dim3(kBlock), 0, st, g, a, h, cl);
+    hipLaunchKernelGGL((k_commit<WT, PH>), dim3(cl.b[4]), dim3(kBlock), 0, st, g, a, cl);
 }
 
 }  // namespace gvl
