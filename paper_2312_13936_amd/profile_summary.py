@@ -27,7 +27,7 @@ import re
 import sys
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-SCAN = re.compile(r"k_decide_|k_hub_(prep|gather|eval|part_eval)")
+SCAN = re.compile(r"k_decide_|k_hub_(gather|eval|part_eval)")
 AGG = re.compile(r"k_agg_(group|rows)|k_gagg_|k_member_degrees")
 COPY = re.compile(r"copyBuffer|copy_kernel|CatArrayBatchedCopy|elementwise_kernel.*copy", re.I)
 
@@ -68,7 +68,7 @@ def stats(stats_csv, bench_json, calls, out, command):
              "One gvl_leiden call: %.1f ms wall, Q = %.4f, %d passes, %s mode." % (
                  bench["ms_per_step"], bench["modularity"], bench["passes"], bench["config"]["mode"]), "",
              "| kernel class | rocprofv3, per call (ms) | HIP events in bench.py, per call (ms) |", "|---|---|---|",
-             "| neighbour-community scan (`k_decide_*`, `k_hub_prep/gather/eval/part_eval`) | %.1f | %.1f |" % (
+             "| neighbour-community scan (`k_decide_*`, `k_hub_gather/eval/part_eval`) | %.1f | %.1f |" % (
                  cls["scan"] / calls, ph.get("scan_kernels_ms", float("nan"))),
              "| aggregation rows (`k_agg_*`, `k_gagg_*`, `k_member_degrees`) | %.1f | %.1f |" % (
                  cls["agg"] / calls, ph.get("agg_kernels_ms", float("nan"))),
