@@ -476,7 +476,7 @@ __device__ __forceinline__ void decide_group_body(const GraphView<WT>& g, const 
   Acc acc;
   const bool sync = DET || (a.sync_moves & 1);
   const int32_t it = launch_iteration<PH>(a, sync);
-  // rows software pipelined as in k_decide_block: a row's state is loaded
+  // rows software pipelined as in decide_block_body: a row's state is loaded
   // while the row before it is scanned, its list entry one row earlier
   const int64_t step = (int64_t)nb * GPB;
   const int64_t v0 = (int64_t)bid * GPB + gb;

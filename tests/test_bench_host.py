@@ -46,7 +46,7 @@ def test_counters_scale_by_the_copy_and_sum_per_class(tmp_path):
              ("void gvl::k_gagg_gather<float>(...)", 100.0),
              ("gvl::k_mod_squares(...)", 7777.0)]          # neither class
     write = [("__amd_rocclr_copyBuffer", calib / 1024),
-             ("void gvl::k_decide_block<11, float, 0, false>(...)", 10.0),
+             ("void gvl::k_decide_groups<float, 0, false>(...)", 10.0),
              ("void gvl::k_agg_group<float, float, 4, 3>(...)", 20.0)]
     fp, wp = tmp_path / "f.csv", tmp_path / "w.csv"
     _counter_csv(fp, "FETCH_SIZE", fetch)
@@ -75,7 +75,7 @@ def test_recorded_traffic_is_dropped_when_sources_change(tmp_path):
 
 def test_pmc_tables_per_call_totals_and_ratios(tmp_path):
     a, b = tmp_path / "a.csv", tmp_path / "b.csv"
-    scan = "void gvl::k_decide_block<11, float, 0, false>(...)"
+    scan = "void gvl::k_decide_groups<float, 0, false>(...)"
     agg = "void gvl::k_agg_rows<float, float, 256, 2048>(...)"
     _counter_csv(a, "SQ_WAVE_CYCLES", [(scan, 1000.0), (agg, 400.0)])
     with open(a, "a", newline="") as f:  # a second counter of the same pass
